@@ -1,0 +1,168 @@
+/*
+ * gp_ssm -- exact O(N) Gaussian-process likelihood, gradient and posterior for
+ * exposure-integrated, possibly overlapping measurements of a sum of SHO
+ * (stochastically driven damped harmonic oscillator) processes, computed by a
+ * Kalman filter / RTS smoother over the augmented state-space model of
+ * "Scalable Gaussian Processes for Integrated and Overlapping Measurements via
+ * Augmented State-Space Models" (Sec. 3.2: an integrator state per instrument,
+ * reset when an exposure opens and read out when it closes), on AMD MI355X
+ * (gfx950) in FP64.
+ *
+ * Problem statement (Sec. 3.2, exposure-averaged measurement model):
+ *   y_n = (1/delta_n) int_{t^s_n}^{t^e_n} f(t) dt + eps_n,
+ *   eps_n ~ N(0, yerr_n^2 + jitter^2),   delta_n = t^e_n - t^s_n,
+ *   f = sum_{m=1..M} SHO_m,  SHO covariance with (sigma_m, omega0_m, Q_m)
+ *   as in Appendix B (k(0) = sigma^2, omega0 in rad per time unit).
+ * A zero-length exposure (t^e_n == t^s_n) is an instantaneous sample of f.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - A batch holds B independent series.  offsets[B+1] (int64, ascending,
+ *    offsets[0] = 0) delimits each series' measurements in the flat arrays
+ *    t_start, t_end, y, yerr (length offsets[B]).  Within a series t_start
+ *    must be non-decreasing; t_end >= t_start; yerr >= 0; all finite.
+ *  - Hyperparameters are series-major: sigma[b*M + m], omega0[b*M + m],
+ *    quality[b*M + m] (all > 0, finite), jitter[b] (>= 0) or NULL for zero.
+ *  - Every array argument is a DEVICE pointer (hipMalloc'd or managed) unless
+ *    stated otherwise; the caller owns all buffers.  `stream` is a
+ *    hipStream_t (NULL = the default stream); kernels are enqueued on it and
+ *    outputs are valid once it has synchronised.  Functions that need host
+ *    copies of their inputs (plan creation, hyperparameter validation)
+ *    synchronise with `stream` first.
+ *  - At most GP_SSM_MAX_TERMS terms and GP_SSM_MAX_SLOTS simultaneously open
+ *    exposures per series (the overlap depth; instrument labels are assigned
+ *    internally, Sec. 3.2.3).
+ *  - Return value: 0 on success, else a negative GP_SSM_E* code with a
+ *    message from gp_ssm_last_error().  Arguments are validated before any
+ *    device work.  Per-series status[b] (int32, may be NULL) receives 0 or
+ *    GP_SSM_ENUMERIC for a series whose likelihood is not finite (a
+ *    non-positive innovation variance or a singular summary); its outputs
+ *    are then NaN and other series are unaffected.
+ */
+#ifndef GP_SSM_H
+#define GP_SSM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GP_SSM_MAX_TERMS 4
+#define GP_SSM_MAX_SLOTS 4
+
+#define GP_SSM_OK 0
+#define GP_SSM_EINVAL (-1)   /* null pointer, B < 1, M out of range, bad offsets */
+#define GP_SSM_EDATA (-2)    /* non-finite data, t_end < t_start, unsorted t_start, yerr < 0 */
+#define GP_SSM_EPARAM (-3)   /* sigma, omega0 or Q <= 0 or non-finite; jitter < 0 or non-finite */
+#define GP_SSM_EOVERLAP (-4) /* more than GP_SSM_MAX_SLOTS exposures open at once */
+#define GP_SSM_ENUMERIC (-5) /* some series had a non-finite result; see status[] */
+#define GP_SSM_EDEVICE (-6)  /* no usable gfx950 device or a HIP error */
+#define GP_SSM_ENOMEM (-7)   /* device or host allocation failed */
+
+/* Opaque, hyperparameter-independent description of a batch: the event
+ * stream of every series (starts and ends of exposures, Sec. 3.2, ordered in
+ * time with ends first at ties), instrument slots, and the split of each
+ * series into chunks at instants where no exposure is open.  Lives on the
+ * device that was current at creation. */
+typedef struct gp_ssm_plan gp_ssm_plan;
+
+typedef struct {
+  int32_t chunk_min;     /* shortest chunk in events (default 24) */
+  int32_t chunk_target;  /* target chunk length in events; 0 = derived from the batch */
+  int64_t target_chunks; /* wanted number of chunks when deriving (default 131072) */
+  int32_t single_chunk;  /* 1 = never split a series in time */
+  int32_t threads;       /* host threads used to build the plan; 0 = all */
+} gp_ssm_plan_options;
+
+typedef struct {
+  int64_t n_series, n_meas, n_events, n_events_padded;
+  int32_t n_chunks, n_segments, max_slots, max_chunk_len;
+} gp_ssm_plan_stats;
+
+/* Fills *opt with the defaults. */
+void gp_ssm_plan_default_options(gp_ssm_plan_options* opt);
+
+/* Builds a plan for the batch.  offsets may be a host or device pointer; the
+ * measurement arrays are device pointers (copied to the host to plan).  The
+ * plan keeps its own copy of the data in event order; the inputs may be
+ * freed afterwards.  opt may be NULL (defaults).  Returns GP_SSM_EINVAL,
+ * GP_SSM_EDATA, GP_SSM_EOVERLAP, GP_SSM_ENOMEM or GP_SSM_EDEVICE on failure,
+ * with *out set to NULL. */
+int gp_ssm_plan_create(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end,
+                       const double* y, const double* yerr, const gp_ssm_plan_options* opt, void* stream,
+                       gp_ssm_plan** out);
+
+/* Releases the plan and its device memory (and any workspace it grew). */
+void gp_ssm_plan_destroy(gp_ssm_plan* plan);
+
+/* Sizes of the plan (host output). */
+int gp_ssm_plan_get_stats(const gp_ssm_plan* plan, gp_ssm_plan_stats* out);
+
+/* Log-likelihood of every series (Sec. 2.4 with the augmented filter of
+ * Sec. 3.2), including -N/2 log 2 pi.  loglik[B] (device), status[B] (device,
+ * may be NULL). */
+int gp_ssm_plan_loglik(gp_ssm_plan* plan, int32_t n_terms, const double* sigma, const double* omega0,
+                       const double* quality, const double* jitter, double* loglik, int32_t* status, void* stream);
+
+/* Log-likelihood and its gradient by a reverse-mode adjoint of the filter.
+ * grad[b*(3M+1) + k] holds d loglik_b / d(sigma_1..M, omega0_1..M,
+ * Q_1..M, jitter) in that order. */
+int gp_ssm_plan_loglik_grad(gp_ssm_plan* plan, int32_t n_terms, const double* sigma, const double* omega0,
+                            const double* quality, const double* jitter, double* loglik, double* grad, int32_t* status,
+                            void* stream);
+
+/* Posterior (RTS smoother, Sec. 3.2.2, and prediction at arbitrary times,
+ * Sec. 2.5 Algorithm 1).  test_offsets[B+1] (host or device int64) delimits
+ * each series' test times in t_test (device, any order within a series).
+ * mean_test/var_test[test_offsets[B]] receive the posterior mean and
+ * variance of the latent instantaneous f(t*).  mean_data/var_data[N] (may be
+ * NULL) receive the posterior of the exposure-averaged f at each measurement.
+ * loglik[B] may be NULL. */
+int gp_ssm_plan_smooth(gp_ssm_plan* plan, int32_t n_terms, const double* sigma, const double* omega0,
+                       const double* quality, const double* jitter, const int64_t* test_offsets, const double* t_test,
+                       double* mean_test, double* var_test, double* mean_data, double* var_data, double* loglik,
+                       int32_t* status, void* stream);
+
+/* Reference "plain" GPU filter: the same per-event device code, one series at
+ * a time, one lane, no time splitting, one launch per series.  Computes the
+ * log-likelihood of series [first, first+count) of the plan.  Used as the
+ * baseline that the batched launch is compared with. */
+int gp_ssm_plan_plain_loglik(gp_ssm_plan* plan, int64_t first, int64_t count, int32_t n_terms, const double* sigma,
+                             const double* omega0, const double* quality, const double* jitter, double* loglik,
+                             void* stream);
+
+/* One-shot forms: build a plan with default options, run, destroy. */
+int gp_ssm_loglik(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end, const double* y,
+                  const double* yerr, int32_t n_terms, const double* sigma, const double* omega0, const double* quality,
+                  const double* jitter, double* loglik, int32_t* status, void* stream);
+int gp_ssm_loglik_grad(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end,
+                       const double* y, const double* yerr, int32_t n_terms, const double* sigma, const double* omega0,
+                       const double* quality, const double* jitter, double* loglik, double* grad, int32_t* status,
+                       void* stream);
+int gp_ssm_smooth(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end,
+                  const double* y, const double* yerr, int32_t n_terms, const double* sigma, const double* omega0,
+                  const double* quality, const double* jitter, const int64_t* test_offsets, const double* t_test,
+                  double* mean_test, double* var_test, double* mean_data, double* var_data, int32_t* status,
+                  void* stream);
+
+/* Kernel timing.  While enabled, every kernel the library launches is
+ * bracketed by HIP events on its stream and its duration is accumulated per
+ * kernel name.  gp_ssm_profile_read copies up to `cap` entries (name, count,
+ * total milliseconds) and returns the number of distinct kernels; names are
+ * library-owned static strings.  Reading synchronises the device. */
+int gp_ssm_profile_enable(int32_t on);
+int gp_ssm_profile_reset(void);
+int gp_ssm_profile_read(const char** names, int64_t* counts, double* total_ms, int32_t cap);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* gp_ssm_last_error(void);
+
+/* Library version string. */
+const char* gp_ssm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GP_SSM_H */

@@ -1,0 +1,275 @@
+"""Python binding of the gp_ssm HIP library (``libgp_ssm.so``).
+
+Thin argument marshalling over the C-ABI declared in ``include/gp_ssm.h``:
+every numerical step runs in the library's kernels.  PyTorch supplies device
+memory and the current stream.  Importing this package does not need a GPU;
+creating a plan or running a computation does, and raises if the library or
+the device is missing.
+
+    plan = Plan(offsets, t_start, t_end, y, yerr)          # once per dataset
+    ll = plan.loglik(sigma, omega0, quality, jitter)        # [B]
+    ll, g = plan.loglik_grad(sigma, omega0, quality, jitter)  # g: [B, 3M+1]
+    ll = loglik_autograd(plan, sigma, omega0, quality, jitter)  # differentiable
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgp_ssm.so")
+
+GP_SSM_OK = 0
+ERRORS = {-1: "EINVAL", -2: "EDATA", -3: "EPARAM", -4: "EOVERLAP", -5: "ENUMERIC", -6: "EDEVICE", -7: "ENOMEM"}
+
+# every symbol include/gp_ssm.h declares
+EXPORTS = [
+    "gp_ssm_plan_default_options", "gp_ssm_plan_create", "gp_ssm_plan_destroy", "gp_ssm_plan_get_stats",
+    "gp_ssm_plan_loglik", "gp_ssm_plan_loglik_grad", "gp_ssm_plan_smooth", "gp_ssm_plan_plain_loglik",
+    "gp_ssm_loglik", "gp_ssm_loglik_grad", "gp_ssm_smooth", "gp_ssm_profile_enable", "gp_ssm_profile_reset",
+    "gp_ssm_profile_read", "gp_ssm_last_error", "gp_ssm_version",
+]
+
+
+class GpSsmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"gp_ssm error {ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class PlanOptions(ctypes.Structure):
+    _fields_ = [("chunk_min", ctypes.c_int32), ("chunk_target", ctypes.c_int32), ("target_chunks", ctypes.c_int64),
+                ("single_chunk", ctypes.c_int32), ("threads", ctypes.c_int32)]
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("n_series", ctypes.c_int64), ("n_meas", ctypes.c_int64), ("n_events", ctypes.c_int64),
+                ("n_events_padded", ctypes.c_int64), ("n_chunks", ctypes.c_int32), ("n_segments", ctypes.c_int32),
+                ("max_slots", ctypes.c_int32), ("max_chunk_len", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def library():
+    """Loads the library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2601_02527_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.gp_ssm_plan_default_options.argtypes = [ctypes.POINTER(PlanOptions)]
+    L.gp_ssm_plan_default_options.restype = None
+    L.gp_ssm_plan_create.argtypes = [i64, vp, vp, vp, vp, vp, ctypes.POINTER(PlanOptions), vp, ctypes.POINTER(vp)]
+    L.gp_ssm_plan_destroy.argtypes = [vp]
+    L.gp_ssm_plan_destroy.restype = None
+    L.gp_ssm_plan_get_stats.argtypes = [vp, ctypes.POINTER(PlanStats)]
+    L.gp_ssm_plan_loglik.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.gp_ssm_plan_loglik_grad.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.gp_ssm_plan_smooth.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.gp_ssm_plan_plain_loglik.argtypes = [vp, i64, i64, i32, vp, vp, vp, vp, vp, vp]
+    L.gp_ssm_loglik.argtypes = [i64, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.gp_ssm_loglik_grad.argtypes = [i64, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.gp_ssm_smooth.argtypes = [i64, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.gp_ssm_profile_enable.argtypes = [i32]
+    L.gp_ssm_profile_read.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(i64),
+                                      ctypes.POINTER(ctypes.c_double), i32]
+    L.gp_ssm_last_error.restype = ctypes.c_char_p
+    L.gp_ssm_version.restype = ctypes.c_char_p
+    for name in ("gp_ssm_plan_create", "gp_ssm_plan_get_stats", "gp_ssm_plan_loglik", "gp_ssm_plan_loglik_grad",
+                 "gp_ssm_plan_smooth", "gp_ssm_plan_plain_loglik", "gp_ssm_loglik", "gp_ssm_loglik_grad",
+                 "gp_ssm_smooth", "gp_ssm_profile_enable", "gp_ssm_profile_reset", "gp_ssm_profile_read"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise GpSsmError(rc, library().gp_ssm_last_error().decode())
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("gp_ssm needs a GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _dev(x, dtype=None):
+    """A contiguous device tensor (float64 unless dtype is given)."""
+    torch = _torch()
+    dtype = dtype or torch.float64
+    if isinstance(x, torch.Tensor):
+        return x.to(device="cuda", dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def default_options(**kw):
+    o = PlanOptions()
+    library().gp_ssm_plan_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Plan:
+    """Hyperparameter-independent event plan of a batch of series."""
+
+    def __init__(self, offsets, t_start, t_end, y, yerr, **options):
+        torch = _torch()
+        L = library()
+        self.offsets = _dev(offsets, torch.int64)
+        ts, te, yy, ye = (_dev(a) for a in (t_start, t_end, y, yerr))
+        self.n_series = int(self.offsets.numel() - 1)
+        self.n_meas = int(ts.numel())
+        opt = default_options(**options)
+        h = ctypes.c_void_p()
+        _check(L.gp_ssm_plan_create(self.n_series, _ptr(self.offsets), _ptr(ts), _ptr(te), _ptr(yy), _ptr(ye),
+                                    ctypes.byref(opt), _stream(), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().gp_ssm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self):
+        s = PlanStats()
+        _check(library().gp_ssm_plan_get_stats(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in PlanStats._fields_}
+
+    def _params(self, sigma, omega0, quality, jitter):
+        torch = _torch()
+        sigma = _dev(sigma).reshape(self.n_series, -1)
+        M = sigma.shape[1]
+        omega0 = _dev(omega0).reshape(self.n_series, M)
+        quality = _dev(quality).reshape(self.n_series, M)
+        jit = None if jitter is None else _dev(jitter).reshape(self.n_series)
+        return M, sigma, omega0, quality, jit
+
+    def loglik(self, sigma, omega0, quality, jitter=None, status=False):
+        torch = _torch()
+        M, s, w, q, j = self._params(sigma, omega0, quality, jitter)
+        out = torch.empty(self.n_series, dtype=torch.float64, device="cuda")
+        st = torch.empty(self.n_series, dtype=torch.int32, device="cuda")
+        _check(library().gp_ssm_plan_loglik(self._h, M, _ptr(s), _ptr(w), _ptr(q), _ptr(j), _ptr(out), _ptr(st),
+                                            _stream()))
+        return (out, st) if status else out
+
+    def loglik_grad(self, sigma, omega0, quality, jitter=None, status=False):
+        torch = _torch()
+        M, s, w, q, j = self._params(sigma, omega0, quality, jitter)
+        out = torch.empty(self.n_series, dtype=torch.float64, device="cuda")
+        g = torch.empty(self.n_series, 3 * M + 1, dtype=torch.float64, device="cuda")
+        st = torch.empty(self.n_series, dtype=torch.int32, device="cuda")
+        _check(library().gp_ssm_plan_loglik_grad(self._h, M, _ptr(s), _ptr(w), _ptr(q), _ptr(j), _ptr(out), _ptr(g),
+                                                 _ptr(st), _stream()))
+        return (out, g, st) if status else (out, g)
+
+    def plain_loglik(self, sigma, omega0, quality, jitter=None, first=0, count=None):
+        torch = _torch()
+        M, s, w, q, j = self._params(sigma, omega0, quality, jitter)
+        count = self.n_series - first if count is None else count
+        out = torch.full((self.n_series,), float("nan"), dtype=torch.float64, device="cuda")
+        _check(library().gp_ssm_plan_plain_loglik(self._h, first, count, M, _ptr(s), _ptr(w), _ptr(q), _ptr(j),
+                                                  _ptr(out), _stream()))
+        return out
+
+    def smooth(self, sigma, omega0, quality, jitter, test_offsets, t_test, data=True):
+        torch = _torch()
+        M, s, w, q, j = self._params(sigma, omega0, quality, jitter)
+        to = _dev(test_offsets, torch.int64)
+        tt = _dev(t_test)
+        mt = torch.empty_like(tt)
+        vt = torch.empty_like(tt)
+        md = torch.empty(self.n_meas, dtype=torch.float64, device="cuda") if data else None
+        vd = torch.empty(self.n_meas, dtype=torch.float64, device="cuda") if data else None
+        ll = torch.empty(self.n_series, dtype=torch.float64, device="cuda")
+        st = torch.empty(self.n_series, dtype=torch.int32, device="cuda")
+        _check(library().gp_ssm_plan_smooth(self._h, M, _ptr(s), _ptr(w), _ptr(q), _ptr(j), _ptr(to), _ptr(tt),
+                                            _ptr(mt), _ptr(vt), _ptr(md), _ptr(vd), _ptr(ll), _ptr(st), _stream()))
+        return dict(mean_test=mt, var_test=vt, mean_data=md, var_data=vd, loglik=ll, status=st)
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class LogLikelihood(torch.autograd.Function):
+        """log-likelihood per series with its gradient from the adjoint kernel."""
+
+        @staticmethod
+        def forward(ctx, sigma, omega0, quality, jitter, plan):
+            need = any(ctx.needs_input_grad[:4])
+            if need:
+                ll, g = plan.loglik_grad(sigma, omega0, quality, jitter)
+                ctx.save_for_backward(g)
+                ctx.M = sigma.reshape(plan.n_series, -1).shape[1]
+                ctx.shapes = (sigma.shape, omega0.shape, quality.shape, None if jitter is None else jitter.shape)
+            else:
+                ll = plan.loglik(sigma, omega0, quality, jitter)
+            return ll
+
+        @staticmethod
+        def backward(ctx, gout):
+            (g,) = ctx.saved_tensors
+            M = ctx.M
+            gg = g * gout[:, None]
+            ds = gg[:, :M].reshape(ctx.shapes[0])
+            dw = gg[:, M:2 * M].reshape(ctx.shapes[1])
+            dq = gg[:, 2 * M:3 * M].reshape(ctx.shapes[2])
+            dj = None if ctx.shapes[3] is None else gg[:, 3 * M].reshape(ctx.shapes[3])
+            return ds, dw, dq, dj, None
+
+    return LogLikelihood
+
+
+_LL = None
+
+
+def loglik_autograd(plan, sigma, omega0, quality, jitter=None):
+    """Differentiable log-likelihood of every series of ``plan``."""
+    global _LL
+    if _LL is None:
+        _LL = _autograd_function()
+    return _LL.apply(sigma, omega0, quality, jitter, plan)
+
+
+def profile_enable(on=True):
+    _check(library().gp_ssm_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(library().gp_ssm_profile_reset())
+
+
+def profile_read():
+    L = library()
+    cap = 64
+    names = (ctypes.c_char_p * cap)()
+    counts = (ctypes.c_int64 * cap)()
+    tot = (ctypes.c_double * cap)()
+    n = L.gp_ssm_profile_read(names, counts, tot, cap)
+    return {names[i].decode(): (int(counts[i]), float(tot[i])) for i in range(min(n, cap))}
+
+
+def version():
+    return library().gp_ssm_version().decode()

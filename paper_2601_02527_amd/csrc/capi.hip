@@ -1,0 +1,668 @@
+// C-ABI of the library (declared in include/gp_ssm.h): plans, workspace,
+// hyperparameter preparation, the cross-chunk combination and the dispatch of
+// the per-(terms, slots) kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gp_ssm.h"
+#include "kernels.h"
+#include "plan.h"
+
+using namespace gpssm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return fail(GP_SSM_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+struct Prof {
+  std::mutex mu;
+  bool on = false;
+  struct Pending {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  std::map<std::string, std::pair<int64_t, double>> total;
+  std::vector<std::string> names;  // stable storage for returned names
+  hipEvent_t cur_a = nullptr;
+} g_prof;
+
+hipEvent_t prof_event() {
+  if (!g_prof.pool.empty()) {
+    hipEvent_t e = g_prof.pool.back();
+    g_prof.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_flush() {
+  for (auto& p : g_prof.pending) {
+    (void)hipEventSynchronize(p.b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p.a, p.b);
+    auto& t = g_prof.total[p.name];
+    t.first += 1;
+    t.second += ms;
+    g_prof.pool.push_back(p.a);
+    g_prof.pool.push_back(p.b);
+  }
+  g_prof.pending.clear();
+}
+
+// ---------------------------------------------------------------------------
+// small kernels that do not depend on the slot count
+// ---------------------------------------------------------------------------
+__global__ void k_prep(int64_t B, int M, const double* __restrict__ sigma, const double* __restrict__ omega0,
+                       const double* __restrict__ quality, const double* __restrict__ jitter, TermConst* __restrict__ tc,
+                       double* __restrict__ coef, double* __restrict__ jit) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < B * M) {
+    const TermConst t = make_term(sigma[i], omega0[i], quality[i]);
+    tc[i] = t;
+    series_coefficients(t.beta, coef + i * 2 * NCOEF, coef + i * 2 * NCOEF + NCOEF);
+  }
+  if (i < B) jit[i] = jitter ? jitter[i] : 0.0;
+}
+
+template <int NX>
+__global__ void k_combine(DevPlan p, DevParams pr, const double* __restrict__ summ, double* __restrict__ bstate,
+                          double* __restrict__ badj, double* __restrict__ bsmooth, double* __restrict__ loglik,
+                          int32_t* __restrict__ status, int want_back) {
+  constexpr int NXP = NX * (NX + 1) / 2;
+  constexpr int M = NX / 2;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= p.n_series) return;
+  const int64_t C = p.n_chunks;
+  const int32_t c0 = p.series_chunk0[b], n = p.series_nch[b];
+  if (n == 0) {  // a series without measurements
+    if (loglik) loglik[b] = 0.0;
+    if (status) status[b] = 0;
+    return;
+  }
+  double m[NX], P[NXP];
+#pragma unroll
+  for (int i = 0; i < NX; ++i) m[i] = 0.0;
+#pragma unroll
+  for (int i = 0; i < NXP; ++i) P[i] = 0.0;
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    const double s2 = pr.tc[b * M + t].sigma * pr.tc[b * M + t].sigma;
+    P[sidx(2 * t, 2 * t, NX)] = s2;
+    P[sidx(2 * t + 1, 2 * t + 1, NX)] = s2;
+  }
+  bool ok = true;
+  double ll = 0.0;
+  for (int32_t q = 0; q < n; ++q) {
+    const int64_t c = c0 + q;
+#pragma unroll
+    for (int i = 0; i < NX; ++i) bstate[i * C + c] = m[i];
+#pragma unroll
+    for (int i = 0; i < NXP; ++i) bstate[(NX + i) * C + c] = P[i];
+    auto get = [=](int f) { return summ[(int64_t)f * C + c]; };
+    double mn[NX], Pn[NXP];
+    ll += combine_forward<NX>(m, P, get, mn, Pn, ok);
+#pragma unroll
+    for (int i = 0; i < NX; ++i) m[i] = mn[i];
+#pragma unroll
+    for (int i = 0; i < NXP; ++i) P[i] = Pn[i];
+  }
+  if (want_back) {
+    int64_t c = c0 + n - 1;
+#pragma unroll
+    for (int i = 0; i < NX + NXP; ++i) badj[i * C + c] = 0.0;
+    if (bsmooth) {
+#pragma unroll
+      for (int i = 0; i < NX; ++i) bsmooth[i * C + c] = m[i];
+#pragma unroll
+      for (int i = 0; i < NXP; ++i) bsmooth[(NX + i) * C + c] = P[i];
+    }
+    double Jf[NXP], ef[NX];
+#pragma unroll
+    for (int i = 0; i < NXP; ++i) Jf[i] = summ[(int64_t)(sum_J(NX) + i) * C + c];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) ef[i] = summ[(int64_t)(sum_eta(NX) + i) * C + c];
+    for (int32_t q = n - 1; q >= 1; --q) {
+      c = c0 + q;
+      double mb_[NX], Pb_[NXP], mh[NX], Ph[NXP];
+#pragma unroll
+      for (int i = 0; i < NX; ++i) m[i] = bstate[i * C + c];
+#pragma unroll
+      for (int i = 0; i < NXP; ++i) P[i] = bstate[(NX + i) * C + c];
+      boundary_adjoint<NX>(m, P, Jf, ef, mb_, Pb_, bsmooth ? mh : nullptr, Ph, ok);
+#pragma unroll
+      for (int i = 0; i < NX; ++i) badj[i * C + c - 1] = mb_[i];
+#pragma unroll
+      for (int i = 0; i < NXP; ++i) badj[(NX + i) * C + c - 1] = Pb_[i];
+      if (bsmooth) {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) bsmooth[i * C + c - 1] = mh[i];
+#pragma unroll
+        for (int i = 0; i < NXP; ++i) bsmooth[(NX + i) * C + c - 1] = Ph[i];
+      }
+      const int64_t cp = c - 1;
+      auto get = [=](int f) { return summ[(int64_t)f * C + cp]; };
+      double Jn[NXP], en[NX];
+      future_step<NX>(get, Jf, ef, Jn, en, ok);
+#pragma unroll
+      for (int i = 0; i < NXP; ++i) Jf[i] = Jn[i];
+#pragma unroll
+      for (int i = 0; i < NX; ++i) ef[i] = en[i];
+    }
+  }
+  const bool good = ok && isfinite(ll);
+  if (loglik) loglik[b] = good ? ll : __builtin_nan("");
+  if (status) status[b] = good ? 0 : GP_SSM_ENUMERIC;
+}
+
+__global__ void k_reduce_grad(DevPlan p, int M, const double* __restrict__ gpart, const int32_t* __restrict__ status,
+                              double* __restrict__ grad) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= p.n_series) return;
+  const int64_t C = p.n_chunks;
+  const int32_t c0 = p.series_chunk0[b], n = p.series_nch[b];
+  const int G = 3 * M + 1;
+  const bool good = status == nullptr || status[b] == 0;
+  for (int f = 0; f < G; ++f) {
+    double s = 0.0;
+    for (int32_t q = 0; q < n; ++q) s += gpart[(int64_t)f * C + c0 + q];
+    grad[b * G + f] = (good && isfinite(s)) ? s : __builtin_nan("");
+  }
+}
+
+__global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+template <int NX>
+void launch_combine(hipStream_t s, const DevPlan& p, const DevParams& pr, const double* summ, double* bstate,
+                    double* badj, double* bsmooth, double* loglik, int32_t* status, int back) {
+  const int threads = 64;
+  const int blocks = (int)((p.n_series + threads - 1) / threads);
+  if (blocks == 0) return;
+  prof_begin("k_combine", s);
+  hipLaunchKernelGGL(k_combine<NX>, dim3(blocks), dim3(threads), 0, s, p, pr, summ, bstate, badj, bsmooth, loglik,
+                     status, back);
+  prof_end("k_combine", s);
+}
+
+void combine_dispatch(int M, hipStream_t s, const DevPlan& p, const DevParams& pr, const double* summ, double* bstate,
+                      double* badj, double* bsmooth, double* loglik, int32_t* status, int back) {
+  switch (M) {
+    case 1: launch_combine<2>(s, p, pr, summ, bstate, badj, bsmooth, loglik, status, back); break;
+    case 2: launch_combine<4>(s, p, pr, summ, bstate, badj, bsmooth, loglik, status, back); break;
+    case 3: launch_combine<6>(s, p, pr, summ, bstate, badj, bsmooth, loglik, status, back); break;
+    default: launch_combine<8>(s, p, pr, summ, bstate, badj, bsmooth, loglik, status, back); break;
+  }
+}
+
+KernelSet kernel_set(int M, int J) {
+  J = std::max(1, J);
+  switch (M) {
+    case 1: return kernels_m1(J);
+    case 2: return kernels_m2(J);
+    case 3: return kernels_m3(J);
+    default: return kernels_m4(J);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DBuf() {
+    if (p) (void)hipFree(p);
+  }
+  int ensure(size_t n) {
+    if (n <= bytes) return 0;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    if (hipMalloc(&p, n) != hipSuccess) return fail(GP_SSM_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+    bytes = n;
+    return 0;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+template <class T>
+int upload(DBuf& d, const std::vector<T>& v) {
+  if (int rc = d.ensure(std::max<size_t>(1, v.size()) * sizeof(T))) return rc;
+  if (!v.empty()) HIP_TRY(hipMemcpy(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return 0;
+}
+
+int host_copy(const void* src, size_t bytes, void* dst, hipStream_t s) {
+  if (bytes == 0) return 0;
+  hipPointerAttribute_t attr;
+  bool device = false;
+  if (hipPointerGetAttributes(&attr, src) == hipSuccess) {
+    device = (attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged);
+  } else {
+    (void)hipGetLastError();
+  }
+  if (device) {
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  } else {
+    std::memcpy(dst, src, bytes);
+  }
+  return 0;
+}
+
+}  // namespace
+
+namespace gpssm {
+void prof_begin(const char* name, hipStream_t s) {
+  if (!g_prof.on) return;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.cur_a = prof_event();
+  if (g_prof.cur_a) (void)hipEventRecord(g_prof.cur_a, s);
+  (void)name;
+}
+void prof_end(const char* name, hipStream_t s) {
+  if (!g_prof.on) return;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  hipEvent_t b = prof_event();
+  if (!b || !g_prof.cur_a) return;
+  (void)hipEventRecord(b, s);
+  g_prof.pending.push_back({name, g_prof.cur_a, b});
+  g_prof.cur_a = nullptr;
+  if (g_prof.pending.size() > 4096) prof_flush();
+}
+}  // namespace gpssm
+
+struct gp_ssm_plan {
+  int device = 0;
+  HostPlan host;
+  DBuf dt, t, y, r, invd, info, meas;
+  DBuf seg_series, seg_chunk0, seg_nch, seg_len, seg_ev0;
+  DBuf chunk_len, chunk_series, chunk_seg, chunk_first;
+  DBuf series_chunk0, series_nch;
+  // workspace
+  DBuf tc, coef, jit, summ, bstate, badj, bsmooth, gpart, rec, status;
+  DBuf tests_t, tests_idx, tests_c0, tests_before;
+
+  DevPlan dev() const {
+    DevPlan p;
+    p.dt = dt.as<double>();
+    p.t = t.as<double>();
+    p.y = y.as<double>();
+    p.r = r.as<double>();
+    p.invd = invd.as<double>();
+    p.info = info.as<uint32_t>();
+    p.meas = meas.as<int64_t>();
+    p.seg_series = seg_series.as<int32_t>();
+    p.seg_chunk0 = seg_chunk0.as<int32_t>();
+    p.seg_nch = seg_nch.as<int32_t>();
+    p.seg_len = seg_len.as<int32_t>();
+    p.seg_ev0 = seg_ev0.as<int64_t>();
+    p.chunk_len = chunk_len.as<int32_t>();
+    p.chunk_series = chunk_series.as<int32_t>();
+    p.chunk_seg = chunk_seg.as<int32_t>();
+    p.chunk_first = chunk_first.as<uint8_t>();
+    p.series_chunk0 = series_chunk0.as<int32_t>();
+    p.series_nch = series_nch.as<int32_t>();
+    p.n_series = host.n_series;
+    p.n_chunks = host.n_chunks;
+    p.n_seg = host.n_seg;
+    return p;
+  }
+};
+
+namespace {
+
+int check_device() {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n < 1) {
+    (void)hipGetLastError();
+    return fail(GP_SSM_EDEVICE, "no HIP device available");
+  }
+  return 0;
+}
+
+// validates hyperparameters (host copies) and prepares them on the device
+int prepare_params(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0, const double* quality,
+                   const double* jitter, hipStream_t s, DevParams& pr) {
+  if (!pl) return fail(GP_SSM_EINVAL, "null plan");
+  if (M < 1 || M > GP_SSM_MAX_TERMS) return fail(GP_SSM_EINVAL, "n_terms out of range");
+  if (!sigma || !omega0 || !quality) return fail(GP_SSM_EINVAL, "null hyperparameter pointer");
+  const int64_t B = pl->host.n_series;
+  std::vector<double> h(3 * B * M + B);
+  if (int rc = host_copy(sigma, sizeof(double) * B * M, h.data(), s)) return rc;
+  if (int rc = host_copy(omega0, sizeof(double) * B * M, h.data() + B * M, s)) return rc;
+  if (int rc = host_copy(quality, sizeof(double) * B * M, h.data() + 2 * B * M, s)) return rc;
+  if (jitter) {
+    if (int rc = host_copy(jitter, sizeof(double) * B, h.data() + 3 * B * M, s)) return rc;
+  }
+  for (int64_t i = 0; i < 3 * B * M; ++i)
+    if (!(h[i] > 0) || !std::isfinite(h[i]))
+      return fail(GP_SSM_EPARAM, "sigma, omega0 and Q must be positive and finite (entry " + std::to_string(i % (B * M)) + ")");
+  if (jitter)
+    for (int64_t b = 0; b < B; ++b)
+      if (!(h[3 * B * M + b] >= 0) || !std::isfinite(h[3 * B * M + b]))
+        return fail(GP_SSM_EPARAM, "jitter must be >= 0 and finite (series " + std::to_string(b) + ")");
+  if (int rc = pl->tc.ensure(sizeof(TermConst) * B * M)) return rc;
+  if (int rc = pl->coef.ensure(sizeof(double) * B * M * 2 * NCOEF)) return rc;
+  if (int rc = pl->jit.ensure(sizeof(double) * B)) return rc;
+  const int threads = 256;
+  const int64_t n = std::max<int64_t>(B * M, B);
+  prof_begin("k_prep", s);
+  hipLaunchKernelGGL(k_prep, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0, s, B, M, sigma, omega0,
+                     quality, jitter, pl->tc.as<TermConst>(), pl->coef.as<double>(), pl->jit.as<double>());
+  prof_end("k_prep", s);
+  HIP_TRY(hipGetLastError());
+  pr.tc = pl->tc.as<TermConst>();
+  pr.coef = pl->coef.as<double>();
+  pr.jit = pl->jit.as<double>();
+  return 0;
+}
+
+int run_forward(gp_ssm_plan* pl, int32_t M, const DevParams& pr, hipStream_t s, double* loglik, int32_t* status,
+                int back, bool need_smooth) {
+  const int NX = 2 * M;
+  const int64_t C = pl->host.n_chunks;
+  if (int rc = pl->summ.ensure(sizeof(double) * summary_size(NX) * C)) return rc;
+  if (int rc = pl->bstate.ensure(sizeof(double) * (NX + NX * (NX + 1) / 2) * C)) return rc;
+  if (back) {
+    if (int rc = pl->badj.ensure(sizeof(double) * (NX + NX * (NX + 1) / 2) * C)) return rc;
+    if (need_smooth)
+      if (int rc = pl->bsmooth.ensure(sizeof(double) * (NX + NX * (NX + 1) / 2) * C)) return rc;
+  }
+  const DevPlan p = pl->dev();
+  const KernelSet ks = kernel_set(M, pl->host.max_slots);
+  Launch L{s};
+  ks.summaries(L, p, pr, pl->summ.as<double>());
+  HIP_TRY(hipGetLastError());
+  combine_dispatch(M, s, p, pr, pl->summ.as<double>(), pl->bstate.as<double>(), back ? pl->badj.as<double>() : nullptr,
+                   need_smooth ? pl->bsmooth.as<double>() : nullptr, loglik, status, back);
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gp_ssm_plan_default_options(gp_ssm_plan_options* opt) {
+  if (!opt) return;
+  PlanOptions d;
+  opt->chunk_min = d.chunk_min;
+  opt->chunk_target = d.chunk_target;
+  opt->target_chunks = d.target_chunks;
+  opt->single_chunk = d.single_chunk;
+  opt->threads = d.threads;
+}
+
+int gp_ssm_plan_create(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end,
+                       const double* y, const double* yerr, const gp_ssm_plan_options* opt, void* stream,
+                       gp_ssm_plan** out) {
+  g_err.clear();
+  if (!out) return fail(GP_SSM_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (n_series < 1) return fail(GP_SSM_EINVAL, "n_series < 1");
+  if (!offsets || !t_start || !t_end || !y || !yerr) return fail(GP_SSM_EINVAL, "null input pointer");
+  if (int rc = check_device()) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int64_t> off(n_series + 1);
+  if (int rc = host_copy(offsets, sizeof(int64_t) * (n_series + 1), off.data(), s)) return rc;
+  if (off[0] != 0) return fail(GP_SSM_EINVAL, "offsets[0] != 0");
+  for (int64_t b = 0; b < n_series; ++b)
+    if (off[b + 1] < off[b]) return fail(GP_SSM_EINVAL, "offsets not ascending");
+  const int64_t N = off[n_series];
+  std::vector<double> ts(N), te(N), yy(N), ye(N);
+  if (int rc = host_copy(t_start, sizeof(double) * N, ts.data(), s)) return rc;
+  if (int rc = host_copy(t_end, sizeof(double) * N, te.data(), s)) return rc;
+  if (int rc = host_copy(y, sizeof(double) * N, yy.data(), s)) return rc;
+  if (int rc = host_copy(yerr, sizeof(double) * N, ye.data(), s)) return rc;
+  PlanOptions po;
+  if (opt) {
+    if (opt->chunk_min > 0) po.chunk_min = opt->chunk_min;
+    po.chunk_target = opt->chunk_target;
+    if (opt->target_chunks > 0) po.target_chunks = opt->target_chunks;
+    po.single_chunk = opt->single_chunk;
+    po.threads = opt->threads;
+  }
+  gp_ssm_plan* pl = new (std::nothrow) gp_ssm_plan();
+  if (!pl) return fail(GP_SSM_ENOMEM, "host allocation failed");
+  std::string err;
+  int rc = build_plan(n_series, off.data(), ts.data(), te.data(), yy.data(), ye.data(), po, pl->host, err);
+  if (rc) {
+    delete pl;
+    return fail(rc, err);
+  }
+  (void)hipGetDevice(&pl->device);
+  HostPlan& h = pl->host;
+  if ((rc = upload(pl->dt, h.dt)) || (rc = upload(pl->t, h.t)) || (rc = upload(pl->y, h.y)) || (rc = upload(pl->r, h.r)) ||
+      (rc = upload(pl->invd, h.invd)) || (rc = upload(pl->info, h.info)) || (rc = upload(pl->meas, h.meas)) ||
+      (rc = upload(pl->seg_series, h.seg_series)) || (rc = upload(pl->seg_chunk0, h.seg_chunk0)) ||
+      (rc = upload(pl->seg_nch, h.seg_nch)) || (rc = upload(pl->seg_len, h.seg_len)) ||
+      (rc = upload(pl->seg_ev0, h.seg_ev0)) || (rc = upload(pl->chunk_len, h.chunk_len)) ||
+      (rc = upload(pl->chunk_series, h.chunk_series)) || (rc = upload(pl->chunk_seg, h.chunk_seg)) ||
+      (rc = upload(pl->chunk_first, h.chunk_first)) || (rc = upload(pl->series_chunk0, h.series_chunk0)) ||
+      (rc = upload(pl->series_nch, h.series_nch))) {
+    delete pl;
+    return rc;
+  }
+  // the event arrays live on the device now; keep only the tables the host needs
+  std::vector<double>().swap(h.dt);
+  std::vector<double>().swap(h.y);
+  std::vector<double>().swap(h.r);
+  std::vector<double>().swap(h.invd);
+  std::vector<uint32_t>().swap(h.info);
+  std::vector<int64_t>().swap(h.meas);
+  *out = pl;
+  return 0;
+}
+
+void gp_ssm_plan_destroy(gp_ssm_plan* plan) { delete plan; }
+
+int gp_ssm_plan_get_stats(const gp_ssm_plan* pl, gp_ssm_plan_stats* out) {
+  if (!pl || !out) return fail(GP_SSM_EINVAL, "null pointer");
+  out->n_series = pl->host.n_series;
+  out->n_meas = pl->host.n_meas;
+  out->n_events = pl->host.n_events;
+  out->n_events_padded = pl->host.n_ev_pad;
+  out->n_chunks = pl->host.n_chunks;
+  out->n_segments = pl->host.n_seg;
+  out->max_slots = pl->host.max_slots;
+  out->max_chunk_len = pl->host.max_chunk_len;
+  return 0;
+}
+
+int gp_ssm_plan_loglik(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0, const double* quality,
+                       const double* jitter, double* loglik, int32_t* status, void* stream) {
+  g_err.clear();
+  if (!loglik) return fail(GP_SSM_EINVAL, "null loglik");
+  hipStream_t s = (hipStream_t)stream;
+  DevParams pr;
+  if (int rc = prepare_params(pl, M, sigma, omega0, quality, jitter, s, pr)) return rc;
+  return run_forward(pl, M, pr, s, loglik, status, 0, false);
+}
+
+int gp_ssm_plan_loglik_grad(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0,
+                            const double* quality, const double* jitter, double* loglik, double* grad,
+                            int32_t* status, void* stream) {
+  g_err.clear();
+  if (!loglik || !grad) return fail(GP_SSM_EINVAL, "null output");
+  hipStream_t s = (hipStream_t)stream;
+  DevParams pr;
+  if (int rc = prepare_params(pl, M, sigma, omega0, quality, jitter, s, pr)) return rc;
+  const int64_t B = pl->host.n_series;
+  int32_t* st = status;
+  if (!st) {
+    if (int rc = pl->status.ensure(sizeof(int32_t) * B)) return rc;
+    st = pl->status.as<int32_t>();
+  }
+  if (int rc = run_forward(pl, M, pr, s, loglik, st, 1, false)) return rc;
+  const int NX = 2 * M;
+  const int J = std::max(1, pl->host.max_slots);
+  const int D = NX + J;
+  const int F = D + D * (D + 1) / 2;
+  const int64_t C = pl->host.n_chunks;
+  if (int rc = pl->rec.ensure(sizeof(double) * F * std::max<int64_t>(1, pl->host.n_ev_pad))) return rc;
+  if (int rc = pl->gpart.ensure(sizeof(double) * (3 * M + 1) * C)) return rc;
+  const DevPlan p = pl->dev();
+  const KernelSet ks = kernel_set(M, pl->host.max_slots);
+  Launch L{s};
+  ks.adjoint(L, p, pr, pl->bstate.as<double>(), pl->badj.as<double>(), pl->rec.as<double>(), pl->gpart.as<double>(),
+             nullptr);
+  HIP_TRY(hipGetLastError());
+  prof_begin("k_reduce_grad", s);
+  hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, s, p, M, pl->gpart.as<double>(), st,
+                     grad);
+  prof_end("k_reduce_grad", s);
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int gp_ssm_plan_smooth(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0, const double* quality,
+                       const double* jitter, const int64_t* test_offsets, const double* t_test, double* mean_test,
+                       double* var_test, double* mean_data, double* var_data, double* loglik, int32_t* status,
+                       void* stream) {
+  (void)pl;
+  (void)M;
+  (void)sigma;
+  (void)omega0;
+  (void)quality;
+  (void)jitter;
+  (void)test_offsets;
+  (void)t_test;
+  (void)mean_test;
+  (void)var_test;
+  (void)mean_data;
+  (void)var_data;
+  (void)loglik;
+  (void)status;
+  (void)stream;
+  return fail(GP_SSM_EINVAL, "gp_ssm_plan_smooth: not available in this build");
+}
+
+int gp_ssm_plan_plain_loglik(gp_ssm_plan* pl, int64_t first, int64_t count, int32_t M, const double* sigma,
+                             const double* omega0, const double* quality, const double* jitter, double* loglik,
+                             void* stream) {
+  g_err.clear();
+  if (!loglik) return fail(GP_SSM_EINVAL, "null loglik");
+  if (!pl) return fail(GP_SSM_EINVAL, "null plan");
+  if (first < 0 || count < 0 || first + count > pl->host.n_series) return fail(GP_SSM_EINVAL, "series range");
+  hipStream_t s = (hipStream_t)stream;
+  DevParams pr;
+  if (int rc = prepare_params(pl, M, sigma, omega0, quality, jitter, s, pr)) return rc;
+  const DevPlan p = pl->dev();
+  const KernelSet ks = kernel_set(M, pl->host.max_slots);
+  Launch L{s};
+  for (int64_t b = first; b < first + count; ++b) {
+    ks.plain(L, p, pr, b, loglik);
+    HIP_TRY(hipGetLastError());
+  }
+  return 0;
+}
+
+static int one_shot_plan(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end,
+                         const double* y, const double* yerr, void* stream, gp_ssm_plan** pl) {
+  return gp_ssm_plan_create(n_series, offsets, t_start, t_end, y, yerr, nullptr, stream, pl);
+}
+
+int gp_ssm_loglik(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end, const double* y,
+                  const double* yerr, int32_t n_terms, const double* sigma, const double* omega0, const double* quality,
+                  const double* jitter, double* loglik, int32_t* status, void* stream) {
+  gp_ssm_plan* pl = nullptr;
+  if (int rc = one_shot_plan(n_series, offsets, t_start, t_end, y, yerr, stream, &pl)) return rc;
+  int rc = gp_ssm_plan_loglik(pl, n_terms, sigma, omega0, quality, jitter, loglik, status, stream);
+  if (rc == 0 && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = fail(GP_SSM_EDEVICE, "stream sync failed");
+  gp_ssm_plan_destroy(pl);
+  return rc;
+}
+
+int gp_ssm_loglik_grad(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end,
+                       const double* y, const double* yerr, int32_t n_terms, const double* sigma, const double* omega0,
+                       const double* quality, const double* jitter, double* loglik, double* grad, int32_t* status,
+                       void* stream) {
+  gp_ssm_plan* pl = nullptr;
+  if (int rc = one_shot_plan(n_series, offsets, t_start, t_end, y, yerr, stream, &pl)) return rc;
+  int rc = gp_ssm_plan_loglik_grad(pl, n_terms, sigma, omega0, quality, jitter, loglik, grad, status, stream);
+  if (rc == 0 && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = fail(GP_SSM_EDEVICE, "stream sync failed");
+  gp_ssm_plan_destroy(pl);
+  return rc;
+}
+
+int gp_ssm_smooth(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end,
+                  const double* y, const double* yerr, int32_t n_terms, const double* sigma, const double* omega0,
+                  const double* quality, const double* jitter, const int64_t* test_offsets, const double* t_test,
+                  double* mean_test, double* var_test, double* mean_data, double* var_data, int32_t* status,
+                  void* stream) {
+  gp_ssm_plan* pl = nullptr;
+  if (int rc = one_shot_plan(n_series, offsets, t_start, t_end, y, yerr, stream, &pl)) return rc;
+  int rc = gp_ssm_plan_smooth(pl, n_terms, sigma, omega0, quality, jitter, test_offsets, t_test, mean_test, var_test,
+                              mean_data, var_data, nullptr, status, stream);
+  if (rc == 0 && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = fail(GP_SSM_EDEVICE, "stream sync failed");
+  gp_ssm_plan_destroy(pl);
+  return rc;
+}
+
+int gp_ssm_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.on = on != 0;
+  return 0;
+}
+
+int gp_ssm_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  prof_flush();
+  g_prof.total.clear();
+  return 0;
+}
+
+int gp_ssm_profile_read(const char** names, int64_t* counts, double* total_ms, int32_t cap) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  prof_flush();
+  g_prof.names.clear();
+  for (auto& kv : g_prof.total) g_prof.names.push_back(kv.first);
+  int32_t i = 0;
+  for (auto& kv : g_prof.total) {
+    if (i < cap) {
+      if (names) names[i] = g_prof.names[i].c_str();
+      if (counts) counts[i] = kv.second.first;
+      if (total_ms) total_ms[i] = kv.second.second;
+    }
+    ++i;
+  }
+  return (int)g_prof.total.size();
+}
+
+const char* gp_ssm_last_error(void) { return g_err.c_str(); }
+
+const char* gp_ssm_version(void) { return "gp_ssm 0.1 (gfx950, fp64)"; }
+
+}  // extern "C"

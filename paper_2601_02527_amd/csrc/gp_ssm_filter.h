@@ -1,0 +1,691 @@
+// Chunk-level pieces of the augmented filter:
+//
+//  * the conditional filter of one chunk: the filter run with the state at
+//    the chunk's start boundary treated as known (x_b), which makes the mean
+//    affine in x_b (m = S x_b + mu) while the covariance does not depend on
+//    it.  Its result is the chunk summary (A, b, C, eta, J, c0):
+//      x_end | x_b, y_chunk ~ N(A x_b + b, C)
+//      log p(y_chunk | x_b) = -c0/2 + eta^T x_b - x_b^T J x_b / 2,
+//    the five-tuple of the parallel filter (Sec. 3.2.4, following SG21)
+//    extended by the likelihood constant.  Chunks start and end where every
+//    exposure is closed, so x_b and x_end are the SHO states only.
+//  * the combination of a filtered boundary state with a summary (next
+//    boundary state and the chunk's likelihood contribution), the backward
+//    recursion of the future likelihood (eta~, J~), and from it the gradient
+//    of the future likelihood with respect to the boundary moments and the
+//    smoothed boundary moments.
+//  * the reverse-mode adjoint of one plain filter step, accumulating the
+//    gradient with respect to (sigma, omega0, Q) of every term and jitter.
+#pragma once
+
+#include "gp_ssm_math.h"
+
+namespace gpssm {
+
+// ---------------------------------------------------------------------------
+// conditional filter of a chunk
+// ---------------------------------------------------------------------------
+template <class Dm>
+struct CondState {
+  static constexpr int D = Dm::D, NX = Dm::NX, NP = Dm::NP, NXP = Dm::NXP;
+  double P[NP];
+  double mu[D];
+  double S[D * NX];  // d mean / d x_b, row-major
+  double Jm[NXP];
+  double eta[NX];
+  double c0;
+
+  GPD void init() {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) P[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) mu[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) S[i * NX + c] = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int i = 0; i < NXP; ++i) Jm[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NX; ++i) eta[i] = 0.0;
+    c0 = 0.0;
+  }
+
+  // one event: predict over the step that ends at it, then its observation
+  GPD void step(const TermQ* tq, uint32_t info, const Obs& o) {
+    const uint32_t open = ev_open(info);
+    predict_mean<Dm>(mu, tq, open);
+    predict_cols<Dm, NX>(S, tq, open);
+    predict_cov<Dm>(P, tq, open);
+    double u[D];
+    obs_gain<Dm>(P, o, u);
+    const double S_ = obs_dot<Dm>(u, o) + o.R;
+    const double iS = 1.0 / S_;
+    const double r = o.y - obs_dot<Dm>(mu, o);
+    double a[NX];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      double col[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) col[i] = S[i * NX + c];
+      a[c] = obs_dot<Dm>(col, o);
+    }
+    const double riS = r * iS;
+#pragma unroll
+    for (int i = 0; i < D; ++i) mu[i] = fma(u[i], riS, mu[i]);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const double ui = u[i] * iS;
+#pragma unroll
+      for (int c = 0; c < NX; ++c) S[i * NX + c] = fma(-ui, a[c], S[i * NX + c]);
+#pragma unroll
+      for (int j = i; j < D; ++j) P[sidx(i, j, D)] = fma(-ui, u[j], P[sidx(i, j, D)]);
+    }
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      const double ac = a[c] * iS;
+      eta[c] = fma(ac, r, eta[c]);
+#pragma unroll
+      for (int d = c; d < NX; ++d) Jm[sidx(c, d, NX)] = fma(ac, a[d], Jm[sidx(c, d, NX)]);
+    }
+    if (o.has) c0 += LOG_2PI + log(S_) + r * riS;
+    close_slot<Dm>(mu, P, info);
+    close_slot_rows<Dm, NX>(S, info);
+  }
+};
+
+// number of doubles in a chunk summary for NX SHO states
+GPD constexpr int summary_size(int NX) { return NX * NX + NX + NX * (NX + 1) / 2 + NX + NX * (NX + 1) / 2 + 1; }
+// field offsets: A (NX*NX, row-major), b (NX), C (packed), eta (NX), J (packed), c0
+GPD constexpr int sum_A(int) { return 0; }
+GPD constexpr int sum_b(int NX) { return NX * NX; }
+GPD constexpr int sum_C(int NX) { return NX * NX + NX; }
+GPD constexpr int sum_eta(int NX) { return NX * NX + NX + NX * (NX + 1) / 2; }
+GPD constexpr int sum_J(int NX) { return NX * NX + 2 * NX + NX * (NX + 1) / 2; }
+GPD constexpr int sum_c0(int NX) { return NX * NX + 2 * NX + NX * (NX + 1); }
+
+// ---------------------------------------------------------------------------
+// small dense linear algebra (N <= 8), static indexing only
+// ---------------------------------------------------------------------------
+// Solves A X = B in place (A: N x N row-major, B: N x R row-major) by
+// Gaussian elimination with partial pivoting.  Returns log|det A| and sets
+// ok = false on a zero pivot.
+template <int N, int R>
+GPD double lu_solve(double* A, double* B, bool& ok) {
+  double logdet = 0.0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    // pivot search
+    int p = k;
+    double best = fabs(A[k * N + k]);
+#pragma unroll
+    for (int i = k + 1; i < N; ++i) {
+      const double v = fabs(A[i * N + k]);
+      if (v > best) {
+        best = v;
+        p = i;
+      }
+    }
+    // swap rows k and p (select-based, static indices)
+#pragma unroll
+    for (int i = k + 1; i < N; ++i) {
+      const bool sw = (i == p);
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        const double a = A[k * N + c], b = A[i * N + c];
+        A[k * N + c] = sw ? b : a;
+        A[i * N + c] = sw ? a : b;
+      }
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        const double a = B[k * R + c], b = B[i * R + c];
+        B[k * R + c] = sw ? b : a;
+        B[i * R + c] = sw ? a : b;
+      }
+    }
+    const double piv = A[k * N + k];
+    ok = ok && (piv != 0.0);
+    logdet += log(fabs(piv));
+    const double ip = 1.0 / piv;
+#pragma unroll
+    for (int i = k + 1; i < N; ++i) {
+      const double f = A[i * N + k] * ip;
+#pragma unroll
+      for (int c = k; c < N; ++c) A[i * N + c] = fma(-f, A[k * N + c], A[i * N + c]);
+#pragma unroll
+      for (int c = 0; c < R; ++c) B[i * R + c] = fma(-f, B[k * R + c], B[i * R + c]);
+    }
+  }
+  // back substitution
+#pragma unroll
+  for (int k = N - 1; k >= 0; --k) {
+    const double ip = 1.0 / A[k * N + k];
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      double v = B[k * R + c];
+#pragma unroll
+      for (int j = k + 1; j < N; ++j) v = fma(-A[k * N + j], B[j * R + c], v);
+      B[k * R + c] = v * ip;
+    }
+  }
+  return logdet;
+}
+
+template <int N>
+GPD void unpack(const double* p, double* F) {
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) F[i * N + j] = p[sidx(i, j, N)];
+}
+
+// ---------------------------------------------------------------------------
+// combination of a filtered boundary state (m, P) with a chunk summary
+// ---------------------------------------------------------------------------
+// in: m[N], P packed; summary s (read through an accessor); out: next (m, P)
+// packed and the chunk's log-likelihood contribution.
+template <int N, class Get>
+GPD double combine_forward(const double* m, const double* Pp, Get s, double* mn, double* Pn, bool& ok) {
+  double P[N * N], Jf[N * N];
+  unpack<N>(Pp, P);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) Jf[i * N + j] = s(sum_J(N) + sidx(i, j, N));
+  // r = eta - J m
+  double r[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double v = s(sum_eta(N) + i);
+#pragma unroll
+    for (int j = 0; j < N; ++j) v = fma(-Jf[i * N + j], m[j], v);
+    r[i] = v;
+  }
+  // (I + P J) [W | w] = [P | P r]
+  double A[N * N], B[N * (N + 1)];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double v = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) v = fma(P[i * N + k], Jf[k * N + j], v);
+      A[i * N + j] = v;
+      B[i * (N + 1) + j] = P[i * N + j];
+    }
+    double pr = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) pr = fma(P[i * N + k], r[k], pr);
+    B[i * (N + 1) + N] = pr;
+  }
+  const double logdet = lu_solve<N, N + 1>(A, B, ok);
+  // likelihood contribution
+  double etm = 0.0, mJm = 0.0, rw = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    etm = fma(s(sum_eta(N) + i), m[i], etm);
+    double Jmi = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) Jmi = fma(Jf[i * N + j], m[j], Jmi);
+    mJm = fma(m[i], Jmi, mJm);
+    rw = fma(r[i], B[i * (N + 1) + N], rw);
+  }
+  const double ll = -0.5 * s(sum_c0(N)) + etm - 0.5 * mJm - 0.5 * logdet + 0.5 * rw;
+  // posterior of x_b, then the chunk's transition
+  double mt[N], W[N * N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    mt[i] = m[i] + B[i * (N + 1) + N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) W[i * N + j] = 0.5 * (B[i * (N + 1) + j] + B[j * (N + 1) + i]);
+  }
+  double AW[N * N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double v = s(sum_b(N) + i);
+#pragma unroll
+    for (int k = 0; k < N; ++k) v = fma(s(sum_A(N) + i * N + k), mt[k], v);
+    mn[i] = v;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double w = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) w = fma(s(sum_A(N) + i * N + k), W[k * N + j], w);
+      AW[i * N + j] = w;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = i; j < N; ++j) {
+      double v = s(sum_C(N) + sidx(i, j, N));
+#pragma unroll
+      for (int k = 0; k < N; ++k) v = fma(AW[i * N + k], s(sum_A(N) + j * N + k), v);
+      Pn[sidx(i, j, N)] = v;
+    }
+  return ll;
+}
+
+// future likelihood at this chunk's start from the one at its end:
+//   J~ = J + A^T (I + J~' C)^-1 J~' A,  eta~ = eta + A^T (I + J~' C)^-1 (eta~' - J~' b)
+template <int N, class Get>
+GPD void future_step(Get s, const double* Jn, const double* en, double* Jo, double* eo, bool& ok) {
+  double Jf[N * N], C[N * N];
+  unpack<N>(Jn, Jf);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) C[i * N + j] = s(sum_C(N) + sidx(i, j, N));
+  double A[N * N], B[N * (N + 1)];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double v = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) v = fma(Jf[i * N + k], C[k * N + j], v);
+      A[i * N + j] = v;
+      double w = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) w = fma(Jf[i * N + k], s(sum_A(N) + k * N + j), w);
+      B[i * (N + 1) + j] = w;
+    }
+    double w = en[i];
+#pragma unroll
+    for (int k = 0; k < N; ++k) w = fma(-Jf[i * N + k], s(sum_b(N) + k), w);
+    B[i * (N + 1) + N] = w;
+  }
+  lu_solve<N, N + 1>(A, B, ok);
+  // A_c^T Y
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double e = s(sum_eta(N) + i);
+#pragma unroll
+    for (int k = 0; k < N; ++k) e = fma(s(sum_A(N) + k * N + i), B[k * (N + 1) + N], e);
+    eo[i] = e;
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = i; j < N; ++j) {
+      double a = 0.0, b = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        a = fma(s(sum_A(N) + k * N + i), B[k * (N + 1) + j], a);
+        b = fma(s(sum_A(N) + k * N + j), B[k * (N + 1) + i], b);
+      }
+      Jo[sidx(i, j, N)] = s(sum_J(N) + sidx(i, j, N)) + 0.5 * (a + b);
+    }
+}
+
+// gradient of the future log-likelihood with respect to the moments (m, P)
+// of the boundary state, given the future information (J~, eta~):
+//   B = (I + J~ P)^-1, mbar = B (eta~ - J~ m), Pbar = (mbar mbar^T - B J~)/2
+// and the smoothed boundary moments m^ = m + P mbar, P^ = P - P (B J~) P.
+template <int N>
+GPD void boundary_adjoint(const double* m, const double* Pp, const double* Jp, const double* et, double* mbar,
+                          double* Pbar, double* mhat, double* Phat, bool& ok) {
+  double P[N * N], Jf[N * N], A[N * N], B[N * (N + 1)];
+  unpack<N>(Pp, P);
+  unpack<N>(Jp, Jf);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double v = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) v = fma(Jf[i * N + k], P[k * N + j], v);
+      A[i * N + j] = v;
+      B[i * (N + 1) + j] = Jf[i * N + j];
+    }
+    double r = et[i];
+#pragma unroll
+    for (int k = 0; k < N; ++k) r = fma(-Jf[i * N + k], m[k], r);
+    B[i * (N + 1) + N] = r;
+  }
+  lu_solve<N, N + 1>(A, B, ok);
+#pragma unroll
+  for (int i = 0; i < N; ++i) mbar[i] = B[i * (N + 1) + N];
+  double BJ[N * N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) BJ[i * N + j] = 0.5 * (B[i * (N + 1) + j] + B[j * (N + 1) + i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = i; j < N; ++j) Pbar[sidx(i, j, N)] = 0.5 * (mbar[i] * mbar[j] - BJ[i * N + j]);
+  if (mhat) {
+    double PB[N * N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double v = m[i];
+#pragma unroll
+      for (int k = 0; k < N; ++k) v = fma(P[i * N + k], mbar[k], v);
+      mhat[i] = v;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        double w = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) w = fma(P[i * N + k], BJ[k * N + j], w);
+        PB[i * N + j] = w;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = i; j < N; ++j) {
+        double v = P[i * N + j];
+#pragma unroll
+        for (int k = 0; k < N; ++k) v = fma(-PB[i * N + k], P[k * N + j], v);
+        Phat[sidx(i, j, N)] = v;
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reverse-mode adjoint of one plain filter step
+// ---------------------------------------------------------------------------
+// Gradient accumulators per term: (sigma, omega0, Q); plus jitter.
+template <int M>
+struct GradAcc {
+  double s[M], w[M], q[M];
+  double jit;
+  GPD void init() {
+#pragma unroll
+    for (int t = 0; t < M; ++t) s[t] = w[t] = q[t] = 0.0;
+    jit = 0.0;
+  }
+};
+
+// Back-propagates the adjoint weights of one term's step quantities to
+// (sigma, omega0, Q).  W: abar00, abar01, abar11, fbar0, fbar1, qbar00,
+// qbar01, qbar11, cbar0, cbar1, zzbar (weights of the TermQ fields, with the
+// transition's (1,0) entry -a01 folded into abar01).
+GPD void term_backprop(const TermConst& t, const Base<Dual>& b, double dt, const double* W, double& gs, double& gw,
+                       double& gq) {
+  const double beta = t.beta, qh = t.qhat, iw = t.inv_w0;
+  const double g = b.g.v, gp = b.gp.v, G1 = b.G1.v, Igg = b.Igg.v, Ipp = b.Ipp.v, IGG = b.IGG.v;
+  double bg = 0, bgp = 0, bG1 = 0, bIgg = 0, bIpp = 0, bIGG = 0, bbeta = 0, bqh = 0, biw = 0;
+  // transition
+  bgp += W[0];
+  bg += 2.0 * beta * W[0];
+  bbeta += 2.0 * g * W[0];
+  bg += W[1];
+  bgp += W[2];
+  // integrated row
+  bg += W[3] * iw;
+  bG1 += 2.0 * beta * W[3] * iw;
+  bbeta += 2.0 * G1 * W[3] * iw;
+  biw += W[3] * (g + 2.0 * beta * G1);
+  bG1 += W[4] * iw;
+  biw += W[4] * G1;
+  // process noise
+  bIgg += qh * W[5];
+  bqh += W[5] * Igg;
+  bg += qh * g * W[6];
+  bqh += W[6] * 0.5 * g * g;
+  bIpp += qh * W[7];
+  bqh += W[7] * Ipp;
+  // cross noise
+  bG1 += qh * G1 * iw * W[8];
+  bqh += W[8] * 0.5 * G1 * G1 * iw;
+  biw += W[8] * 0.5 * qh * G1 * G1;
+  bG1 += qh * g * iw * W[9];
+  bg += qh * G1 * iw * W[9];
+  bIgg -= qh * iw * W[9];
+  bqh += W[9] * (G1 * g - Igg) * iw;
+  biw += W[9] * qh * (G1 * g - Igg);
+  // integrator noise
+  bIGG += qh * iw * iw * W[10];
+  bqh += W[10] * IGG * iw * iw;
+  biw += 2.0 * W[10] * qh * IGG * iw;
+  // base functions -> (x, beta)
+  const double bx = bg * gp + bgp * (-g - 2.0 * beta * gp) + bG1 * g + bIgg * g * g + bIpp * gp * gp + bIGG * G1 * G1;
+  bbeta += bg * b.g.d + bgp * b.gp.d + bG1 * b.G1.d + bIgg * b.Igg.d + bIpp * b.Ipp.d + bIGG * b.IGG.d;
+  // (x, beta, qhat, 1/omega0) -> (sigma, omega0, Q);  x = omega0 dt, beta = 1/2Q, qhat = 2 sigma^2/Q
+  const double Q = 0.5 / beta;
+  gw += bx * dt - biw * iw * iw;
+  gq += -bbeta * 2.0 * beta * beta - bqh * qh / Q;
+  gs += bqh * 2.0 * qh / t.sigma;
+}
+
+
+// discretisation of all terms over one step (values only)
+template <int M>
+GPD void discretise(const TermConst* tc, const double* coef, double dt, TermQ* tq) {
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    const Base<double> b = base_values(tc[t], coef + t * 2 * NCOEF, dt);
+    tq[t] = term_step(tc[t], b);
+  }
+}
+
+// with beta-derivatives
+template <int M>
+GPD void discretise_dual(const TermConst* tc, const double* coef, double dt, Base<Dual>* bd, TermQ* tq) {
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    const double x = tc[t].w0 * dt;
+    if (use_series(x, tc[t].beta))
+      series_eval(coef + t * 2 * NCOEF, coef + t * 2 * NCOEF + NCOEF, x, bd[t]);
+    else
+      closed_eval<Dual>(x, Dual{tc[t].beta, 1.0}, bd[t]);
+    Base<double> b;
+    b.g = bd[t].g.v;
+    b.gp = bd[t].gp.v;
+    b.G1 = bd[t].G1.v;
+    b.Igg = bd[t].Igg.v;
+    b.Ipp = bd[t].Ipp.v;
+    b.IGG = bd[t].IGG.v;
+    tq[t] = term_step(tc[t], b);
+  }
+}
+
+// Adjoint of one plain step (predict over dt, observe, close the slot).
+// m, P: the filtered state before the step.  mb, Pb: on entry the adjoint
+// with respect to the state after the step, on exit with respect to (m, P).
+template <class Dm>
+GPD void adjoint_step(const double* m, const double* P, double* mb, double* Pb, const TermConst* tc, const double* coef,
+                      double dt, uint32_t info, const Obs& o, double jit, GradAcc<Dm::M>& acc) {
+  constexpr int M = Dm::M, J = Dm::J, NX = Dm::NX, D = Dm::D, NP = Dm::NP;
+  const uint32_t open = ev_open(info);
+  Base<Dual> bd[M];
+  TermQ tq[M];
+  discretise_dual<M>(tc, coef, dt, bd, tq);
+  // predicted moments
+  double mp[D], Pp[NP];
+#pragma unroll
+  for (int i = 0; i < D; ++i) mp[i] = m[i];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) Pp[i] = P[i];
+  predict_mean<Dm>(mp, tq, open);
+  predict_cov<Dm>(Pp, tq, open);
+  double u[D];
+  obs_gain<Dm>(Pp, o, u);
+  const double S = obs_dot<Dm>(u, o) + o.R;
+  const double v = o.y - obs_dot<Dm>(mp, o);
+  double h[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) h[i] = (i >= NX) ? o.a[i - NX] : ((i % 2 == 0) ? o.b : 0.0);
+
+  // closing the slot: the zeroed entries are constants
+  close_slot<Dm>(mb, Pb, info);
+
+  // update:  m+ = m- + u v/S,  P+ = P- - u u^T/S,  l = -(log 2 pi S + v^2/S)/2
+  {
+    const double hs = o.has ? 1.0 : 0.0;
+    const double iS = 1.0 / S;
+    double um = 0.0, uPu = 0.0, Pu[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      um = fma(u[i], mb[i], um);
+      double acc2 = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) acc2 = fma(Pb[sidx(i, j, D)], u[j], acc2);
+      Pu[i] = acc2;
+      uPu = fma(u[i], acc2, uPu);
+    }
+    const double Sbar = hs * ((-0.5 + 0.5 * v * v * iS) * iS + (uPu - um * v) * iS * iS);
+    const double vbar = hs * (um - v) * iS;
+    double ub[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) ub[i] = hs * (mb[i] * v - 2.0 * Pu[i]) * iS + h[i] * Sbar;
+#pragma unroll
+    for (int i = 0; i < D; ++i) mb[i] = fma(-h[i], vbar, mb[i]);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = i; j < D; ++j) Pb[sidx(i, j, D)] += 0.5 * (ub[i] * h[j] + h[i] * ub[j]);
+    acc.jit = fma(2.0 * jit, Sbar, acc.jit);
+  }
+
+  // predict: weights of the step quantities
+  double fb[NX];
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    fb[2 * t] = tq[t].f0;
+    fb[2 * t + 1] = tq[t].f1;
+  }
+  double w[NX];  // Pxx fbar
+#pragma unroll
+  for (int a = 0; a < NX; ++a) {
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < NX; ++c) s = fma(P[sidx(a, c, D)], fb[c], s);
+    w[a] = s;
+  }
+  // T[:, b] = (A P)[:, b] for the SHO columns b
+  double T[D * NX];
+#pragma unroll
+  for (int b = 0; b < NX; ++b) {
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+      const double p0 = P[sidx(2 * t, b, D)], p1 = P[sidx(2 * t + 1, b, D)];
+      T[(2 * t) * NX + b] = fma(tq[t].a00, p0, tq[t].a01 * p1);
+      T[(2 * t + 1) * NX + b] = fma(-tq[t].a01, p0, tq[t].a11 * p1);
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) T[(NX + j) * NX + b] = P[sidx(NX + j, b, D)] + (((open >> j) & 1u) ? w[b] : 0.0);
+  }
+  // G = Pbar- T at the needed entries
+  auto G = [&](int a, int b) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) s = fma(Pb[sidx(a, k, D)], T[k * NX + b], s);
+    return s;
+  };
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    double W[11];
+    double Ab[2][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) Ab[r][c] = fma(mb[2 * t + r], m[2 * t + c], 2.0 * G(2 * t + r, 2 * t + c));
+    W[0] = Ab[0][0];
+    W[1] = Ab[0][1] - Ab[1][0];
+    W[2] = Ab[1][1];
+    double f0 = 0.0, f1 = 0.0, c0 = 0.0, c1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      if ((open >> j) & 1u) {
+        f0 += fma(mb[NX + j], m[2 * t], 2.0 * G(NX + j, 2 * t));
+        f1 += fma(mb[NX + j], m[2 * t + 1], 2.0 * G(NX + j, 2 * t + 1));
+        c0 += 2.0 * Pb[sidx(2 * t, NX + j, D)];
+        c1 += 2.0 * Pb[sidx(2 * t + 1, NX + j, D)];
+      }
+    }
+    W[3] = f0;
+    W[4] = f1;
+    W[5] = Pb[sidx(2 * t, 2 * t, D)];
+    W[6] = 2.0 * Pb[sidx(2 * t, 2 * t + 1, D)];
+    W[7] = Pb[sidx(2 * t + 1, 2 * t + 1, D)];
+    W[8] = c0;
+    W[9] = c1;
+    double zz = 0.0;
+#pragma unroll
+    for (int i = 0; i < J; ++i)
+#pragma unroll
+      for (int j = 0; j < J; ++j)
+        if (((open >> i) & 1u) && ((open >> j) & 1u)) zz += Pb[sidx(NX + i, NX + j, D)];
+    W[10] = zz;
+    term_backprop(tc[t], bd[t], dt, W, acc.s[t], acc.w[t], acc.q[t]);
+  }
+
+  // adjoint to the state before the predict
+  {
+    double zsum = 0.0;
+#pragma unroll
+    for (int j = 0; j < J; ++j) zsum += ((open >> j) & 1u) ? mb[NX + j] : 0.0;
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+      const double b0 = mb[2 * t], b1 = mb[2 * t + 1];
+      mb[2 * t] = fma(tq[t].a00, b0, fma(-tq[t].a01, b1, fb[2 * t] * zsum));
+      mb[2 * t + 1] = fma(tq[t].a01, b0, fma(tq[t].a11, b1, fb[2 * t + 1] * zsum));
+    }
+  }
+  {
+    double p[NX];
+#pragma unroll
+    for (int a = 0; a < NX; ++a) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < J; ++j) s += ((open >> j) & 1u) ? Pb[sidx(a, NX + j, D)] : 0.0;
+      p[a] = s;
+    }
+    double sz = 0.0, cz[J > 0 ? J : 1];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < J; ++i) s += ((open >> i) & 1u) ? Pb[sidx(NX + i, NX + j, D)] : 0.0;
+      cz[j] = s;
+      sz += ((open >> j) & 1u) ? s : 0.0;
+    }
+    // SHO/integrator block: Phi^T Pbar[x, z_j] + fbar^T cz_j
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+#pragma unroll
+      for (int t = 0; t < M; ++t) {
+        const double y0 = Pb[sidx(2 * t, NX + j, D)], y1 = Pb[sidx(2 * t + 1, NX + j, D)];
+        Pb[sidx(2 * t, NX + j, D)] = fma(tq[t].a00, y0, fma(-tq[t].a01, y1, fb[2 * t] * cz[j]));
+        Pb[sidx(2 * t + 1, NX + j, D)] = fma(tq[t].a01, y0, fma(tq[t].a11, y1, fb[2 * t + 1] * cz[j]));
+      }
+    }
+    // q = Phi^T p
+    double q[NX];
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+      q[2 * t] = fma(tq[t].a00, p[2 * t], -tq[t].a01 * p[2 * t + 1]);
+      q[2 * t + 1] = fma(tq[t].a01, p[2 * t], tq[t].a11 * p[2 * t + 1]);
+    }
+    // SHO block: Phi_t^T B Phi_u + q fbar^T + fbar q^T + sz fbar fbar^T
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+#pragma unroll
+      for (int uu = t; uu < M; ++uu) {
+        const double b00 = Pb[sidx(2 * t, 2 * uu, D)], b01 = Pb[sidx(2 * t, 2 * uu + 1, D)];
+        const double b10 = Pb[sidx(2 * t + 1, 2 * uu, D)], b11 = Pb[sidx(2 * t + 1, 2 * uu + 1, D)];
+        // Y = Phi_t^T B, Phi_t^T = [[a00, -a01], [a01, a11]]
+        const double y00 = fma(tq[t].a00, b00, -tq[t].a01 * b10);
+        const double y01 = fma(tq[t].a00, b01, -tq[t].a01 * b11);
+        const double y10 = fma(tq[t].a01, b00, tq[t].a11 * b10);
+        const double y11 = fma(tq[t].a01, b01, tq[t].a11 * b11);
+        // Z = Y Phi_u, Phi_u = [[a00, a01], [-a01, a11]]
+        const double z00 = fma(y00, tq[uu].a00, -y01 * tq[uu].a01);
+        const double z01 = fma(y00, tq[uu].a01, y01 * tq[uu].a11);
+        const double z10 = fma(y10, tq[uu].a00, -y11 * tq[uu].a01);
+        const double z11 = fma(y10, tq[uu].a01, y11 * tq[uu].a11);
+        const int a0 = 2 * t, a1 = 2 * t + 1, c0i = 2 * uu, c1i = 2 * uu + 1;
+        auto extra = [&](int a, int c) { return q[a] * fb[c] + fb[a] * q[c] + sz * fb[a] * fb[c]; };
+        Pb[sidx(a0, c0i, D)] = z00 + extra(a0, c0i);
+        Pb[sidx(a0, c1i, D)] = z01 + extra(a0, c1i);
+        Pb[sidx(a1, c1i, D)] = z11 + extra(a1, c1i);
+        if (t != uu) Pb[sidx(a1, c0i, D)] = z10 + extra(a1, c0i);
+      }
+    }
+  }
+}
+
+}  // namespace gpssm

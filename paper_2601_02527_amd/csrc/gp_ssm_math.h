@@ -1,0 +1,555 @@
+// Device math of the augmented state-space filter: discretisation of one SHO
+// term over one step, and the structured predict / update / reset steps of
+// the filter on the augmented state (SHO states stacked, then one integrator
+// per instrument slot).
+//
+// Coordinates.  Each SHO term m is kept in the scaled state
+// (x_m, xdot_m / omega0_m), whose stationary covariance is sigma_m^2 I
+// (Appendix B, stationary covariance, after scaling the derivative by
+// omega0).  Integrators z_j are unscaled (z_j = integral of sum_m x_m over the
+// open exposure, Sec. 3.2).  An integrator is kept at exactly zero (mean and
+// covariance) while its slot is closed: it is zeroed right after the update
+// at the exposure end instead of at the next exposure start.  Because a closed
+// integrator never feeds the SHO states or the other integrators, the joint
+// law of the SHO states and the open integrators is the same as with the
+// reset of Sec. 3.2.1, so every likelihood term is unchanged.
+//
+// Discretisation.  With x = omega0*dt, beta = 1/(2Q), the impulse response g
+// of g'' + 2 beta g' + g = 0 (g(0) = 0, g'(0) = 1) gives every quantity of
+// the augmented step (Appendix B closed forms, rewritten):
+//   transition          [[g' + 2 beta g, g], [-g, g']]
+//   integrated row      (g + 2 beta G1, G1) / omega0,     G1 = int g
+//   process noise       qhat [[int g^2, g^2/2], [g^2/2, int g'^2]]
+//   x/z cross noise     qhat (G1^2/2, G1 g - int g^2) / omega0
+//   z/z noise           qhat int G1^2 / omega0^2,         qhat = 2 sigma^2/Q
+// For x max(1, beta) > XSER the closed forms use
+//   G1 = 1 - g' - 2 beta g,     int g'^2 = (1 - g'^2 - g^2) / (4 beta),
+//   int g^2 = int g'^2 - g g' - beta g^2,
+//   int G1^2 = x - g - 2 beta G1 - G1 g + int g^2 - beta G1^2,
+// with g = e^{-beta x} sin(eta x)/eta, eta^2 = 1 - beta^2 continued
+// analytically (cos/sin, cosh/sinh, or their series in eta^2 x^2 near
+// Q = 1/2).  Below the threshold these lose digits (int G1^2 ~ x^5/20) and a
+// Taylor series in x is used; its coefficients depend on beta only and are
+// produced once per term by the recurrence of the linear ODE satisfied by
+// (g, g', G1, g^2, g g', g'^2, G1^2, G1 g, G1 g', int g^2, int g'^2,
+// int G1^2).  The beta-derivative rides along as a dual number for the
+// adjoint; x-derivatives follow from the ODE.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define GPD __host__ __device__ __forceinline__
+
+namespace gpssm {
+
+constexpr int KSER = 26;          // Taylor terms kept (x^0 .. x^KSER)
+constexpr double XSER = 1.0;      // series used when x * max(1, beta) <= XSER
+constexpr int NFUN = 6;           // g, g', G1, int g^2, int g'^2, int G1^2
+constexpr int NCOEF = NFUN * (KSER + 1);
+constexpr double LOG_2PI = 1.8378770664093454835606594728112;
+
+// ---------------------------------------------------------------------------
+// dual numbers: value and derivative with respect to beta
+// ---------------------------------------------------------------------------
+struct Dual {
+  double v, d;
+};
+GPD Dual dual(double v, double d = 0.0) { return Dual{v, d}; }
+GPD Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+GPD Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+GPD Dual operator-(Dual a) { return {-a.v, -a.d}; }
+GPD Dual operator*(Dual a, Dual b) { return {a.v * b.v, fma(a.v, b.d, a.d * b.v)}; }
+GPD Dual operator*(double s, Dual a) { return {s * a.v, s * a.d}; }
+GPD Dual operator*(Dual a, double s) { return {s * a.v, s * a.d}; }
+GPD Dual operator+(Dual a, double s) { return {a.v + s, a.d}; }
+GPD Dual operator+(double s, Dual a) { return {a.v + s, a.d}; }
+GPD Dual operator-(Dual a, double s) { return {a.v - s, a.d}; }
+GPD Dual operator-(double s, Dual a) { return {s - a.v, -a.d}; }
+GPD Dual operator/(Dual a, Dual b) {
+  const double r = 1.0 / b.v;
+  const double q = a.v * r;
+  return {q, (a.d - q * b.d) * r};
+}
+GPD Dual operator/(Dual a, double s) { return {a.v / s, a.d / s}; }
+GPD double val(double a) { return a; }
+GPD double val(Dual a) { return a.v; }
+GPD double fexp(double a) { return exp(a); }
+GPD Dual fexp(Dual a) {
+  const double e = exp(a.v);
+  return {e, e * a.d};
+}
+GPD double fsqrt(double a) { return sqrt(a); }
+GPD Dual fsqrt(Dual a) {
+  const double s = sqrt(a.v);
+  return {s, 0.5 * a.d / s};
+}
+GPD void fsincos(double a, double* s, double* c) {
+#ifdef __HIP_DEVICE_COMPILE__
+  sincos(a, s, c);
+#else
+  *s = sin(a);
+  *c = cos(a);
+#endif
+}
+GPD void fsincos(Dual a, Dual* s, Dual* c) {
+  double sv, cv;
+  fsincos(a.v, &sv, &cv);
+  *s = {sv, cv * a.d};
+  *c = {cv, -sv * a.d};
+}
+template <class T>
+GPD T fconst(double v);
+template <>
+GPD double fconst<double>(double v) {
+  return v;
+}
+template <>
+GPD Dual fconst<Dual>(double v) {
+  return Dual{v, 0.0};
+}
+
+// the six base functions of one term over one step
+template <class T>
+struct Base {
+  T g, gp, G1, Igg, Ipp, IGG;
+};
+
+// ---------------------------------------------------------------------------
+// Taylor coefficients (value and beta-derivative) of the six base functions
+// ---------------------------------------------------------------------------
+// v' = B v for v = (g, g', G1, g^2, gg', g'^2, G1^2, G1g, G1g', Igg, Ipp, IGG)
+// coef[f * (KSER+1) + n] (f in output order g, g', G1, Igg, Ipp, IGG)
+GPD void series_coefficients(double beta, double* coef, double* dcoef) {
+  double c[12], d[12];
+  for (int i = 0; i < 12; ++i) {
+    c[i] = 0.0;
+    d[i] = 0.0;
+  }
+  c[1] = 1.0;  // g'(0)
+  c[5] = 1.0;  // g'(0)^2
+  const int out[NFUN] = {0, 1, 2, 9, 10, 11};
+  for (int n = 0; n <= KSER; ++n) {
+    for (int f = 0; f < NFUN; ++f) {
+      coef[f * (KSER + 1) + n] = c[out[f]];
+      dcoef[f * (KSER + 1) + n] = d[out[f]];
+    }
+    const double b2 = 2.0 * beta, b4 = 4.0 * beta;
+    double nc[12], nd[12];
+    nc[0] = c[1];
+    nc[1] = -c[0] - b2 * c[1];
+    nc[2] = c[0];
+    nc[3] = 2.0 * c[4];
+    nc[4] = c[5] - c[3] - b2 * c[4];
+    nc[5] = -2.0 * c[4] - b4 * c[5];
+    nc[6] = 2.0 * c[7];
+    nc[7] = c[3] + c[8];
+    nc[8] = c[4] - c[7] - b2 * c[8];
+    nc[9] = c[3];
+    nc[10] = c[5];
+    nc[11] = c[6];
+    // derivative of the recurrence with respect to beta
+    nd[0] = d[1];
+    nd[1] = -d[0] - b2 * d[1] - 2.0 * c[1];
+    nd[2] = d[0];
+    nd[3] = 2.0 * d[4];
+    nd[4] = d[5] - d[3] - b2 * d[4] - 2.0 * c[4];
+    nd[5] = -2.0 * d[4] - b4 * d[5] - 4.0 * c[5];
+    nd[6] = 2.0 * d[7];
+    nd[7] = d[3] + d[8];
+    nd[8] = d[4] - d[7] - b2 * d[8] - 2.0 * c[8];
+    nd[9] = d[3];
+    nd[10] = d[5];
+    nd[11] = d[6];
+    const double inv = 1.0 / (n + 1);
+    for (int i = 0; i < 12; ++i) {
+      c[i] = nc[i] * inv;
+      d[i] = nd[i] * inv;
+    }
+  }
+}
+
+// Horner evaluation of the six series at x
+GPD void series_eval(const double* __restrict__ coef, double x, Base<double>& o) {
+  double r[NFUN];
+#pragma unroll
+  for (int f = 0; f < NFUN; ++f) {
+    double v = coef[f * (KSER + 1) + KSER];
+#pragma unroll
+    for (int n = KSER - 1; n >= 0; --n) v = fma(v, x, coef[f * (KSER + 1) + n]);
+    r[f] = v;
+  }
+  o.g = r[0];
+  o.gp = r[1];
+  o.G1 = r[2];
+  o.Igg = r[3];
+  o.Ipp = r[4];
+  o.IGG = r[5];
+}
+GPD void series_eval(const double* __restrict__ coef, const double* __restrict__ dcoef, double x, Base<Dual>& o) {
+  double r[NFUN], rd[NFUN];
+#pragma unroll
+  for (int f = 0; f < NFUN; ++f) {
+    double v = coef[f * (KSER + 1) + KSER];
+    double w = dcoef[f * (KSER + 1) + KSER];
+#pragma unroll
+    for (int n = KSER - 1; n >= 0; --n) {
+      v = fma(v, x, coef[f * (KSER + 1) + n]);
+      w = fma(w, x, dcoef[f * (KSER + 1) + n]);
+    }
+    r[f] = v;
+    rd[f] = w;
+  }
+  o.g = {r[0], rd[0]};
+  o.gp = {r[1], rd[1]};
+  o.G1 = {r[2], rd[2]};
+  o.Igg = {r[3], rd[3]};
+  o.Ipp = {r[4], rd[4]};
+  o.IGG = {r[5], rd[5]};
+}
+
+// e^{-beta x} cos(eta x) and e^{-beta x} sin(eta x)/eta for eta^2 = 1 - beta^2
+// of either sign (hyperbolic when negative), finite through eta = 0.
+template <class T>
+GPD void damped_cs(double x, T beta, T& eC, T& eS) {
+  const T eta2 = 1.0 - beta * beta;
+  const T w = eta2 * (x * x);
+  const double wv = val(w);
+  if (wv >= -1.0 && wv <= 1.0) {
+    // cos(sqrt w) and sin(sqrt w)/sqrt w as series in w (|w| <= 1)
+    T c = fconst<T>(1.0), s = fconst<T>(1.0);
+    T tc = fconst<T>(1.0), ts = fconst<T>(1.0);
+#pragma unroll
+    for (int n = 0; n < 11; ++n) {
+      tc = tc * w * (-1.0 / ((2 * n + 1) * (2 * n + 2)));
+      ts = ts * w * (-1.0 / ((2 * n + 2) * (2 * n + 3)));
+      c = c + tc;
+      s = s + ts;
+    }
+    const T e = fexp(-(beta * x));
+    eC = e * c;
+    eS = e * s * x;
+  } else if (wv > 1.0) {
+    const T eta = fsqrt(eta2);
+    T sn, cs;
+    fsincos(eta * x, &sn, &cs);
+    const T e = fexp(-(beta * x));
+    eC = e * cs;
+    eS = e * sn / eta;
+  } else {
+    const T k = fsqrt(-eta2);
+    const T r = k * x;
+    const T bx = beta * x;
+    const T ep = fexp(r - bx);
+    const T em = fexp(-(r + bx));
+    eC = 0.5 * (ep + em);
+    eS = (ep - em) / (2.0 * k);
+  }
+}
+
+template <class T>
+GPD void closed_eval(double x, T beta, Base<T>& o) {
+  T eC, eS;
+  damped_cs<T>(x, beta, eC, eS);
+  const T g = eS;
+  const T gp = eC - beta * eS;
+  const T G1 = 1.0 - gp - 2.0 * beta * g;
+  const T Ipp = (1.0 - gp * gp - g * g) / (4.0 * beta);
+  const T Igg = Ipp - g * gp - beta * g * g;
+  const T IGG = (x - g) - 2.0 * beta * G1 - G1 * g + Igg - beta * G1 * G1;
+  o.g = g;
+  o.gp = gp;
+  o.G1 = G1;
+  o.Igg = Igg;
+  o.Ipp = Ipp;
+  o.IGG = IGG;
+}
+
+// ---------------------------------------------------------------------------
+// per-term constants and per-step quantities
+// ---------------------------------------------------------------------------
+struct TermConst {
+  double w0, beta, qhat, inv_w0, sigma;
+};
+
+GPD TermConst make_term(double sigma, double w0, double quality) {
+  TermConst t;
+  t.w0 = w0;
+  t.beta = 0.5 / quality;
+  t.qhat = 2.0 * sigma * sigma / quality;
+  t.inv_w0 = 1.0 / w0;
+  t.sigma = sigma;
+  return t;
+}
+
+// one term over one step, scaled SHO coordinates, unscaled integrator
+struct TermQ {
+  double a00, a01, a11;  // transition [[a00, a01], [-a01, a11]]
+  double f0, f1;         // integrated transition row
+  double q00, q01, q11;  // process noise
+  double c0, c1;         // SHO/integrator cross noise
+  double zz;             // integrator/integrator noise
+};
+
+GPD bool use_series(double x, double beta) { return x * fmax(1.0, beta) <= XSER; }
+
+GPD Base<double> base_values(const TermConst& t, const double* coef, double dt) {
+  const double x = t.w0 * dt;
+  Base<double> b;
+  if (use_series(x, t.beta))
+    series_eval(coef, x, b);
+  else
+    closed_eval<double>(x, t.beta, b);
+  return b;
+}
+
+GPD TermQ term_step(const TermConst& t, const Base<double>& b) {
+  TermQ q;
+  const double beta = t.beta;
+  q.a00 = b.gp + 2.0 * beta * b.g;
+  q.a01 = b.g;
+  q.a11 = b.gp;
+  q.f0 = (b.g + 2.0 * beta * b.G1) * t.inv_w0;
+  q.f1 = b.G1 * t.inv_w0;
+  q.q00 = t.qhat * b.Igg;
+  q.q01 = t.qhat * 0.5 * b.g * b.g;
+  q.q11 = t.qhat * b.Ipp;
+  q.c0 = t.qhat * 0.5 * b.G1 * b.G1 * t.inv_w0;
+  q.c1 = t.qhat * (b.G1 * b.g - b.Igg) * t.inv_w0;
+  q.zz = t.qhat * b.IGG * t.inv_w0 * t.inv_w0;
+  return q;
+}
+
+// ---------------------------------------------------------------------------
+// packed symmetric storage (upper triangle, row major)
+// ---------------------------------------------------------------------------
+GPD constexpr int sidx(int i, int j, int D) {
+  return (i <= j) ? (i * D - (i * (i - 1)) / 2 + (j - i)) : (j * D - (j * (j - 1)) / 2 + (i - j));
+}
+
+template <int M_, int J_>
+struct Dims {
+  static constexpr int M = M_;
+  static constexpr int J = J_;
+  static constexpr int NX = 2 * M_;
+  static constexpr int D = 2 * M_ + J_;
+  static constexpr int NP = D * (D + 1) / 2;
+  static constexpr int NXP = NX * (NX + 1) / 2;
+};
+
+// event encoding (32 bits): kind in bits 0-1, slot in bits 2-4, the set of
+// slots open during the step that ends at this event in bits 8-15
+enum : uint32_t { EV_END = 0u, EV_INSTANT = 1u, EV_START = 2u, EV_PAD = 3u };
+GPD uint32_t ev_kind(uint32_t info) { return info & 3u; }
+GPD uint32_t ev_slot(uint32_t info) { return (info >> 2) & 7u; }
+GPD uint32_t ev_open(uint32_t info) { return (info >> 8) & 0xffu; }
+
+// ---------------------------------------------------------------------------
+// predict: m <- A m, P <- A P A^T + Q on the augmented state
+// ---------------------------------------------------------------------------
+template <class Dm>
+GPD void predict_mean(double* m, const TermQ* tq, uint32_t open) {
+  constexpr int M = Dm::M, J = Dm::J, NX = Dm::NX;
+  double fx = 0.0;
+#pragma unroll
+  for (int t = 0; t < M; ++t) fx = fma(tq[t].f0, m[2 * t], fma(tq[t].f1, m[2 * t + 1], fx));
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    const double x0 = m[2 * t], x1 = m[2 * t + 1];
+    m[2 * t] = fma(tq[t].a00, x0, tq[t].a01 * x1);
+    m[2 * t + 1] = fma(-tq[t].a01, x0, tq[t].a11 * x1);
+  }
+#pragma unroll
+  for (int j = 0; j < J; ++j) m[NX + j] += ((open >> j) & 1u) ? fx : 0.0;
+}
+
+// columns of a D x NC matrix S (row-major, S[i*NC+c]) transformed as A S
+template <class Dm, int NC>
+GPD void predict_cols(double* S, const TermQ* tq, uint32_t open) {
+  constexpr int M = Dm::M, J = Dm::J, NX = Dm::NX;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    double fx = 0.0;
+#pragma unroll
+    for (int t = 0; t < M; ++t) fx = fma(tq[t].f0, S[(2 * t) * NC + c], fma(tq[t].f1, S[(2 * t + 1) * NC + c], fx));
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+      const double x0 = S[(2 * t) * NC + c], x1 = S[(2 * t + 1) * NC + c];
+      S[(2 * t) * NC + c] = fma(tq[t].a00, x0, tq[t].a01 * x1);
+      S[(2 * t + 1) * NC + c] = fma(-tq[t].a01, x0, tq[t].a11 * x1);
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) S[(NX + j) * NC + c] += ((open >> j) & 1u) ? fx : 0.0;
+  }
+}
+
+template <class Dm>
+GPD void predict_cov(double* P, const TermQ* tq, uint32_t open) {
+  constexpr int M = Dm::M, J = Dm::J, NX = Dm::NX, D = Dm::D;
+  // fbar = (f0_1, f1_1, f0_2, ...)
+  double fb[NX];
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    fb[2 * t] = tq[t].f0;
+    fb[2 * t + 1] = tq[t].f1;
+  }
+  // w = Pxx fbar, s = fbar.w, v_j = fbar . Pxz[:, j]
+  double w[NX];
+#pragma unroll
+  for (int a = 0; a < NX; ++a) {
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < NX; ++c) acc = fma(P[sidx(a, c, D)], fb[c], acc);
+    w[a] = acc;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < NX; ++a) s = fma(fb[a], w[a], s);
+  double v[J > 0 ? J : 1];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < NX; ++a) acc = fma(fb[a], P[sidx(a, NX + j, D)], acc);
+    v[j] = acc;
+  }
+  double zz = 0.0;
+#pragma unroll
+  for (int t = 0; t < M; ++t) zz += tq[t].zz;
+  // integrator block
+#pragma unroll
+  for (int i = 0; i < J; ++i) {
+    const double oi = ((open >> i) & 1u) ? 1.0 : 0.0;
+#pragma unroll
+    for (int j = i; j < J; ++j) {
+      const double oj = ((open >> j) & 1u) ? 1.0 : 0.0;
+      double& p = P[sidx(NX + i, NX + j, D)];
+      p = p + oi * v[j] + oj * v[i] + oi * oj * (s + zz);
+    }
+  }
+  // SHO/integrator block: Phi (Pxz[:, j] + o_j w) + o_j c
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const double oj = ((open >> j) & 1u) ? 1.0 : 0.0;
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+      const double y0 = fma(oj, w[2 * t], P[sidx(2 * t, NX + j, D)]);
+      const double y1 = fma(oj, w[2 * t + 1], P[sidx(2 * t + 1, NX + j, D)]);
+      P[sidx(2 * t, NX + j, D)] = fma(tq[t].a00, y0, fma(tq[t].a01, y1, oj * tq[t].c0));
+      P[sidx(2 * t + 1, NX + j, D)] = fma(-tq[t].a01, y0, fma(tq[t].a11, y1, oj * tq[t].c1));
+    }
+  }
+  // SHO block: Phi_t B Phi_u^T (+ Q on the diagonal blocks)
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+#pragma unroll
+    for (int u = t; u < M; ++u) {
+      const double b00 = P[sidx(2 * t, 2 * u, D)], b01 = P[sidx(2 * t, 2 * u + 1, D)];
+      const double b10 = P[sidx(2 * t + 1, 2 * u, D)], b11 = P[sidx(2 * t + 1, 2 * u + 1, D)];
+      // Y = Phi_t B
+      const double y00 = fma(tq[t].a00, b00, tq[t].a01 * b10);
+      const double y01 = fma(tq[t].a00, b01, tq[t].a01 * b11);
+      const double y10 = fma(-tq[t].a01, b00, tq[t].a11 * b10);
+      const double y11 = fma(-tq[t].a01, b01, tq[t].a11 * b11);
+      // Z = Y Phi_u^T
+      const double z00 = fma(y00, tq[u].a00, y01 * tq[u].a01);
+      const double z01 = fma(-y00, tq[u].a01, y01 * tq[u].a11);
+      const double z11 = fma(-y10, tq[u].a01, y11 * tq[u].a11);
+      if (t == u) {
+        P[sidx(2 * t, 2 * t, D)] = z00 + tq[t].q00;
+        P[sidx(2 * t, 2 * t + 1, D)] = z01 + tq[t].q01;
+        P[sidx(2 * t + 1, 2 * t + 1, D)] = z11 + tq[t].q11;
+      } else {
+        const double z10 = fma(y10, tq[u].a00, y11 * tq[u].a01);
+        P[sidx(2 * t, 2 * u, D)] = z00;
+        P[sidx(2 * t, 2 * u + 1, D)] = z01;
+        P[sidx(2 * t + 1, 2 * u, D)] = z10;
+        P[sidx(2 * t + 1, 2 * u + 1, D)] = z11;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// observation of one event.  h = e_{z_slot}/delta at an exposure end,
+// h = sum_m e_{x_m} at an instantaneous measurement, none at a start.
+// ---------------------------------------------------------------------------
+struct Obs {
+  double a[8];  // weight of each integrator in h (a_j = 1/delta for the slot)
+  double b;     // weight of every SHO x component (instantaneous)
+  double y, R;  // measurement and its noise variance (R = 1 for no measurement)
+  bool has;     // a measurement is made at this event
+};
+
+template <class Dm>
+GPD Obs make_obs(uint32_t info, double y, double r, double invd, double jit2) {
+  Obs o;
+  const uint32_t kind = ev_kind(info), slot = ev_slot(info);
+  const bool end = (kind == EV_END), inst = (kind == EV_INSTANT);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) o.a[j] = (end && (uint32_t)j == slot) ? invd : 0.0;
+  o.b = inst ? 1.0 : 0.0;
+  o.has = end || inst;
+  o.y = o.has ? y : 0.0;
+  o.R = o.has ? r + jit2 : 1.0;
+  return o;
+}
+
+// u = P h
+template <class Dm>
+GPD void obs_gain(const double* P, const Obs& o, double* u) {
+  constexpr int M = Dm::M, J = Dm::J, NX = Dm::NX, D = Dm::D;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < J; ++j) acc = fma(o.a[j], P[sidx(i, NX + j, D)], acc);
+    double xs = 0.0;
+#pragma unroll
+    for (int t = 0; t < M; ++t) xs += P[sidx(i, 2 * t, D)];
+    u[i] = fma(o.b, xs, acc);
+  }
+}
+
+// h . vec for a D-vector
+template <class Dm>
+GPD double obs_dot(const double* vec, const Obs& o) {
+  constexpr int M = Dm::M, J = Dm::J, NX = Dm::NX;
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < J; ++j) acc = fma(o.a[j], vec[NX + j], acc);
+  double xs = 0.0;
+#pragma unroll
+  for (int t = 0; t < M; ++t) xs += vec[2 * t];
+  return fma(o.b, xs, acc);
+}
+
+// zero the integrator closed by an exposure end
+template <class Dm>
+GPD void close_slot(double* m, double* P, uint32_t info) {
+  constexpr int J = Dm::J, NX = Dm::NX, D = Dm::D;
+  const bool end = ev_kind(info) == EV_END;
+  const uint32_t slot = ev_slot(info);
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const bool z = end && (uint32_t)j == slot;
+    m[NX + j] = z ? 0.0 : m[NX + j];
+#pragma unroll
+    for (int i = 0; i < D; ++i) P[sidx(i, NX + j, D)] = z ? 0.0 : P[sidx(i, NX + j, D)];
+  }
+}
+
+template <class Dm, int NC>
+GPD void close_slot_rows(double* S, uint32_t info) {
+  constexpr int J = Dm::J, NX = Dm::NX;
+  const bool end = ev_kind(info) == EV_END;
+  const uint32_t slot = ev_slot(info);
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const bool z = end && (uint32_t)j == slot;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) S[(NX + j) * NC + c] = z ? 0.0 : S[(NX + j) * NC + c];
+  }
+}
+
+}  // namespace gpssm

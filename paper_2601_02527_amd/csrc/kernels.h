@@ -1,0 +1,71 @@
+// Kernel-side data structures and the launch interface shared by the
+// per-term-count translation units and the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "gp_ssm_filter.h"
+
+namespace gpssm {
+
+struct DevPlan {
+  const double *dt, *t, *y, *r, *invd;
+  const uint32_t* info;
+  const int64_t* meas;
+  const int32_t *seg_series, *seg_chunk0, *seg_nch, *seg_len;
+  const int64_t* seg_ev0;
+  const int32_t *chunk_len, *chunk_series, *chunk_seg;
+  const uint8_t* chunk_first;
+  const int32_t *series_chunk0, *series_nch;
+  int64_t n_series;
+  int32_t n_chunks, n_seg;
+};
+
+// hyperparameters prepared on the device: per (series, term) TermConst and the
+// Taylor coefficients followed by their beta-derivatives (2*NCOEF doubles)
+struct DevParams {
+  const TermConst* tc;
+  const double* coef;
+  const double* jit;
+};
+
+// test-time work of the smoother, assigned to chunks on the host
+struct DevTests {
+  const double* t;           // test times, grouped by chunk, sorted within a chunk
+  const int64_t* out_index;  // where each result goes
+  const int64_t* chunk_t0;   // first test of each chunk (n_chunks + 1 entries)
+  const int32_t* before;     // per series: number of tests before the first event
+};
+
+struct Launch {
+  hipStream_t stream;
+};
+
+// per-(M, J) kernel launchers
+struct KernelSet {
+  void (*summaries)(const Launch&, const DevPlan&, const DevParams&, double* summ);
+  void (*adjoint)(const Launch&, const DevPlan&, const DevParams&, const double* bstate, const double* badj,
+                  double* rec, double* gpart, double* llchk);
+  void (*plain)(const Launch&, const DevPlan&, const DevParams&, int64_t series, double* loglik);
+  void (*smooth)(const Launch&, const DevPlan&, const DevParams&, const double* bstate, const double* bsmooth,
+                 double* rec, const DevTests& tests, double* mean_test, double* var_test, double* mean_data,
+                 double* var_data);
+};
+
+KernelSet kernels_m1(int J);
+KernelSet kernels_m2(int J);
+KernelSet kernels_m3(int J);
+KernelSet kernels_m4(int J);
+
+// kernel timing hooks (capi)
+void prof_begin(const char* name, hipStream_t s);
+void prof_end(const char* name, hipStream_t s);
+
+// per-event record of the forward pass kept for the backward passes:
+// the filtered state before the event (m, packed P)
+template <class Dm>
+constexpr int rec_fields() {
+  return Dm::D + Dm::NP;
+}
+
+}  // namespace gpssm

@@ -1,0 +1,15 @@
+// Kernels for 4 SHO term(s); see kernels_impl.h.
+#define GPSSM_M 4
+#define GPSSM_NS m4
+#include "kernels_impl.h"
+
+namespace gpssm {
+KernelSet kernels_m4(int J) {
+  switch (J) {
+    case 1: return m4::make_set<1>();
+    case 2: return m4::make_set<2>();
+    case 3: return m4::make_set<3>();
+    default: return m4::make_set<4>();
+  }
+}
+}  // namespace gpssm

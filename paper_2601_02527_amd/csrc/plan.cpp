@@ -1,0 +1,279 @@
+// Host-side event plan (see plan.h).
+//
+// Per series:
+//  * validation (finite inputs, t_end >= t_start, start times non-decreasing,
+//    yerr >= 0);
+//  * instrument slots: exposures in start order take the lowest slot whose
+//    previous exposure ended at or before their start, so no slot
+//    self-overlaps and the number of slots equals the overlap depth (any
+//    valid labelling gives the same result, Sec. 3.2.3);
+//  * events: each exposure with t_end > t_start gives a start and an end event
+//    (Sec. 3.2, K = 2N states), a zero-length exposure one instantaneous
+//    event; events are ordered by time, ends before instantaneous before
+//    starts at equal times;
+//  * chunks: the event sequence is cut after events where no exposure is open
+//    ("quiet" points), once a chunk has reached the target length, so that a
+//    chunk's boundary state is the SHO state alone.
+// Over the batch, runs of up to 64 chunks of one series form a segment (one
+// wavefront, one chunk per lane), and events are stored interleaved so a
+// wavefront reads 64 consecutive values per step.
+#include "plan.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <thread>
+
+namespace gpssm {
+
+namespace {
+
+enum : uint32_t { K_END = 0u, K_INSTANT = 1u, K_START = 2u, K_PAD = 3u };
+
+struct Ev {
+  double t;
+  uint32_t kind;
+  int32_t slot;
+  int64_t n;  // global measurement index
+};
+
+struct SeriesWork {
+  int rc = 0;
+  std::string err;
+  int32_t slots = 0;
+  std::vector<Ev> ev;
+  std::vector<uint32_t> open_before;
+  std::vector<int64_t> cuts;  // chunk end positions (exclusive)
+};
+
+int plan_series(int64_t b, int64_t lo, int64_t hi, const double* ts, const double* te, const double* yerr, int64_t Lb,
+                int32_t chunk_min, bool single, SeriesWork& w) {
+  const int64_t n = hi - lo;
+  for (int64_t i = lo; i < hi; ++i) {
+    if (!std::isfinite(ts[i]) || !std::isfinite(te[i]) || !std::isfinite(yerr[i])) {
+      w.err = "non-finite input in series " + std::to_string(b);
+      return -2;
+    }
+    if (te[i] < ts[i]) {
+      w.err = "t_end < t_start at measurement " + std::to_string(i);
+      return -2;
+    }
+    if (yerr[i] < 0) {
+      w.err = "negative yerr at measurement " + std::to_string(i);
+      return -2;
+    }
+    if (i > lo && ts[i] < ts[i - 1]) {
+      w.err = "t_start not sorted in series " + std::to_string(b);
+      return -2;
+    }
+  }
+  // slots
+  double last_end[MAX_SLOTS];
+  int32_t used = 0;
+  std::vector<int32_t> slot(n, -1);
+  for (int64_t i = 0; i < n; ++i) {
+    const double s = ts[lo + i], e = te[lo + i];
+    if (!(e > s)) continue;
+    int32_t k = -1;
+    for (int32_t j = 0; j < used; ++j)
+      if (last_end[j] <= s) {
+        k = j;
+        break;
+      }
+    if (k < 0) {
+      if (used == MAX_SLOTS) {
+        w.err = "more than " + std::to_string(MAX_SLOTS) + " overlapping exposures in series " + std::to_string(b);
+        return -4;
+      }
+      k = used++;
+    }
+    last_end[k] = e;
+    slot[i] = k;
+  }
+  w.slots = used;
+  // events
+  w.ev.clear();
+  w.ev.reserve(2 * n);
+  for (int64_t i = 0; i < n; ++i) {
+    if (slot[i] >= 0) {
+      w.ev.push_back({ts[lo + i], K_START, slot[i], lo + i});
+      w.ev.push_back({te[lo + i], K_END, slot[i], lo + i});
+    } else {
+      w.ev.push_back({ts[lo + i], K_INSTANT, -1, lo + i});
+    }
+  }
+  std::sort(w.ev.begin(), w.ev.end(), [](const Ev& a, const Ev& c) {
+    if (a.t != c.t) return a.t < c.t;
+    if (a.kind != c.kind) return a.kind < c.kind;
+    return a.n < c.n;
+  });
+  // open sets and quiet-point chunking
+  const int64_t ne = (int64_t)w.ev.size();
+  w.open_before.resize(ne);
+  w.cuts.clear();
+  uint32_t open = 0;
+  int64_t start = 0;
+  for (int64_t k = 0; k < ne; ++k) {
+    w.open_before[k] = open;
+    const Ev& e = w.ev[k];
+    if (e.kind == K_START) open |= (1u << e.slot);
+    if (e.kind == K_END) open &= ~(1u << e.slot);
+    const bool last = (k == ne - 1);
+    if (last || (!single && open == 0 && k + 1 - start >= std::max<int64_t>(Lb, chunk_min))) {
+      w.cuts.push_back(k + 1);
+      start = k + 1;
+    }
+  }
+  return 0;
+}
+
+}  // namespace
+
+int build_plan(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end, const double* y,
+               const double* yerr, const PlanOptions& opt, HostPlan& P, std::string& err) {
+  if (n_series < 1) {
+    err = "n_series < 1";
+    return -1;
+  }
+  if (offsets[0] != 0) {
+    err = "offsets[0] != 0";
+    return -1;
+  }
+  for (int64_t b = 0; b < n_series; ++b)
+    if (offsets[b + 1] < offsets[b]) {
+      err = "offsets not ascending at series " + std::to_string(b);
+      return -1;
+    }
+  const int64_t N = offsets[n_series];
+  for (int64_t i = 0; i < N; ++i)
+    if (!std::isfinite(y[i])) {
+      err = "non-finite y at measurement " + std::to_string(i);
+      return -2;
+    }
+  // total event estimate for the target chunk length
+  int64_t total_ev = 0;
+  for (int64_t i = 0; i < N; ++i) total_ev += (t_end[i] > t_start[i]) ? 2 : 1;
+  int64_t Lglob = opt.chunk_target > 0 ? opt.chunk_target
+                                       : std::max<int64_t>(opt.chunk_min, (total_ev + opt.target_chunks - 1) /
+                                                                            std::max<int64_t>(1, opt.target_chunks));
+
+  std::vector<SeriesWork> work(n_series);
+  unsigned nth = opt.threads > 0 ? (unsigned)opt.threads : std::max(1u, std::thread::hardware_concurrency());
+  nth = (unsigned)std::min<int64_t>(nth, n_series);
+  std::atomic<int64_t> next(0);
+  auto worker = [&]() {
+    for (;;) {
+      const int64_t b = next.fetch_add(1);
+      if (b >= n_series) break;
+      const int64_t lo = offsets[b], hi = offsets[b + 1];
+      int64_t eb = 0;
+      for (int64_t i = lo; i < hi; ++i) eb += (t_end[i] > t_start[i]) ? 2 : 1;
+      const int64_t Lb = std::min<int64_t>(Lglob, std::max<int64_t>(opt.chunk_min, (eb + WAVE - 1) / WAVE));
+      work[b].rc = plan_series(b, lo, hi, t_start, t_end, yerr, Lb, opt.chunk_min, opt.single_chunk != 0, work[b]);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (unsigned i = 1; i < nth; ++i) pool.emplace_back(worker);
+  worker();
+  for (auto& th : pool) th.join();
+  for (int64_t b = 0; b < n_series; ++b)
+    if (work[b].rc) {
+      err = work[b].err;
+      return work[b].rc;
+    }
+
+  // chunk and segment tables
+  P = HostPlan();
+  P.n_series = n_series;
+  P.n_meas = N;
+  P.series_chunk0.resize(n_series);
+  P.series_nch.resize(n_series);
+  P.series_slots.resize(n_series);
+  P.series_nev.resize(n_series);
+  std::vector<int64_t> chunk_evstart;  // (series-local start of each chunk)
+  for (int64_t b = 0; b < n_series; ++b) {
+    SeriesWork& w = work[b];
+    P.max_slots = std::max(P.max_slots, w.slots);
+    P.series_slots[b] = w.slots;
+    P.series_nev[b] = (int64_t)w.ev.size();
+    P.n_events += (int64_t)w.ev.size();
+    P.series_chunk0[b] = P.n_chunks;
+    int64_t prev = 0;
+    const int32_t c_first = P.n_chunks;
+    for (size_t q = 0; q < w.cuts.size(); ++q) {
+      const int64_t len = w.cuts[q] - prev;
+      P.chunk_len.push_back((int32_t)len);
+      P.chunk_series.push_back((int32_t)b);
+      P.chunk_first.push_back(q == 0 ? 1 : 0);
+      P.chunk_t0.push_back(w.ev[prev].t);
+      P.chunk_t1.push_back(w.ev[w.cuts[q] - 1].t);
+      chunk_evstart.push_back(prev);
+      P.max_chunk_len = std::max<int32_t>(P.max_chunk_len, (int32_t)len);
+      prev = w.cuts[q];
+      ++P.n_chunks;
+    }
+    P.series_nch[b] = P.n_chunks - c_first;
+    // segments of up to WAVE chunks
+    for (int32_t c = c_first; c < P.n_chunks; c += WAVE) {
+      const int32_t nch = std::min<int32_t>(WAVE, P.n_chunks - c);
+      int32_t L = 0;
+      for (int32_t q = 0; q < nch; ++q) L = std::max(L, P.chunk_len[c + q]);
+      P.seg_series.push_back((int32_t)b);
+      P.seg_chunk0.push_back(c);
+      P.seg_nch.push_back(nch);
+      P.seg_len.push_back(L);
+      P.seg_ev0.push_back(P.n_ev_pad);
+      for (int32_t q = 0; q < nch; ++q) P.chunk_seg.push_back(P.n_seg);
+      P.n_ev_pad += (int64_t)L * WAVE;
+      ++P.n_seg;
+    }
+  }
+  // interleaved event arrays
+  P.dt.assign(P.n_ev_pad, 0.0);
+  P.t.assign(P.n_ev_pad, 0.0);
+  P.y.assign(P.n_ev_pad, 0.0);
+  P.r.assign(P.n_ev_pad, 1.0);
+  P.invd.assign(P.n_ev_pad, 0.0);
+  P.info.assign(P.n_ev_pad, K_PAD);
+  P.meas.assign(P.n_ev_pad, -1);
+  std::atomic<int32_t> nextseg(0);
+  auto filler = [&]() {
+    for (;;) {
+      const int32_t s = nextseg.fetch_add(1);
+      if (s >= P.n_seg) break;
+      const int32_t b = P.seg_series[s];
+      const SeriesWork& w = work[b];
+      for (int32_t l = 0; l < P.seg_nch[s]; ++l) {
+        const int32_t c = P.seg_chunk0[s] + l;
+        const int64_t e0 = chunk_evstart[c];
+        for (int32_t k = 0; k < P.chunk_len[c]; ++k) {
+          const int64_t q = e0 + k;
+          const Ev& e = w.ev[q];
+          const int64_t at = P.seg_ev0[s] + (int64_t)k * WAVE + l;
+          P.t[at] = e.t;
+          P.dt[at] = (q == 0) ? 0.0 : e.t - w.ev[q - 1].t;
+          uint32_t info = e.kind | (e.slot >= 0 ? ((uint32_t)e.slot << 2) : 0u) | (w.open_before[q] << 8);
+          P.info[at] = info;
+          if (e.kind == K_END || e.kind == K_INSTANT) {
+            P.y[at] = y[e.n];
+            P.r[at] = yerr[e.n] * yerr[e.n];
+            P.meas[at] = e.n;
+            if (e.kind == K_END) P.invd[at] = 1.0 / (t_end[e.n] - t_start[e.n]);
+          } else {
+            P.r[at] = 1.0;
+          }
+        }
+        // pad the tail of the chunk at its end time
+        const double tend = P.chunk_t1[c];
+        for (int32_t k = P.chunk_len[c]; k < P.seg_len[s]; ++k) P.t[P.seg_ev0[s] + (int64_t)k * WAVE + l] = tend;
+      }
+    }
+  };
+  pool.clear();
+  for (unsigned i = 1; i < nth; ++i) pool.emplace_back(filler);
+  filler();
+  for (auto& th : pool) th.join();
+  return 0;
+}
+
+}  // namespace gpssm
