@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0, help="series for the CPU oracle (0 = one per core)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a device-to-device copy of 1 GiB (10 times), to scale HBM byte counters")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -99,6 +101,16 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(1)
+
+    if args.copy_calibration:
+        n = (1 << 30) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch_read": n * 8, "copy_bytes_per_launch_write": n * 8, "launches": 10}))
+        return
 
     t0 = time.perf_counter()
     batch = W.grad_1024() if args.workload == "grad_1024" else W.batch_4096()

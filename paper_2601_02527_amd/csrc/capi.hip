@@ -15,6 +15,7 @@
 #include "../../include/gp_ssm.h"
 #include "kernels.h"
 #include "plan.h"
+#include "scan.h"
 
 using namespace gpssm;
 
@@ -90,96 +91,6 @@ __global__ void k_prep(int64_t B, int M, const double* __restrict__ sigma, const
   if (i < B) jit[i] = jitter ? jitter[i] : 0.0;
 }
 
-template <int NX>
-__global__ void k_combine(DevPlan p, DevParams pr, const double* __restrict__ summ, double* __restrict__ bstate,
-                          double* __restrict__ badj, double* __restrict__ bsmooth, double* __restrict__ loglik,
-                          int32_t* __restrict__ status, int want_back) {
-  constexpr int NXP = NX * (NX + 1) / 2;
-  constexpr int M = NX / 2;
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= p.n_series) return;
-  const int64_t C = p.n_chunks;
-  const int32_t c0 = p.series_chunk0[b], n = p.series_nch[b];
-  if (n == 0) {  // a series without measurements
-    if (loglik) loglik[b] = 0.0;
-    if (status) status[b] = 0;
-    return;
-  }
-  double m[NX], P[NXP];
-#pragma unroll
-  for (int i = 0; i < NX; ++i) m[i] = 0.0;
-#pragma unroll
-  for (int i = 0; i < NXP; ++i) P[i] = 0.0;
-#pragma unroll
-  for (int t = 0; t < M; ++t) {
-    const double s2 = pr.tc[b * M + t].sigma * pr.tc[b * M + t].sigma;
-    P[sidx(2 * t, 2 * t, NX)] = s2;
-    P[sidx(2 * t + 1, 2 * t + 1, NX)] = s2;
-  }
-  bool ok = true;
-  double ll = 0.0;
-  for (int32_t q = 0; q < n; ++q) {
-    const int64_t c = c0 + q;
-#pragma unroll
-    for (int i = 0; i < NX; ++i) bstate[i * C + c] = m[i];
-#pragma unroll
-    for (int i = 0; i < NXP; ++i) bstate[(NX + i) * C + c] = P[i];
-    auto get = [=](int f) { return summ[(int64_t)f * C + c]; };
-    double mn[NX], Pn[NXP];
-    ll += combine_forward<NX>(m, P, get, mn, Pn, ok);
-#pragma unroll
-    for (int i = 0; i < NX; ++i) m[i] = mn[i];
-#pragma unroll
-    for (int i = 0; i < NXP; ++i) P[i] = Pn[i];
-  }
-  if (want_back) {
-    int64_t c = c0 + n - 1;
-#pragma unroll
-    for (int i = 0; i < NX + NXP; ++i) badj[i * C + c] = 0.0;
-    if (bsmooth) {
-#pragma unroll
-      for (int i = 0; i < NX; ++i) bsmooth[i * C + c] = m[i];
-#pragma unroll
-      for (int i = 0; i < NXP; ++i) bsmooth[(NX + i) * C + c] = P[i];
-    }
-    double Jf[NXP], ef[NX];
-#pragma unroll
-    for (int i = 0; i < NXP; ++i) Jf[i] = summ[(int64_t)(sum_J(NX) + i) * C + c];
-#pragma unroll
-    for (int i = 0; i < NX; ++i) ef[i] = summ[(int64_t)(sum_eta(NX) + i) * C + c];
-    for (int32_t q = n - 1; q >= 1; --q) {
-      c = c0 + q;
-      double mb_[NX], Pb_[NXP], mh[NX], Ph[NXP];
-#pragma unroll
-      for (int i = 0; i < NX; ++i) m[i] = bstate[i * C + c];
-#pragma unroll
-      for (int i = 0; i < NXP; ++i) P[i] = bstate[(NX + i) * C + c];
-      boundary_adjoint<NX>(m, P, Jf, ef, mb_, Pb_, bsmooth ? mh : nullptr, Ph, ok);
-#pragma unroll
-      for (int i = 0; i < NX; ++i) badj[i * C + c - 1] = mb_[i];
-#pragma unroll
-      for (int i = 0; i < NXP; ++i) badj[(NX + i) * C + c - 1] = Pb_[i];
-      if (bsmooth) {
-#pragma unroll
-        for (int i = 0; i < NX; ++i) bsmooth[i * C + c - 1] = mh[i];
-#pragma unroll
-        for (int i = 0; i < NXP; ++i) bsmooth[(NX + i) * C + c - 1] = Ph[i];
-      }
-      const int64_t cp = c - 1;
-      auto get = [=](int f) { return summ[(int64_t)f * C + cp]; };
-      double Jn[NXP], en[NX];
-      future_step<NX>(get, Jf, ef, Jn, en, ok);
-#pragma unroll
-      for (int i = 0; i < NXP; ++i) Jf[i] = Jn[i];
-#pragma unroll
-      for (int i = 0; i < NX; ++i) ef[i] = en[i];
-    }
-  }
-  const bool good = ok && isfinite(ll);
-  if (loglik) loglik[b] = good ? ll : __builtin_nan("");
-  if (status) status[b] = good ? 0 : GP_SSM_ENUMERIC;
-}
-
 __global__ void k_reduce_grad(DevPlan p, int M, const double* __restrict__ gpart, const int32_t* __restrict__ status,
                               double* __restrict__ grad) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -192,33 +103,6 @@ __global__ void k_reduce_grad(DevPlan p, int M, const double* __restrict__ gpart
     double s = 0.0;
     for (int32_t q = 0; q < n; ++q) s += gpart[(int64_t)f * C + c0 + q];
     grad[b * G + f] = (good && isfinite(s)) ? s : __builtin_nan("");
-  }
-}
-
-__global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) a[i] = v;
-}
-
-template <int NX>
-void launch_combine(hipStream_t s, const DevPlan& p, const DevParams& pr, const double* summ, double* bstate,
-                    double* badj, double* bsmooth, double* loglik, int32_t* status, int back) {
-  const int threads = 64;
-  const int blocks = (int)((p.n_series + threads - 1) / threads);
-  if (blocks == 0) return;
-  prof_begin("k_combine", s);
-  hipLaunchKernelGGL(k_combine<NX>, dim3(blocks), dim3(threads), 0, s, p, pr, summ, bstate, badj, bsmooth, loglik,
-                     status, back);
-  prof_end("k_combine", s);
-}
-
-void combine_dispatch(int M, hipStream_t s, const DevPlan& p, const DevParams& pr, const double* summ, double* bstate,
-                      double* badj, double* bsmooth, double* loglik, int32_t* status, int back) {
-  switch (M) {
-    case 1: launch_combine<2>(s, p, pr, summ, bstate, badj, bsmooth, loglik, status, back); break;
-    case 2: launch_combine<4>(s, p, pr, summ, bstate, badj, bsmooth, loglik, status, back); break;
-    case 3: launch_combine<6>(s, p, pr, summ, bstate, badj, bsmooth, loglik, status, back); break;
-    default: launch_combine<8>(s, p, pr, summ, bstate, badj, bsmooth, loglik, status, back); break;
   }
 }
 
@@ -309,9 +193,10 @@ struct gp_ssm_plan {
   DBuf dt, t, y, r, invd, info, meas;
   DBuf seg_series, seg_chunk0, seg_nch, seg_len, seg_ev0;
   DBuf chunk_len, chunk_series, chunk_seg, chunk_first;
-  DBuf series_chunk0, series_nch;
+  DBuf series_chunk0, series_nch, series_seg0, series_nseg;
   // workspace
   DBuf tc, coef, jit, summ, bstate, badj, bsmooth, gpart, rec, status;
+  DBuf pre, suf, segtot, segstate, segfut, segll, segok;
   DBuf tests_t, tests_idx, tests_c0, tests_before;
 
   DevPlan dev() const {
@@ -334,6 +219,8 @@ struct gp_ssm_plan {
     p.chunk_first = chunk_first.as<uint8_t>();
     p.series_chunk0 = series_chunk0.as<int32_t>();
     p.series_nch = series_nch.as<int32_t>();
+    p.series_seg0 = series_seg0.as<int32_t>();
+    p.series_nseg = series_nseg.as<int32_t>();
     p.n_series = host.n_series;
     p.n_chunks = host.n_chunks;
     p.n_seg = host.n_seg;
@@ -392,21 +279,42 @@ int prepare_params(gp_ssm_plan* pl, int32_t M, const double* sigma, const double
 int run_forward(gp_ssm_plan* pl, int32_t M, const DevParams& pr, hipStream_t s, double* loglik, int32_t* status,
                 int back, bool need_smooth) {
   const int NX = 2 * M;
-  const int64_t C = pl->host.n_chunks;
+  const int NXP = NX * (NX + 1) / 2;
+  const int64_t C = std::max<int64_t>(1, pl->host.n_chunks);
+  const int64_t S = std::max<int64_t>(1, pl->host.n_seg);
+  const int EF = elem_fields(NX);
   if (int rc = pl->summ.ensure(sizeof(double) * summary_size(NX) * C)) return rc;
-  if (int rc = pl->bstate.ensure(sizeof(double) * (NX + NX * (NX + 1) / 2) * C)) return rc;
+  if (int rc = pl->bstate.ensure(sizeof(double) * (NX + NXP) * C)) return rc;
+  if (int rc = pl->pre.ensure(sizeof(double) * EF * C)) return rc;
+  if (int rc = pl->suf.ensure(sizeof(double) * EF * C)) return rc;
+  if (int rc = pl->segtot.ensure(sizeof(double) * EF * S)) return rc;
+  if (int rc = pl->segstate.ensure(sizeof(double) * (NX + NXP) * S)) return rc;
+  if (int rc = pl->segfut.ensure(sizeof(double) * (NX + NXP) * S)) return rc;
+  if (int rc = pl->segll.ensure(sizeof(double) * S)) return rc;
+  if (int rc = pl->segok.ensure(sizeof(int32_t) * S)) return rc;
   if (back) {
-    if (int rc = pl->badj.ensure(sizeof(double) * (NX + NX * (NX + 1) / 2) * C)) return rc;
+    if (int rc = pl->badj.ensure(sizeof(double) * (NX + NXP) * C)) return rc;
     if (need_smooth)
-      if (int rc = pl->bsmooth.ensure(sizeof(double) * (NX + NX * (NX + 1) / 2) * C)) return rc;
+      if (int rc = pl->bsmooth.ensure(sizeof(double) * (NX + NXP) * C)) return rc;
   }
   const DevPlan p = pl->dev();
   const KernelSet ks = kernel_set(M, pl->host.max_slots);
   Launch L{s};
   ks.summaries(L, p, pr, pl->summ.as<double>());
   HIP_TRY(hipGetLastError());
-  combine_dispatch(M, s, p, pr, pl->summ.as<double>(), pl->bstate.as<double>(), back ? pl->badj.as<double>() : nullptr,
-                   need_smooth ? pl->bsmooth.as<double>() : nullptr, loglik, status, back);
+  ScanWork w;
+  w.summ = pl->summ.as<double>();
+  w.pre = pl->pre.as<double>();
+  w.suf = pl->suf.as<double>();
+  w.segtot = pl->segtot.as<double>();
+  w.segstate = pl->segstate.as<double>();
+  w.segfut = pl->segfut.as<double>();
+  w.bstate = pl->bstate.as<double>();
+  w.badj = back ? pl->badj.as<double>() : nullptr;
+  w.bsmooth = (back && need_smooth) ? pl->bsmooth.as<double>() : nullptr;
+  w.segll = pl->segll.as<double>();
+  w.segok = pl->segok.as<int32_t>();
+  run_scan(M, s, p, pr, w, loglik, status, back);
   HIP_TRY(hipGetLastError());
   return 0;
 }
@@ -471,7 +379,8 @@ int gp_ssm_plan_create(int64_t n_series, const int64_t* offsets, const double* t
       (rc = upload(pl->seg_ev0, h.seg_ev0)) || (rc = upload(pl->chunk_len, h.chunk_len)) ||
       (rc = upload(pl->chunk_series, h.chunk_series)) || (rc = upload(pl->chunk_seg, h.chunk_seg)) ||
       (rc = upload(pl->chunk_first, h.chunk_first)) || (rc = upload(pl->series_chunk0, h.series_chunk0)) ||
-      (rc = upload(pl->series_nch, h.series_nch))) {
+      (rc = upload(pl->series_nch, h.series_nch)) || (rc = upload(pl->series_seg0, h.series_seg0)) ||
+      (rc = upload(pl->series_nseg, h.series_nseg))) {
     delete pl;
     return rc;
   }
@@ -551,22 +460,91 @@ int gp_ssm_plan_smooth(gp_ssm_plan* pl, int32_t M, const double* sigma, const do
                        const double* jitter, const int64_t* test_offsets, const double* t_test, double* mean_test,
                        double* var_test, double* mean_data, double* var_data, double* loglik, int32_t* status,
                        void* stream) {
-  (void)pl;
-  (void)M;
-  (void)sigma;
-  (void)omega0;
-  (void)quality;
-  (void)jitter;
-  (void)test_offsets;
-  (void)t_test;
-  (void)mean_test;
-  (void)var_test;
-  (void)mean_data;
-  (void)var_data;
-  (void)loglik;
-  (void)status;
-  (void)stream;
-  return fail(GP_SSM_EINVAL, "gp_ssm_plan_smooth: not available in this build");
+  g_err.clear();
+  if (!pl) return fail(GP_SSM_EINVAL, "null plan");
+  if (!test_offsets) return fail(GP_SSM_EINVAL, "null test_offsets");
+  hipStream_t s = (hipStream_t)stream;
+  const HostPlan& h = pl->host;
+  const int64_t B = h.n_series;
+  std::vector<int64_t> to(B + 1);
+  if (int rc = host_copy(test_offsets, sizeof(int64_t) * (B + 1), to.data(), s)) return rc;
+  if (to[0] != 0) return fail(GP_SSM_EINVAL, "test_offsets[0] != 0");
+  for (int64_t q = 0; q < B; ++q)
+    if (to[q + 1] < to[q]) return fail(GP_SSM_EINVAL, "test_offsets not ascending");
+  const int64_t T = to[B];
+  if (T > 0 && (!t_test || !mean_test || !var_test)) return fail(GP_SSM_EINVAL, "null test arrays");
+  std::vector<double> tt(T);
+  if (int rc = host_copy(t_test, sizeof(double) * T, tt.data(), s)) return rc;
+  for (int64_t i = 0; i < T; ++i)
+    if (!std::isfinite(tt[i])) return fail(GP_SSM_EDATA, "non-finite test time");
+  // assign each test time to the chunk whose event interval holds it
+  const int64_t C = h.n_chunks;
+  std::vector<int32_t> owner(T);
+  std::vector<int64_t> cnt(C + 1, 0);
+  for (int64_t q = 0; q < B; ++q) {
+    const int32_t c0 = h.series_chunk0[q], n = h.series_nch[q];
+    if (to[q + 1] > to[q] && n == 0) return fail(GP_SSM_EINVAL, "test times for a series without measurements");
+    for (int64_t i = to[q]; i < to[q + 1]; ++i) {
+      int32_t lo = c0, hi = c0 + n - 1;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) / 2;
+        if (h.chunk_t1[mid] >= tt[i])
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      owner[i] = lo;
+      ++cnt[lo + 1];
+    }
+  }
+  std::vector<int64_t> c0v(C + 1, 0);
+  for (int64_t c = 0; c < C; ++c) c0v[c + 1] = c0v[c] + cnt[c + 1];
+  std::vector<int64_t> fillp(c0v.begin(), c0v.end() - 1), idx(T);
+  for (int64_t i = 0; i < T; ++i) idx[fillp[owner[i]]++] = i;
+  std::vector<double> tsort(T);
+  for (int64_t c = 0; c < C; ++c) {
+    std::stable_sort(idx.begin() + c0v[c], idx.begin() + c0v[c + 1], [&](int64_t x, int64_t y) { return tt[x] < tt[y]; });
+  }
+  for (int64_t i = 0; i < T; ++i) tsort[i] = tt[idx[i]];
+  std::vector<double> tprev(std::max<int64_t>(1, C), 0.0);
+  for (int64_t c = 0; c < C; ++c) tprev[c] = h.chunk_first[c] ? 0.0 : h.chunk_t1[c - 1];
+  if (int rc = upload(pl->tests_t, tsort)) return rc;
+  if (int rc = upload(pl->tests_idx, idx)) return rc;
+  if (int rc = upload(pl->tests_c0, c0v)) return rc;
+  if (int rc = upload(pl->tests_before, tprev)) return rc;
+
+  DevParams pr;
+  if (int rc = prepare_params(pl, M, sigma, omega0, quality, jitter, s, pr)) return rc;
+  int32_t* st = status;
+  if (!st) {
+    if (int rc = pl->status.ensure(sizeof(int32_t) * B)) return rc;
+    st = pl->status.as<int32_t>();
+  }
+  double* ll = loglik;
+  DBuf tmpll;
+  if (!ll) {
+    if (int rc = tmpll.ensure(sizeof(double) * B)) return rc;
+    ll = tmpll.as<double>();
+  }
+  if (int rc = run_forward(pl, M, pr, s, ll, st, 1, true)) return rc;
+  const int NX = 2 * M;
+  const int J = std::max(1, h.max_slots);
+  const int D = NX + J;
+  const int F = D + D * (D + 1) / 2;
+  if (int rc = pl->rec.ensure(sizeof(double) * F * std::max<int64_t>(1, h.n_ev_pad))) return rc;
+  const DevPlan p = pl->dev();
+  const KernelSet ks = kernel_set(M, h.max_slots);
+  DevTests dt;
+  dt.t = pl->tests_t.as<double>();
+  dt.out_index = pl->tests_idx.as<int64_t>();
+  dt.chunk_t0 = pl->tests_c0.as<int64_t>();
+  dt.chunk_tprev = pl->tests_before.as<double>();
+  Launch L{s};
+  ks.smooth(L, p, pr, pl->bstate.as<double>(), pl->bsmooth.as<double>(), pl->rec.as<double>(), dt, mean_test, var_test,
+            mean_data, var_data);
+  HIP_TRY(hipGetLastError());
+  if (!loglik) HIP_TRY(hipStreamSynchronize(s));  // the temporary log-likelihood buffer is freed on return
+  return 0;
 }
 
 int gp_ssm_plan_plain_loglik(gp_ssm_plan* pl, int64_t first, int64_t count, int32_t M, const double* sigma,

@@ -318,6 +318,176 @@ GPD void future_step(Get s, const double* Jn, const double* en, double* Jo, doub
     }
 }
 
+// A chunk summary (or a composition of consecutive ones) in registers.
+template <int N>
+struct Elem {
+  static constexpr int NP = N * (N + 1) / 2;
+  double A[N * N], b[N], C[NP], eta[N], J[NP];
+
+  GPD void identity() {
+#pragma unroll
+    for (int i = 0; i < N * N; ++i) A[i] = (i % (N + 1) == 0) ? 1.0 : 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) b[i] = eta[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) C[i] = J[i] = 0.0;
+  }
+  template <class Get>
+  GPD void load(Get g) {
+#pragma unroll
+    for (int i = 0; i < N * N; ++i) A[i] = g(sum_A(N) + i);
+#pragma unroll
+    for (int i = 0; i < N; ++i) b[i] = g(sum_b(N) + i);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) C[i] = g(sum_C(N) + i);
+#pragma unroll
+    for (int i = 0; i < N; ++i) eta[i] = g(sum_eta(N) + i);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) J[i] = g(sum_J(N) + i);
+  }
+  template <class Put>
+  GPD void store(Put p) const {
+#pragma unroll
+    for (int i = 0; i < N * N; ++i) p(sum_A(N) + i, A[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) p(sum_b(N) + i, b[i]);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) p(sum_C(N) + i, C[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) p(sum_eta(N) + i, eta[i]);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) p(sum_J(N) + i, J[i]);
+  }
+  // accessor in the summary field numbering (c0 reads as 0)
+  GPD double get(int f) const {
+    if (f < sum_b(N)) return A[f];
+    if (f < sum_C(N)) return b[f - sum_b(N)];
+    if (f < sum_eta(N)) return C[f - sum_C(N)];
+    if (f < sum_J(N)) return eta[f - sum_eta(N)];
+    if (f < sum_c0(N)) return J[f - sum_J(N)];
+    return 0.0;
+  }
+};
+
+// Associative composition of two consecutive summaries (i earlier, j
+// later), the filtering operator of the parallel Kalman filter (SG21):
+//   X = (I + C_i J_j)^-1
+//   A = A_j X A_i,  b = A_j X (b_i + C_i eta_j) + b_j,  C = A_j X C_i A_j^T + C_j
+//   eta = A_i^T X^T (eta_j - J_j b_i) + eta_i,  J = A_i^T J_j X A_i + J_i
+// with X^T v = v - J_j X C_i v and J_j X = X^T J_j.  Result in o (may alias
+// neither input).
+template <int N>
+GPD void compose(const Elem<N>& ei, const Elem<N>& ej, Elem<N>& o, bool& ok) {
+  double Ci[N * N], Jj[N * N];
+  unpack<N>(ei.C, Ci);
+  unpack<N>(ej.J, Jj);
+  // [X A_i | X (b_i + C_i eta_j) | X C_i]
+  constexpr int R = 2 * N + 1;
+  double Mx[N * N], B[N * R];
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      double v = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) v = fma(Ci[r * N + k], Jj[k * N + c], v);
+      Mx[r * N + c] = v;
+      B[r * R + c] = ei.A[r * N + c];
+      B[r * R + N + 1 + c] = Ci[r * N + c];
+    }
+    double v = ei.b[r];
+#pragma unroll
+    for (int k = 0; k < N; ++k) v = fma(Ci[r * N + k], ej.eta[k], v);
+    B[r * R + N] = v;
+  }
+  lu_solve<N, R>(Mx, B, ok);
+  // A = A_j XA, b = A_j Xb + b_j, C = A_j XC A_j^T + C_j
+  double AjXC[N * N];
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    double bb = ej.b[r];
+#pragma unroll
+    for (int k = 0; k < N; ++k) bb = fma(ej.A[r * N + k], B[k * R + N], bb);
+    o.b[r] = bb;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      double a = 0.0, x = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        a = fma(ej.A[r * N + k], B[k * R + c], a);
+        x = fma(ej.A[r * N + k], B[k * R + N + 1 + c], x);
+      }
+      o.A[r * N + c] = a;
+      AjXC[r * N + c] = x;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int c = r; c < N; ++c) {
+      double v = ej.C[sidx(r, c, N)], w = ej.C[sidx(r, c, N)];
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        v = fma(AjXC[r * N + k], ej.A[c * N + k], v);
+        w = fma(AjXC[c * N + k], ej.A[r * N + k], w);
+      }
+      o.C[sidx(r, c, N)] = 0.5 * (v + w);
+    }
+  // v = eta_j - J_j b_i ; Xt v = v - J_j (X C_i v)
+  double vv[N], t1[N], xtv[N];
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    double v = ej.eta[r];
+#pragma unroll
+    for (int k = 0; k < N; ++k) v = fma(-Jj[r * N + k], ei.b[k], v);
+    vv[r] = v;
+  }
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) v = fma(B[r * R + N + 1 + k], vv[k], v);
+    t1[r] = v;
+  }
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    double v = vv[r];
+#pragma unroll
+    for (int k = 0; k < N; ++k) v = fma(-Jj[r * N + k], t1[k], v);
+    xtv[r] = v;
+  }
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    double v = ei.eta[r];
+#pragma unroll
+    for (int k = 0; k < N; ++k) v = fma(ei.A[k * N + r], xtv[k], v);
+    o.eta[r] = v;
+  }
+  // J = A_i^T (J_j XA) + J_i
+  double JXA[N * N];
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) v = fma(Jj[r * N + k], B[k * R + c], v);
+      JXA[r * N + c] = v;
+    }
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int c = r; c < N; ++c) {
+      double v = 0.0, w = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        v = fma(ei.A[k * N + r], JXA[k * N + c], v);
+        w = fma(ei.A[k * N + c], JXA[k * N + r], w);
+      }
+      o.J[sidx(r, c, N)] = ei.J[sidx(r, c, N)] + 0.5 * (v + w);
+    }
+}
+
 // gradient of the future log-likelihood with respect to the moments (m, P)
 // of the boundary state, given the future information (J~, eta~):
 //   B = (I + J~ P)^-1, mbar = B (eta~ - J~ m), Pbar = (mbar mbar^T - B J~)/2
@@ -384,6 +554,150 @@ GPD void boundary_adjoint(const double* m, const double* Pp, const double* Jp, c
 }
 
 // ---------------------------------------------------------------------------
+// RTS smoothing step on the augmented state
+// ---------------------------------------------------------------------------
+// X = Pm^-1 Y for a packed symmetric Pm restricted to the active indices
+// (inactive rows/columns are replaced by the identity and their rows of Y
+// must be zero), by Cholesky.  Y is D x R row-major.  Returns false on a
+// non-positive pivot.
+template <int D, int R>
+GPD bool chol_solve_masked(const double* Pm, const bool* act, double* Y) {
+  double L[D * (D + 1) / 2];
+  bool good = true;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    double d = act[j] ? Pm[sidx(j, j, D)] : 1.0;
+#pragma unroll
+    for (int k = 0; k < j; ++k) d = fma(-L[sidx(j, k, D)], L[sidx(j, k, D)], d);
+    good = good && (d > 0.0);
+    const double ljj = sqrt(fmax(d, 1e-300));
+    L[sidx(j, j, D)] = ljj;
+    const double inv = 1.0 / ljj;
+#pragma unroll
+    for (int i = j + 1; i < D; ++i) {
+      double v = (act[i] && act[j]) ? Pm[sidx(i, j, D)] : 0.0;
+#pragma unroll
+      for (int k = 0; k < j; ++k) v = fma(-L[sidx(i, k, D)], L[sidx(j, k, D)], v);
+      L[sidx(i, j, D)] = v * inv;
+    }
+  }
+  // forward then backward substitution
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double v = Y[i * R + c];
+#pragma unroll
+      for (int k = 0; k < i; ++k) v = fma(-L[sidx(i, k, D)], Y[k * R + c], v);
+      Y[i * R + c] = v / L[sidx(i, i, D)];
+    }
+#pragma unroll
+    for (int i = D - 1; i >= 0; --i) {
+      double v = Y[i * R + c];
+#pragma unroll
+      for (int k = i + 1; k < D; ++k) v = fma(-L[sidx(k, i, D)], Y[k * R + c], v);
+      Y[i * R + c] = v / L[sidx(i, i, D)];
+    }
+  }
+  return good;
+}
+
+// One RTS step: given the filtered state (m, P) of the current step, the
+// transition to the next state x_next = F x + q (F = A applied after zeroing
+// the integrators in `zmask`, q ~ N(0, Q) over `open`), and the smoothed
+// moments (ms, Ps) of the next state, returns the smoothed moments of the
+// current state in (m, P):
+//   Pm = F P F^T + Q,  G = P F^T Pm^-1,
+//   m <- m + G (ms - F m),  P <- P + G (Ps - Pm) G^T.
+// Pm is inverted on the SHO states and the integrators that are open over
+// the step with positive predicted variance (the others are deterministic
+// zeros).  zmask: integrators zeroed before the transition.
+template <class Dm>
+GPD bool rts_step(double* m, double* P, const TermQ* tq, uint32_t open, uint32_t zmask, const double* ms,
+                  const double* Ps) {
+  constexpr int NX = Dm::NX, D = Dm::D, NP = Dm::NP, J = Dm::J;
+  // zero the closed integrators (they are constants after the zeroing)
+  double mz[D], Pz[NP];
+#pragma unroll
+  for (int i = 0; i < D; ++i) mz[i] = (i >= NX && ((zmask >> (i - NX)) & 1u)) ? 0.0 : m[i];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = i; j < D; ++j) {
+      const bool zi = i >= NX && ((zmask >> (i - NX)) & 1u), zj = j >= NX && ((zmask >> (j - NX)) & 1u);
+      Pz[sidx(i, j, D)] = (zi || zj) ? 0.0 : P[sidx(i, j, D)];
+    }
+  // predicted moments of the next state
+  double mp[D], Pm[NP];
+#pragma unroll
+  for (int i = 0; i < D; ++i) mp[i] = mz[i];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) Pm[i] = Pz[i];
+  predict_mean<Dm>(mp, tq, open);
+  predict_cov<Dm>(Pm, tq, open);
+  // Y = F P = A (R P)  (= (P F^T)^T): rows = next-state index, columns =
+  // current-state index (the zeroed integrators keep their columns, so their
+  // pre-zeroing values are smoothed too)
+  double Y[D * D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    double col[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) col[i] = (i >= NX && ((zmask >> (i - NX)) & 1u)) ? 0.0 : P[sidx(i, c, D)];
+    predict_mean<Dm>(col, tq, open);
+#pragma unroll
+    for (int i = 0; i < D; ++i) Y[i * D + c] = col[i];
+  }
+  bool act[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) act[i] = (i < NX) || (((open >> (i - NX)) & 1u) && Pm[sidx(i, i, D)] > 0.0);
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+    if (!act[i])
+#pragma unroll
+      for (int c = 0; c < D; ++c) Y[i * D + c] = 0.0;
+  const bool ok = chol_solve_masked<D, D>(Pm, act, Y);  // Y <- Pm^-1 F P = G^T
+  // m <- m + G (ms - mp)
+  double dm[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) dm[i] = act[i] ? ms[i] - mp[i] : 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    double v = m[i];
+#pragma unroll
+    for (int k = 0; k < D; ++k) v = fma(Y[k * D + i], dm[k], v);
+    m[i] = v;
+  }
+  // P <- P + G (Ps - Pm) G^T
+  double dP[D * D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) dP[i * D + j] = (act[i] && act[j]) ? Ps[sidx(i, j, D)] - Pm[sidx(i, j, D)] : 0.0;
+  double T2[D * D];  // dP G^T = dP Y
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) v = fma(dP[i * D + k], Y[k * D + c], v);
+      T2[i * D + c] = v;
+    }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = i; j < D; ++j) {
+      double v = P[sidx(i, j, D)];
+#pragma unroll
+      for (int k = 0; k < D; ++k) v = fma(Y[k * D + i], T2[k * D + j], v);
+      P[sidx(i, j, D)] = v;
+    }
+  (void)J;
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
 // reverse-mode adjoint of one plain filter step
 // ---------------------------------------------------------------------------
 // Gradient accumulators per term: (sigma, omega0, Q); plus jitter.
@@ -401,11 +715,14 @@ struct GradAcc {
 // Back-propagates the adjoint weights of one term's step quantities to
 // (sigma, omega0, Q).  W: abar00, abar01, abar11, fbar0, fbar1, qbar00,
 // qbar01, qbar11, cbar0, cbar1, zzbar (weights of the TermQ fields, with the
-// transition's (1,0) entry -a01 folded into abar01).
-GPD void term_backprop(const TermConst& t, const Base<Dual>& b, double dt, const double* W, double& gs, double& gw,
-                       double& gq) {
-  const double beta = t.beta, qh = t.qhat, iw = t.inv_w0;
-  const double g = b.g.v, gp = b.gp.v, G1 = b.G1.v, Igg = b.Igg.v, Ipp = b.Ipp.v, IGG = b.IGG.v;
+// transition's (1,0) entry -a01 folded into abar01).  The base-function
+// values are read back from the step quantities; db holds their
+// beta-derivatives (g, g', G1, int g^2, int g'^2, int G1^2).
+GPD void term_backprop(const TermConst& t, const TermQ& q, const double* db, double dt, const double* W, double& gs,
+                       double& gw, double& gq) {
+  const double beta = t.beta, qh = t.qhat, iw = t.inv_w0, w0 = t.w0;
+  const double iq = 1.0 / qh;
+  const double g = q.a01, gp = q.a11, G1 = q.f1 * w0, Igg = q.q00 * iq, Ipp = q.q11 * iq, IGG = q.zz * w0 * w0 * iq;
   double bg = 0, bgp = 0, bG1 = 0, bIgg = 0, bIpp = 0, bIGG = 0, bbeta = 0, bqh = 0, biw = 0;
   // transition
   bgp += W[0];
@@ -440,16 +757,15 @@ GPD void term_backprop(const TermConst& t, const Base<Dual>& b, double dt, const
   bIGG += qh * iw * iw * W[10];
   bqh += W[10] * IGG * iw * iw;
   biw += 2.0 * W[10] * qh * IGG * iw;
-  // base functions -> (x, beta)
+  // base functions -> (x, beta): d/dx from the ODE, d/dbeta from the duals
   const double bx = bg * gp + bgp * (-g - 2.0 * beta * gp) + bG1 * g + bIgg * g * g + bIpp * gp * gp + bIGG * G1 * G1;
-  bbeta += bg * b.g.d + bgp * b.gp.d + bG1 * b.G1.d + bIgg * b.Igg.d + bIpp * b.Ipp.d + bIGG * b.IGG.d;
+  bbeta += bg * db[0] + bgp * db[1] + bG1 * db[2] + bIgg * db[3] + bIpp * db[4] + bIGG * db[5];
   // (x, beta, qhat, 1/omega0) -> (sigma, omega0, Q);  x = omega0 dt, beta = 1/2Q, qhat = 2 sigma^2/Q
   const double Q = 0.5 / beta;
   gw += bx * dt - biw * iw * iw;
   gq += -bbeta * 2.0 * beta * beta - bqh * qh / Q;
   gs += bqh * 2.0 * qh / t.sigma;
 }
-
 
 // discretisation of all terms over one step (values only)
 template <int M>
@@ -461,23 +777,30 @@ GPD void discretise(const TermConst* tc, const double* coef, double dt, TermQ* t
   }
 }
 
-// with beta-derivatives
+// with the beta-derivatives of the base functions (db[t*6 + f])
 template <int M>
-GPD void discretise_dual(const TermConst* tc, const double* coef, double dt, Base<Dual>* bd, TermQ* tq) {
+GPD void discretise_dual(const TermConst* tc, const double* coef, double dt, double* db, TermQ* tq) {
 #pragma unroll
   for (int t = 0; t < M; ++t) {
     const double x = tc[t].w0 * dt;
-    if (use_series(x, tc[t].beta))
-      series_eval(coef + t * 2 * NCOEF, coef + t * 2 * NCOEF + NCOEF, x, bd[t]);
+    Base<Dual> bd;
+    if (use_series(x, tc[t]))
+      series_eval(coef + t * 2 * NCOEF, coef + t * 2 * NCOEF + NCOEF, x, bd);
     else
-      closed_eval<Dual>(x, Dual{tc[t].beta, 1.0}, bd[t]);
+      closed_eval(x, Dual{tc[t].beta, 1.0}, bd);
     Base<double> b;
-    b.g = bd[t].g.v;
-    b.gp = bd[t].gp.v;
-    b.G1 = bd[t].G1.v;
-    b.Igg = bd[t].Igg.v;
-    b.Ipp = bd[t].Ipp.v;
-    b.IGG = bd[t].IGG.v;
+    b.g = bd.g.v;
+    b.gp = bd.gp.v;
+    b.G1 = bd.G1.v;
+    b.Igg = bd.Igg.v;
+    b.Ipp = bd.Ipp.v;
+    b.IGG = bd.IGG.v;
+    db[t * 6 + 0] = bd.g.d;
+    db[t * 6 + 1] = bd.gp.d;
+    db[t * 6 + 2] = bd.G1.d;
+    db[t * 6 + 3] = bd.Igg.d;
+    db[t * 6 + 4] = bd.Ipp.d;
+    db[t * 6 + 5] = bd.IGG.d;
     tq[t] = term_step(tc[t], b);
   }
 }
@@ -485,29 +808,69 @@ GPD void discretise_dual(const TermConst* tc, const double* coef, double dt, Bas
 // Adjoint of one plain step (predict over dt, observe, close the slot).
 // m, P: the filtered state before the step.  mb, Pb: on entry the adjoint
 // with respect to the state after the step, on exit with respect to (m, P).
+// The predicted moments are not formed: the gain u = (A P A^T + Q) h is
+// computed as A (P (A^T h)) + Q h, and (A P) one column at a time.
 template <class Dm>
 GPD void adjoint_step(const double* m, const double* P, double* mb, double* Pb, const TermConst* tc, const double* coef,
                       double dt, uint32_t info, const Obs& o, double jit, GradAcc<Dm::M>& acc) {
-  constexpr int M = Dm::M, J = Dm::J, NX = Dm::NX, D = Dm::D, NP = Dm::NP;
+  constexpr int M = Dm::M, J = Dm::J, NX = Dm::NX, D = Dm::D;
   const uint32_t open = ev_open(info);
-  Base<Dual> bd[M];
+  double db[6 * M];
   TermQ tq[M];
-  discretise_dual<M>(tc, coef, dt, bd, tq);
-  // predicted moments
-  double mp[D], Pp[NP];
+  discretise_dual<M>(tc, coef, dt, db, tq);
+  double oj[J > 0 ? J : 1];
 #pragma unroll
-  for (int i = 0; i < D; ++i) mp[i] = m[i];
-#pragma unroll
-  for (int i = 0; i < NP; ++i) Pp[i] = P[i];
-  predict_mean<Dm>(mp, tq, open);
-  predict_cov<Dm>(Pp, tq, open);
-  double u[D];
-  obs_gain<Dm>(Pp, o, u);
-  const double S = obs_dot<Dm>(u, o) + o.R;
-  const double v = o.y - obs_dot<Dm>(mp, o);
+  for (int j = 0; j < J; ++j) oj[j] = ((open >> j) & 1u) ? 1.0 : 0.0;
+  // h, the sum of h over open integrators, and A^T h
   double h[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) h[i] = (i >= NX) ? o.a[i - NX] : ((i % 2 == 0) ? o.b : 0.0);
+  double hz = 0.0;
+#pragma unroll
+  for (int j = 0; j < J; ++j) hz = fma(oj[j], h[NX + j], hz);
+  double ht[D];
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    ht[2 * t] = fma(tq[t].a00, h[2 * t], fma(-tq[t].a01, h[2 * t + 1], tq[t].f0 * hz));
+    ht[2 * t + 1] = fma(tq[t].a01, h[2 * t], fma(tq[t].a11, h[2 * t + 1], tq[t].f1 * hz));
+  }
+#pragma unroll
+  for (int j = 0; j < J; ++j) ht[NX + j] = h[NX + j];
+  // y = P ht, u = A y + Q h
+  double u[D];
+  {
+    double y[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double acc2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) acc2 = fma(P[sidx(i, k, D)], ht[k], acc2);
+      y[i] = acc2;
+    }
+    double fy = 0.0, ch = 0.0, zz = 0.0;
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+      fy = fma(tq[t].f0, y[2 * t], fma(tq[t].f1, y[2 * t + 1], fy));
+      ch = fma(tq[t].c0, h[2 * t], fma(tq[t].c1, h[2 * t + 1], ch));
+      zz += tq[t].zz;
+    }
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+      u[2 * t] = fma(tq[t].a00, y[2 * t], tq[t].a01 * y[2 * t + 1]) + fma(tq[t].q00, h[2 * t], tq[t].q01 * h[2 * t + 1]) +
+                 tq[t].c0 * hz;
+      u[2 * t + 1] = fma(-tq[t].a01, y[2 * t], tq[t].a11 * y[2 * t + 1]) +
+                     fma(tq[t].q01, h[2 * t], tq[t].q11 * h[2 * t + 1]) + tq[t].c1 * hz;
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) u[NX + j] = y[NX + j] + oj[j] * (fy + ch + zz * hz);
+  }
+  double hm = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) hm = fma(ht[i], m[i], hm);
+  double S = o.R;
+#pragma unroll
+  for (int i = 0; i < D; ++i) S = fma(h[i], u[i], S);
+  const double v = o.y - hm;
 
   // closing the slot: the zeroed entries are constants
   close_slot<Dm>(mb, Pb, info);
@@ -540,84 +903,85 @@ GPD void adjoint_step(const double* m, const double* P, double* mb, double* Pb, 
     acc.jit = fma(2.0 * jit, Sbar, acc.jit);
   }
 
-  // predict: weights of the step quantities
+  // predict: weights of the step quantities.  Abar = mb- m^T + 2 Pb- (A P).
   double fb[NX];
 #pragma unroll
   for (int t = 0; t < M; ++t) {
     fb[2 * t] = tq[t].f0;
     fb[2 * t + 1] = tq[t].f1;
   }
-  double w[NX];  // Pxx fbar
+  double W[M][11];
+  double fw[M][2];
 #pragma unroll
-  for (int a = 0; a < NX; ++a) {
-    double s = 0.0;
+  for (int t = 0; t < M; ++t) fw[t][0] = fw[t][1] = 0.0;
 #pragma unroll
-    for (int c = 0; c < NX; ++c) s = fma(P[sidx(a, c, D)], fb[c], s);
-    w[a] = s;
-  }
-  // T[:, b] = (A P)[:, b] for the SHO columns b
-  double T[D * NX];
+  for (int bcol = 0; bcol < NX; ++bcol) {
+    // column bcol of A P
+    double T[D];
+    double wv = 0.0;  // (Pxx fbar)[bcol]
 #pragma unroll
-  for (int b = 0; b < NX; ++b) {
+    for (int c = 0; c < NX; ++c) wv = fma(P[sidx(bcol, c, D)], fb[c], wv);
 #pragma unroll
     for (int t = 0; t < M; ++t) {
-      const double p0 = P[sidx(2 * t, b, D)], p1 = P[sidx(2 * t + 1, b, D)];
-      T[(2 * t) * NX + b] = fma(tq[t].a00, p0, tq[t].a01 * p1);
-      T[(2 * t + 1) * NX + b] = fma(-tq[t].a01, p0, tq[t].a11 * p1);
+      const double p0 = P[sidx(2 * t, bcol, D)], p1 = P[sidx(2 * t + 1, bcol, D)];
+      T[2 * t] = fma(tq[t].a00, p0, tq[t].a01 * p1);
+      T[2 * t + 1] = fma(-tq[t].a01, p0, tq[t].a11 * p1);
     }
 #pragma unroll
-    for (int j = 0; j < J; ++j) T[(NX + j) * NX + b] = P[sidx(NX + j, b, D)] + (((open >> j) & 1u) ? w[b] : 0.0);
-  }
-  // G = Pbar- T at the needed entries
-  auto G = [&](int a, int b) {
-    double s = 0.0;
+    for (int j = 0; j < J; ++j) T[NX + j] = fma(oj[j], wv, P[sidx(NX + j, bcol, D)]);
+    const int tb = bcol / 2, cb = bcol % 2;
+    // rows of the same term's transition block
 #pragma unroll
-    for (int k = 0; k < D; ++k) s = fma(Pb[sidx(a, k, D)], T[k * NX + b], s);
-    return s;
-  };
+    for (int r = 0; r < 2; ++r) {
+      double g2 = 0.0;
 #pragma unroll
-  for (int t = 0; t < M; ++t) {
-    double W[11];
-    double Ab[2][2];
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) Ab[r][c] = fma(mb[2 * t + r], m[2 * t + c], 2.0 * G(2 * t + r, 2 * t + c));
-    W[0] = Ab[0][0];
-    W[1] = Ab[0][1] - Ab[1][0];
-    W[2] = Ab[1][1];
-    double f0 = 0.0, f1 = 0.0, c0 = 0.0, c1 = 0.0;
+      for (int k = 0; k < D; ++k) g2 = fma(Pb[sidx(2 * tb + r, k, D)], T[k], g2);
+      W[tb][r * 2 + cb] = fma(mb[2 * tb + r], m[bcol], 2.0 * g2);  // Abar[r][cb], fixed up below
+    }
+    // integrator rows (integrated transition row)
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      if ((open >> j) & 1u) {
-        f0 += fma(mb[NX + j], m[2 * t], 2.0 * G(NX + j, 2 * t));
-        f1 += fma(mb[NX + j], m[2 * t + 1], 2.0 * G(NX + j, 2 * t + 1));
-        c0 += 2.0 * Pb[sidx(2 * t, NX + j, D)];
-        c1 += 2.0 * Pb[sidx(2 * t + 1, NX + j, D)];
-      }
+      double g2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) g2 = fma(Pb[sidx(NX + j, k, D)], T[k], g2);
+      fw[tb][cb] += oj[j] * fma(mb[NX + j], m[bcol], 2.0 * g2);
     }
-    W[3] = f0;
-    W[4] = f1;
-    W[5] = Pb[sidx(2 * t, 2 * t, D)];
-    W[6] = 2.0 * Pb[sidx(2 * t, 2 * t + 1, D)];
-    W[7] = Pb[sidx(2 * t + 1, 2 * t + 1, D)];
-    W[8] = c0;
-    W[9] = c1;
+  }
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    // W[t][0..3] hold Abar00, Abar01, Abar10, Abar11
+    const double a00 = W[t][0], a01 = W[t][1], a10 = W[t][2], a11 = W[t][3];
+    double w[11];
+    w[0] = a00;
+    w[1] = a01 - a10;
+    w[2] = a11;
+    w[3] = fw[t][0];
+    w[4] = fw[t][1];
+    w[5] = Pb[sidx(2 * t, 2 * t, D)];
+    w[6] = 2.0 * Pb[sidx(2 * t, 2 * t + 1, D)];
+    w[7] = Pb[sidx(2 * t + 1, 2 * t + 1, D)];
+    double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      c0 = fma(oj[j], 2.0 * Pb[sidx(2 * t, NX + j, D)], c0);
+      c1 = fma(oj[j], 2.0 * Pb[sidx(2 * t + 1, NX + j, D)], c1);
+    }
+    w[8] = c0;
+    w[9] = c1;
     double zz = 0.0;
 #pragma unroll
     for (int i = 0; i < J; ++i)
 #pragma unroll
-      for (int j = 0; j < J; ++j)
-        if (((open >> i) & 1u) && ((open >> j) & 1u)) zz += Pb[sidx(NX + i, NX + j, D)];
-    W[10] = zz;
-    term_backprop(tc[t], bd[t], dt, W, acc.s[t], acc.w[t], acc.q[t]);
+      for (int j = 0; j < J; ++j) zz = fma(oj[i] * oj[j], Pb[sidx(NX + i, NX + j, D)], zz);
+    w[10] = zz;
+    term_backprop(tc[t], tq[t], db + 6 * t, dt, w, acc.s[t], acc.w[t], acc.q[t]);
   }
 
   // adjoint to the state before the predict
   {
     double zsum = 0.0;
 #pragma unroll
-    for (int j = 0; j < J; ++j) zsum += ((open >> j) & 1u) ? mb[NX + j] : 0.0;
+    for (int j = 0; j < J; ++j) zsum = fma(oj[j], mb[NX + j], zsum);
 #pragma unroll
     for (int t = 0; t < M; ++t) {
       const double b0 = mb[2 * t], b1 = mb[2 * t + 1];
@@ -631,7 +995,7 @@ GPD void adjoint_step(const double* m, const double* P, double* mb, double* Pb, 
     for (int a = 0; a < NX; ++a) {
       double s = 0.0;
 #pragma unroll
-      for (int j = 0; j < J; ++j) s += ((open >> j) & 1u) ? Pb[sidx(a, NX + j, D)] : 0.0;
+      for (int j = 0; j < J; ++j) s = fma(oj[j], Pb[sidx(a, NX + j, D)], s);
       p[a] = s;
     }
     double sz = 0.0, cz[J > 0 ? J : 1];
@@ -639,9 +1003,9 @@ GPD void adjoint_step(const double* m, const double* P, double* mb, double* Pb, 
     for (int j = 0; j < J; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < J; ++i) s += ((open >> i) & 1u) ? Pb[sidx(NX + i, NX + j, D)] : 0.0;
+      for (int i = 0; i < J; ++i) s = fma(oj[i], Pb[sidx(NX + i, NX + j, D)], s);
       cz[j] = s;
-      sz += ((open >> j) & 1u) ? s : 0.0;
+      sz = fma(oj[j], s, sz);
     }
     // SHO/integrator block: Phi^T Pbar[x, z_j] + fbar^T cz_j
 #pragma unroll
@@ -667,18 +1031,16 @@ GPD void adjoint_step(const double* m, const double* P, double* mb, double* Pb, 
       for (int uu = t; uu < M; ++uu) {
         const double b00 = Pb[sidx(2 * t, 2 * uu, D)], b01 = Pb[sidx(2 * t, 2 * uu + 1, D)];
         const double b10 = Pb[sidx(2 * t + 1, 2 * uu, D)], b11 = Pb[sidx(2 * t + 1, 2 * uu + 1, D)];
-        // Y = Phi_t^T B, Phi_t^T = [[a00, -a01], [a01, a11]]
         const double y00 = fma(tq[t].a00, b00, -tq[t].a01 * b10);
         const double y01 = fma(tq[t].a00, b01, -tq[t].a01 * b11);
         const double y10 = fma(tq[t].a01, b00, tq[t].a11 * b10);
         const double y11 = fma(tq[t].a01, b01, tq[t].a11 * b11);
-        // Z = Y Phi_u, Phi_u = [[a00, a01], [-a01, a11]]
         const double z00 = fma(y00, tq[uu].a00, -y01 * tq[uu].a01);
         const double z01 = fma(y00, tq[uu].a01, y01 * tq[uu].a11);
         const double z10 = fma(y10, tq[uu].a00, -y11 * tq[uu].a01);
         const double z11 = fma(y10, tq[uu].a01, y11 * tq[uu].a11);
         const int a0 = 2 * t, a1 = 2 * t + 1, c0i = 2 * uu, c1i = 2 * uu + 1;
-        auto extra = [&](int a, int c) { return q[a] * fb[c] + fb[a] * q[c] + sz * fb[a] * fb[c]; };
+        auto extra = [&](int a, int c) { return fma(q[a], fb[c], fma(fb[a], q[c], sz * fb[a] * fb[c])); };
         Pb[sidx(a0, c0i, D)] = z00 + extra(a0, c0i);
         Pb[sidx(a0, c1i, D)] = z01 + extra(a0, c1i);
         Pb[sidx(a1, c1i, D)] = z11 + extra(a1, c1i);

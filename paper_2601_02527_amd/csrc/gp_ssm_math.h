@@ -209,16 +209,17 @@ GPD void series_eval(const double* __restrict__ coef, const double* __restrict__
 }
 
 // e^{-beta x} cos(eta x) and e^{-beta x} sin(eta x)/eta for eta^2 = 1 - beta^2
-// of either sign (hyperbolic when negative), finite through eta = 0.
-template <class T>
-GPD void damped_cs(double x, T beta, T& eC, T& eS) {
-  const T eta2 = 1.0 - beta * beta;
-  const T w = eta2 * (x * x);
-  const double wv = val(w);
+// of either sign (hyperbolic when negative), finite through eta = 0, with the
+// beta-derivative.  Near eta = 0 (|eta x| <= 1) the functions are taken as
+// series in w = eta^2 x^2 so that their derivatives with respect to eta^2
+// stay accurate.
+GPD void damped_cs(double x, Dual beta, Dual& eC, Dual& eS) {
+  const Dual eta2 = 1.0 - beta * beta;
+  const Dual w = eta2 * (x * x);
+  const double wv = w.v;
   if (wv >= -1.0 && wv <= 1.0) {
-    // cos(sqrt w) and sin(sqrt w)/sqrt w as series in w (|w| <= 1)
-    T c = fconst<T>(1.0), s = fconst<T>(1.0);
-    T tc = fconst<T>(1.0), ts = fconst<T>(1.0);
+    Dual c = fconst<Dual>(1.0), s = fconst<Dual>(1.0);
+    Dual tc = fconst<Dual>(1.0), ts = fconst<Dual>(1.0);
 #pragma unroll
     for (int n = 0; n < 11; ++n) {
       tc = tc * w * (-1.0 / ((2 * n + 1) * (2 * n + 2)));
@@ -226,37 +227,37 @@ GPD void damped_cs(double x, T beta, T& eC, T& eS) {
       c = c + tc;
       s = s + ts;
     }
-    const T e = fexp(-(beta * x));
+    const Dual e = fexp(-(beta * x));
     eC = e * c;
     eS = e * s * x;
   } else if (wv > 1.0) {
-    const T eta = fsqrt(eta2);
-    T sn, cs;
+    const Dual eta = fsqrt(eta2);
+    Dual sn, cs;
     fsincos(eta * x, &sn, &cs);
-    const T e = fexp(-(beta * x));
+    const Dual e = fexp(-(beta * x));
     eC = e * cs;
     eS = e * sn / eta;
   } else {
-    const T k = fsqrt(-eta2);
-    const T r = k * x;
-    const T bx = beta * x;
-    const T ep = fexp(r - bx);
-    const T em = fexp(-(r + bx));
+    const Dual k = fsqrt(-eta2);
+    const Dual r = k * x;
+    const Dual bx = beta * x;
+    const Dual ep = fexp(r - bx);
+    const Dual em = fexp(-(r + bx));
     eC = 0.5 * (ep + em);
     eS = (ep - em) / (2.0 * k);
   }
 }
 
-template <class T>
-GPD void closed_eval(double x, T beta, Base<T>& o) {
-  T eC, eS;
-  damped_cs<T>(x, beta, eC, eS);
-  const T g = eS;
-  const T gp = eC - beta * eS;
-  const T G1 = 1.0 - gp - 2.0 * beta * g;
-  const T Ipp = (1.0 - gp * gp - g * g) / (4.0 * beta);
-  const T Igg = Ipp - g * gp - beta * g * g;
-  const T IGG = (x - g) - 2.0 * beta * G1 - G1 * g + Igg - beta * G1 * G1;
+// closed forms with the beta-derivative
+GPD void closed_eval(double x, Dual beta, Base<Dual>& o) {
+  Dual eC, eS;
+  damped_cs(x, beta, eC, eS);
+  const Dual g = eS;
+  const Dual gp = eC - beta * eS;
+  const Dual G1 = 1.0 - gp - 2.0 * beta * g;
+  const Dual Ipp = (1.0 - gp * gp - g * g) / (4.0 * beta);
+  const Dual Igg = Ipp - g * gp - beta * g * g;
+  const Dual IGG = (x - g) - 2.0 * beta * G1 - G1 * g + Igg - beta * G1 * G1;
   o.g = g;
   o.gp = gp;
   o.G1 = G1;
@@ -270,6 +271,11 @@ GPD void closed_eval(double x, T beta, Base<T>& o) {
 // ---------------------------------------------------------------------------
 struct TermConst {
   double w0, beta, qhat, inv_w0, sigma;
+  double eta2;     // 1 - beta^2 (its sign selects the damping regime)
+  double eta;      // sqrt(|eta2|)
+  double inv_eta;  // 1/sqrt(|eta2|), 0 at critical damping
+  double inv_4b;   // 1/(4 beta)
+  double xser;     // the series is used for omega0 dt <= xser
 };
 
 GPD TermConst make_term(double sigma, double w0, double quality) {
@@ -279,7 +285,54 @@ GPD TermConst make_term(double sigma, double w0, double quality) {
   t.qhat = 2.0 * sigma * sigma / quality;
   t.inv_w0 = 1.0 / w0;
   t.sigma = sigma;
+  t.eta2 = 1.0 - t.beta * t.beta;
+  t.eta = sqrt(fabs(t.eta2));
+  t.inv_eta = (t.eta2 != 0.0) ? 1.0 / t.eta : 0.0;
+  t.inv_4b = 0.25 / t.beta;
+  t.xser = XSER / fmax(1.0, t.beta);
   return t;
+}
+
+// value-only closed forms.  The damping regime is a property of the term, so
+// this branch is uniform over a wavefront that shares hyperparameters.
+GPD void closed_eval(double x, const TermConst& t, Base<double>& o) {
+  const double beta = t.beta;
+  double eC, eS;
+  if (t.eta2 > 0.0) {
+    double sn, cs;
+    fsincos(t.eta * x, &sn, &cs);
+    const double e = exp(-beta * x);
+    eC = e * cs;
+    eS = e * sn * t.inv_eta;
+  } else if (t.eta2 < 0.0) {
+    const double r = t.eta * x, bx = beta * x;
+    if (r > 0.5) {
+      const double ep = exp(r - bx), em = exp(-r - bx);
+      eC = 0.5 * (ep + em);
+      eS = 0.5 * (ep - em) * t.inv_eta;
+    } else {  // sinh without cancellation near critical damping
+      const double e = exp(-bx);
+      const double a = expm1(r), b = expm1(-r);
+      eC = e * (1.0 + 0.5 * (a + b));
+      eS = e * 0.5 * (a - b) * t.inv_eta;
+    }
+  } else {
+    const double e = exp(-beta * x);
+    eC = e;
+    eS = e * x;
+  }
+  const double g = eS;
+  const double gp = fma(-beta, eS, eC);
+  const double G1 = (1.0 - gp) - 2.0 * beta * g;
+  const double Ipp = (1.0 - gp * gp - g * g) * t.inv_4b;
+  const double Igg = Ipp - g * gp - beta * g * g;
+  const double IGG = (x - g) - 2.0 * beta * G1 - G1 * g + Igg - beta * G1 * G1;
+  o.g = g;
+  o.gp = gp;
+  o.G1 = G1;
+  o.Igg = Igg;
+  o.Ipp = Ipp;
+  o.IGG = IGG;
 }
 
 // one term over one step, scaled SHO coordinates, unscaled integrator
@@ -291,15 +344,15 @@ struct TermQ {
   double zz;             // integrator/integrator noise
 };
 
-GPD bool use_series(double x, double beta) { return x * fmax(1.0, beta) <= XSER; }
+GPD bool use_series(double x, const TermConst& t) { return x <= t.xser; }
 
 GPD Base<double> base_values(const TermConst& t, const double* coef, double dt) {
   const double x = t.w0 * dt;
   Base<double> b;
-  if (use_series(x, t.beta))
+  if (use_series(x, t))
     series_eval(coef, x, b);
   else
-    closed_eval<double>(x, t.beta, b);
+    closed_eval(x, t, b);
   return b;
 }
 

@@ -16,7 +16,7 @@ struct DevPlan {
   const int64_t* seg_ev0;
   const int32_t *chunk_len, *chunk_series, *chunk_seg;
   const uint8_t* chunk_first;
-  const int32_t *series_chunk0, *series_nch;
+  const int32_t *series_chunk0, *series_nch, *series_seg0, *series_nseg;
   int64_t n_series;
   int32_t n_chunks, n_seg;
 };
@@ -31,10 +31,10 @@ struct DevParams {
 
 // test-time work of the smoother, assigned to chunks on the host
 struct DevTests {
-  const double* t;           // test times, grouped by chunk, sorted within a chunk
-  const int64_t* out_index;  // where each result goes
-  const int64_t* chunk_t0;   // first test of each chunk (n_chunks + 1 entries)
-  const int32_t* before;     // per series: number of tests before the first event
+  const double* t;            // test times, grouped by chunk, sorted within a chunk
+  const int64_t* out_index;   // where each result goes
+  const int64_t* chunk_t0;    // first test of each chunk (n_chunks + 1 entries)
+  const double* chunk_tprev;  // time of the previous chunk's last event
 };
 
 struct Launch {

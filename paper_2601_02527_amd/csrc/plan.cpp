@@ -189,6 +189,8 @@ int build_plan(int64_t n_series, const int64_t* offsets, const double* t_start, 
   P.series_chunk0.resize(n_series);
   P.series_nch.resize(n_series);
   P.series_slots.resize(n_series);
+  P.series_seg0.resize(n_series);
+  P.series_nseg.resize(n_series);
   P.series_nev.resize(n_series);
   std::vector<int64_t> chunk_evstart;  // (series-local start of each chunk)
   for (int64_t b = 0; b < n_series; ++b) {
@@ -213,6 +215,7 @@ int build_plan(int64_t n_series, const int64_t* offsets, const double* t_start, 
       ++P.n_chunks;
     }
     P.series_nch[b] = P.n_chunks - c_first;
+    P.series_seg0[b] = P.n_seg;
     // segments of up to WAVE chunks
     for (int32_t c = c_first; c < P.n_chunks; c += WAVE) {
       const int32_t nch = std::min<int32_t>(WAVE, P.n_chunks - c);
@@ -227,6 +230,7 @@ int build_plan(int64_t n_series, const int64_t* offsets, const double* t_start, 
       P.n_ev_pad += (int64_t)L * WAVE;
       ++P.n_seg;
     }
+    P.series_nseg[b] = P.n_seg - P.series_seg0[b];
   }
   // interleaved event arrays
   P.dt.assign(P.n_ev_pad, 0.0);

@@ -37,7 +37,7 @@ struct HostPlan {
   std::vector<int32_t> chunk_len, chunk_series, chunk_seg;
   std::vector<uint8_t> chunk_first;
   std::vector<double> chunk_t0, chunk_t1;  // time of the first / last event of each chunk
-  std::vector<int32_t> series_chunk0, series_nch, series_slots;
+  std::vector<int32_t> series_chunk0, series_nch, series_slots, series_seg0, series_nseg;
   std::vector<int64_t> series_nev;
 };
 

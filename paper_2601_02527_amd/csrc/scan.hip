@@ -1,0 +1,333 @@
+// Time-parallel combination of chunk summaries (the associative scan of the
+// parallel Kalman filter, Sec. 3.2.4 following SG21, over chunk summaries
+// instead of single events):
+//
+//  k_seg_scan   one wavefront per segment (<= 64 chunks of one series):
+//               Kogge-Stone inclusive prefix and suffix compositions of the
+//               chunk summaries across the lanes, and the segment total.
+//  k_series_scan one wavefront per series: the filtered state at the start
+//               of every segment (prefix over segment totals applied to the
+//               prior) and the future information (eta~, J~) after every
+//               segment (suffix over segment totals).
+//  k_seg_fix    one wavefront per segment: the filtered state at every chunk
+//               boundary, each chunk's log-likelihood contribution, and, for
+//               the gradient and the smoother, the future information at each
+//               chunk's end, from which the adjoint and the smoothed moments
+//               of the boundary state follow.
+//  k_series_finish  sums the per-segment log-likelihoods of each series.
+#include <hip/hip_runtime.h>
+
+#include "../../include/gp_ssm.h"
+#include "kernels.h"
+#include "plan.h"
+#include "scan.h"
+
+namespace gpssm {
+
+namespace {
+
+template <int N>
+__device__ __forceinline__ void prior_state(const DevParams& pr, int64_t b, double* m, double* P) {
+  constexpr int M = N / 2;
+#pragma unroll
+  for (int i = 0; i < N; ++i) m[i] = 0.0;
+#pragma unroll
+  for (int i = 0; i < N * (N + 1) / 2; ++i) P[i] = 0.0;
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    const double s2 = pr.tc[b * M + t].sigma * pr.tc[b * M + t].sigma;
+    P[sidx(2 * t, 2 * t, N)] = s2;
+    P[sidx(2 * t + 1, 2 * t + 1, N)] = s2;
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void lds_put(double* lds, int lane, const Elem<N>& e) {
+  e.store([&](int f, double v) { lds[f * WAVE + lane] = v; });
+}
+template <int N>
+__device__ __forceinline__ void lds_get(const double* lds, int lane, Elem<N>& e) {
+  e.load([&](int f) { return lds[f * WAVE + lane]; });
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+template <int N>
+__global__ __launch_bounds__(WAVE) void k_seg_scan(DevPlan p, const double* __restrict__ summ, double* __restrict__ pre,
+                                                   double* __restrict__ suf, double* __restrict__ segtot) {
+  constexpr int EF = elem_fields(N);
+  __shared__ double lds[EF * WAVE];
+  const int s = blockIdx.x, lane = threadIdx.x;
+  const int32_t nch = p.seg_nch[s];
+  const int64_t C = p.n_chunks, S = p.n_seg;
+  const int64_t c = p.seg_chunk0[s] + lane;
+  const bool valid = lane < nch;
+  bool ok = true;
+  Elem<N> own, part, tmp;
+  // inclusive prefix
+  if (valid)
+    own.load([&](int f) { return summ[(int64_t)f * C + c]; });
+  else
+    own.identity();
+#pragma unroll 1
+  for (int d = 1; d < WAVE; d <<= 1) {
+    lds_put<N>(lds, lane, own);
+    __syncthreads();
+    if (lane >= d) {
+      lds_get<N>(lds, lane - d, part);
+      compose<N>(part, own, tmp, ok);
+      own = tmp;
+    }
+    __syncthreads();
+  }
+  if (valid) own.store([&](int f, double v) { pre[(int64_t)f * C + c] = v; });
+  if (lane == nch - 1) own.store([&](int f, double v) { segtot[(int64_t)f * S + s] = v; });
+  // inclusive suffix
+  if (valid)
+    own.load([&](int f) { return summ[(int64_t)f * C + c]; });
+  else
+    own.identity();
+#pragma unroll 1
+  for (int d = 1; d < WAVE; d <<= 1) {
+    lds_put<N>(lds, lane, own);
+    __syncthreads();
+    if (lane + d < WAVE) {
+      lds_get<N>(lds, lane + d, part);
+      compose<N>(own, part, tmp, ok);
+      own = tmp;
+    }
+    __syncthreads();
+  }
+  if (valid) own.store([&](int f, double v) { suf[(int64_t)f * C + c] = v; });
+}
+
+template <int N>
+__global__ __launch_bounds__(WAVE) void k_series_scan(DevPlan p, DevParams pr, const double* __restrict__ segtot,
+                                                      double* __restrict__ segstate, double* __restrict__ segfut,
+                                                      int want_back) {
+  constexpr int EF = elem_fields(N);
+  constexpr int NP = N * (N + 1) / 2;
+  __shared__ double lds[EF * WAVE];
+  const int64_t b = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t S = p.n_seg;
+  const int32_t s0 = p.series_seg0[b], ns = p.series_nseg[b];
+  if (ns == 0) return;
+  const int32_t q = (ns + WAVE - 1) / WAVE;
+  const int32_t lo = min(ns, lane * q), hi = min(ns, lo + q);
+  bool ok = true;
+  auto tot = [&](int32_t k) { return [=](int f) { return segtot[(int64_t)f * S + s0 + k]; }; };
+  // block total of this lane
+  Elem<N> blk, part, tmp;
+  blk.identity();
+  for (int32_t k = lo; k < hi; ++k) {
+    Elem<N> e;
+    e.load(tot(k));
+    compose<N>(blk, e, tmp, ok);
+    blk = tmp;
+  }
+  // exclusive prefix over lanes
+  Elem<N> own = blk;
+#pragma unroll 1
+  for (int d = 1; d < WAVE; d <<= 1) {
+    lds_put<N>(lds, lane, own);
+    __syncthreads();
+    if (lane >= d) {
+      lds_get<N>(lds, lane - d, part);
+      compose<N>(part, own, tmp, ok);
+      own = tmp;
+    }
+    __syncthreads();
+  }
+  lds_put<N>(lds, lane, own);
+  __syncthreads();
+  double m[N], P[NP], mn[N], Pn[NP];
+  prior_state<N>(pr, b, m, P);
+  if (lane > 0) {
+    lds_get<N>(lds, lane - 1, part);
+    combine_forward<N>(m, P, [&](int f) { return part.get(f); }, mn, Pn, ok);
+#pragma unroll
+    for (int i = 0; i < N; ++i) m[i] = mn[i];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) P[i] = Pn[i];
+  }
+  __syncthreads();
+  for (int32_t k = lo; k < hi; ++k) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) segstate[(int64_t)i * S + s0 + k] = m[i];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) segstate[(int64_t)(N + i) * S + s0 + k] = P[i];
+    combine_forward<N>(m, P, tot(k), mn, Pn, ok);
+#pragma unroll
+    for (int i = 0; i < N; ++i) m[i] = mn[i];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) P[i] = Pn[i];
+  }
+  if (!want_back) return;
+  // inclusive suffix over lanes; the future after this lane's block is the
+  // information of the next lane's suffix
+  own = blk;
+#pragma unroll 1
+  for (int d = 1; d < WAVE; d <<= 1) {
+    lds_put<N>(lds, lane, own);
+    __syncthreads();
+    if (lane + d < WAVE) {
+      lds_get<N>(lds, lane + d, part);
+      compose<N>(own, part, tmp, ok);
+      own = tmp;
+    }
+    __syncthreads();
+  }
+  lds_put<N>(lds, lane, own);
+  __syncthreads();
+  double Jf[NP], ef[N];
+  if (lane + 1 < WAVE) {
+    lds_get<N>(lds, lane + 1, part);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) Jf[i] = part.J[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) ef[i] = part.eta[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) Jf[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) ef[i] = 0.0;
+  }
+  for (int32_t k = hi - 1; k >= lo; --k) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) segfut[(int64_t)i * S + s0 + k] = Jf[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) segfut[(int64_t)(NP + i) * S + s0 + k] = ef[i];
+    double Jn[NP], en[N];
+    future_step<N>(tot(k), Jf, ef, Jn, en, ok);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) Jf[i] = Jn[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) ef[i] = en[i];
+  }
+  (void)ok;
+}
+
+template <int N>
+__global__ __launch_bounds__(WAVE) void k_seg_fix(DevPlan p, const double* __restrict__ summ,
+                                                  const double* __restrict__ pre, const double* __restrict__ suf,
+                                                  const double* __restrict__ segstate, const double* __restrict__ segfut,
+                                                  double* __restrict__ bstate, double* __restrict__ badj,
+                                                  double* __restrict__ bsmooth, double* __restrict__ segll,
+                                                  int32_t* __restrict__ segok, int want_back) {
+  constexpr int NP = N * (N + 1) / 2;
+  const int s = blockIdx.x, lane = threadIdx.x;
+  const int32_t nch = p.seg_nch[s];
+  const int64_t C = p.n_chunks, S = p.n_seg;
+  const int64_t c = p.seg_chunk0[s] + lane;
+  const bool valid = lane < nch;
+  bool ok = true;
+  double ll = 0.0;
+  if (valid) {
+    double m[N], P[NP], mn[N], Pn[NP];
+#pragma unroll
+    for (int i = 0; i < N; ++i) m[i] = segstate[(int64_t)i * S + s];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) P[i] = segstate[(int64_t)(N + i) * S + s];
+    if (lane > 0) {
+      combine_forward<N>(m, P, [&](int f) { return f == sum_c0(N) ? 0.0 : pre[(int64_t)f * C + c - 1]; }, mn, Pn, ok);
+#pragma unroll
+      for (int i = 0; i < N; ++i) m[i] = mn[i];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) P[i] = Pn[i];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) bstate[(int64_t)i * C + c] = m[i];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) bstate[(int64_t)(N + i) * C + c] = P[i];
+    ll = combine_forward<N>(m, P, [&](int f) { return summ[(int64_t)f * C + c]; }, mn, Pn, ok);
+    if (want_back) {
+      double Jf[NP], ef[N];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) Jf[i] = segfut[(int64_t)i * S + s];
+#pragma unroll
+      for (int i = 0; i < N; ++i) ef[i] = segfut[(int64_t)(NP + i) * S + s];
+      if (lane + 1 < nch) {
+        double Jn[NP], en[N];
+        future_step<N>([&](int f) { return suf[(int64_t)f * C + c + 1]; }, Jf, ef, Jn, en, ok);
+#pragma unroll
+        for (int i = 0; i < NP; ++i) Jf[i] = Jn[i];
+#pragma unroll
+        for (int i = 0; i < N; ++i) ef[i] = en[i];
+      }
+      double mb[N], Pb[NP], mh[N], Ph[NP];
+      boundary_adjoint<N>(mn, Pn, Jf, ef, mb, Pb, bsmooth ? mh : nullptr, Ph, ok);
+#pragma unroll
+      for (int i = 0; i < N; ++i) badj[(int64_t)i * C + c] = mb[i];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) badj[(int64_t)(N + i) * C + c] = Pb[i];
+      if (bsmooth) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) bsmooth[(int64_t)i * C + c] = mh[i];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) bsmooth[(int64_t)(N + i) * C + c] = Ph[i];
+      }
+    }
+  }
+  const double tot = wave_sum(ll);
+  const int bad = __any((!ok || !isfinite(ll)) && valid);
+  if (lane == 0) {
+    segll[s] = tot;
+    segok[s] = bad ? 0 : 1;
+  }
+}
+
+__global__ void k_series_finish(DevPlan p, const double* __restrict__ segll, const int32_t* __restrict__ segok,
+                                double* __restrict__ loglik, int32_t* __restrict__ status) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= p.n_series) return;
+  const int32_t s0 = p.series_seg0[b], ns = p.series_nseg[b];
+  double ll = 0.0;
+  bool good = true;
+  for (int32_t k = 0; k < ns; ++k) {
+    ll += segll[s0 + k];
+    good = good && segok[s0 + k];
+  }
+  good = good && isfinite(ll);
+  if (loglik) loglik[b] = good ? ll : __builtin_nan("");
+  if (status) status[b] = good ? 0 : GP_SSM_ENUMERIC;
+}
+
+template <int N>
+void run_scan_n(hipStream_t st, const DevPlan& p, const DevParams& pr, const ScanWork& w, double* loglik,
+                int32_t* status, int back) {
+  if (p.n_seg == 0) return;
+  prof_begin("k_seg_scan", st);
+  hipLaunchKernelGGL(k_seg_scan<N>, dim3(p.n_seg), dim3(WAVE), 0, st, p, w.summ, w.pre, w.suf, w.segtot);
+  prof_end("k_seg_scan", st);
+  prof_begin("k_series_scan", st);
+  hipLaunchKernelGGL(k_series_scan<N>, dim3((unsigned)p.n_series), dim3(WAVE), 0, st, p, pr, w.segtot, w.segstate,
+                     w.segfut, back);
+  prof_end("k_series_scan", st);
+  prof_begin("k_seg_fix", st);
+  hipLaunchKernelGGL(k_seg_fix<N>, dim3(p.n_seg), dim3(WAVE), 0, st, p, w.summ, w.pre, w.suf, w.segstate, w.segfut,
+                     w.bstate, w.badj, w.bsmooth, w.segll, w.segok, back);
+  prof_end("k_seg_fix", st);
+  prof_begin("k_series_finish", st);
+  hipLaunchKernelGGL(k_series_finish, dim3((unsigned)((p.n_series + 63) / 64)), dim3(64), 0, st, p, w.segll, w.segok,
+                     loglik, status);
+  prof_end("k_series_finish", st);
+}
+
+}  // namespace
+
+void run_scan(int M, hipStream_t st, const DevPlan& p, const DevParams& pr, const ScanWork& w, double* loglik,
+              int32_t* status, int back) {
+  switch (M) {
+    case 1: run_scan_n<2>(st, p, pr, w, loglik, status, back); break;
+    case 2: run_scan_n<4>(st, p, pr, w, loglik, status, back); break;
+    case 3: run_scan_n<6>(st, p, pr, w, loglik, status, back); break;
+    default: run_scan_n<8>(st, p, pr, w, loglik, status, back); break;
+  }
+}
+
+}  // namespace gpssm

@@ -197,3 +197,24 @@ def test_autograd_function(lib):
     assert np.allclose(w.grad.cpu().numpy(), g[:, 2:4], rtol=1e-14, atol=0)
     assert np.allclose(q.grad.cpu().numpy(), g[:, 4:6], rtol=1e-14, atol=0)
     assert np.allclose(j.grad.cpu().numpy(), g[:, 6], rtol=1e-14, atol=0)
+
+
+def test_long_series_multi_level_scan(lib):
+    """One series split into thousands of chunks (more than 64 segments, so
+    the scan over segment totals runs several segments per lane), plus a
+    second short series: likelihood and gradient against the oracle."""
+    b = W.random_small_batch(77, B=2, n_lo=6000, n_hi=6000, M=2, J=2, T=600.0)
+    ref = _oracle_ll(b)
+    for opt in (dict(chunk_min=1, chunk_target=1), dict(chunk_min=2, chunk_target=3), dict()):
+        plan = _plan(lib, b, **opt)
+        st = plan.stats()
+        ll, g = plan.loglik_grad(b.sigma, b.omega0, b.quality, b.jitter)
+        ll = ll.cpu().numpy()
+        print(opt, st, _rel(ll, ref))
+        assert np.all(_rel(ll, ref) < LL_TOL)
+        if opt.get("chunk_target") == 1:
+            assert st["n_segments"] > 64
+            s = b.series(1)
+            gfd = kalman.loglik_grad_fd(s["ts"], s["te"], s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"],
+                                        s["jitter"])
+            assert _grad_err(g.cpu().numpy()[1], gfd) < GRAD_TOL

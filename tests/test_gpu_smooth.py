@@ -1,0 +1,82 @@
+"""GPU parity of the smoother: posterior of the exposure-averaged process at
+the data and of the latent process at test times, against the oracle's
+sequential RTS smoother with Algorithm 1 and against the dense posterior.
+
+Tolerance: absolute 1e-9 times the prior scale (sum of sigma^2 for
+variances, its square root for means)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import dense, kalman
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+def _run(lib, b, t_test, test_offsets, **opt):
+    plan = lib.Plan(b.offsets, b.t_start, b.t_end, b.y, b.yerr, **opt)
+    out = plan.smooth(b.sigma, b.omega0, b.quality, b.jitter, test_offsets, t_test)
+    return {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}, plan
+
+
+def _check(b, out, t_test, test_offsets, use_dense=False):
+    for i in range(b.n_series):
+        s = b.series(i)
+        tt = t_test[test_offsets[i]:test_offsets[i + 1]]
+        args = (s["ts"], s["te"], s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"], s["jitter"])
+        L, mt, vt, md, vd = kalman.smooth(*args, t_test=tt)
+        k0 = float(np.sum(np.asarray(s["sigma"]) ** 2))
+        a, e = int(b.offsets[i]), int(b.offsets[i + 1])
+        gm = out["mean_data"][a:e]
+        gv = out["var_data"][a:e]
+        tm = out["mean_test"][test_offsets[i]:test_offsets[i + 1]]
+        tv = out["var_test"][test_offsets[i]:test_offsets[i + 1]]
+        errs = (np.max(np.abs(gm - md), initial=0) / np.sqrt(k0), np.max(np.abs(gv - vd), initial=0) / k0,
+                np.max(np.abs(tm - mt), initial=0) / np.sqrt(k0), np.max(np.abs(tv - vt), initial=0) / k0)
+        print(i, errs)
+        assert max(errs) < TOL, (i, errs)
+        assert abs(out["loglik"][i] - L) < 1e-9 * abs(L)
+        if use_dense:
+            dmd, dvd, dmt, dvt = dense.posterior(*args, t_test=tt)
+            assert np.max(np.abs(gm - dmd)) < 1e-9 * np.sqrt(k0)
+            assert np.max(np.abs(gv - dvd)) < 1e-9 * k0
+            assert np.max(np.abs(tm - dmt)) < 1e-9 * np.sqrt(k0)
+            assert np.max(np.abs(tv - dvt)) < 1e-9 * k0
+
+
+@pytest.mark.parametrize("make", [W.small_single, W.small_multi])
+def test_validation_scenarios(lib, make):
+    b = make()
+    b.jitter[:] = 0.01
+    for opt in (dict(), dict(chunk_min=2, chunk_target=3)):
+        out, plan = _run(lib, b, b.t_test, b.test_offsets, **opt)
+        _check(b, out, b.t_test, b.test_offsets, use_dense=True)
+
+
+@pytest.mark.parametrize("opt", [dict(), dict(chunk_min=1, chunk_target=1), dict(chunk_min=5, chunk_target=7),
+                                 dict(single_chunk=1)])
+def test_random_batches(lib, opt):
+    b = W.random_small_batch(41, B=7, n_lo=2, n_hi=50, M=2, J=3)
+    rng = np.random.default_rng(3)
+    parts = []
+    for i in range(b.n_series):
+        s = b.series(i)
+        lo, hi = s["ts"].min(), s["te"].max()
+        t = np.concatenate([rng.uniform(lo - 0.3, hi + 0.3, 23), s["ts"][:3], s["te"][-2:], [lo - 5.0, hi + 5.0]])
+        parts.append(t)
+    to = np.concatenate([[0], np.cumsum([len(p) for p in parts])]).astype(np.int64)
+    tt = np.concatenate(parts)
+    out, plan = _run(lib, b, tt, to, **opt)
+    _check(b, out, tt, to)
+
+
+def test_parameter_regimes(lib):
+    b = W.random_small_batch(43, B=4, n_lo=20, n_hi=40, M=2, J=2)
+    b.quality[:] = np.array([[0.3, 0.5], [0.5 + 1e-9, 2.0], [0.45, 50.0], [30.0, 0.7]])
+    to = np.arange(b.n_series + 1, dtype=np.int64) * 15
+    tt = np.concatenate([np.linspace(b.series(i)["ts"].min() - 0.1, b.series(i)["te"].max() + 0.1, 15)
+                         for i in range(b.n_series)])
+    out, plan = _run(lib, b, tt, to, chunk_min=3, chunk_target=5)
+    _check(b, out, tt, to)
