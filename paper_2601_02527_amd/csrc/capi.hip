@@ -95,13 +95,13 @@ __global__ void k_reduce_grad(DevPlan p, int M, const double* __restrict__ gpart
                               double* __restrict__ grad) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= p.n_series) return;
-  const int64_t C = p.n_chunks;
-  const int32_t c0 = p.series_chunk0[b], n = p.series_nch[b];
+  const int64_t S = p.n_seg;
+  const int32_t s0 = p.series_seg0[b], n = p.series_nseg[b];
   const int G = 3 * M + 1;
   const bool good = status == nullptr || status[b] == 0;
   for (int f = 0; f < G; ++f) {
     double s = 0.0;
-    for (int32_t q = 0; q < n; ++q) s += gpart[(int64_t)f * C + c0 + q];
+    for (int32_t q = 0; q < n; ++q) s += gpart[(int64_t)f * S + s0 + q];
     grad[b * G + f] = (good && isfinite(s)) ? s : __builtin_nan("");
   }
 }
@@ -441,7 +441,7 @@ int gp_ssm_plan_loglik_grad(gp_ssm_plan* pl, int32_t M, const double* sigma, con
   const int F = D + D * (D + 1) / 2;
   const int64_t C = pl->host.n_chunks;
   if (int rc = pl->rec.ensure(sizeof(double) * F * std::max<int64_t>(1, pl->host.n_ev_pad))) return rc;
-  if (int rc = pl->gpart.ensure(sizeof(double) * (3 * M + 1) * C)) return rc;
+  if (int rc = pl->gpart.ensure(sizeof(double) * (3 * M + 1) * std::max<int64_t>(1, pl->host.n_seg))) return rc;
   const DevPlan p = pl->dev();
   const KernelSet ks = kernel_set(M, pl->host.max_slots);
   Launch L{s};

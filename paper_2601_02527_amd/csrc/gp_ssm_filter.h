@@ -787,7 +787,7 @@ GPD void discretise_dual(const TermConst* tc, const double* coef, double dt, dou
     if (use_series(x, tc[t]))
       series_eval(coef + t * 2 * NCOEF, coef + t * 2 * NCOEF + NCOEF, x, bd);
     else
-      closed_eval(x, Dual{tc[t].beta, 1.0}, bd);
+      closed_eval(x, tc[t], bd);
     Base<double> b;
     b.g = bd.g.v;
     b.gp = bd.gp.v;
@@ -1048,6 +1048,15 @@ GPD void adjoint_step(const double* m, const double* P, double* mb, double* Pb, 
       }
     }
   }
+}
+
+// sum over the 64 lanes of a wavefront (fixed order: identical on every lane)
+__device__ __forceinline__ double wave_sum(double v) {
+#ifdef __HIP_DEVICE_COMPILE__
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+#endif
+  return v;
 }
 
 }  // namespace gpssm

@@ -43,8 +43,8 @@
 
 namespace gpssm {
 
-constexpr int KSER = 26;          // Taylor terms kept (x^0 .. x^KSER)
-constexpr double XSER = 1.0;      // series used when x * max(1, beta) <= XSER
+constexpr int KSER = 23;          // Taylor terms kept (x^0 .. x^KSER)
+constexpr double XSER = 0.75;     // series used when x * max(1, beta) <= XSER
 constexpr int NFUN = 6;           // g, g', G1, int g^2, int g'^2, int G1^2
 constexpr int NCOEF = NFUN * (KSER + 1);
 constexpr double LOG_2PI = 1.8378770664093454835606594728112;
@@ -208,64 +208,6 @@ GPD void series_eval(const double* __restrict__ coef, const double* __restrict__
   o.IGG = {r[5], rd[5]};
 }
 
-// e^{-beta x} cos(eta x) and e^{-beta x} sin(eta x)/eta for eta^2 = 1 - beta^2
-// of either sign (hyperbolic when negative), finite through eta = 0, with the
-// beta-derivative.  Near eta = 0 (|eta x| <= 1) the functions are taken as
-// series in w = eta^2 x^2 so that their derivatives with respect to eta^2
-// stay accurate.
-GPD void damped_cs(double x, Dual beta, Dual& eC, Dual& eS) {
-  const Dual eta2 = 1.0 - beta * beta;
-  const Dual w = eta2 * (x * x);
-  const double wv = w.v;
-  if (wv >= -1.0 && wv <= 1.0) {
-    Dual c = fconst<Dual>(1.0), s = fconst<Dual>(1.0);
-    Dual tc = fconst<Dual>(1.0), ts = fconst<Dual>(1.0);
-#pragma unroll
-    for (int n = 0; n < 11; ++n) {
-      tc = tc * w * (-1.0 / ((2 * n + 1) * (2 * n + 2)));
-      ts = ts * w * (-1.0 / ((2 * n + 2) * (2 * n + 3)));
-      c = c + tc;
-      s = s + ts;
-    }
-    const Dual e = fexp(-(beta * x));
-    eC = e * c;
-    eS = e * s * x;
-  } else if (wv > 1.0) {
-    const Dual eta = fsqrt(eta2);
-    Dual sn, cs;
-    fsincos(eta * x, &sn, &cs);
-    const Dual e = fexp(-(beta * x));
-    eC = e * cs;
-    eS = e * sn / eta;
-  } else {
-    const Dual k = fsqrt(-eta2);
-    const Dual r = k * x;
-    const Dual bx = beta * x;
-    const Dual ep = fexp(r - bx);
-    const Dual em = fexp(-(r + bx));
-    eC = 0.5 * (ep + em);
-    eS = (ep - em) / (2.0 * k);
-  }
-}
-
-// closed forms with the beta-derivative
-GPD void closed_eval(double x, Dual beta, Base<Dual>& o) {
-  Dual eC, eS;
-  damped_cs(x, beta, eC, eS);
-  const Dual g = eS;
-  const Dual gp = eC - beta * eS;
-  const Dual G1 = 1.0 - gp - 2.0 * beta * g;
-  const Dual Ipp = (1.0 - gp * gp - g * g) / (4.0 * beta);
-  const Dual Igg = Ipp - g * gp - beta * g * g;
-  const Dual IGG = (x - g) - 2.0 * beta * G1 - G1 * g + Igg - beta * G1 * G1;
-  o.g = g;
-  o.gp = gp;
-  o.G1 = G1;
-  o.Igg = Igg;
-  o.Ipp = Ipp;
-  o.IGG = IGG;
-}
-
 // ---------------------------------------------------------------------------
 // per-term constants and per-step quantities
 // ---------------------------------------------------------------------------
@@ -291,6 +233,101 @@ GPD TermConst make_term(double sigma, double w0, double quality) {
   t.inv_4b = 0.25 / t.beta;
   t.xser = XSER / fmax(1.0, t.beta);
   return t;
+}
+
+// cos(u) - sin(u)/u and its hyperbolic counterpart cosh(u) - sinh(u)/u,
+// without cancellation for small u (series below 0.1)
+GPD double cos_minus_sinc(double u, double s, double c) {
+  if (fabs(u) < 0.1) {
+    const double u2 = u * u;
+    return u2 * (-1.0 / 3.0 + u2 * (1.0 / 30.0 + u2 * (-1.0 / 840.0 + u2 * (1.0 / 45360.0))));
+  }
+  return c - s / u;
+}
+GPD double cosh_minus_sinhc(double u, double sh, double ch) {
+  if (fabs(u) < 0.1) {
+    const double u2 = u * u;
+    return u2 * (1.0 / 3.0 + u2 * (1.0 / 30.0 + u2 * (1.0 / 840.0 + u2 * (1.0 / 45360.0))));
+  }
+  return ch - sh / u;
+}
+
+// e^{-beta x} cos(eta x) and e^{-beta x} sin(eta x)/eta (eta^2 = 1 - beta^2,
+// hyperbolic when negative, the limit at eta = 0) with their beta-derivatives.
+// The regime is a property of the term (uniform over a wavefront); the
+// eta-derivatives use d eta/d beta = -beta/eta and the cancellation-free
+// combinations above.
+GPD void damped_cs(double x, const TermConst& t, Dual& eC, Dual& eS) {
+  const double beta = t.beta;
+  const double e = exp(-beta * x);
+  const double de = -x * e;  // d e / d beta
+  double C, S, dC, dS;       // C(x; beta), S(x; beta) and their beta-derivatives
+  if (t.eta2 > 0.0) {
+    const double eta = t.eta, u = eta * x;
+    double sn, cs;
+    fsincos(u, &sn, &cs);
+    C = cs;
+    S = sn * t.inv_eta;
+    // dC/d(eta^2) = -x S / 2 ; dS/d(eta^2) = x^2 (cos u - sin u/u) / (2 u^2) * ... written as below
+    const double dC_deta2 = -0.5 * x * S;
+    const double dS_deta2 = 0.5 * x * x * x * cos_minus_sinc(u, sn, cs) / (u * u + (u == 0.0));
+    dC = -2.0 * beta * dC_deta2;
+    dS = -2.0 * beta * dS_deta2;
+  } else if (t.eta2 < 0.0) {
+    const double k = t.eta, u = k * x;
+    double sh, ch;
+    if (u > 0.5) {
+      // e^{-beta x} cosh/sinh through exponentials (no overflow), then divide e back out below
+      const double ep = exp(u - beta * x), em = exp(-u - beta * x);
+      const double eCv = 0.5 * (ep + em), eSv = 0.5 * (ep - em) * t.inv_eta;
+      // derivatives: d/dbeta of e^{-bx} cosh(kx) with k^2 = beta^2 - 1, dk/dbeta = beta/k
+      const double dk = beta * t.inv_eta;
+      const double deC = -x * eCv + x * dk * (eSv * k);
+      // S = sinh(u)/k:  dS/dk = (x cosh u - sinh(u)/k)/k
+      const double dSdk = (x * (eCv) - eSv) * t.inv_eta;  // times e already included
+      const double deS = -x * eSv + dk * dSdk;
+      eC = Dual{eCv, deC};
+      eS = Dual{eSv, deS};
+      return;
+    }
+    const double a = expm1(u), bm = expm1(-u);
+    sh = 0.5 * (a - bm);
+    ch = 1.0 + 0.5 * (a + bm);
+    C = ch;
+    S = sh * t.inv_eta;
+    // with kappa = k^2 = beta^2 - 1: dC/dkappa = x S/2, dS/dkappa = x^3 (cosh u - sinh u/u)/(2 u^2)
+    const double dC_dk2 = 0.5 * x * S;
+    const double dS_dk2 = 0.5 * x * x * x * cosh_minus_sinhc(u, sh, ch) / (u * u);
+    dC = 2.0 * beta * dC_dk2;
+    dS = 2.0 * beta * dS_dk2;
+  } else {
+    // critical damping: C = 1, S = x, dC/d(eta^2) = -x^2/2, dS/d(eta^2) = -x^3/6
+    C = 1.0;
+    S = x;
+    dC = -2.0 * beta * (-0.5 * x * x);
+    dS = -2.0 * beta * (-x * x * x / 6.0);
+  }
+  eC = Dual{e * C, fma(de, C, e * dC)};
+  eS = Dual{e * S, fma(de, S, e * dS)};
+}
+
+// closed forms with the beta-derivative
+GPD void closed_eval(double x, const TermConst& t, Base<Dual>& o) {
+  const Dual beta{t.beta, 1.0};
+  Dual eC, eS;
+  damped_cs(x, t, eC, eS);
+  const Dual g = eS;
+  const Dual gp = eC - beta * eS;
+  const Dual G1 = 1.0 - gp - 2.0 * beta * g;
+  const Dual Ipp = (1.0 - gp * gp - g * g) / (4.0 * beta);
+  const Dual Igg = Ipp - g * gp - beta * g * g;
+  const Dual IGG = (x - g) - 2.0 * beta * G1 - G1 * g + Igg - beta * G1 * G1;
+  o.g = g;
+  o.gp = gp;
+  o.G1 = G1;
+  o.Igg = Igg;
+  o.Ipp = Ipp;
+  o.IGG = IGG;
 }
 
 // value-only closed forms.  The damping regime is a property of the term, so

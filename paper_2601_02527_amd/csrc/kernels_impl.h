@@ -194,22 +194,29 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
     const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2);
     adjoint_step<Dm>(m, P, mb, Pb, tc, coef, cur.dt, cur.info, o, jit, acc);
   }
-  if (active) {
-    if (p.chunk_first[c]) {
-      // prior of the SHO states: sigma_t^2 I in scaled coordinates
+  if (active && p.chunk_first[c]) {
+    // prior of the SHO states: sigma_t^2 I in scaled coordinates
 #pragma unroll
-      for (int t = 0; t < M; ++t)
-        acc.s[t] += 2.0 * tc[t].sigma * (Pb[sidx(2 * t, 2 * t, D)] + Pb[sidx(2 * t + 1, 2 * t + 1, D)]);
-    }
-#pragma unroll
-    for (int t = 0; t < M; ++t) {
-      gpart[(0 * M + t) * C + c] = acc.s[t];
-      gpart[(1 * M + t) * C + c] = acc.w[t];
-      gpart[(2 * M + t) * C + c] = acc.q[t];
-    }
-    gpart[(3 * M) * C + c] = acc.jit;
+    for (int t = 0; t < M; ++t)
+      acc.s[t] += 2.0 * tc[t].sigma * (Pb[sidx(2 * t, 2 * t, D)] + Pb[sidx(2 * t + 1, 2 * t + 1, D)]);
   }
+  // sum over the segment's lanes (one series), one partial per segment
+  const int64_t S = p.n_seg;
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    const double a0 = wave_sum(active ? acc.s[t] : 0.0);
+    const double a1 = wave_sum(active ? acc.w[t] : 0.0);
+    const double a2 = wave_sum(active ? acc.q[t] : 0.0);
+    if (lane == 0) {
+      gpart[(0 * M + t) * S + seg] = a0;
+      gpart[(1 * M + t) * S + seg] = a1;
+      gpart[(2 * M + t) * S + seg] = a2;
+    }
+  }
+  const double aj = wave_sum(active ? acc.jit : 0.0);
+  if (lane == 0) gpart[(3 * M) * S + seg] = aj;
   (void)NXP;
+  (void)C;
 }
 
 // ---------------------------------------------------------------------------

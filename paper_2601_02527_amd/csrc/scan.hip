@@ -50,12 +50,6 @@ __device__ __forceinline__ void lds_get(const double* lds, int lane, Elem<N>& e)
   e.load([&](int f) { return lds[f * WAVE + lane]; });
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-  return v;
-}
-
 template <int N>
 __global__ __launch_bounds__(WAVE) void k_seg_scan(DevPlan p, const double* __restrict__ summ, double* __restrict__ pre,
                                                    double* __restrict__ suf, double* __restrict__ segtot) {
