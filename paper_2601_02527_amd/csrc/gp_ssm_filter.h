@@ -785,7 +785,7 @@ GPD void discretise_dual(const TermConst* tc, const double* coef, double dt, dou
     const double x = tc[t].w0 * dt;
     Base<Dual> bd;
     if (use_series(x, tc[t]))
-      series_eval(coef + t * 2 * NCOEF, coef + t * 2 * NCOEF + NCOEF, x, bd);
+      series_eval(coef + t * 2 * NCOEF, x, bd);
     else
       closed_eval(x, tc[t], bd);
     Base<double> b;

@@ -43,10 +43,11 @@
 
 namespace gpssm {
 
-constexpr int KSER = 23;          // Taylor terms kept (x^0 .. x^KSER)
+constexpr int KSER = 25;          // highest power kept in the series of G1 and of the integrals
 constexpr double XSER = 0.75;     // series used when x * max(1, beta) <= XSER
-constexpr int NFUN = 6;           // g, g', G1, int g^2, int g'^2, int G1^2
-constexpr int NCOEF = NFUN * (KSER + 1);
+constexpr int NSET = 4;           // coefficient sets: G1, int g^2, int g'^2, int G1^2
+constexpr int NS = KSER + 1;      // coefficients per set (x^0 .. x^KSER)
+constexpr int NCOEF = NSET * NS;  // per term; the beta-derivatives follow
 constexpr double LOG_2PI = 1.8378770664093454835606594728112;
 
 // ---------------------------------------------------------------------------
@@ -116,10 +117,12 @@ struct Base {
 };
 
 // ---------------------------------------------------------------------------
-// Taylor coefficients (value and beta-derivative) of the six base functions
+// Taylor coefficients (value and beta-derivative) of the base functions
 // ---------------------------------------------------------------------------
-// v' = B v for v = (g, g', G1, g^2, gg', g'^2, G1^2, G1g, G1g', Igg, Ipp, IGG)
-// coef[f * (KSER+1) + n] (f in output order g, g', G1, Igg, Ipp, IGG)
+// v' = B v for v = (g, g', G1, g^2, gg', g'^2, G1^2, G1g, G1g', Igg, Ipp, IGG).
+// Kept: coef[n * NSET + s] for the sets s = G1, Igg, Ipp, IGG (degree-major,
+// so one Horner step reads all four sets at once).  g = G1' and g' = G1''
+// come out of the same Horner pass as G1.
 GPD void series_coefficients(double beta, double* coef, double* dcoef) {
   double c[12], d[12];
   for (int i = 0; i < 12; ++i) {
@@ -128,11 +131,11 @@ GPD void series_coefficients(double beta, double* coef, double* dcoef) {
   }
   c[1] = 1.0;  // g'(0)
   c[5] = 1.0;  // g'(0)^2
-  const int out[NFUN] = {0, 1, 2, 9, 10, 11};
+  const int out[NSET] = {2, 9, 10, 11};
   for (int n = 0; n <= KSER; ++n) {
-    for (int f = 0; f < NFUN; ++f) {
-      coef[f * (KSER + 1) + n] = c[out[f]];
-      dcoef[f * (KSER + 1) + n] = d[out[f]];
+    for (int f = 0; f < NSET; ++f) {
+      coef[n * NSET + f] = c[out[f]];
+      dcoef[n * NSET + f] = d[out[f]];
     }
     const double b2 = 2.0 * beta, b4 = 4.0 * beta;
     double nc[12], nd[12];
@@ -169,43 +172,68 @@ GPD void series_coefficients(double beta, double* coef, double* dcoef) {
   }
 }
 
-// Horner evaluation of the six series at x
-GPD void series_eval(const double* __restrict__ coef, double x, Base<double>& o) {
-  double r[NFUN];
-#pragma unroll
-  for (int f = 0; f < NFUN; ++f) {
-    double v = coef[f * (KSER + 1) + KSER];
-#pragma unroll
-    for (int n = KSER - 1; n >= 0; --n) v = fma(v, x, coef[f * (KSER + 1) + n]);
-    r[f] = v;
-  }
-  o.g = r[0];
-  o.gp = r[1];
-  o.G1 = r[2];
-  o.Igg = r[3];
-  o.Ipp = r[4];
-  o.IGG = r[5];
+// The kernels stage a series' tables in LDS once; every lane then reads the
+// same address (a broadcast read) in the Horner loops below.  The tables are
+// never written while a kernel evaluates them, so without a compiler fence
+// their reads are hoisted out of the event loops or shared between calls and
+// held in (spilled) registers; table_fence keeps each evaluation's reads at
+// its own use.
+typedef const double* coef_ptr;
+GPD void table_fence() {
+#ifdef __HIP_DEVICE_COMPILE__
+  __asm__ __volatile__("" ::: "memory");
+#endif
 }
-GPD void series_eval(const double* __restrict__ coef, const double* __restrict__ dcoef, double x, Base<Dual>& o) {
-  double r[NFUN], rd[NFUN];
+
+// Horner evaluation of the four series at x, all sets in one pass:
+// G1 with G1' = g and G1''/2, and the three integrals
+struct Series4 {
+  double G1, g, gph, Igg, Ipp, IGG;
+};
+GPD Series4 horner4(coef_ptr e, double x) {
+  constexpr int K = KSER;
+  Series4 r;
+  double b = e[K * NSET + 0], d = 0.0, dd = 0.0;
+  double i1 = e[K * NSET + 1], i2 = e[K * NSET + 2], i3 = e[K * NSET + 3];
 #pragma unroll
-  for (int f = 0; f < NFUN; ++f) {
-    double v = coef[f * (KSER + 1) + KSER];
-    double w = dcoef[f * (KSER + 1) + KSER];
-#pragma unroll
-    for (int n = KSER - 1; n >= 0; --n) {
-      v = fma(v, x, coef[f * (KSER + 1) + n]);
-      w = fma(w, x, dcoef[f * (KSER + 1) + n]);
-    }
-    r[f] = v;
-    rd[f] = w;
+  for (int n = K - 1; n >= 0; --n) {
+    dd = fma(dd, x, d);
+    d = fma(d, x, b);
+    b = fma(b, x, e[n * NSET + 0]);
+    i1 = fma(i1, x, e[n * NSET + 1]);
+    i2 = fma(i2, x, e[n * NSET + 2]);
+    i3 = fma(i3, x, e[n * NSET + 3]);
   }
-  o.g = {r[0], rd[0]};
-  o.gp = {r[1], rd[1]};
-  o.G1 = {r[2], rd[2]};
-  o.Igg = {r[3], rd[3]};
-  o.Ipp = {r[4], rd[4]};
-  o.IGG = {r[5], rd[5]};
+  r.G1 = b;
+  r.g = d;
+  r.gph = dd;
+  r.Igg = i1;
+  r.Ipp = i2;
+  r.IGG = i3;
+  return r;
+}
+
+// the series at x (coef: the term's table, value part then beta-derivative)
+GPD void series_eval(const double* coef, double x, Base<double>& o) {
+  table_fence();
+  const Series4 v = horner4(coef, x);
+  o.G1 = v.G1;
+  o.g = v.g;
+  o.gp = 2.0 * v.gph;
+  o.Igg = v.Igg;
+  o.Ipp = v.Ipp;
+  o.IGG = v.IGG;
+}
+GPD void series_eval(const double* coef, double x, Base<Dual>& o) {
+  table_fence();
+  const Series4 v = horner4(coef, x);
+  const Series4 d = horner4(coef + NCOEF, x);
+  o.G1 = {v.G1, d.G1};
+  o.g = {v.g, d.g};
+  o.gp = {2.0 * v.gph, 2.0 * d.gph};
+  o.Igg = {v.Igg, d.Igg};
+  o.Ipp = {v.Ipp, d.Ipp};
+  o.IGG = {v.IGG, d.IGG};
 }
 
 // ---------------------------------------------------------------------------

@@ -35,6 +35,16 @@ __device__ __forceinline__ Obs load_event(const DevPlan& p, int64_t e, double ji
   return make_obs<Dm>(info, p.y[e], p.r[e], p.invd[e], jit2);
 }
 
+// the series' Taylor tables (value and beta-derivative, all terms), staged in
+// LDS by the workgroup's single wavefront
+template <class Dm>
+__device__ __forceinline__ const double* stage_coef(const DevParams& pr, int64_t b, double* lds) {
+  const double* g = pr.coef + b * Dm::M * 2 * NCOEF;
+  for (int i = threadIdx.x; i < Dm::M * 2 * NCOEF; i += WAVE) lds[i] = g[i];
+  __syncthreads();
+  return lds;
+}
+
 // the raw fields of one event, loaded one step ahead of their use
 struct EvRaw {
   double dt, y, r, invd;
@@ -89,7 +99,8 @@ __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, dou
   const int64_t ev0 = p.seg_ev0[seg];
   TermConst tc[M];
   load_terms<Dm>(pr, b, tc);
-  const double* coef = pr.coef + b * M * 2 * NCOEF;
+  __shared__ double lcoef[M * 2 * NCOEF];
+  const double* coef = stage_coef<Dm>(pr, b, lcoef);
   const double jit = pr.jit[b];
   const double jit2 = jit * jit;
   CondState<Dm> st;
@@ -145,7 +156,8 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
   const int64_t c = p.seg_chunk0[seg] + (active ? lane : 0);
   TermConst tc[M];
   load_terms<Dm>(pr, b, tc);
-  const double* coef = pr.coef + b * M * 2 * NCOEF;
+  __shared__ double lcoef[M * 2 * NCOEF];
+  const double* coef = stage_coef<Dm>(pr, b, lcoef);
   const double jit = pr.jit[b];
   const double jit2 = jit * jit;
   double* rb = rec + ev0 * F;
@@ -226,10 +238,11 @@ template <int J>
 __global__ __launch_bounds__(WAVE) void k_plain(DevPlan p, DevParams pr, int64_t b, double* __restrict__ loglik) {
   using Dm = Dims<M, J>;
   constexpr int D = Dm::D, NP = Dm::NP;
+  __shared__ double lcoef[M * 2 * NCOEF];
+  const double* coef = stage_coef<Dm>(pr, b, lcoef);
   if (threadIdx.x != 0) return;
   TermConst tc[M];
   load_terms<Dm>(pr, b, tc);
-  const double* coef = pr.coef + b * M * 2 * NCOEF;
   const double jit = pr.jit[b];
   const double jit2 = jit * jit;
   double m[D], P[NP];
@@ -329,7 +342,8 @@ __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const 
   const int32_t len = active ? p.chunk_len[c] : 0;
   TermConst tc[M];
   load_terms<Dm>(pr, b, tc);
-  const double* coef = pr.coef + b * M * 2 * NCOEF;
+  __shared__ double lcoef[M * 2 * NCOEF];
+  const double* coef = stage_coef<Dm>(pr, b, lcoef);
   const double jit = pr.jit[b];
   const double jit2 = jit * jit;
   double* rb = rec + ev0 * F;
