@@ -445,8 +445,7 @@ int gp_ssm_plan_loglik_grad(gp_ssm_plan* pl, int32_t M, const double* sigma, con
   const DevPlan p = pl->dev();
   const KernelSet ks = kernel_set(M, pl->host.max_slots);
   Launch L{s};
-  ks.adjoint(L, p, pr, pl->bstate.as<double>(), pl->badj.as<double>(), pl->rec.as<double>(), pl->gpart.as<double>(),
-             nullptr);
+  ks.adjoint(L, p, pr, pl->bstate.as<double>(), pl->badj.as<double>(), pl->rec.as<double>(), pl->gpart.as<double>());
   HIP_TRY(hipGetLastError());
   prof_begin("k_reduce_grad", s);
   hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, s, p, M, pl->gpart.as<double>(), st,

@@ -25,15 +25,32 @@ namespace gpssm {
 // ---------------------------------------------------------------------------
 // conditional filter of a chunk
 // ---------------------------------------------------------------------------
-template <class Dm>
+// A lane's slots of an LDS array laid out field-major across the wavefront:
+// element f at base[f * 64].
+struct LaneLds {
+  double* base;
+  GPD double& operator[](int f) const { return base[f * 64]; }
+};
+
+// SL: the sensitivity block S lives in LDS (a LaneLds view set by the
+// caller before init) instead of registers.
+template <class Dm, bool SL = false>
 struct CondState {
   static constexpr int D = Dm::D, NX = Dm::NX, NP = Dm::NP, NXP = Dm::NXP;
   double P[NP];
   double mu[D];
-  double S[D * NX];  // d mean / d x_b, row-major
+  double Sr[SL ? 1 : D * NX];  // d mean / d x_b, row-major
+  LaneLds Sl;
   double Jm[NXP];
   double eta[NX];
   double c0;
+
+  GPD double& S(int i) {
+    if constexpr (SL)
+      return Sl[i];
+    else
+      return Sr[i];
+  }
 
   GPD void init() {
 #pragma unroll
@@ -43,7 +60,7 @@ struct CondState {
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
-      for (int c = 0; c < NX; ++c) S[i * NX + c] = (i == c) ? 1.0 : 0.0;
+      for (int c = 0; c < NX; ++c) S(i * NX + c) = (i == c) ? 1.0 : 0.0;
 #pragma unroll
     for (int i = 0; i < NXP; ++i) Jm[i] = 0.0;
 #pragma unroll
@@ -51,11 +68,14 @@ struct CondState {
     c0 = 0.0;
   }
 
-  // one event: predict over the step that ends at it, then its observation
+  // one event: predict over the step that ends at it, then its observation.
+  // S is processed one column at a time in two passes (predict and project;
+  // then the rank-one update and the slot close), so that only one column is
+  // live at once.
   GPD void step(const TermQ* tq, uint32_t info, const Obs& o) {
+    constexpr int M = Dm::M, J = Dm::J;
     const uint32_t open = ev_open(info);
     predict_mean<Dm>(mu, tq, open);
-    predict_cols<Dm, NX>(S, tq, open);
     predict_cov<Dm>(P, tq, open);
     double u[D];
     obs_gain<Dm>(P, o, u);
@@ -67,17 +87,38 @@ struct CondState {
     for (int c = 0; c < NX; ++c) {
       double col[D];
 #pragma unroll
-      for (int i = 0; i < D; ++i) col[i] = S[i * NX + c];
+      for (int i = 0; i < D; ++i) col[i] = S(i * NX + c);
+      double fx = 0.0;
+#pragma unroll
+      for (int t = 0; t < M; ++t) fx = fma(tq[t].f0, col[2 * t], fma(tq[t].f1, col[2 * t + 1], fx));
+#pragma unroll
+      for (int t = 0; t < M; ++t) {
+        const double x0 = col[2 * t], x1 = col[2 * t + 1];
+        col[2 * t] = fma(tq[t].a00, x0, tq[t].a01 * x1);
+        col[2 * t + 1] = fma(-tq[t].a01, x0, tq[t].a11 * x1);
+      }
+#pragma unroll
+      for (int j = 0; j < J; ++j) col[NX + j] += ((open >> j) & 1u) ? fx : 0.0;
       a[c] = obs_dot<Dm>(col, o);
+#pragma unroll
+      for (int i = 0; i < D; ++i) S(i * NX + c) = col[i];
     }
+    if constexpr (SL) table_fence();
     const double riS = r * iS;
 #pragma unroll
     for (int i = 0; i < D; ++i) mu[i] = fma(u[i], riS, mu[i]);
+    const bool end = ev_kind(info) == EV_END;
+    const uint32_t slot = ev_slot(info);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       const double ui = u[i] * iS;
+      // integrator rows of the slot closed by this event end at zero
+      const bool z = (i >= NX) && end && (uint32_t)(i - NX) == slot;
 #pragma unroll
-      for (int c = 0; c < NX; ++c) S[i * NX + c] = fma(-ui, a[c], S[i * NX + c]);
+      for (int c = 0; c < NX; ++c) {
+        const double v = fma(-ui, a[c], S(i * NX + c));
+        S(i * NX + c) = z ? 0.0 : v;
+      }
 #pragma unroll
       for (int j = i; j < D; ++j) P[sidx(i, j, D)] = fma(-ui, u[j], P[sidx(i, j, D)]);
     }
@@ -90,7 +131,6 @@ struct CondState {
     }
     if (o.has) c0 += LOG_2PI + log(S_) + r * riS;
     close_slot<Dm>(mu, P, info);
-    close_slot_rows<Dm, NX>(S, info);
   }
 };
 
@@ -721,7 +761,7 @@ struct GradAcc {
 GPD void term_backprop(const TermConst& t, const TermQ& q, const double* db, double dt, const double* W, double& gs,
                        double& gw, double& gq) {
   const double beta = t.beta, qh = t.qhat, iw = t.inv_w0, w0 = t.w0;
-  const double iq = 1.0 / qh;
+  const double iq = t.inv_qhat;
   const double g = q.a01, gp = q.a11, G1 = q.f1 * w0, Igg = q.q00 * iq, Ipp = q.q11 * iq, IGG = q.zz * w0 * w0 * iq;
   double bg = 0, bgp = 0, bG1 = 0, bIgg = 0, bIpp = 0, bIGG = 0, bbeta = 0, bqh = 0, biw = 0;
   // transition
@@ -761,31 +801,50 @@ GPD void term_backprop(const TermConst& t, const TermQ& q, const double* db, dou
   const double bx = bg * gp + bgp * (-g - 2.0 * beta * gp) + bG1 * g + bIgg * g * g + bIpp * gp * gp + bIGG * G1 * G1;
   bbeta += bg * db[0] + bgp * db[1] + bG1 * db[2] + bIgg * db[3] + bIpp * db[4] + bIGG * db[5];
   // (x, beta, qhat, 1/omega0) -> (sigma, omega0, Q);  x = omega0 dt, beta = 1/2Q, qhat = 2 sigma^2/Q
-  const double Q = 0.5 / beta;
+  // 1/Q = 2 beta, so qhat/Q = 2 beta qhat and 2 qhat/sigma = 8 beta sigma
   gw += bx * dt - biw * iw * iw;
-  gq += -bbeta * 2.0 * beta * beta - bqh * qh / Q;
-  gs += bqh * 2.0 * qh / t.sigma;
+  gq += -bbeta * 2.0 * beta * beta - bqh * qh * (2.0 * beta);
+  gs += bqh * 8.0 * beta * t.sigma;
 }
 
+// Accuracy policies of the discretisation.  DiscFull: series to degree KSER
+// below x max(1, beta) = XSER, about 1e-15 relative everywhere (likelihood,
+// smoother).  DiscGrad: degree KSER_G below XSER_G, about 1e-11 on the step
+// quantities and 1e-9 on their beta-derivatives, for the passes that only
+// feed the gradient (checked against the full policy over Q in [0.3, 50]).
+struct DiscFull {
+  static constexpr int K = KSER;
+  GPD static bool series(double x, const TermConst& t) { return x <= t.xser; }
+};
+struct DiscGrad {
+  static constexpr int K = KSER_G;
+  GPD static bool series(double x, const TermConst& t) { return x <= t.xser_g; }
+};
+
 // discretisation of all terms over one step (values only)
-template <int M>
+template <int M, class Acc = DiscFull>
 GPD void discretise(const TermConst* tc, const double* coef, double dt, TermQ* tq) {
 #pragma unroll
   for (int t = 0; t < M; ++t) {
-    const Base<double> b = base_values(tc[t], coef + t * 2 * NCOEF, dt);
+    const double x = tc[t].w0 * dt;
+    Base<double> b;
+    if (Acc::series(x, tc[t]))
+      series_eval<Acc::K>(coef + t * 2 * NCOEF, x, b);
+    else
+      closed_eval(x, tc[t], b);
     tq[t] = term_step(tc[t], b);
   }
 }
 
 // with the beta-derivatives of the base functions (db[t*6 + f])
-template <int M>
+template <int M, class Acc = DiscFull>
 GPD void discretise_dual(const TermConst* tc, const double* coef, double dt, double* db, TermQ* tq) {
 #pragma unroll
   for (int t = 0; t < M; ++t) {
     const double x = tc[t].w0 * dt;
     Base<Dual> bd;
-    if (use_series(x, tc[t]))
-      series_eval(coef + t * 2 * NCOEF, x, bd);
+    if (Acc::series(x, tc[t]))
+      series_eval<Acc::K>(coef + t * 2 * NCOEF, x, bd);
     else
       closed_eval(x, tc[t], bd);
     Base<double> b;
@@ -817,7 +876,7 @@ GPD void adjoint_step(const double* m, const double* P, double* mb, double* Pb, 
   const uint32_t open = ev_open(info);
   double db[6 * M];
   TermQ tq[M];
-  discretise_dual<M>(tc, coef, dt, db, tq);
+  discretise_dual<M, DiscGrad>(tc, coef, dt, db, tq);
   double oj[J > 0 ? J : 1];
 #pragma unroll
   for (int j = 0; j < J; ++j) oj[j] = ((open >> j) & 1u) ? 1.0 : 0.0;

@@ -45,6 +45,8 @@ namespace gpssm {
 
 constexpr int KSER = 25;          // highest power kept in the series of G1 and of the integrals
 constexpr double XSER = 0.75;     // series used when x * max(1, beta) <= XSER
+constexpr int KSER_G = 17;        // gradient-only passes: degree and switch point
+constexpr double XSER_G = 0.4;
 constexpr int NSET = 4;           // coefficient sets: G1, int g^2, int g'^2, int G1^2
 constexpr int NS = KSER + 1;      // coefficients per set (x^0 .. x^KSER)
 constexpr int NCOEF = NSET * NS;  // per term; the beta-derivatives follow
@@ -190,8 +192,8 @@ GPD void table_fence() {
 struct Series4 {
   double G1, g, gph, Igg, Ipp, IGG;
 };
+template <int K>
 GPD Series4 horner4(coef_ptr e, double x) {
-  constexpr int K = KSER;
   Series4 r;
   double b = e[K * NSET + 0], d = 0.0, dd = 0.0;
   double i1 = e[K * NSET + 1], i2 = e[K * NSET + 2], i3 = e[K * NSET + 3];
@@ -213,10 +215,12 @@ GPD Series4 horner4(coef_ptr e, double x) {
   return r;
 }
 
-// the series at x (coef: the term's table, value part then beta-derivative)
+// the series at x truncated after degree K (coef: the term's table, value
+// part then beta-derivative)
+template <int K = KSER>
 GPD void series_eval(const double* coef, double x, Base<double>& o) {
   table_fence();
-  const Series4 v = horner4(coef, x);
+  const Series4 v = horner4<K>(coef, x);
   o.G1 = v.G1;
   o.g = v.g;
   o.gp = 2.0 * v.gph;
@@ -224,10 +228,11 @@ GPD void series_eval(const double* coef, double x, Base<double>& o) {
   o.Ipp = v.Ipp;
   o.IGG = v.IGG;
 }
+template <int K = KSER>
 GPD void series_eval(const double* coef, double x, Base<Dual>& o) {
   table_fence();
-  const Series4 v = horner4(coef, x);
-  const Series4 d = horner4(coef + NCOEF, x);
+  const Series4 v = horner4<K>(coef, x);
+  const Series4 d = horner4<K>(coef + NCOEF, x);
   o.G1 = {v.G1, d.G1};
   o.g = {v.g, d.g};
   o.gp = {2.0 * v.gph, 2.0 * d.gph};
@@ -246,6 +251,8 @@ struct TermConst {
   double inv_eta;  // 1/sqrt(|eta2|), 0 at critical damping
   double inv_4b;   // 1/(4 beta)
   double xser;     // the series is used for omega0 dt <= xser
+  double inv_qhat; // 1/qhat
+  double xser_g;   // switch point of the gradient-only passes
 };
 
 GPD TermConst make_term(double sigma, double w0, double quality) {
@@ -260,24 +267,26 @@ GPD TermConst make_term(double sigma, double w0, double quality) {
   t.inv_eta = (t.eta2 != 0.0) ? 1.0 / t.eta : 0.0;
   t.inv_4b = 0.25 / t.beta;
   t.xser = XSER / fmax(1.0, t.beta);
+  t.inv_qhat = 1.0 / t.qhat;
+  t.xser_g = XSER_G / fmax(1.0, t.beta);
   return t;
 }
 
-// cos(u) - sin(u)/u and its hyperbolic counterpart cosh(u) - sinh(u)/u,
-// without cancellation for small u (series below 0.1)
-GPD double cos_minus_sinc(double u, double s, double c) {
+// cos(u) - sin(u)/u and its hyperbolic counterpart cosh(u) - sinh(u)/u
+// (ru = 1/u), without cancellation for small u (series below 0.1)
+GPD double cos_minus_sinc(double u, double ru, double s, double c) {
   if (fabs(u) < 0.1) {
     const double u2 = u * u;
     return u2 * (-1.0 / 3.0 + u2 * (1.0 / 30.0 + u2 * (-1.0 / 840.0 + u2 * (1.0 / 45360.0))));
   }
-  return c - s / u;
+  return fma(-s, ru, c);
 }
-GPD double cosh_minus_sinhc(double u, double sh, double ch) {
+GPD double cosh_minus_sinhc(double u, double ru, double sh, double ch) {
   if (fabs(u) < 0.1) {
     const double u2 = u * u;
     return u2 * (1.0 / 3.0 + u2 * (1.0 / 30.0 + u2 * (1.0 / 840.0 + u2 * (1.0 / 45360.0))));
   }
-  return ch - sh / u;
+  return fma(-sh, ru, ch);
 }
 
 // e^{-beta x} cos(eta x) and e^{-beta x} sin(eta x)/eta (eta^2 = 1 - beta^2,
@@ -298,7 +307,9 @@ GPD void damped_cs(double x, const TermConst& t, Dual& eC, Dual& eS) {
     S = sn * t.inv_eta;
     // dC/d(eta^2) = -x S / 2 ; dS/d(eta^2) = x^2 (cos u - sin u/u) / (2 u^2) * ... written as below
     const double dC_deta2 = -0.5 * x * S;
-    const double dS_deta2 = 0.5 * x * x * x * cos_minus_sinc(u, sn, cs) / (u * u + (u == 0.0));
+    // x^3/u^2 = x/eta^2; x > 0 on the closed-form branch
+    const double ru = t.inv_eta / x;
+    const double dS_deta2 = 0.5 * x * cos_minus_sinc(u, ru, sn, cs) * (t.inv_eta * t.inv_eta);
     dC = -2.0 * beta * dC_deta2;
     dS = -2.0 * beta * dS_deta2;
   } else if (t.eta2 < 0.0) {
@@ -325,7 +336,8 @@ GPD void damped_cs(double x, const TermConst& t, Dual& eC, Dual& eS) {
     S = sh * t.inv_eta;
     // with kappa = k^2 = beta^2 - 1: dC/dkappa = x S/2, dS/dkappa = x^3 (cosh u - sinh u/u)/(2 u^2)
     const double dC_dk2 = 0.5 * x * S;
-    const double dS_dk2 = 0.5 * x * x * x * cosh_minus_sinhc(u, sh, ch) / (u * u);
+    const double ru = t.inv_eta / x;
+    const double dS_dk2 = 0.5 * x * cosh_minus_sinhc(u, ru, sh, ch) * (t.inv_eta * t.inv_eta);
     dC = 2.0 * beta * dC_dk2;
     dS = 2.0 * beta * dS_dk2;
   } else {
@@ -333,7 +345,7 @@ GPD void damped_cs(double x, const TermConst& t, Dual& eC, Dual& eS) {
     C = 1.0;
     S = x;
     dC = -2.0 * beta * (-0.5 * x * x);
-    dS = -2.0 * beta * (-x * x * x / 6.0);
+    dS = -2.0 * beta * (-(1.0 / 6.0) * x * x * x);
   }
   eC = Dual{e * C, fma(de, C, e * dC)};
   eS = Dual{e * S, fma(de, S, e * dS)};
@@ -347,7 +359,9 @@ GPD void closed_eval(double x, const TermConst& t, Base<Dual>& o) {
   const Dual g = eS;
   const Dual gp = eC - beta * eS;
   const Dual G1 = 1.0 - gp - 2.0 * beta * g;
-  const Dual Ipp = (1.0 - gp * gp - g * g) / (4.0 * beta);
+  const Dual ipn = 1.0 - gp * gp - g * g;  // Ipp = ipn / (4 beta)
+  const double ipv = ipn.v * t.inv_4b;
+  const Dual Ipp{ipv, (ipn.d - 4.0 * ipv) * t.inv_4b};
   const Dual Igg = Ipp - g * gp - beta * g * g;
   const Dual IGG = (x - g) - 2.0 * beta * G1 - G1 * g + Igg - beta * G1 * G1;
   o.g = g;
@@ -411,16 +425,6 @@ struct TermQ {
 
 GPD bool use_series(double x, const TermConst& t) { return x <= t.xser; }
 
-GPD Base<double> base_values(const TermConst& t, const double* coef, double dt) {
-  const double x = t.w0 * dt;
-  Base<double> b;
-  if (use_series(x, t))
-    series_eval(coef, x, b);
-  else
-    closed_eval(x, t, b);
-  return b;
-}
-
 GPD TermQ term_step(const TermConst& t, const Base<double>& b) {
   TermQ q;
   const double beta = t.beta;
@@ -479,26 +483,6 @@ GPD void predict_mean(double* m, const TermQ* tq, uint32_t open) {
   }
 #pragma unroll
   for (int j = 0; j < J; ++j) m[NX + j] += ((open >> j) & 1u) ? fx : 0.0;
-}
-
-// columns of a D x NC matrix S (row-major, S[i*NC+c]) transformed as A S
-template <class Dm, int NC>
-GPD void predict_cols(double* S, const TermQ* tq, uint32_t open) {
-  constexpr int M = Dm::M, J = Dm::J, NX = Dm::NX;
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    double fx = 0.0;
-#pragma unroll
-    for (int t = 0; t < M; ++t) fx = fma(tq[t].f0, S[(2 * t) * NC + c], fma(tq[t].f1, S[(2 * t + 1) * NC + c], fx));
-#pragma unroll
-    for (int t = 0; t < M; ++t) {
-      const double x0 = S[(2 * t) * NC + c], x1 = S[(2 * t + 1) * NC + c];
-      S[(2 * t) * NC + c] = fma(tq[t].a00, x0, tq[t].a01 * x1);
-      S[(2 * t + 1) * NC + c] = fma(-tq[t].a01, x0, tq[t].a11 * x1);
-    }
-#pragma unroll
-    for (int j = 0; j < J; ++j) S[(NX + j) * NC + c] += ((open >> j) & 1u) ? fx : 0.0;
-  }
 }
 
 template <class Dm>
@@ -654,19 +638,6 @@ GPD void close_slot(double* m, double* P, uint32_t info) {
     m[NX + j] = z ? 0.0 : m[NX + j];
 #pragma unroll
     for (int i = 0; i < D; ++i) P[sidx(i, NX + j, D)] = z ? 0.0 : P[sidx(i, NX + j, D)];
-  }
-}
-
-template <class Dm, int NC>
-GPD void close_slot_rows(double* S, uint32_t info) {
-  constexpr int J = Dm::J, NX = Dm::NX;
-  const bool end = ev_kind(info) == EV_END;
-  const uint32_t slot = ev_slot(info);
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const bool z = end && (uint32_t)j == slot;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) S[(NX + j) * NC + c] = z ? 0.0 : S[(NX + j) * NC + c];
   }
 }
 

@@ -45,7 +45,7 @@ struct Launch {
 struct KernelSet {
   void (*summaries)(const Launch&, const DevPlan&, const DevParams&, double* summ);
   void (*adjoint)(const Launch&, const DevPlan&, const DevParams&, const double* bstate, const double* badj,
-                  double* rec, double* gpart, double* llchk);
+                  double* rec, double* gpart);
   void (*plain)(const Launch&, const DevPlan&, const DevParams&, int64_t series, double* loglik);
   void (*smooth)(const Launch&, const DevPlan&, const DevParams&, const double* bstate, const double* bsmooth,
                  double* rec, const DevTests& tests, double* mean_test, double* var_test, double* mean_data,

@@ -60,8 +60,8 @@ __device__ __forceinline__ EvRaw fetch_event(const DevPlan& p, int64_t e) {
   return v;
 }
 
-// one plain filter step; returns the log-likelihood term
-template <class Dm>
+// one plain filter step; returns the log-likelihood term (0 unless LL)
+template <class Dm, bool LL = true>
 __device__ __forceinline__ double plain_step(double* m, double* P, const TermQ* tq, uint32_t info, const Obs& o) {
   constexpr int D = Dm::D;
   const uint32_t open = ev_open(info);
@@ -82,7 +82,10 @@ __device__ __forceinline__ double plain_step(double* m, double* P, const TermQ* 
     for (int j = i; j < D; ++j) P[sidx(i, j, D)] = fma(-ui, u[j], P[sidx(i, j, D)]);
   }
   close_slot<Dm>(m, P, info);
-  return o.has ? -0.5 * (LOG_2PI + log(S) + v * viS) : 0.0;
+  if constexpr (LL)
+    return o.has ? -0.5 * (LOG_2PI + log(S) + v * viS) : 0.0;
+  else
+    return 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -103,7 +106,11 @@ __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, dou
   const double* coef = stage_coef<Dm>(pr, b, lcoef);
   const double jit = pr.jit[b];
   const double jit2 = jit * jit;
-  CondState<Dm> st;
+  // the sensitivity block in LDS when four workgroups still fit in a CU
+  constexpr bool USE_LDS = 8 * (M * 2 * NCOEF + Dm::D * NX * WAVE) <= 40960;
+  __shared__ double lS[USE_LDS ? Dm::D * NX * WAVE : 1];
+  CondState<Dm, USE_LDS> st;
+  st.Sl = LaneLds{lS + lane};
   st.init();
   EvRaw nxt = fetch_event(p, ev0 + lane);
   for (int32_t k = 0; k < L; ++k) {
@@ -120,7 +127,7 @@ __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, dou
 #pragma unroll
     for (int i = 0; i < NX; ++i)
 #pragma unroll
-      for (int k = 0; k < NX; ++k) summ[(sum_A(NX) + i * NX + k) * C + c] = st.S[i * NX + k];
+      for (int k = 0; k < NX; ++k) summ[(sum_A(NX) + i * NX + k) * C + c] = st.S(i * NX + k);
 #pragma unroll
     for (int i = 0; i < NX; ++i) summ[(sum_b(NX) + i) * C + c] = st.mu[i];
 #pragma unroll
@@ -142,7 +149,7 @@ __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, dou
 template <int J>
 __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const double* __restrict__ bstate,
                                                   const double* __restrict__ badj, double* __restrict__ rec,
-                                                  double* __restrict__ gpart, double* __restrict__ llchk) {
+                                                  double* __restrict__ gpart) {
   using Dm = Dims<M, J>;
   constexpr int NX = Dm::NX, D = Dm::D, NP = Dm::NP, NXP = Dm::NXP;
   constexpr int F = rec_fields<Dm>();
@@ -170,7 +177,6 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
 #pragma unroll
     for (int j = i; j < D; ++j) P[sidx(i, j, D)] = (j < NX && active) ? bstate[(NX + sidx(i, j, NX)) * C + c] : 0.0;
 
-  double ll = 0.0;
   EvRaw nxt = fetch_event(p, ev0 + lane);
   for (int32_t k = 0; k < L; ++k) {
     const EvRaw cur = nxt;
@@ -181,10 +187,9 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
     for (int f = 0; f < NP; ++f) rb[((int64_t)k * F + D + f) * WAVE + lane] = P[f];
     const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2);
     TermQ tq[M];
-    discretise<M>(tc, coef, cur.dt, tq);
-    ll += plain_step<Dm>(m, P, tq, cur.info, o);
+    discretise<M, DiscGrad>(tc, coef, cur.dt, tq);
+    plain_step<Dm, false>(m, P, tq, cur.info, o);
   }
-  if (active && llchk) llchk[c] = ll;
 
   double mb[D], Pb[NP];
 #pragma unroll
@@ -516,10 +521,10 @@ void launch_summaries(const Launch& L, const DevPlan& p, const DevParams& pr, do
 }
 template <int J>
 void launch_adjoint(const Launch& L, const DevPlan& p, const DevParams& pr, const double* bstate, const double* badj,
-                    double* rec, double* gpart, double* llchk) {
+                    double* rec, double* gpart) {
   if (p.n_seg == 0) return;
   prof_begin("k_adjoint", L.stream);
-  hipLaunchKernelGGL(k_adjoint<J>, dim3(p.n_seg), dim3(WAVE), 0, L.stream, p, pr, bstate, badj, rec, gpart, llchk);
+  hipLaunchKernelGGL(k_adjoint<J>, dim3(p.n_seg), dim3(WAVE), 0, L.stream, p, pr, bstate, badj, rec, gpart);
   prof_end("k_adjoint", L.stream);
 }
 template <int J>

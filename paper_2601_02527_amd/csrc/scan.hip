@@ -62,13 +62,15 @@ __global__ __launch_bounds__(WAVE) void k_seg_scan(DevPlan p, const double* __re
   const bool valid = lane < nch;
   bool ok = true;
   Elem<N> own, part, tmp;
+  // Kogge-Stone levels d < nch suffice: the lanes past the segment hold the
+  // identity
   // inclusive prefix
   if (valid)
     own.load([&](int f) { return summ[(int64_t)f * C + c]; });
   else
     own.identity();
 #pragma unroll 1
-  for (int d = 1; d < WAVE; d <<= 1) {
+  for (int d = 1; d < nch; d <<= 1) {
     lds_put<N>(lds, lane, own);
     __syncthreads();
     if (lane >= d) {
@@ -86,7 +88,7 @@ __global__ __launch_bounds__(WAVE) void k_seg_scan(DevPlan p, const double* __re
   else
     own.identity();
 #pragma unroll 1
-  for (int d = 1; d < WAVE; d <<= 1) {
+  for (int d = 1; d < nch; d <<= 1) {
     lds_put<N>(lds, lane, own);
     __syncthreads();
     if (lane + d < WAVE) {
@@ -112,6 +114,7 @@ __global__ __launch_bounds__(WAVE) void k_series_scan(DevPlan p, DevParams pr, c
   const int32_t s0 = p.series_seg0[b], ns = p.series_nseg[b];
   if (ns == 0) return;
   const int32_t q = (ns + WAVE - 1) / WAVE;
+  const int32_t nl = (ns + q - 1) / q;  // lanes holding a block; the rest hold the identity
   const int32_t lo = min(ns, lane * q), hi = min(ns, lo + q);
   bool ok = true;
   auto tot = [&](int32_t k) { return [=](int f) { return segtot[(int64_t)f * S + s0 + k]; }; };
@@ -127,7 +130,7 @@ __global__ __launch_bounds__(WAVE) void k_series_scan(DevPlan p, DevParams pr, c
   // exclusive prefix over lanes
   Elem<N> own = blk;
 #pragma unroll 1
-  for (int d = 1; d < WAVE; d <<= 1) {
+  for (int d = 1; d < nl; d <<= 1) {
     lds_put<N>(lds, lane, own);
     __syncthreads();
     if (lane >= d) {
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(WAVE) void k_series_scan(DevPlan p, DevParams pr, c
   // information of the next lane's suffix
   own = blk;
 #pragma unroll 1
-  for (int d = 1; d < WAVE; d <<= 1) {
+  for (int d = 1; d < nl; d <<= 1) {
     lds_put<N>(lds, lane, own);
     __syncthreads();
     if (lane + d < WAVE) {
