@@ -57,6 +57,44 @@ def algorithmic_bytes_per_point(M, J, grad):
     return 2 * base + 2 * 2 * (D + D * (D + 1) / 2) * 8
 
 
+def kernel_source_fingerprint():
+    """sha256 (16 hex digits) of the kernel sources and their build flags."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2601_02527_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_2601_02527_amd", "build.py"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a device copy of known size), or None
+    when the summary is missing or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("| ") and line.count("|") >= 3:
+                cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
+                if len(cells) >= 2:
+                    fields[cells[0]] = cells[1:]
+    fp = fields.get("kernel sources", [None])[0]
+    row = fields.get(kernel)
+    if fp != kernel_source_fingerprint() or row is None:
+        return None
+    try:
+        return {"fetch_bytes": float(row[0]), "write_bytes": float(row[1]), "bytes": float(row[2])}
+    except (ValueError, IndexError):
+        return None
+
+
 def cpu_oracle_baseline(batch, n_series, threads):
     """Oracle log-likelihood + central-difference gradient (21 evaluations for
     10 parameters) of the first n_series series, one series per thread."""
@@ -192,8 +230,10 @@ def main():
         avg_s = kern[dom]["avg_ms"] * 1e-3
         if flops_per_launch is not None:
             ach = flops_per_launch / avg_s / 1e12
+            tr = measured_traffic(dom, args.workload)
             roof = {"bound": "alu", "kernel": dom, "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                    "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS,
+                    "traffic": tr["bytes"] if tr else None, "traffic_detail": tr,
                     "avg_ms": kern[dom]["avg_ms"], "flops_per_launch": flops_per_launch}
     step_flops = grad_pt * points
     step_roof = {"achieved_tflops": step_flops / (ms_step * 1e-3) / 1e12,
