@@ -82,13 +82,17 @@ void prof_flush() {
 __global__ void k_prep(int64_t B, int M, const double* __restrict__ sigma, const double* __restrict__ omega0,
                        const double* __restrict__ quality, const double* __restrict__ jitter, TermConst* __restrict__ tc,
                        double* __restrict__ coef, double* __restrict__ jit) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < B * M) {
+  // one thread per (series, term, series interval)
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < B * M * NI) {
+    const int64_t i = j / NI;
+    const int iv = (int)(j - i * NI);
     const TermConst t = make_term(sigma[i], omega0[i], quality[i]);
-    tc[i] = t;
-    series_coefficients(t.beta, coef + i * 2 * NCOEF, coef + i * 2 * NCOEF + NCOEF);
+    if (iv == 0) tc[i] = t;
+    double* c = coef + i * 2 * NCOEF + iv * ISTRIDE;
+    series_interval_table(t.beta, interval_centre(iv, t.b1ser, t.wser), c, c + NCOEF);
   }
-  if (i < B) jit[i] = jitter ? jitter[i] : 0.0;
+  if (j < B) jit[j] = jitter ? jitter[j] : 0.0;
 }
 
 __global__ void k_reduce_grad(DevPlan p, int M, const double* __restrict__ gpart, const int32_t* __restrict__ status,
@@ -264,7 +268,7 @@ int prepare_params(gp_ssm_plan* pl, int32_t M, const double* sigma, const double
   if (int rc = pl->coef.ensure(sizeof(double) * B * M * 2 * NCOEF)) return rc;
   if (int rc = pl->jit.ensure(sizeof(double) * B)) return rc;
   const int threads = 256;
-  const int64_t n = std::max<int64_t>(B * M, B);
+  const int64_t n = std::max<int64_t>(B * M * NI, B);
   prof_begin("k_prep", s);
   hipLaunchKernelGGL(k_prep, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0, s, B, M, sigma, omega0,
                      quality, jitter, pl->tc.as<TermConst>(), pl->coef.as<double>(), pl->jit.as<double>());

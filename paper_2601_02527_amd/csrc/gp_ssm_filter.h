@@ -821,22 +821,24 @@ struct DiscGrad {
   GPD static bool series(double x, const TermConst& t) { return x <= t.xser_g; }
 };
 
-// discretisation of all terms over one step (values only)
-template <int M, class Acc = DiscFull>
+// discretisation of all terms over one step (values only); the tables of
+// term t start at coef + t * TS
+template <int M, class Acc = DiscFull, int TS = NCOEF>
 GPD void discretise(const TermConst* tc, const double* coef, double dt, TermQ* tq) {
 #pragma unroll
   for (int t = 0; t < M; ++t) {
     const double x = tc[t].w0 * dt;
     Base<double> b;
     if (Acc::series(x, tc[t]))
-      series_eval<Acc::K>(coef + t * 2 * NCOEF, x, b);
+      series_eval<Acc::K>(coef + t * TS, x, tc[t], b);
     else
       closed_eval(x, tc[t], b);
     tq[t] = term_step(tc[t], b);
   }
 }
 
-// with the beta-derivatives of the base functions (db[t*6 + f])
+// with the beta-derivatives of the base functions (db[t*6 + f]); the tables
+// of term t (values, then beta-derivatives) start at coef + t * 2 NCOEF
 template <int M, class Acc = DiscFull>
 GPD void discretise_dual(const TermConst* tc, const double* coef, double dt, double* db, TermQ* tq) {
 #pragma unroll
@@ -844,7 +846,7 @@ GPD void discretise_dual(const TermConst* tc, const double* coef, double dt, dou
     const double x = tc[t].w0 * dt;
     Base<Dual> bd;
     if (Acc::series(x, tc[t]))
-      series_eval<Acc::K>(coef + t * 2 * NCOEF, x, bd);
+      series_eval<Acc::K>(coef + t * 2 * NCOEF, x, tc[t], bd);
     else
       closed_eval(x, tc[t], bd);
     Base<double> b;

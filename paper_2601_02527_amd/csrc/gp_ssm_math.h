@@ -43,13 +43,19 @@
 
 namespace gpssm {
 
-constexpr int KSER = 25;          // highest power kept in the series of G1 and of the integrals
 constexpr double XSER = 0.75;     // series used when x * max(1, beta) <= XSER
-constexpr int KSER_G = 17;        // gradient-only passes: degree and switch point
+constexpr int NI = 4;             // series intervals on [0, xser]: [0, F0 xser], then NI - 1 equal ones
+constexpr double F0 = 0.16;
+constexpr int KSER = 15;          // highest power kept in each interval's expansion
+constexpr int KSER_G = 12;        // gradient-only passes: degree and switch point
 constexpr double XSER_G = 0.4;
 constexpr int NSET = 4;           // coefficient sets: G1, int g^2, int g'^2, int G1^2
-constexpr int NS = KSER + 1;      // coefficients per set (x^0 .. x^KSER)
-constexpr int NCOEF = NSET * NS;  // per term; the beta-derivatives follow
+constexpr int NS = KSER + 1;      // coefficients per set (u^0 .. u^KSER)
+// doubles per interval table: the coefficients, padded by 32 bytes so that
+// the tables of the NI intervals start on different LDS banks (lanes in
+// different intervals read them in the same instruction)
+constexpr int ISTRIDE = NS * NSET + 4;
+constexpr int NCOEF = NI * ISTRIDE;  // value tables of one term; the beta-derivatives follow
 constexpr double LOG_2PI = 1.8378770664093454835606594728112;
 
 // ---------------------------------------------------------------------------
@@ -121,57 +127,98 @@ struct Base {
 // ---------------------------------------------------------------------------
 // Taylor coefficients (value and beta-derivative) of the base functions
 // ---------------------------------------------------------------------------
-// v' = B v for v = (g, g', G1, g^2, gg', g'^2, G1^2, G1g, G1g', Igg, Ipp, IGG).
-// Kept: coef[n * NSET + s] for the sets s = G1, Igg, Ipp, IGG (degree-major,
-// so one Horner step reads all four sets at once).  g = G1' and g' = G1''
-// come out of the same Horner pass as G1.
-GPD void series_coefficients(double beta, double* coef, double* dcoef) {
-  double c[12], d[12];
+// v' = B v for v = (g, g', G1, g^2, gg', g'^2, G1^2, G1g, G1g', Igg, Ipp, IGG)
+// is linear, so the Taylor coefficients about any point xc follow
+// c_{n+1} = B c_n / (n + 1) from c_0 = v(xc), and their beta-derivatives (at
+// fixed xc) follow d_{n+1} = (B d_n + (dB/dbeta) c_n) / (n + 1).
+GPD void ode_step(double beta, int n, double* c, double* d) {
+  const double b2 = 2.0 * beta, b4 = 4.0 * beta;
+  double nc[12], nd[12];
+  nc[0] = c[1];
+  nc[1] = -c[0] - b2 * c[1];
+  nc[2] = c[0];
+  nc[3] = 2.0 * c[4];
+  nc[4] = c[5] - c[3] - b2 * c[4];
+  nc[5] = -2.0 * c[4] - b4 * c[5];
+  nc[6] = 2.0 * c[7];
+  nc[7] = c[3] + c[8];
+  nc[8] = c[4] - c[7] - b2 * c[8];
+  nc[9] = c[3];
+  nc[10] = c[5];
+  nc[11] = c[6];
+  nd[0] = d[1];
+  nd[1] = -d[0] - b2 * d[1] - 2.0 * c[1];
+  nd[2] = d[0];
+  nd[3] = 2.0 * d[4];
+  nd[4] = d[5] - d[3] - b2 * d[4] - 2.0 * c[4];
+  nd[5] = -2.0 * d[4] - b4 * d[5] - 4.0 * c[5];
+  nd[6] = 2.0 * d[7];
+  nd[7] = d[3] + d[8];
+  nd[8] = d[4] - d[7] - b2 * d[8] - 2.0 * c[8];
+  nd[9] = d[3];
+  nd[10] = d[5];
+  nd[11] = d[6];
+  const double inv = 1.0 / (n + 1);
+#pragma unroll
   for (int i = 0; i < 12; ++i) {
-    c[i] = 0.0;
-    d[i] = 0.0;
+    c[i] = nc[i] * inv;
+    d[i] = nd[i] * inv;
   }
+}
+
+// expansion point of series interval i: 0 for the first interval [0, b1],
+// whose expansion about 0 keeps the relative accuracy of the functions that
+// vanish there (int G1^2 ~ x^5/20), the midpoint of the others (width w)
+GPD double interval_centre(int i, double b1, double w) { return i == 0 ? 0.0 : b1 + (i - 0.5) * w; }
+
+// The tables of one term: coef[i * ISTRIDE + n * NSET + s], the coefficient
+// of u^n (u = x - xc_i) of set s = G1, Igg, Ipp, IGG in interval i (degree-
+// major, so one Horner step reads all four sets at once); dcoef likewise for
+// the beta-derivatives.  g = G1' and g' = G1'' come out of the same Horner
+// pass as G1.  The state at an interval centre xc > 0 is the series about 0
+// summed to degree KSUM (terms below 1e-30 there).
+//
+// One interval's table (coef, dcoef point at interval i's slots):
+GPD void series_interval_table(double beta, double xc, double* coef, double* dcoef) {
+  constexpr int KSUM = 44;
+  double c[12], d[12], v[12], dv[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) c[k] = d[k] = v[k] = dv[k] = 0.0;
   c[1] = 1.0;  // g'(0)
   c[5] = 1.0;  // g'(0)^2
-  const int out[NSET] = {2, 9, 10, 11};
-  for (int n = 0; n <= KSER; ++n) {
-    for (int f = 0; f < NSET; ++f) {
-      coef[n * NSET + f] = c[out[f]];
-      dcoef[n * NSET + f] = d[out[f]];
-    }
-    const double b2 = 2.0 * beta, b4 = 4.0 * beta;
-    double nc[12], nd[12];
-    nc[0] = c[1];
-    nc[1] = -c[0] - b2 * c[1];
-    nc[2] = c[0];
-    nc[3] = 2.0 * c[4];
-    nc[4] = c[5] - c[3] - b2 * c[4];
-    nc[5] = -2.0 * c[4] - b4 * c[5];
-    nc[6] = 2.0 * c[7];
-    nc[7] = c[3] + c[8];
-    nc[8] = c[4] - c[7] - b2 * c[8];
-    nc[9] = c[3];
-    nc[10] = c[5];
-    nc[11] = c[6];
-    // derivative of the recurrence with respect to beta
-    nd[0] = d[1];
-    nd[1] = -d[0] - b2 * d[1] - 2.0 * c[1];
-    nd[2] = d[0];
-    nd[3] = 2.0 * d[4];
-    nd[4] = d[5] - d[3] - b2 * d[4] - 2.0 * c[4];
-    nd[5] = -2.0 * d[4] - b4 * d[5] - 4.0 * c[5];
-    nd[6] = 2.0 * d[7];
-    nd[7] = d[3] + d[8];
-    nd[8] = d[4] - d[7] - b2 * d[8] - 2.0 * c[8];
-    nd[9] = d[3];
-    nd[10] = d[5];
-    nd[11] = d[6];
-    const double inv = 1.0 / (n + 1);
-    for (int i = 0; i < 12; ++i) {
-      c[i] = nc[i] * inv;
-      d[i] = nd[i] * inv;
+  if (xc == 0.0) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = c[k];
+  } else {
+    double pw = 1.0;
+#pragma unroll
+    for (int n = 0; n <= KSUM; ++n) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        v[k] = fma(c[k], pw, v[k]);
+        dv[k] = fma(d[k], pw, dv[k]);
+      }
+      pw *= xc;
+      ode_step(beta, n, c, d);
     }
   }
+  const int out[NSET] = {2, 9, 10, 11};
+#pragma unroll
+  for (int n = 0; n <= KSER; ++n) {
+#pragma unroll
+    for (int f = 0; f < NSET; ++f) {
+      coef[n * NSET + f] = v[out[f]];
+      dcoef[n * NSET + f] = dv[out[f]];
+    }
+    ode_step(beta, n, v, dv);
+  }
+#pragma unroll
+  for (int k = NS * NSET; k < ISTRIDE; ++k) coef[k] = dcoef[k] = 0.0;
+}
+// all intervals of one term
+GPD void series_coefficients(double beta, double b1, double w, double* coef, double* dcoef) {
+  for (int i = 0; i < NI; ++i)
+    series_interval_table(beta, interval_centre(i, b1, w), coef + i * ISTRIDE, dcoef + i * ISTRIDE);
 }
 
 // The kernels stage a series' tables in LDS once; every lane then reads the
@@ -187,7 +234,7 @@ GPD void table_fence() {
 #endif
 }
 
-// Horner evaluation of the four series at x, all sets in one pass:
+// Horner evaluation of the four series at u, all sets in one pass:
 // G1 with G1' = g and G1''/2, and the three integrals
 struct Series4 {
   double G1, g, gph, Igg, Ipp, IGG;
@@ -215,30 +262,15 @@ GPD Series4 horner4(coef_ptr e, double x) {
   return r;
 }
 
-// the series at x truncated after degree K (coef: the term's table, value
-// part then beta-derivative)
-template <int K = KSER>
-GPD void series_eval(const double* coef, double x, Base<double>& o) {
-  table_fence();
-  const Series4 v = horner4<K>(coef, x);
-  o.G1 = v.G1;
-  o.g = v.g;
-  o.gp = 2.0 * v.gph;
-  o.Igg = v.Igg;
-  o.Ipp = v.Ipp;
-  o.IGG = v.IGG;
-}
-template <int K = KSER>
-GPD void series_eval(const double* coef, double x, Base<Dual>& o) {
-  table_fence();
-  const Series4 v = horner4<K>(coef, x);
-  const Series4 d = horner4<K>(coef + NCOEF, x);
-  o.G1 = {v.G1, d.G1};
-  o.g = {v.g, d.g};
-  o.gp = {2.0 * v.gph, 2.0 * d.gph};
-  o.Igg = {v.Igg, d.Igg};
-  o.Ipp = {v.Ipp, d.Ipp};
-  o.IGG = {v.IGG, d.IGG};
+// interval of x (first interval [0, b1], then width w, 1/w = iw) and the
+// offset from its expansion point; the index stays in [0, NI) whatever x is
+GPD int series_interval(double x, double b1, double w, double iw, double& u) {
+  const double q = (x - b1) * iw;
+  int i = (x >= b1) ? 1 : 0;
+#pragma unroll
+  for (int k = 1; k < NI - 1; ++k) i += (q >= (double)k) ? 1 : 0;
+  u = x - interval_centre(i, b1, w);
+  return i;
 }
 
 // ---------------------------------------------------------------------------
@@ -253,6 +285,9 @@ struct TermConst {
   double xser;     // the series is used for omega0 dt <= xser
   double inv_qhat; // 1/qhat
   double xser_g;   // switch point of the gradient-only passes
+  double b1ser;    // end of the first series interval, F0 xser
+  double wser;     // width of the other series intervals, (xser - b1ser) / (NI - 1)
+  double inv_wser; // 1 / wser
 };
 
 GPD TermConst make_term(double sigma, double w0, double quality) {
@@ -269,7 +304,40 @@ GPD TermConst make_term(double sigma, double w0, double quality) {
   t.xser = XSER / fmax(1.0, t.beta);
   t.inv_qhat = 1.0 / t.qhat;
   t.xser_g = XSER_G / fmax(1.0, t.beta);
+  t.b1ser = F0 * t.xser;
+  t.wser = (t.xser - t.b1ser) / (NI - 1);
+  t.inv_wser = 1.0 / t.wser;
   return t;
+}
+
+// the series at x truncated after degree K (coef: the term's tables, value
+// part then beta-derivative)
+template <int K = KSER>
+GPD void series_eval(const double* coef, double x, const TermConst& t, Base<double>& o) {
+  table_fence();
+  double u;
+  const int i = series_interval(x, t.b1ser, t.wser, t.inv_wser, u);
+  const Series4 v = horner4<K>(coef + i * ISTRIDE, u);
+  o.G1 = v.G1;
+  o.g = v.g;
+  o.gp = 2.0 * v.gph;
+  o.Igg = v.Igg;
+  o.Ipp = v.Ipp;
+  o.IGG = v.IGG;
+}
+template <int K = KSER>
+GPD void series_eval(const double* coef, double x, const TermConst& t, Base<Dual>& o) {
+  table_fence();
+  double u;
+  const int i = series_interval(x, t.b1ser, t.wser, t.inv_wser, u);
+  const Series4 v = horner4<K>(coef + i * ISTRIDE, u);
+  const Series4 d = horner4<K>(coef + NCOEF + i * ISTRIDE, u);
+  o.G1 = {v.G1, d.G1};
+  o.g = {v.g, d.g};
+  o.gp = {2.0 * v.gph, 2.0 * d.gph};
+  o.Igg = {v.Igg, d.Igg};
+  o.Ipp = {v.Ipp, d.Ipp};
+  o.IGG = {v.IGG, d.IGG};
 }
 
 // cos(u) - sin(u)/u and its hyperbolic counterpart cosh(u) - sinh(u)/u
@@ -423,7 +491,6 @@ struct TermQ {
   double zz;             // integrator/integrator noise
 };
 
-GPD bool use_series(double x, const TermConst& t) { return x <= t.xser; }
 
 GPD TermQ term_step(const TermConst& t, const Base<double>& b) {
   TermQ q;

@@ -35,12 +35,17 @@ __device__ __forceinline__ Obs load_event(const DevPlan& p, int64_t e, double ji
   return make_obs<Dm>(info, p.y[e], p.r[e], p.invd[e], jit2);
 }
 
-// the series' Taylor tables (value and beta-derivative, all terms), staged in
-// LDS by the workgroup's single wavefront
-template <class Dm>
+// the series' Taylor tables of all terms, staged in LDS by the workgroup's
+// single wavefront: the value tables only (term stride NCOEF), or with DUAL
+// the values followed by the beta-derivatives (term stride 2 NCOEF)
+template <class Dm, bool DUAL>
 __device__ __forceinline__ const double* stage_coef(const DevParams& pr, int64_t b, double* lds) {
   const double* g = pr.coef + b * Dm::M * 2 * NCOEF;
-  for (int i = threadIdx.x; i < Dm::M * 2 * NCOEF; i += WAVE) lds[i] = g[i];
+  constexpr int TS = DUAL ? 2 * NCOEF : NCOEF;
+  for (int i = threadIdx.x; i < Dm::M * TS; i += WAVE) {
+    const int t = i / TS, j = i - t * TS;
+    lds[i] = g[t * 2 * NCOEF + j];
+  }
   __syncthreads();
   return lds;
 }
@@ -102,12 +107,12 @@ __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, dou
   const int64_t ev0 = p.seg_ev0[seg];
   TermConst tc[M];
   load_terms<Dm>(pr, b, tc);
-  __shared__ double lcoef[M * 2 * NCOEF];
-  const double* coef = stage_coef<Dm>(pr, b, lcoef);
+  __shared__ double lcoef[M * NCOEF];
+  const double* coef = stage_coef<Dm, false>(pr, b, lcoef);
   const double jit = pr.jit[b];
   const double jit2 = jit * jit;
   // the sensitivity block in LDS when four workgroups still fit in a CU
-  constexpr bool USE_LDS = 8 * (M * 2 * NCOEF + Dm::D * NX * WAVE) <= 40960;
+  constexpr bool USE_LDS = 8 * (M * NCOEF + Dm::D * NX * WAVE) <= 40960;
   __shared__ double lS[USE_LDS ? Dm::D * NX * WAVE : 1];
   CondState<Dm, USE_LDS> st;
   st.Sl = LaneLds{lS + lane};
@@ -164,7 +169,7 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
   TermConst tc[M];
   load_terms<Dm>(pr, b, tc);
   __shared__ double lcoef[M * 2 * NCOEF];
-  const double* coef = stage_coef<Dm>(pr, b, lcoef);
+  const double* coef = stage_coef<Dm, true>(pr, b, lcoef);
   const double jit = pr.jit[b];
   const double jit2 = jit * jit;
   double* rb = rec + ev0 * F;
@@ -187,7 +192,7 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
     for (int f = 0; f < NP; ++f) rb[((int64_t)k * F + D + f) * WAVE + lane] = P[f];
     const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2);
     TermQ tq[M];
-    discretise<M, DiscGrad>(tc, coef, cur.dt, tq);
+    discretise<M, DiscGrad, 2 * NCOEF>(tc, coef, cur.dt, tq);
     plain_step<Dm, false>(m, P, tq, cur.info, o);
   }
 
@@ -243,8 +248,8 @@ template <int J>
 __global__ __launch_bounds__(WAVE) void k_plain(DevPlan p, DevParams pr, int64_t b, double* __restrict__ loglik) {
   using Dm = Dims<M, J>;
   constexpr int D = Dm::D, NP = Dm::NP;
-  __shared__ double lcoef[M * 2 * NCOEF];
-  const double* coef = stage_coef<Dm>(pr, b, lcoef);
+  __shared__ double lcoef[M * NCOEF];
+  const double* coef = stage_coef<Dm, false>(pr, b, lcoef);
   if (threadIdx.x != 0) return;
   TermConst tc[M];
   load_terms<Dm>(pr, b, tc);
@@ -347,8 +352,8 @@ __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const 
   const int32_t len = active ? p.chunk_len[c] : 0;
   TermConst tc[M];
   load_terms<Dm>(pr, b, tc);
-  __shared__ double lcoef[M * 2 * NCOEF];
-  const double* coef = stage_coef<Dm>(pr, b, lcoef);
+  __shared__ double lcoef[M * NCOEF];
+  const double* coef = stage_coef<Dm, false>(pr, b, lcoef);
   const double jit = pr.jit[b];
   const double jit2 = jit * jit;
   double* rb = rec + ev0 * F;
