@@ -202,6 +202,20 @@ struct gp_ssm_plan {
   DBuf tc, coef, jit, summ, bstate, badj, bsmooth, gpart, rec, status;
   DBuf pre, suf, segtot, segstate, segfut, segll, segok;
   DBuf tests_t, tests_idx, tests_c0, tests_before;
+  // launch order of the per-segment kernels (most expensive segment first):
+  // written on the host into pinned memory, copied on the call's stream;
+  // order_ev marks the copy so the buffer is not rewritten before it is done
+  DBuf seg_order;
+  int32_t* order_host = nullptr;
+  hipEvent_t order_ev = nullptr;
+
+  ~gp_ssm_plan() {
+    if (order_ev) {
+      (void)hipEventSynchronize(order_ev);
+      (void)hipEventDestroy(order_ev);
+    }
+    if (order_host) (void)hipHostFree(order_host);
+  }
 
   DevPlan dev() const {
     DevPlan p;
@@ -225,6 +239,7 @@ struct gp_ssm_plan {
     p.series_nch = series_nch.as<int32_t>();
     p.series_seg0 = series_seg0.as<int32_t>();
     p.series_nseg = series_nseg.as<int32_t>();
+    p.seg_order = seg_order.as<int32_t>();
     p.n_series = host.n_series;
     p.n_chunks = host.n_chunks;
     p.n_seg = host.n_seg;
@@ -244,6 +259,57 @@ int check_device() {
 }
 
 // validates hyperparameters (host copies) and prepares them on the device
+// Launch order of the per-segment kernels.  Two or so wavefronts share each
+// SIMD over a launch, and a segment's cost varies with its series' terms: a
+// wavefront pays for the Taylor branch of a term at a step when any of its
+// lanes needs it, and for the closed-form branch when any lane needs that.
+// With p the fraction of the series' steps below the switch point, the
+// expected cost per step and term is C_SER (1 - (1-p)^64) + C_CLO (1 - p^64)
+// on top of W0 for the filter step; p comes from the series' step-length
+// distribution.  Dispatching the costliest segments first (longest
+// processing time first) evens out the SIMDs' loads.
+int set_launch_order(gp_ssm_plan* pl, int32_t M, const double* omega0, const double* quality, hipStream_t s) {
+  constexpr double W0 = 4.0, C_SER = 1.0, C_CLO = 1.5;
+  const HostPlan& h = pl->host;
+  const int64_t S = h.n_seg;
+  if (S == 0) return 0;
+  if (!pl->order_host) {
+    HIP_TRY(hipHostMalloc((void**)&pl->order_host, sizeof(int32_t) * S, hipHostMallocDefault));
+    HIP_TRY(hipEventCreateWithFlags(&pl->order_ev, hipEventDisableTiming));
+    if (int rc = pl->seg_order.ensure(sizeof(int32_t) * S)) return rc;
+  } else {
+    HIP_TRY(hipEventSynchronize(pl->order_ev));
+  }
+  std::vector<double> term_cost(h.n_series);
+  for (int64_t b = 0; b < h.n_series; ++b) {
+    const float* cdf = h.series_dt_cdf.data() + b * DT_NE;
+    double c = W0;
+    for (int t = 0; t < M; ++t) {
+      const double w0 = omega0[b * M + t], beta = 0.5 / quality[b * M + t];
+      const double thr = XSER / std::max(1.0, beta) / w0;  // steps with dt <= thr take the series
+      int ex;
+      const double fr = std::frexp(thr, &ex);  // thr = fr 2^ex, fr in [0.5, 1)
+      const int k = ex - DT_KMIN;
+      double p;
+      if (k <= 0)
+        p = cdf[0];
+      else if (k >= DT_NE)
+        p = 1.0;
+      else  // linear in log2(dt) between the edges 2^(ex-1) and 2^ex
+        p = cdf[k - 1] + (cdf[k] - cdf[k - 1]) * (std::log2(fr) + 1.0);
+      c += C_SER * (1.0 - std::pow(1.0 - p, WAVE)) + C_CLO * (1.0 - std::pow(p, WAVE));
+    }
+    term_cost[b] = c;
+  }
+  std::vector<std::pair<double, int32_t>> key(S);
+  for (int64_t q = 0; q < S; ++q) key[q] = {-(double)h.seg_len[q] * term_cost[h.seg_series[q]], (int32_t)q};
+  std::sort(key.begin(), key.end());
+  for (int64_t q = 0; q < S; ++q) pl->order_host[q] = key[q].second;
+  HIP_TRY(hipMemcpyAsync(pl->seg_order.p, pl->order_host, sizeof(int32_t) * S, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(pl->order_ev, s));
+  return 0;
+}
+
 int prepare_params(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0, const double* quality,
                    const double* jitter, hipStream_t s, DevParams& pr) {
   if (!pl) return fail(GP_SSM_EINVAL, "null plan");
@@ -264,6 +330,7 @@ int prepare_params(gp_ssm_plan* pl, int32_t M, const double* sigma, const double
     for (int64_t b = 0; b < B; ++b)
       if (!(h[3 * B * M + b] >= 0) || !std::isfinite(h[3 * B * M + b]))
         return fail(GP_SSM_EPARAM, "jitter must be >= 0 and finite (series " + std::to_string(b) + ")");
+  if (int rc = set_launch_order(pl, M, h.data() + B * M, h.data() + 2 * B * M, s)) return rc;
   if (int rc = pl->tc.ensure(sizeof(TermConst) * B * M)) return rc;
   if (int rc = pl->coef.ensure(sizeof(double) * B * M * 2 * NCOEF)) return rc;
   if (int rc = pl->jit.ensure(sizeof(double) * B)) return rc;

@@ -17,6 +17,7 @@ struct DevPlan {
   const int32_t *chunk_len, *chunk_series, *chunk_seg;
   const uint8_t* chunk_first;
   const int32_t *series_chunk0, *series_nch, *series_seg0, *series_nseg;
+  const int32_t* seg_order;  // launch order of the per-segment kernels (null: natural order)
   int64_t n_series;
   int32_t n_chunks, n_seg;
 };

@@ -100,7 +100,7 @@ template <int J>
 __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, double* __restrict__ summ) {
   using Dm = Dims<M, J>;
   constexpr int NX = Dm::NX, NXP = Dm::NXP;
-  const int seg = blockIdx.x;
+  const int seg = p.seg_order ? p.seg_order[blockIdx.x] : (int)blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t b = p.seg_series[seg];
   const int32_t nch = p.seg_nch[seg], L = p.seg_len[seg];
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
   using Dm = Dims<M, J>;
   constexpr int NX = Dm::NX, D = Dm::D, NP = Dm::NP, NXP = Dm::NXP;
   constexpr int F = rec_fields<Dm>();
-  const int seg = blockIdx.x;
+  const int seg = p.seg_order ? p.seg_order[blockIdx.x] : (int)blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t b = p.seg_series[seg];
   const int32_t nch = p.seg_nch[seg], L = p.seg_len[seg];
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const 
   using Dm = Dims<M, J>;
   constexpr int NX = Dm::NX, D = Dm::D, NP = Dm::NP;
   constexpr int F = rec_fields<Dm>();
-  const int seg = blockIdx.x;
+  const int seg = p.seg_order ? p.seg_order[blockIdx.x] : (int)blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t b = p.seg_series[seg];
   const int32_t nch = p.seg_nch[seg], L = p.seg_len[seg];

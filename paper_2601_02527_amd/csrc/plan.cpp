@@ -44,6 +44,7 @@ struct SeriesWork {
   std::vector<Ev> ev;
   std::vector<uint32_t> open_before;
   std::vector<int64_t> cuts;  // chunk end positions (exclusive)
+  float dt_cdf[DT_NE] = {};   // see HostPlan::series_dt_cdf
 };
 
 int plan_series(int64_t b, int64_t lo, int64_t hi, const double* ts, const double* te, const double* yerr, int64_t Lb,
@@ -124,6 +125,23 @@ int plan_series(int64_t b, int64_t lo, int64_t hi, const double* ts, const doubl
       start = k + 1;
     }
   }
+  // step-length histogram in powers of two, then its cumulative fractions
+  int64_t cnt[DT_NE] = {};
+  for (int64_t k = 1; k < ne; ++k) {
+    const double d = w.ev[k].t - w.ev[k - 1].t;
+    int bin = 0;
+    if (d > 0.0) {
+      int ex;
+      std::frexp(d, &ex);  // d in [2^(ex-1), 2^ex)
+      bin = std::min(DT_NE - 1, std::max(0, ex - DT_KMIN));
+    }
+    ++cnt[bin];
+  }
+  int64_t acc = 0;
+  for (int k = 0; k < DT_NE; ++k) {
+    acc += cnt[k];
+    w.dt_cdf[k] = ne > 1 ? (float)((double)acc / (double)(ne - 1)) : 1.0f;
+  }
   return 0;
 }
 
@@ -198,6 +216,7 @@ int build_plan(int64_t n_series, const int64_t* offsets, const double* t_start, 
     P.max_slots = std::max(P.max_slots, w.slots);
     P.series_slots[b] = w.slots;
     P.series_nev[b] = (int64_t)w.ev.size();
+    P.series_dt_cdf.insert(P.series_dt_cdf.end(), w.dt_cdf, w.dt_cdf + DT_NE);
     P.n_events += (int64_t)w.ev.size();
     P.series_chunk0[b] = P.n_chunks;
     int64_t prev = 0;

@@ -12,6 +12,11 @@ constexpr int WAVE = 64;        // lanes per wavefront; chunks per segment
 constexpr int MAX_TERMS = 4;
 constexpr int MAX_SLOTS = 4;
 
+// step-length distribution kept per series for the launch-order cost model:
+// the fraction of the series' steps with dt <= 2^(DT_KMIN + k), k < DT_NE
+constexpr int DT_KMIN = -30;
+constexpr int DT_NE = 48;
+
 struct PlanOptions {
   int32_t chunk_min = 24;          // shortest chunk the planner makes (events)
   int32_t chunk_target = 0;        // target chunk length; 0 = derive from the batch size
@@ -39,6 +44,7 @@ struct HostPlan {
   std::vector<double> chunk_t0, chunk_t1;  // time of the first / last event of each chunk
   std::vector<int32_t> series_chunk0, series_nch, series_slots, series_seg0, series_nseg;
   std::vector<int64_t> series_nev;
+  std::vector<float> series_dt_cdf;  // n_series * DT_NE, see DT_KMIN
 };
 
 // Builds the plan from host copies of the inputs.  Returns 0 or a negative
