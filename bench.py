@@ -95,6 +95,109 @@ def measured_traffic(kernel, workload):
         return None
 
 
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def run_legs(gp, steps=3, warmup=1):
+    """The other configurations of the hot path, each on one GPU:
+    C3 (4096 series of 1e3..5e4 exposures, M = 2: batched launch),
+    C5 (one series of 1e7 exposures, M = 3, J = 4: time-parallel scan) with the
+    plain one-lane filter's rate projected to that length, and C2 (one series
+    of 1e5 exposures, M = 2, 1e4 test times: smoother and prediction)."""
+    import torch
+    legs = {}
+    dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda")
+
+    def prof_run(fn):
+        gp.profile_enable(True)
+        gp.profile_reset()
+        fn()
+        torch.cuda.synchronize()
+        p = gp.profile_read()
+        gp.profile_enable(False)
+        return {k: round(v[1] / max(1, v[0]), 4) for k, v in p.items()}
+
+    # C3
+    t0 = time.perf_counter()
+    b = W.batch_4096()
+    gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan = gp.Plan(b.offsets, b.t_start, b.t_end, b.y, b.yerr)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    a = (dev(b.sigma), dev(b.omega0), dev(b.quality), dev(b.jitter))
+    pts = int(b.offsets[-1])
+    tg = _timed(lambda: plan.loglik_grad(*a), steps, warmup)
+    tl = _timed(lambda: plan.loglik(*a), steps, warmup)
+    ll, _ = plan.loglik_grad(*a)
+    legs["C3_batch_4096"] = {
+        "series": b.n_series, "points": pts, "terms": b.n_terms, "slots": plan.stats()["max_slots"],
+        "loglik_grad_ms": tg * 1e3, "loglik_grad_points_per_s": pts / tg,
+        "loglik_ms": tl * 1e3, "loglik_points_per_s": pts / tl, "nan_series": int(torch.isnan(ll).sum().item()),
+        "kernels_ms": prof_run(lambda: plan.loglik_grad(*a)), "plan_s": tp, "generate_s": gen}
+    print(f"[bench] C3 {legs['C3_batch_4096']}", file=sys.stderr, flush=True)
+    del plan, b, a
+    torch.cuda.empty_cache()
+
+    # C2: smoother first (its plain-filter rate also projects C5)
+    b = W.long_100k()
+    plan = gp.Plan(b.offsets, b.t_start, b.t_end, b.y, b.yerr)
+    a = (dev(b.sigma), dev(b.omega0), dev(b.quality), dev(b.jitter))
+    to, tt = dev(b.test_offsets).long(), dev(b.t_test)
+    ts = _timed(lambda: plan.smooth(*a, to, tt), steps, warmup)
+    tl = _timed(lambda: plan.loglik(*a), steps, warmup)
+    tplain = _timed(lambda: plan.plain_loglik(*a, first=0, count=1), 1, 1)
+    out = plan.smooth(*a, to, tt)
+    legs["C2_long_100k_smooth"] = {
+        "points": int(b.offsets[-1]), "test_times": int(len(b.t_test)), "terms": b.n_terms,
+        "slots": plan.stats()["max_slots"], "smooth_ms": ts * 1e3, "loglik_ms": tl * 1e3,
+        "plain_gpu_filter_ms": tplain * 1e3,
+        "finite": bool(torch.isfinite(out["mean_test"]).all().item() and torch.isfinite(out["var_test"]).all().item()),
+        "kernels_ms": prof_run(lambda: plan.smooth(*a, to, tt))}
+    print(f"[bench] C2 {legs['C2_long_100k_smooth']}", file=sys.stderr, flush=True)
+    del plan, b, a
+    torch.cuda.empty_cache()
+
+    # C5
+    t0 = time.perf_counter()
+    b = W.long_1e7()
+    gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan = gp.Plan(b.offsets, b.t_start, b.t_end, b.y, b.yerr)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    a = (dev(b.sigma), dev(b.omega0), dev(b.quality), dev(b.jitter))
+    pts = int(b.offsets[-1])
+    tl = _timed(lambda: plan.loglik(*a), steps, warmup)
+    tg = _timed(lambda: plan.loglik_grad(*a), steps, warmup)
+    ll, _ = plan.loglik_grad(*a)
+    # the plain filter on the first 1e5 exposures of the same series (a sub-plan), projected to 1e7
+    nsub = 100_000
+    sub = gp.Plan(np.array([0, nsub], dtype=np.int64), b.t_start[:nsub], b.t_end[:nsub], b.y[:nsub], b.yerr[:nsub])
+    tsub = _timed(lambda: sub.plain_loglik(*a, first=0, count=1), 1, 1)
+    proj = tsub * pts / nsub
+    st = plan.stats()
+    legs["C5_long_1e7"] = {
+        "points": pts, "terms": b.n_terms, "slots": st["max_slots"], "chunks": st["n_chunks"],
+        "segments": st["n_segments"], "loglik_ms": tl * 1e3, "loglik_grad_ms": tg * 1e3,
+        "plain_gpu_filter_projected_ms": proj * 1e3, "plain_gpu_filter_measured": f"{nsub} exposures in {tsub * 1e3:.1f} ms",
+        "scan_speedup_vs_plain": proj / tl, "loglik_finite": bool(torch.isfinite(ll).all().item()),
+        "kernels_ms": prof_run(lambda: plan.loglik_grad(*a)), "plan_s": tp, "generate_s": gen}
+    print(f"[bench] C5 {legs['C5_long_1e7']}", file=sys.stderr, flush=True)
+    del plan, sub, b, a
+    torch.cuda.empty_cache()
+    return legs
+
+
 def cpu_oracle_baseline(batch, n_series, threads):
     """Oracle log-likelihood + central-difference gradient (21 evaluations for
     10 parameters) of the first n_series series, one series per thread."""
@@ -124,6 +227,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0, help="series for the CPU oracle (0 = one per core)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-legs", action="store_true", help="skip the C2, C3 and C5 configurations")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 1 GiB (10 times), to scale HBM byte counters")
     args = ap.parse_args()
@@ -256,6 +360,10 @@ def main():
                          f"one series per thread, {secs:.1f}s"}
         print(f"[bench] cpu {cpu}", file=sys.stderr, flush=True)
 
+    legs = None
+    if not args.no_legs:
+        legs = run_legs(gp)
+
     out = {
         "metric": "series-points/sec for loglik+grad at 1e-9 rel err; batched vs plain GPU filter",
         "value": value,
@@ -282,6 +390,7 @@ def main():
         "step_roofline": step_roof,
         "algorithmic_flops_per_point": {"fwd": fwd_pt, "fwd_grad": grad_pt},
         "nan_series": bad,
+        "legs": legs,
     }
     print(json.dumps(out))
 

@@ -95,18 +95,21 @@ __global__ void k_prep(int64_t B, int M, const double* __restrict__ sigma, const
   if (j < B) jit[j] = jitter ? jitter[j] : 0.0;
 }
 
-__global__ void k_reduce_grad(DevPlan p, int M, const double* __restrict__ gpart, const int32_t* __restrict__ status,
-                              double* __restrict__ grad) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= p.n_series) return;
+// gradient partials of a series' segments summed: one wavefront per series,
+// lane l takes segments l, l + 64, ..., then a fixed-order wave reduction
+__global__ __launch_bounds__(WAVE) void k_reduce_grad(DevPlan p, int M, const double* __restrict__ gpart,
+                                                      const int32_t* __restrict__ status, double* __restrict__ grad) {
+  const int64_t b = blockIdx.x;
+  const int lane = threadIdx.x;
   const int64_t S = p.n_seg;
   const int32_t s0 = p.series_seg0[b], n = p.series_nseg[b];
   const int G = 3 * M + 1;
   const bool good = status == nullptr || status[b] == 0;
   for (int f = 0; f < G; ++f) {
     double s = 0.0;
-    for (int32_t q = 0; q < n; ++q) s += gpart[(int64_t)f * S + s0 + q];
-    grad[b * G + f] = (good && isfinite(s)) ? s : __builtin_nan("");
+    for (int32_t q = lane; q < n; q += WAVE) s += gpart[(int64_t)f * S + s0 + q];
+    s = wave_sum(s);
+    if (lane == 0) grad[b * G + f] = (good && isfinite(s)) ? s : __builtin_nan("");
   }
 }
 
@@ -519,7 +522,7 @@ int gp_ssm_plan_loglik_grad(gp_ssm_plan* pl, int32_t M, const double* sigma, con
   ks.adjoint(L, p, pr, pl->bstate.as<double>(), pl->badj.as<double>(), pl->rec.as<double>(), pl->gpart.as<double>());
   HIP_TRY(hipGetLastError());
   prof_begin("k_reduce_grad", s);
-  hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, s, p, M, pl->gpart.as<double>(), st,
+  hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)B), dim3(WAVE), 0, s, p, M, pl->gpart.as<double>(), st,
                      grad);
   prof_end("k_reduce_grad", s);
   HIP_TRY(hipGetLastError());

@@ -278,20 +278,26 @@ __global__ __launch_bounds__(WAVE) void k_seg_fix(DevPlan p, const double* __res
   }
 }
 
-__global__ void k_series_finish(DevPlan p, const double* __restrict__ segll, const int32_t* __restrict__ segok,
-                                double* __restrict__ loglik, int32_t* __restrict__ status) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= p.n_series) return;
+// one wavefront per series: lane l sums segments l, l + 64, ..., then a
+// fixed-order wave reduction (the same result on every run)
+__global__ __launch_bounds__(WAVE) void k_series_finish(DevPlan p, const double* __restrict__ segll,
+                                                        const int32_t* __restrict__ segok, double* __restrict__ loglik,
+                                                        int32_t* __restrict__ status) {
+  const int64_t b = blockIdx.x;
+  const int lane = threadIdx.x;
   const int32_t s0 = p.series_seg0[b], ns = p.series_nseg[b];
   double ll = 0.0;
-  bool good = true;
-  for (int32_t k = 0; k < ns; ++k) {
+  bool bad = false;
+  for (int32_t k = lane; k < ns; k += WAVE) {
     ll += segll[s0 + k];
-    good = good && segok[s0 + k];
+    bad = bad || !segok[s0 + k];
   }
-  good = good && isfinite(ll);
-  if (loglik) loglik[b] = good ? ll : __builtin_nan("");
-  if (status) status[b] = good ? 0 : GP_SSM_ENUMERIC;
+  ll = wave_sum(ll);
+  const bool good = !__any(bad) && isfinite(ll);
+  if (lane == 0) {
+    if (loglik) loglik[b] = good ? ll : __builtin_nan("");
+    if (status) status[b] = good ? 0 : GP_SSM_ENUMERIC;
+  }
 }
 
 template <int N>
@@ -310,7 +316,7 @@ void run_scan_n(hipStream_t st, const DevPlan& p, const DevParams& pr, const Sca
                      w.bstate, w.badj, w.bsmooth, w.segll, w.segok, back);
   prof_end("k_seg_fix", st);
   prof_begin("k_series_finish", st);
-  hipLaunchKernelGGL(k_series_finish, dim3((unsigned)((p.n_series + 63) / 64)), dim3(64), 0, st, p, w.segll, w.segok,
+  hipLaunchKernelGGL(k_series_finish, dim3((unsigned)p.n_series), dim3(WAVE), 0, st, p, w.segll, w.segok,
                      loglik, status);
   prof_end("k_series_finish", st);
 }

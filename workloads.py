@@ -128,7 +128,7 @@ def surrogate_y(rng, ts, te, yerr, jitter, sigma, omega0, quality, n_waves=8):
     return f + rng.normal(0.0, 1.0, len(ts)) * np.sqrt(np.asarray(yerr) ** 2 + jitter ** 2)
 
 
-def _series(rng, T, slot_counts, dur_lo, dur_hi, sigma, omega0, quality, jitter, yerr_fn):
+def _series(rng, T, slot_counts, dur_lo, dur_hi, sigma, omega0, quality, jitter, yerr_fn, n_waves=8):
     tss, tes = [], []
     for n in slot_counts:
         d = rng.uniform(dur_lo, dur_hi, n)
@@ -140,7 +140,7 @@ def _series(rng, T, slot_counts, dur_lo, dur_hi, sigma, omega0, quality, jitter,
     order = np.argsort(ts, kind="stable")
     ts, te = ts[order], te[order]
     yerr = yerr_fn(len(ts))
-    y = surrogate_y(rng, ts, te, yerr, jitter, sigma, omega0, quality)
+    y = surrogate_y(rng, ts, te, yerr, jitter, sigma, omega0, quality, n_waves)
     return ts, te, y, yerr
 
 
@@ -192,7 +192,7 @@ def _random_terms(rng, B, M):
     return sig, w0, q
 
 
-def batch_4096(seed=3, B=4096, n_lo=1000, n_hi=50_000, T=365.0):
+def batch_4096(seed=3, B=4096, n_lo=1000, n_hi=50_000, T=365.0, n_waves=2):
     rng = np.random.default_rng(seed)
     sig, w0, q = _random_terms(rng, B, 2)
     nb = np.round(_loguniform(rng, n_lo, n_hi, B)).astype(np.int64)
@@ -200,7 +200,7 @@ def batch_4096(seed=3, B=4096, n_lo=1000, n_hi=50_000, T=365.0):
     err = lognormal_errors(rng)
     for b in range(B):
         counts = [int(nb[b]) // 2, int(nb[b]) - int(nb[b]) // 2]
-        parts.append(_series(rng, T, counts, 1 * MIN, 20 * MIN, sig[b], w0[b], q[b], 0.0, err))
+        parts.append(_series(rng, T, counts, 1 * MIN, 20 * MIN, sig[b], w0[b], q[b], 0.0, err, n_waves))
     return _pack("batch_4096", parts, sig, w0, q, np.zeros(B))
 
 
@@ -215,13 +215,13 @@ def grad_1024(seed=4, B=1024, n=10_000, T=365.0, jitter=0.05):
     return _pack("grad_1024", parts, sig, w0, q, np.full(B, jitter))
 
 
-def long_1e7(seed=5, n=10_000_000, T=3652.5):
+def long_1e7(seed=5, n=10_000_000, T=3652.5, n_waves=4):
     rng = np.random.default_rng(seed)
     sig = [1.0, 0.5, 2.0]
     w0 = [2 * np.pi / 0.2, 2 * np.pi * 1440 / 5, 2 * np.pi / 30]
     q = [1 / np.sqrt(2), 30.0, 1 / np.sqrt(2)]
     counts = [n // 4 + (1 if i < n % 4 else 0) for i in range(4)]
-    part = _series(rng, T, counts, 20 * SEC, 100 * SEC, sig, w0, q, 0.0, lognormal_errors(rng))
+    part = _series(rng, T, counts, 20 * SEC, 100 * SEC, sig, w0, q, 0.0, lognormal_errors(rng), n_waves)
     return _pack("long_1e7", [part], [sig], [w0], [q], [0.0])
 
 
