@@ -743,12 +743,18 @@ GPD bool rts_step(double* m, double* P, const TermQ* tq, uint32_t open, uint32_t
 // Gradient accumulators per term: (sigma, omega0, Q); plus jitter.
 template <int M>
 struct GradAcc {
-  double s[M], w[M], q[M];
-  double jit;
-  GPD void init() {
+  // this lane's slots of an LDS array laid out [field][lane] (fields s_t, w_t,
+  // q_t, jit): the accumulators are touched a few times per event, and keeping
+  // them out of the register file across the backward sweep leaves room for
+  // the step itself
+  double* base;
+  GPD double& s(int t) const { return base[(0 * M + t) * 64]; }
+  GPD double& w(int t) const { return base[(1 * M + t) * 64]; }
+  GPD double& q(int t) const { return base[(2 * M + t) * 64]; }
+  GPD double& jit() const { return base[(3 * M) * 64]; }
+  GPD void init() const {
 #pragma unroll
-    for (int t = 0; t < M; ++t) s[t] = w[t] = q[t] = 0.0;
-    jit = 0.0;
+    for (int f = 0; f < 3 * M + 1; ++f) base[f * 64] = 0.0;
   }
 };
 
@@ -873,7 +879,7 @@ GPD void discretise_dual(const TermConst* tc, const double* coef, double dt, dou
 // computed as A (P (A^T h)) + Q h, and (A P) one column at a time.
 template <class Dm>
 GPD void adjoint_step(const double* m, const double* P, double* mb, double* Pb, const TermConst* tc, const double* coef,
-                      double dt, uint32_t info, const Obs& o, double jit, GradAcc<Dm::M>& acc) {
+                      double dt, uint32_t info, const Obs& o, double jit, const GradAcc<Dm::M>& acc) {
   constexpr int M = Dm::M, J = Dm::J, NX = Dm::NX, D = Dm::D;
   const uint32_t open = ev_open(info);
   double db[6 * M];
@@ -961,7 +967,7 @@ GPD void adjoint_step(const double* m, const double* P, double* mb, double* Pb, 
     for (int i = 0; i < D; ++i)
 #pragma unroll
       for (int j = i; j < D; ++j) Pb[sidx(i, j, D)] += 0.5 * (ub[i] * h[j] + h[i] * ub[j]);
-    acc.jit = fma(2.0 * jit, Sbar, acc.jit);
+    acc.jit() = fma(2.0 * jit, Sbar, acc.jit());
   }
 
   // predict: weights of the step quantities.  Abar = mb- m^T + 2 Pb- (A P).
@@ -1035,7 +1041,7 @@ GPD void adjoint_step(const double* m, const double* P, double* mb, double* Pb, 
 #pragma unroll
       for (int j = 0; j < J; ++j) zz = fma(oj[i] * oj[j], Pb[sidx(NX + i, NX + j, D)], zz);
     w[10] = zz;
-    term_backprop(tc[t], tq[t], db + 6 * t, dt, w, acc.s[t], acc.w[t], acc.q[t]);
+    term_backprop(tc[t], tq[t], db + 6 * t, dt, w, acc.s(t), acc.w(t), acc.q(t));
   }
 
   // adjoint to the state before the predict

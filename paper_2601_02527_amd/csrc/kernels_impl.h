@@ -203,7 +203,8 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int j = i; j < D; ++j) Pb[sidx(i, j, D)] = (j < NX && active) ? badj[(NX + sidx(i, j, NX)) * C + c] : 0.0;
-  GradAcc<M> acc;
+  __shared__ double lacc[(3 * M + 1) * WAVE];
+  const GradAcc<M> acc{lacc + lane};
   acc.init();
   nxt = fetch_event(p, ev0 + (int64_t)(L - 1) * WAVE + lane);
   for (int32_t k = L - 1; k >= 0; --k) {
@@ -220,22 +221,22 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
     // prior of the SHO states: sigma_t^2 I in scaled coordinates
 #pragma unroll
     for (int t = 0; t < M; ++t)
-      acc.s[t] += 2.0 * tc[t].sigma * (Pb[sidx(2 * t, 2 * t, D)] + Pb[sidx(2 * t + 1, 2 * t + 1, D)]);
+      acc.s(t) += 2.0 * tc[t].sigma * (Pb[sidx(2 * t, 2 * t, D)] + Pb[sidx(2 * t + 1, 2 * t + 1, D)]);
   }
   // sum over the segment's lanes (one series), one partial per segment
   const int64_t S = p.n_seg;
 #pragma unroll
   for (int t = 0; t < M; ++t) {
-    const double a0 = wave_sum(active ? acc.s[t] : 0.0);
-    const double a1 = wave_sum(active ? acc.w[t] : 0.0);
-    const double a2 = wave_sum(active ? acc.q[t] : 0.0);
+    const double a0 = wave_sum(active ? acc.s(t) : 0.0);
+    const double a1 = wave_sum(active ? acc.w(t) : 0.0);
+    const double a2 = wave_sum(active ? acc.q(t) : 0.0);
     if (lane == 0) {
       gpart[(0 * M + t) * S + seg] = a0;
       gpart[(1 * M + t) * S + seg] = a1;
       gpart[(2 * M + t) * S + seg] = a2;
     }
   }
-  const double aj = wave_sum(active ? acc.jit : 0.0);
+  const double aj = wave_sum(active ? acc.jit() : 0.0);
   if (lane == 0) gpart[(3 * M) * S + seg] = aj;
   (void)NXP;
   (void)C;
