@@ -33,17 +33,18 @@ struct LaneLds {
 };
 
 // SL: the sensitivity block S lives in LDS (a LaneLds view set by the
-// caller before init) instead of registers.
-template <class Dm, bool SL = false>
+// caller before init) instead of registers.  IL: likewise the information
+// accumulators (J, eta, c0), which change once per event.
+template <class Dm, bool SL = false, bool IL = false>
 struct CondState {
   static constexpr int D = Dm::D, NX = Dm::NX, NP = Dm::NP, NXP = Dm::NXP;
+  static constexpr int NINFO = NXP + NX + 1;  // fields of the information accumulators
   double P[NP];
   double mu[D];
   double Sr[SL ? 1 : D * NX];  // d mean / d x_b, row-major
   LaneLds Sl;
-  double Jm[NXP];
-  double eta[NX];
-  double c0;
+  double Ir[IL ? 1 : NINFO];  // J (packed), eta, c0
+  LaneLds Il;
 
   GPD double& S(int i) {
     if constexpr (SL)
@@ -51,6 +52,15 @@ struct CondState {
     else
       return Sr[i];
   }
+  GPD double& info(int i) {
+    if constexpr (IL)
+      return Il[i];
+    else
+      return Ir[i];
+  }
+  GPD double& Jm(int i) { return info(i); }
+  GPD double& eta(int i) { return info(NXP + i); }
+  GPD double& c0() { return info(NXP + NX); }
 
   GPD void init() {
 #pragma unroll
@@ -62,10 +72,7 @@ struct CondState {
 #pragma unroll
       for (int c = 0; c < NX; ++c) S(i * NX + c) = (i == c) ? 1.0 : 0.0;
 #pragma unroll
-    for (int i = 0; i < NXP; ++i) Jm[i] = 0.0;
-#pragma unroll
-    for (int i = 0; i < NX; ++i) eta[i] = 0.0;
-    c0 = 0.0;
+    for (int i = 0; i < NINFO; ++i) info(i) = 0.0;
   }
 
   // one event: predict over the step that ends at it, then its observation.
@@ -125,11 +132,11 @@ struct CondState {
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
       const double ac = a[c] * iS;
-      eta[c] = fma(ac, r, eta[c]);
+      eta(c) = fma(ac, r, eta(c));
 #pragma unroll
-      for (int d = c; d < NX; ++d) Jm[sidx(c, d, NX)] = fma(ac, a[d], Jm[sidx(c, d, NX)]);
+      for (int d = c; d < NX; ++d) Jm(sidx(c, d, NX)) = fma(ac, a[d], Jm(sidx(c, d, NX)));
     }
-    if (o.has) c0 += LOG_2PI + log(S_) + r * riS;
+    if (o.has) c0() += LOG_2PI + log(S_) + r * riS;
     close_slot<Dm>(mu, P, info);
   }
 };

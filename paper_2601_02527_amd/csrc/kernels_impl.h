@@ -111,11 +111,18 @@ __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, dou
   const double* coef = stage_coef<Dm, false>(pr, b, lcoef);
   const double jit = pr.jit[b];
   const double jit2 = jit * jit;
-  // the sensitivity block in LDS when four workgroups still fit in a CU
-  constexpr bool USE_LDS = 8 * (M * NCOEF + Dm::D * NX * WAVE) <= 40960;
-  __shared__ double lS[USE_LDS ? Dm::D * NX * WAVE : 1];
-  CondState<Dm, USE_LDS> st;
+  // LDS for the sensitivity block S when it is larger than at M = 3, J = 3
+  // (where it stays in registers without spills) and for the information
+  // accumulators (J, eta, c0), as long as four workgroups still fit in a CU
+  using St0 = CondState<Dm, false, false>;
+  constexpr int CB = 8 * M * NCOEF, SB = 8 * Dm::D * NX * WAVE, IB = 8 * St0::NINFO * WAVE;
+  constexpr bool SL = Dm::D * NX > 54 && CB + SB <= 40960;
+  constexpr bool IL = CB + (SL ? SB : 0) + IB <= 40960;
+  __shared__ double lS[SL ? Dm::D * NX * WAVE : 1];
+  __shared__ double lI[IL ? St0::NINFO * WAVE : 1];
+  CondState<Dm, SL, IL> st;
   st.Sl = LaneLds{lS + lane};
+  st.Il = LaneLds{lI + lane};
   st.init();
   EvRaw nxt = fetch_event(p, ev0 + lane);
   for (int32_t k = 0; k < L; ++k) {
@@ -140,10 +147,10 @@ __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, dou
 #pragma unroll
       for (int k = i; k < NX; ++k) summ[(sum_C(NX) + sidx(i, k, NX)) * C + c] = st.P[sidx(i, k, Dm::D)];
 #pragma unroll
-    for (int i = 0; i < NX; ++i) summ[(sum_eta(NX) + i) * C + c] = st.eta[i];
+    for (int i = 0; i < NX; ++i) summ[(sum_eta(NX) + i) * C + c] = st.eta(i);
 #pragma unroll
-    for (int i = 0; i < NXP; ++i) summ[(sum_J(NX) + i) * C + c] = st.Jm[i];
-    summ[sum_c0(NX) * C + c] = st.c0;
+    for (int i = 0; i < NXP; ++i) summ[(sum_J(NX) + i) * C + c] = st.Jm(i);
+    summ[sum_c0(NX) * C + c] = st.c0();
   }
 }
 
