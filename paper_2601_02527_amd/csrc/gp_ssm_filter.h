@@ -218,6 +218,13 @@ GPD double lu_solve(double* A, double* B, bool& ok) {
   return logdet;
 }
 
+template <int N, class Src>
+GPD void unpack_from(const Src& p, double* F) {
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) F[i * N + j] = p[sidx(i, j, N)];
+}
 template <int N>
 GPD void unpack(const double* p, double* F) {
 #pragma unroll
@@ -416,6 +423,20 @@ struct Elem {
   }
 };
 
+// A lane's element in an LDS exchange area laid out [field][lane] in the
+// summary field numbering, with the same indexing as Elem<N>.
+template <int N>
+struct ElemLds {
+  struct Field {
+    const double* p;
+    GPD double operator[](int i) const { return p[i * 64]; }
+  };
+  Field A, b, C, eta, J;
+  GPD explicit ElemLds(const double* base)
+      : A{base + sum_A(N) * 64}, b{base + sum_b(N) * 64}, C{base + sum_C(N) * 64}, eta{base + sum_eta(N) * 64},
+        J{base + sum_J(N) * 64} {}
+};
+
 // Associative composition of two consecutive summaries (i earlier, j
 // later), the filtering operator of the parallel Kalman filter (SG21):
 //   X = (I + C_i J_j)^-1
@@ -423,11 +444,13 @@ struct Elem {
 //   eta = A_i^T X^T (eta_j - J_j b_i) + eta_i,  J = A_i^T J_j X A_i + J_i
 // with X^T v = v - J_j X C_i v and J_j X = X^T J_j.  Result in o (may alias
 // neither input).
-template <int N>
-GPD void compose(const Elem<N>& ei, const Elem<N>& ej, Elem<N>& o, bool& ok) {
+// The inputs are Elem<N> in registers or ElemLds<N> views of a wavefront's
+// LDS exchange area (the neighbour's element, read where it is used).
+template <int N, class EI, class EJ>
+GPD void compose(const EI& ei, const EJ& ej, Elem<N>& o, bool& ok) {
   double Ci[N * N], Jj[N * N];
-  unpack<N>(ei.C, Ci);
-  unpack<N>(ej.J, Jj);
+  unpack_from<N>(ei.C, Ci);
+  unpack_from<N>(ej.J, Jj);
   // [X A_i | X (b_i + C_i eta_j) | X C_i]
   constexpr int R = 2 * N + 1;
   double Mx[N * N], B[N * R];

@@ -52,7 +52,7 @@ __device__ __forceinline__ void lds_get(const double* lds, int lane, Elem<N>& e)
 
 template <int N>
 __global__ __launch_bounds__(WAVE) void k_seg_scan(DevPlan p, const double* __restrict__ summ, double* __restrict__ pre,
-                                                   double* __restrict__ suf, double* __restrict__ segtot) {
+                                                   double* __restrict__ suf, double* __restrict__ segtot, int want_back) {
   constexpr int EF = elem_fields(N);
   __shared__ double lds[EF * WAVE];
   const int s = blockIdx.x, lane = threadIdx.x;
@@ -74,14 +74,14 @@ __global__ __launch_bounds__(WAVE) void k_seg_scan(DevPlan p, const double* __re
     lds_put<N>(lds, lane, own);
     __syncthreads();
     if (lane >= d) {
-      lds_get<N>(lds, lane - d, part);
-      compose<N>(part, own, tmp, ok);
+      compose<N>(ElemLds<N>(lds + lane - d), own, tmp, ok);
       own = tmp;
     }
     __syncthreads();
   }
   if (valid) own.store([&](int f, double v) { pre[(int64_t)f * C + c] = v; });
   if (lane == nch - 1) own.store([&](int f, double v) { segtot[(int64_t)f * S + s] = v; });
+  if (!want_back) return;  // the suffixes serve the backward passes only
   // inclusive suffix
   if (valid)
     own.load([&](int f) { return summ[(int64_t)f * C + c]; });
@@ -92,8 +92,7 @@ __global__ __launch_bounds__(WAVE) void k_seg_scan(DevPlan p, const double* __re
     lds_put<N>(lds, lane, own);
     __syncthreads();
     if (lane + d < WAVE) {
-      lds_get<N>(lds, lane + d, part);
-      compose<N>(own, part, tmp, ok);
+      compose<N>(own, ElemLds<N>(lds + lane + d), tmp, ok);
       own = tmp;
     }
     __syncthreads();
@@ -134,8 +133,7 @@ __global__ __launch_bounds__(WAVE) void k_series_scan(DevPlan p, DevParams pr, c
     lds_put<N>(lds, lane, own);
     __syncthreads();
     if (lane >= d) {
-      lds_get<N>(lds, lane - d, part);
-      compose<N>(part, own, tmp, ok);
+      compose<N>(ElemLds<N>(lds + lane - d), own, tmp, ok);
       own = tmp;
     }
     __syncthreads();
@@ -173,8 +171,7 @@ __global__ __launch_bounds__(WAVE) void k_series_scan(DevPlan p, DevParams pr, c
     lds_put<N>(lds, lane, own);
     __syncthreads();
     if (lane + d < WAVE) {
-      lds_get<N>(lds, lane + d, part);
-      compose<N>(own, part, tmp, ok);
+      compose<N>(own, ElemLds<N>(lds + lane + d), tmp, ok);
       own = tmp;
     }
     __syncthreads();
@@ -305,7 +302,7 @@ void run_scan_n(hipStream_t st, const DevPlan& p, const DevParams& pr, const Sca
                 int32_t* status, int back) {
   if (p.n_seg == 0) return;
   prof_begin("k_seg_scan", st);
-  hipLaunchKernelGGL(k_seg_scan<N>, dim3(p.n_seg), dim3(WAVE), 0, st, p, w.summ, w.pre, w.suf, w.segtot);
+  hipLaunchKernelGGL(k_seg_scan<N>, dim3(p.n_seg), dim3(WAVE), 0, st, p, w.summ, w.pre, w.suf, w.segtot, back);
   prof_end("k_seg_scan", st);
   prof_begin("k_series_scan", st);
   hipLaunchKernelGGL(k_series_scan<N>, dim3((unsigned)p.n_series), dim3(WAVE), 0, st, p, pr, w.segtot, w.segstate,
