@@ -194,11 +194,12 @@ GPD double lu_solve(double* A, double* B, bool& ok) {
     ok = ok && (piv != 0.0);
     logdet += log(fabs(piv));
     const double ip = 1.0 / piv;
+    A[k * N + k] = ip;  // kept as its reciprocal for the back substitution
 #pragma unroll
     for (int i = k + 1; i < N; ++i) {
       const double f = A[i * N + k] * ip;
 #pragma unroll
-      for (int c = k; c < N; ++c) A[i * N + c] = fma(-f, A[k * N + c], A[i * N + c]);
+      for (int c = k + 1; c < N; ++c) A[i * N + c] = fma(-f, A[k * N + c], A[i * N + c]);
 #pragma unroll
       for (int c = 0; c < R; ++c) B[i * R + c] = fma(-f, B[k * R + c], B[i * R + c]);
     }
@@ -206,7 +207,7 @@ GPD double lu_solve(double* A, double* B, bool& ok) {
   // back substitution
 #pragma unroll
   for (int k = N - 1; k >= 0; --k) {
-    const double ip = 1.0 / A[k * N + k];
+    const double ip = A[k * N + k];
 #pragma unroll
     for (int c = 0; c < R; ++c) {
       double v = B[k * R + c];
@@ -218,13 +219,6 @@ GPD double lu_solve(double* A, double* B, bool& ok) {
   return logdet;
 }
 
-template <int N, class Src>
-GPD void unpack_from(const Src& p, double* F) {
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int j = 0; j < N; ++j) F[i * N + j] = p[sidx(i, j, N)];
-}
 template <int N>
 GPD void unpack(const double* p, double* F) {
 #pragma unroll
@@ -442,120 +436,133 @@ struct ElemLds {
 //   X = (I + C_i J_j)^-1
 //   A = A_j X A_i,  b = A_j X (b_i + C_i eta_j) + b_j,  C = A_j X C_i A_j^T + C_j
 //   eta = A_i^T X^T (eta_j - J_j b_i) + eta_i,  J = A_i^T J_j X A_i + J_i
-// with X^T v = v - J_j X C_i v and J_j X = X^T J_j.  Result in o (may alias
-// neither input).
-// The inputs are Elem<N> in registers or ElemLds<N> views of a wavefront's
-// LDS exchange area (the neighbour's element, read where it is used).
+// X is never formed: one LU solve gives [X A_i | X (b_i + C_i eta_j) | X C_i]
+// (an explicit inverse loses accuracy the smoothed moments need), and
+// X^T v = v - J_j (X C_i) v follows from X^T = (I + J_j C_i)^-1.
+// The inputs are Elem<N> in registers or ElemLds<N> views, read where they
+// are used, so that only the solve and the result occupy registers; the
+// result o may alias neither input.  The fences between the stages keep the
+// compiler from hoisting every operand read to the top.
 template <int N, class EI, class EJ>
 GPD void compose(const EI& ei, const EJ& ej, Elem<N>& o, bool& ok) {
-  double Ci[N * N], Jj[N * N];
-  unpack_from<N>(ei.C, Ci);
-  unpack_from<N>(ej.J, Jj);
-  // [X A_i | X (b_i + C_i eta_j) | X C_i]
   constexpr int R = 2 * N + 1;
-  double Mx[N * N], B[N * R];
+  double B[N * R];
+  {
+    double Mx[N * N];
 #pragma unroll
-  for (int r = 0; r < N; ++r) {
+    for (int r = 0; r < N; ++r) {
 #pragma unroll
-    for (int c = 0; c < N; ++c) {
-      double v = (r == c) ? 1.0 : 0.0;
+      for (int c = 0; c < N; ++c) {
+        double v = (r == c) ? 1.0 : 0.0;
 #pragma unroll
-      for (int k = 0; k < N; ++k) v = fma(Ci[r * N + k], Jj[k * N + c], v);
-      Mx[r * N + c] = v;
-      B[r * R + c] = ei.A[r * N + c];
-      B[r * R + N + 1 + c] = Ci[r * N + c];
+        for (int k = 0; k < N; ++k) v = fma(ei.C[sidx(r, k, N)], ej.J[sidx(k, c, N)], v);
+        Mx[r * N + c] = v;
+        B[r * R + c] = ei.A[r * N + c];
+        B[r * R + N + 1 + c] = ei.C[sidx(r, c, N)];
+      }
+      double v = ei.b[r];
+#pragma unroll
+      for (int k = 0; k < N; ++k) v = fma(ei.C[sidx(r, k, N)], ej.eta[k], v);
+      B[r * R + N] = v;
     }
-    double v = ei.b[r];
-#pragma unroll
-    for (int k = 0; k < N; ++k) v = fma(Ci[r * N + k], ej.eta[k], v);
-    B[r * R + N] = v;
+    lu_solve<N, R>(Mx, B, ok);
   }
-  lu_solve<N, R>(Mx, B, ok);
+  table_fence();
   // A = A_j XA, b = A_j Xb + b_j, C = A_j XC A_j^T + C_j
-  double AjXC[N * N];
+  {
+    double AjXC[N * N];
 #pragma unroll
-  for (int r = 0; r < N; ++r) {
-    double bb = ej.b[r];
+    for (int r = 0; r < N; ++r) {
+      double bb = ej.b[r];
 #pragma unroll
-    for (int k = 0; k < N; ++k) bb = fma(ej.A[r * N + k], B[k * R + N], bb);
-    o.b[r] = bb;
+      for (int k = 0; k < N; ++k) bb = fma(ej.A[r * N + k], B[k * R + N], bb);
+      o.b[r] = bb;
 #pragma unroll
-    for (int c = 0; c < N; ++c) {
-      double a = 0.0, x = 0.0;
+      for (int c = 0; c < N; ++c) {
+        double a = 0.0, x = 0.0;
 #pragma unroll
-      for (int k = 0; k < N; ++k) {
-        a = fma(ej.A[r * N + k], B[k * R + c], a);
-        x = fma(ej.A[r * N + k], B[k * R + N + 1 + c], x);
+        for (int k = 0; k < N; ++k) {
+          a = fma(ej.A[r * N + k], B[k * R + c], a);
+          x = fma(ej.A[r * N + k], B[k * R + N + 1 + c], x);
+        }
+        o.A[r * N + c] = a;
+        AjXC[r * N + c] = x;
       }
-      o.A[r * N + c] = a;
-      AjXC[r * N + c] = x;
     }
-  }
+    table_fence();
 #pragma unroll
-  for (int r = 0; r < N; ++r)
+    for (int r = 0; r < N; ++r)
 #pragma unroll
-    for (int c = r; c < N; ++c) {
-      double v = ej.C[sidx(r, c, N)], w = ej.C[sidx(r, c, N)];
+      for (int c = r; c < N; ++c) {
+        double v = ej.C[sidx(r, c, N)], w = v;
 #pragma unroll
-      for (int k = 0; k < N; ++k) {
-        v = fma(AjXC[r * N + k], ej.A[c * N + k], v);
-        w = fma(AjXC[c * N + k], ej.A[r * N + k], w);
+        for (int k = 0; k < N; ++k) {
+          v = fma(AjXC[r * N + k], ej.A[c * N + k], v);
+          w = fma(AjXC[c * N + k], ej.A[r * N + k], w);
+        }
+        o.C[sidx(r, c, N)] = 0.5 * (v + w);
       }
-      o.C[sidx(r, c, N)] = 0.5 * (v + w);
+  }
+  table_fence();
+  // eta = A_i^T X^T v + eta_i with v = eta_j - J_j b_i
+  {
+    double vv[N], t1[N], xtv[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      double v = ej.eta[r];
+#pragma unroll
+      for (int k = 0; k < N; ++k) v = fma(-ej.J[sidx(r, k, N)], ei.b[k], v);
+      vv[r] = v;
     }
-  // v = eta_j - J_j b_i ; Xt v = v - J_j (X C_i v)
-  double vv[N], t1[N], xtv[N];
 #pragma unroll
-  for (int r = 0; r < N; ++r) {
-    double v = ej.eta[r];
-#pragma unroll
-    for (int k = 0; k < N; ++k) v = fma(-Jj[r * N + k], ei.b[k], v);
-    vv[r] = v;
-  }
-#pragma unroll
-  for (int r = 0; r < N; ++r) {
-    double v = 0.0;
-#pragma unroll
-    for (int k = 0; k < N; ++k) v = fma(B[r * R + N + 1 + k], vv[k], v);
-    t1[r] = v;
-  }
-#pragma unroll
-  for (int r = 0; r < N; ++r) {
-    double v = vv[r];
-#pragma unroll
-    for (int k = 0; k < N; ++k) v = fma(-Jj[r * N + k], t1[k], v);
-    xtv[r] = v;
-  }
-#pragma unroll
-  for (int r = 0; r < N; ++r) {
-    double v = ei.eta[r];
-#pragma unroll
-    for (int k = 0; k < N; ++k) v = fma(ei.A[k * N + r], xtv[k], v);
-    o.eta[r] = v;
-  }
-  // J = A_i^T (J_j XA) + J_i
-  double JXA[N * N];
-#pragma unroll
-  for (int r = 0; r < N; ++r)
-#pragma unroll
-    for (int c = 0; c < N; ++c) {
+    for (int r = 0; r < N; ++r) {
       double v = 0.0;
 #pragma unroll
-      for (int k = 0; k < N; ++k) v = fma(Jj[r * N + k], B[k * R + c], v);
-      JXA[r * N + c] = v;
+      for (int k = 0; k < N; ++k) v = fma(B[r * R + N + 1 + k], vv[k], v);
+      t1[r] = v;
     }
 #pragma unroll
-  for (int r = 0; r < N; ++r)
+    for (int r = 0; r < N; ++r) {
+      double v = vv[r];
 #pragma unroll
-    for (int c = r; c < N; ++c) {
-      double v = 0.0, w = 0.0;
+      for (int k = 0; k < N; ++k) v = fma(-ej.J[sidx(r, k, N)], t1[k], v);
+      xtv[r] = v;
+    }
 #pragma unroll
-      for (int k = 0; k < N; ++k) {
-        v = fma(ei.A[k * N + r], JXA[k * N + c], v);
-        w = fma(ei.A[k * N + c], JXA[k * N + r], w);
+    for (int r = 0; r < N; ++r) {
+      double v = ei.eta[r];
+#pragma unroll
+      for (int k = 0; k < N; ++k) v = fma(ei.A[k * N + r], xtv[k], v);
+      o.eta[r] = v;
+    }
+  }
+  table_fence();
+  // J = A_i^T (J_j XA) + J_i
+  {
+    double JXA[N * N];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) v = fma(ej.J[sidx(r, k, N)], B[k * R + c], v);
+        JXA[r * N + c] = v;
       }
-      o.J[sidx(r, c, N)] = ei.J[sidx(r, c, N)] + 0.5 * (v + w);
-    }
+    table_fence();
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int c = r; c < N; ++c) {
+        double v = 0.0, w = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          v = fma(ei.A[k * N + r], JXA[k * N + c], v);
+          w = fma(ei.A[k * N + c], JXA[k * N + r], w);
+        }
+        o.J[sidx(r, c, N)] = ei.J[sidx(r, c, N)] + 0.5 * (v + w);
+      }
+  }
 }
 
 // gradient of the future log-likelihood with respect to the moments (m, P)

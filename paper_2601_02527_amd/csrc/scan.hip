@@ -45,10 +45,6 @@ template <int N>
 __device__ __forceinline__ void lds_put(double* lds, int lane, const Elem<N>& e) {
   e.store([&](int f, double v) { lds[f * WAVE + lane] = v; });
 }
-template <int N>
-__device__ __forceinline__ void lds_get(const double* lds, int lane, Elem<N>& e) {
-  e.load([&](int f) { return lds[f * WAVE + lane]; });
-}
 
 template <int N>
 __global__ __launch_bounds__(WAVE) void k_seg_scan(DevPlan p, const double* __restrict__ summ, double* __restrict__ pre,
@@ -61,43 +57,44 @@ __global__ __launch_bounds__(WAVE) void k_seg_scan(DevPlan p, const double* __re
   const int64_t c = p.seg_chunk0[s] + lane;
   const bool valid = lane < nch;
   bool ok = true;
-  Elem<N> own, part, tmp;
-  // Kogge-Stone levels d < nch suffice: the lanes past the segment hold the
-  // identity
+  Elem<N> tmp;
+  // The running compositions live in the LDS exchange area, so both operands
+  // of a composition are read from LDS and only its result is held in
+  // registers.  A lane composes only with lanes of the segment (Kogge-Stone
+  // levels d < nch), so the lanes past the segment are never read.
   // inclusive prefix
   if (valid)
-    own.load([&](int f) { return summ[(int64_t)f * C + c]; });
-  else
-    own.identity();
+    for (int f = 0; f < EF; ++f) lds[f * WAVE + lane] = summ[(int64_t)f * C + c];
+  __syncthreads();
 #pragma unroll 1
   for (int d = 1; d < nch; d <<= 1) {
-    lds_put<N>(lds, lane, own);
+    const bool act = lane >= d && valid;
+    if (act) compose<N>(ElemLds<N>(lds + lane - d), ElemLds<N>(lds + lane), tmp, ok);
     __syncthreads();
-    if (lane >= d) {
-      compose<N>(ElemLds<N>(lds + lane - d), own, tmp, ok);
-      own = tmp;
-    }
+    if (act) lds_put<N>(lds, lane, tmp);
     __syncthreads();
   }
-  if (valid) own.store([&](int f, double v) { pre[(int64_t)f * C + c] = v; });
-  if (lane == nch - 1) own.store([&](int f, double v) { segtot[(int64_t)f * S + s] = v; });
+  if (valid)
+    for (int f = 0; f < EF; ++f) pre[(int64_t)f * C + c] = lds[f * WAVE + lane];
+  if (lane == nch - 1)
+    for (int f = 0; f < EF; ++f) segtot[(int64_t)f * S + s] = lds[f * WAVE + lane];
   if (!want_back) return;  // the suffixes serve the backward passes only
   // inclusive suffix
+  __syncthreads();
   if (valid)
-    own.load([&](int f) { return summ[(int64_t)f * C + c]; });
-  else
-    own.identity();
+    for (int f = 0; f < EF; ++f) lds[f * WAVE + lane] = summ[(int64_t)f * C + c];
+  __syncthreads();
 #pragma unroll 1
   for (int d = 1; d < nch; d <<= 1) {
-    lds_put<N>(lds, lane, own);
+    const bool act = lane + d < nch;
+    if (act) compose<N>(ElemLds<N>(lds + lane), ElemLds<N>(lds + lane + d), tmp, ok);
     __syncthreads();
-    if (lane + d < WAVE) {
-      compose<N>(own, ElemLds<N>(lds + lane + d), tmp, ok);
-      own = tmp;
-    }
+    if (act) lds_put<N>(lds, lane, tmp);
     __syncthreads();
   }
-  if (valid) own.store([&](int f, double v) { suf[(int64_t)f * C + c] = v; });
+  if (valid)
+    for (int f = 0; f < EF; ++f) suf[(int64_t)f * C + c] = lds[f * WAVE + lane];
+  (void)ok;
 }
 
 template <int N>
@@ -106,85 +103,91 @@ __global__ __launch_bounds__(WAVE) void k_series_scan(DevPlan p, DevParams pr, c
                                                       int want_back) {
   constexpr int EF = elem_fields(N);
   constexpr int NP = N * (N + 1) / 2;
-  __shared__ double lds[EF * WAVE];
+  // xch: the exchange area of the lane scans; blk: each lane's block total
+  __shared__ double lds[2 * EF * WAVE];
+  double* const xch = lds;
+  double* const blk = lds + EF * WAVE;
   const int64_t b = blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t S = p.n_seg;
   const int32_t s0 = p.series_seg0[b], ns = p.series_nseg[b];
   if (ns == 0) return;
   const int32_t q = (ns + WAVE - 1) / WAVE;
-  const int32_t nl = (ns + q - 1) / q;  // lanes holding a block; the rest hold the identity
+  const int32_t nl = (ns + q - 1) / q;  // lanes holding a block of segments, each non-empty
   const int32_t lo = min(ns, lane * q), hi = min(ns, lo + q);
+  const bool has = lane < nl;
   bool ok = true;
   auto tot = [&](int32_t k) { return [=](int f) { return segtot[(int64_t)f * S + s0 + k]; }; };
-  // block total of this lane
-  Elem<N> blk, part, tmp;
-  blk.identity();
-  for (int32_t k = lo; k < hi; ++k) {
-    Elem<N> e;
-    e.load(tot(k));
-    compose<N>(blk, e, tmp, ok);
-    blk = tmp;
+  Elem<N> tmp;
+  // block total of this lane (a lane reads and writes only its own slots;
+  // each segment total is staged in the lane's exchange slot, so that both
+  // operands of the composition are LDS views at fixed offsets)
+  if (has) {
+    for (int f = 0; f < EF; ++f) blk[f * WAVE + lane] = segtot[(int64_t)f * S + s0 + lo];
+    for (int32_t k = lo + 1; k < hi; ++k) {
+      for (int f = 0; f < EF; ++f) xch[f * WAVE + lane] = segtot[(int64_t)f * S + s0 + k];
+      compose<N>(ElemLds<N>(blk + lane), ElemLds<N>(xch + lane), tmp, ok);
+      lds_put<N>(blk, lane, tmp);
+    }
+    for (int f = 0; f < EF; ++f) xch[f * WAVE + lane] = blk[f * WAVE + lane];
   }
-  // exclusive prefix over lanes
-  Elem<N> own = blk;
+  __syncthreads();
+  // inclusive prefix over the lanes holding a block
 #pragma unroll 1
   for (int d = 1; d < nl; d <<= 1) {
-    lds_put<N>(lds, lane, own);
+    const bool act = lane >= d && has;
+    if (act) compose<N>(ElemLds<N>(xch + lane - d), ElemLds<N>(xch + lane), tmp, ok);
     __syncthreads();
-    if (lane >= d) {
-      compose<N>(ElemLds<N>(lds + lane - d), own, tmp, ok);
-      own = tmp;
+    if (act) lds_put<N>(xch, lane, tmp);
+    __syncthreads();
+  }
+  // the state entering this lane's block: the prior advanced through the
+  // blocks of the lanes before it
+  if (has) {
+    double m[N], P[NP], mn[N], Pn[NP];
+    prior_state<N>(pr, b, m, P);
+    if (lane > 0) {
+      combine_forward<N>(
+          m, P, [&](int f) { return f == sum_c0(N) ? 0.0 : xch[f * WAVE + lane - 1]; }, mn, Pn, ok);
+#pragma unroll
+      for (int i = 0; i < N; ++i) m[i] = mn[i];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) P[i] = Pn[i];
     }
-    __syncthreads();
-  }
-  lds_put<N>(lds, lane, own);
-  __syncthreads();
-  double m[N], P[NP], mn[N], Pn[NP];
-  prior_state<N>(pr, b, m, P);
-  if (lane > 0) {
-    lds_get<N>(lds, lane - 1, part);
-    combine_forward<N>(m, P, [&](int f) { return part.get(f); }, mn, Pn, ok);
+    for (int32_t k = lo; k < hi; ++k) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) m[i] = mn[i];
+      for (int i = 0; i < N; ++i) segstate[(int64_t)i * S + s0 + k] = m[i];
 #pragma unroll
-    for (int i = 0; i < NP; ++i) P[i] = Pn[i];
-  }
-  __syncthreads();
-  for (int32_t k = lo; k < hi; ++k) {
+      for (int i = 0; i < NP; ++i) segstate[(int64_t)(N + i) * S + s0 + k] = P[i];
+      combine_forward<N>(m, P, tot(k), mn, Pn, ok);
 #pragma unroll
-    for (int i = 0; i < N; ++i) segstate[(int64_t)i * S + s0 + k] = m[i];
+      for (int i = 0; i < N; ++i) m[i] = mn[i];
 #pragma unroll
-    for (int i = 0; i < NP; ++i) segstate[(int64_t)(N + i) * S + s0 + k] = P[i];
-    combine_forward<N>(m, P, tot(k), mn, Pn, ok);
-#pragma unroll
-    for (int i = 0; i < N; ++i) m[i] = mn[i];
-#pragma unroll
-    for (int i = 0; i < NP; ++i) P[i] = Pn[i];
+      for (int i = 0; i < NP; ++i) P[i] = Pn[i];
+    }
   }
   if (!want_back) return;
-  // inclusive suffix over lanes; the future after this lane's block is the
-  // information of the next lane's suffix
-  own = blk;
+  // inclusive suffix over the lanes holding a block; the future after this
+  // lane's block is the information of the next lane's suffix
+  __syncthreads();
+  if (has)
+    for (int f = 0; f < EF; ++f) xch[f * WAVE + lane] = blk[f * WAVE + lane];
+  __syncthreads();
 #pragma unroll 1
   for (int d = 1; d < nl; d <<= 1) {
-    lds_put<N>(lds, lane, own);
+    const bool act = lane + d < nl;
+    if (act) compose<N>(ElemLds<N>(xch + lane), ElemLds<N>(xch + lane + d), tmp, ok);
     __syncthreads();
-    if (lane + d < WAVE) {
-      compose<N>(own, ElemLds<N>(lds + lane + d), tmp, ok);
-      own = tmp;
-    }
+    if (act) lds_put<N>(xch, lane, tmp);
     __syncthreads();
   }
-  lds_put<N>(lds, lane, own);
-  __syncthreads();
+  if (!has) return;
   double Jf[NP], ef[N];
-  if (lane + 1 < WAVE) {
-    lds_get<N>(lds, lane + 1, part);
+  if (lane + 1 < nl) {
 #pragma unroll
-    for (int i = 0; i < NP; ++i) Jf[i] = part.J[i];
+    for (int i = 0; i < NP; ++i) Jf[i] = xch[(sum_J(N) + i) * WAVE + lane + 1];
 #pragma unroll
-    for (int i = 0; i < N; ++i) ef[i] = part.eta[i];
+    for (int i = 0; i < N; ++i) ef[i] = xch[(sum_eta(N) + i) * WAVE + lane + 1];
   } else {
 #pragma unroll
     for (int i = 0; i < NP; ++i) Jf[i] = 0.0;
