@@ -12,8 +12,8 @@
 //  * the combination of a filtered boundary state with a summary (next
 //    boundary state and the chunk's likelihood contribution), the backward
 //    recursion of the future likelihood (eta~, J~), and from it the gradient
-//    of the future likelihood with respect to the boundary moments and the
-//    smoothed boundary moments.
+//    of the future likelihood with respect to the boundary moments.
+//  * the smoother's backward sweep in adjoint (Bryson-Frazier) form.
 //  * the reverse-mode adjoint of one plain filter step, accumulating the
 //    gradient with respect to (sigma, omega0, Q) of every term and jitter.
 #pragma once
@@ -567,11 +567,13 @@ GPD void compose(const EI& ei, const EJ& ej, Elem<N>& o, bool& ok) {
 
 // gradient of the future log-likelihood with respect to the moments (m, P)
 // of the boundary state, given the future information (J~, eta~):
-//   B = (I + J~ P)^-1, mbar = B (eta~ - J~ m), Pbar = (mbar mbar^T - B J~)/2
-// and the smoothed boundary moments m^ = m + P mbar, P^ = P - P (B J~) P.
+//   B = (I + J~ P)^-1, mbar = B (eta~ - J~ m), Pbar = (mbar mbar^T - B J~)/2.
+// Lam (optional) receives the symmetric B J~, which with mbar is the pair
+// (lambda, Lambda) of the smoother's backward sweep: the smoothed boundary
+// moments are m + P mbar and P - P Lambda P.
 template <int N>
 GPD void boundary_adjoint(const double* m, const double* Pp, const double* Jp, const double* et, double* mbar,
-                          double* Pbar, double* mhat, double* Phat, bool& ok) {
+                          double* Pbar, double* Lam, bool& ok) {
   double P[N * N], Jf[N * N], A[N * N], B[N * (N + 1)];
   unpack<N>(Pp, P);
   unpack<N>(Jp, Jf);
@@ -593,185 +595,195 @@ GPD void boundary_adjoint(const double* m, const double* Pp, const double* Jp, c
   lu_solve<N, N + 1>(A, B, ok);
 #pragma unroll
   for (int i = 0; i < N; ++i) mbar[i] = B[i * (N + 1) + N];
-  double BJ[N * N];
 #pragma unroll
   for (int i = 0; i < N; ++i)
 #pragma unroll
-    for (int j = 0; j < N; ++j) BJ[i * N + j] = 0.5 * (B[i * (N + 1) + j] + B[j * (N + 1) + i]);
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int j = i; j < N; ++j) Pbar[sidx(i, j, N)] = 0.5 * (mbar[i] * mbar[j] - BJ[i * N + j]);
-  if (mhat) {
-    double PB[N * N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      double v = m[i];
-#pragma unroll
-      for (int k = 0; k < N; ++k) v = fma(P[i * N + k], mbar[k], v);
-      mhat[i] = v;
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        double w = 0.0;
-#pragma unroll
-        for (int k = 0; k < N; ++k) w = fma(P[i * N + k], BJ[k * N + j], w);
-        PB[i * N + j] = w;
-      }
+    for (int j = i; j < N; ++j) {
+      const double bj = 0.5 * (B[i * (N + 1) + j] + B[j * (N + 1) + i]);
+      Pbar[sidx(i, j, N)] = 0.5 * (mbar[i] * mbar[j] - bj);
+      if (Lam) Lam[sidx(i, j, N)] = bj;
     }
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int j = i; j < N; ++j) {
-        double v = P[i * N + j];
-#pragma unroll
-        for (int k = 0; k < N; ++k) v = fma(-PB[i * N + k], P[k * N + j], v);
-        Phat[sidx(i, j, N)] = v;
-      }
-  }
 }
 
 // ---------------------------------------------------------------------------
-// RTS smoothing step on the augmented state
+// smoother backward sweep in adjoint form (modified Bryson-Frazier)
 // ---------------------------------------------------------------------------
-// X = Pm^-1 Y for a packed symmetric Pm restricted to the active indices
-// (inactive rows/columns are replaced by the identity and their rows of Y
-// must be zero), by Cholesky.  Y is D x R row-major.  Returns false on a
-// non-positive pivot.
-template <int D, int R>
-GPD bool chol_solve_masked(const double* Pm, const bool* act, double* Y) {
-  double L[D * (D + 1) / 2];
-  bool good = true;
-#pragma unroll
-  for (int j = 0; j < D; ++j) {
-    double d = act[j] ? Pm[sidx(j, j, D)] : 1.0;
-#pragma unroll
-    for (int k = 0; k < j; ++k) d = fma(-L[sidx(j, k, D)], L[sidx(j, k, D)], d);
-    good = good && (d > 0.0);
-    const double ljj = sqrt(fmax(d, 1e-300));
-    L[sidx(j, j, D)] = ljj;
-    const double inv = 1.0 / ljj;
-#pragma unroll
-    for (int i = j + 1; i < D; ++i) {
-      double v = (act[i] && act[j]) ? Pm[sidx(i, j, D)] : 0.0;
-#pragma unroll
-      for (int k = 0; k < j; ++k) v = fma(-L[sidx(i, k, D)], L[sidx(j, k, D)], v);
-      L[sidx(i, j, D)] = v * inv;
-    }
-  }
-  // forward then backward substitution
-#pragma unroll
-  for (int c = 0; c < R; ++c) {
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      double v = Y[i * R + c];
-#pragma unroll
-      for (int k = 0; k < i; ++k) v = fma(-L[sidx(i, k, D)], Y[k * R + c], v);
-      Y[i * R + c] = v / L[sidx(i, i, D)];
-    }
-#pragma unroll
-    for (int i = D - 1; i >= 0; --i) {
-      double v = Y[i * R + c];
-#pragma unroll
-      for (int k = i + 1; k < D; ++k) v = fma(-L[sidx(k, i, D)], Y[k * R + c], v);
-      Y[i * R + c] = v / L[sidx(i, i, D)];
-    }
-  }
-  return good;
-}
+// At any point of the forward filter with moments (m, P), the data after it
+// enter the smoothed moments through a pair (lambda, Lambda):
+//   m^ = m + P lambda,   P^ = P - P Lambda P
+// (lambda = B (eta~ - J~ m), Lambda = B J~ with B = (I + J~ P)^-1 in terms of
+// the future information).  The pair runs backward through the forward
+// operations without any matrix inverse:
+//   predict m <- A m, P <- A P A^T + Q:   lambda <- A^T lambda, Lambda <- A^T Lambda A
+//   update with gain K = u / S (u = P h, S = h.u + R, innovation v):
+//     lambda <- lambda + h (v - u.lambda) / S
+//     Lambda <- (I - K h^T)^T Lambda (I - K h^T) + h h^T / S
+//   closing integrator j (z_j <- 0):      row and column j of both cleared.
+// This is the same posterior as the RTS recursion of Sec. 3.2.2; it avoids
+// inverting the predicted covariance, which is nearly singular when two
+// exposures start almost together (their integrators are nearly equal).
 
-// One RTS step: given the filtered state (m, P) of the current step, the
-// transition to the next state x_next = F x + q (F = A applied after zeroing
-// the integrators in `zmask`, q ~ N(0, Q) over `open`), and the smoothed
-// moments (ms, Ps) of the next state, returns the smoothed moments of the
-// current state in (m, P):
-//   Pm = F P F^T + Q,  G = P F^T Pm^-1,
-//   m <- m + G (ms - F m),  P <- P + G (Ps - Pm) G^T.
-// Pm is inverted on the SHO states and the integrators that are open over
-// the step with positive predicted variance (the others are deterministic
-// zeros).  zmask: integrators zeroed before the transition.
+// lambda <- A^T lambda, Lambda <- A^T Lambda A for the augmented transition
+// A = [[Phi, 0], [o fbar^T, I]] (o: the integrators open over the step)
 template <class Dm>
-GPD bool rts_step(double* m, double* P, const TermQ* tq, uint32_t open, uint32_t zmask, const double* ms,
-                  const double* Ps) {
-  constexpr int NX = Dm::NX, D = Dm::D, NP = Dm::NP, J = Dm::J;
-  // zero the closed integrators (they are constants after the zeroing)
-  double mz[D], Pz[NP];
+GPD void bf_predict(double* lam, double* Lam, const TermQ* tq, uint32_t open) {
+  constexpr int M = Dm::M, J = Dm::J, NX = Dm::NX, D = Dm::D;
+  double fb[NX];
 #pragma unroll
-  for (int i = 0; i < D; ++i) mz[i] = (i >= NX && ((zmask >> (i - NX)) & 1u)) ? 0.0 : m[i];
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int j = i; j < D; ++j) {
-      const bool zi = i >= NX && ((zmask >> (i - NX)) & 1u), zj = j >= NX && ((zmask >> (j - NX)) & 1u);
-      Pz[sidx(i, j, D)] = (zi || zj) ? 0.0 : P[sidx(i, j, D)];
-    }
-  // predicted moments of the next state
-  double mp[D], Pm[NP];
-#pragma unroll
-  for (int i = 0; i < D; ++i) mp[i] = mz[i];
-#pragma unroll
-  for (int i = 0; i < NP; ++i) Pm[i] = Pz[i];
-  predict_mean<Dm>(mp, tq, open);
-  predict_cov<Dm>(Pm, tq, open);
-  // Y = F P = A (R P)  (= (P F^T)^T): rows = next-state index, columns =
-  // current-state index (the zeroed integrators keep their columns, so their
-  // pre-zeroing values are smoothed too)
-  double Y[D * D];
-#pragma unroll
-  for (int c = 0; c < D; ++c) {
-    double col[D];
-#pragma unroll
-    for (int i = 0; i < D; ++i) col[i] = (i >= NX && ((zmask >> (i - NX)) & 1u)) ? 0.0 : P[sidx(i, c, D)];
-    predict_mean<Dm>(col, tq, open);
-#pragma unroll
-    for (int i = 0; i < D; ++i) Y[i * D + c] = col[i];
+  for (int t = 0; t < M; ++t) {
+    fb[2 * t] = tq[t].f0;
+    fb[2 * t + 1] = tq[t].f1;
   }
-  bool act[D];
+  double oj[J > 0 ? J : 1];
 #pragma unroll
-  for (int i = 0; i < D; ++i) act[i] = (i < NX) || (((open >> (i - NX)) & 1u) && Pm[sidx(i, i, D)] > 0.0);
+  for (int j = 0; j < J; ++j) oj[j] = ((open >> j) & 1u) ? 1.0 : 0.0;
+  // lambda
+  double lz = 0.0;
 #pragma unroll
-  for (int i = 0; i < D; ++i)
-    if (!act[i])
+  for (int j = 0; j < J; ++j) lz = fma(oj[j], lam[NX + j], lz);
 #pragma unroll
-      for (int c = 0; c < D; ++c) Y[i * D + c] = 0.0;
-  const bool ok = chol_solve_masked<D, D>(Pm, act, Y);  // Y <- Pm^-1 F P = G^T
-  // m <- m + G (ms - mp)
-  double dm[D];
+  for (int t = 0; t < M; ++t) {
+    const double l0 = lam[2 * t], l1 = lam[2 * t + 1];
+    lam[2 * t] = fma(tq[t].a00, l0, fma(-tq[t].a01, l1, fb[2 * t] * lz));
+    lam[2 * t + 1] = fma(tq[t].a01, l0, fma(tq[t].a11, l1, fb[2 * t + 1] * lz));
+  }
+  // Lambda: g = Lxz o, h = Lzz o, s = o^T Lzz o (from the old blocks)
+  double g[NX], h[J > 0 ? J : 1];
 #pragma unroll
-  for (int i = 0; i < D; ++i) dm[i] = act[i] ? ms[i] - mp[i] : 0.0;
+  for (int a = 0; a < NX; ++a) {
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < J; ++j) v = fma(oj[j], Lam[sidx(a, NX + j, D)], v);
+    g[a] = v;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < J; ++i) v = fma(oj[i], Lam[sidx(NX + j, NX + i, D)], v);
+    h[j] = v;
+    s = fma(oj[j], v, s);
+  }
+  // SHO/integrator block: Phi^T Lxz + fbar h^T
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+      const double y0 = Lam[sidx(2 * t, NX + j, D)], y1 = Lam[sidx(2 * t + 1, NX + j, D)];
+      Lam[sidx(2 * t, NX + j, D)] = fma(tq[t].a00, y0, fma(-tq[t].a01, y1, fb[2 * t] * h[j]));
+      Lam[sidx(2 * t + 1, NX + j, D)] = fma(tq[t].a01, y0, fma(tq[t].a11, y1, fb[2 * t + 1] * h[j]));
+    }
+  // g' = Phi^T g
+  double gp[NX];
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    gp[2 * t] = fma(tq[t].a00, g[2 * t], -tq[t].a01 * g[2 * t + 1]);
+    gp[2 * t + 1] = fma(tq[t].a01, g[2 * t], tq[t].a11 * g[2 * t + 1]);
+  }
+  // SHO block: Phi^T Lxx Phi + g' fbar^T + fbar g'^T + s fbar fbar^T
+#pragma unroll
+  for (int t = 0; t < M; ++t)
+#pragma unroll
+    for (int u = t; u < M; ++u) {
+      const double b00 = Lam[sidx(2 * t, 2 * u, D)], b01 = Lam[sidx(2 * t, 2 * u + 1, D)];
+      const double b10 = Lam[sidx(2 * t + 1, 2 * u, D)], b11 = Lam[sidx(2 * t + 1, 2 * u + 1, D)];
+      // Y = Phi_t^T B
+      const double y00 = fma(tq[t].a00, b00, -tq[t].a01 * b10);
+      const double y01 = fma(tq[t].a00, b01, -tq[t].a01 * b11);
+      const double y10 = fma(tq[t].a01, b00, tq[t].a11 * b10);
+      const double y11 = fma(tq[t].a01, b01, tq[t].a11 * b11);
+      // Z = Y Phi_u
+      const double z00 = fma(y00, tq[u].a00, -y01 * tq[u].a01);
+      const double z01 = fma(y00, tq[u].a01, y01 * tq[u].a11);
+      const double z10 = fma(y10, tq[u].a00, -y11 * tq[u].a01);
+      const double z11 = fma(y10, tq[u].a01, y11 * tq[u].a11);
+      const int r0 = 2 * t, r1 = 2 * t + 1, c0 = 2 * u, c1 = 2 * u + 1;
+      auto add = [&](int r, int c, double z) {
+        return z + gp[r] * fb[c] + fb[r] * gp[c] + s * fb[r] * fb[c];
+      };
+      Lam[sidx(r0, c0, D)] = add(r0, c0, z00);
+      Lam[sidx(r0, c1, D)] = add(r0, c1, z01);
+      if (t != u) Lam[sidx(r1, c0, D)] = add(r1, c0, z10);
+      Lam[sidx(r1, c1, D)] = add(r1, c1, z11);
+    }
+}
+
+// back through a measurement update (u = P h of the predicted covariance,
+// S = h.u + R, v = y - h.m of the predicted mean); no-op without a measurement
+template <class Dm>
+GPD void bf_update(double* lam, double* Lam, const double* u, const Obs& o, double S, double v) {
+  constexpr int M = Dm::M, J = Dm::J, NX = Dm::NX, D = Dm::D;
+  if (!o.has) return;
+  double hv[D];
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    hv[2 * t] = o.b;
+    hv[2 * t + 1] = 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < J; ++j) hv[NX + j] = o.a[j];
+  const double iS = 1.0 / S;
+  double ul = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) ul = fma(u[i], lam[i], ul);
+  const double c1 = (v - ul) * iS;
+#pragma unroll
+  for (int i = 0; i < D; ++i) lam[i] = fma(hv[i], c1, lam[i]);
+  // w = Lambda u / S, c = u^T Lambda u / S^2 + 1 / S
+  double w[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) {
-    double v = m[i];
+    double a = 0.0;
 #pragma unroll
-    for (int k = 0; k < D; ++k) v = fma(Y[k * D + i], dm[k], v);
-    m[i] = v;
+    for (int k = 0; k < D; ++k) a = fma(Lam[sidx(i, k, D)], u[k], a);
+    w[i] = a * iS;
   }
-  // P <- P + G (Ps - Pm) G^T
-  double dP[D * D];
+  double uw = 0.0;
 #pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int j = 0; j < D; ++j) dP[i * D + j] = (act[i] && act[j]) ? Ps[sidx(i, j, D)] - Pm[sidx(i, j, D)] : 0.0;
-  double T2[D * D];  // dP G^T = dP Y
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-      double v = 0.0;
-#pragma unroll
-      for (int k = 0; k < D; ++k) v = fma(dP[i * D + k], Y[k * D + c], v);
-      T2[i * D + c] = v;
-    }
+  for (int i = 0; i < D; ++i) uw = fma(u[i], w[i], uw);
+  const double c = (uw + 1.0) * iS;
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int j = i; j < D; ++j) {
-      double v = P[sidx(i, j, D)];
-#pragma unroll
-      for (int k = 0; k < D; ++k) v = fma(Y[k * D + i], T2[k * D + j], v);
-      P[sidx(i, j, D)] = v;
+      double& L = Lam[sidx(i, j, D)];
+      L = fma(c * hv[i], hv[j], fma(-hv[i], w[j], fma(-w[i], hv[j], L)));
     }
-  (void)J;
-  return ok;
+}
+
+// back through the closing of an exposure's integrator
+template <class Dm>
+GPD void bf_close(double* lam, double* Lam, uint32_t info) {
+  constexpr int J = Dm::J, NX = Dm::NX, D = Dm::D;
+  const bool end = ev_kind(info) == EV_END;
+  const uint32_t slot = ev_slot(info);
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const bool z = end && (uint32_t)j == slot;
+    lam[NX + j] = z ? 0.0 : lam[NX + j];
+#pragma unroll
+    for (int i = 0; i < D; ++i) Lam[sidx(i, NX + j, D)] = z ? 0.0 : Lam[sidx(i, NX + j, D)];
+  }
+}
+
+// posterior of h.x at a point with forward moments (m, P) and adjoint pair
+// (lambda, Lambda), given u = P h:  mean h.m + u.lambda, variance h.u - u^T Lambda u
+template <class Dm>
+GPD void bf_posterior(double hm, double hu, const double* u, const double* lam, const double* Lam, double& mean,
+                      double& var) {
+  constexpr int D = Dm::D;
+  double ul = 0.0, uLu = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    ul = fma(u[i], lam[i], ul);
+    double a = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) a = fma(Lam[sidx(i, k, D)], u[k], a);
+    uLu = fma(u[i], a, uLu);
+  }
+  mean = hm + ul;
+  var = hu - uLu;
 }
 
 // ---------------------------------------------------------------------------

@@ -295,49 +295,53 @@ __global__ __launch_bounds__(WAVE) void k_plain(DevPlan p, DevParams pr, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// smoother: forward pass storing the filtered state after each event's
-// update (before its integrator is closed), then the RTS sweep backward from
-// the smoothed state at the chunk's end, with the exposure-averaged
+// smoother (Sec. 3.2.2, Algorithm 1): a forward pass storing each event's
+// predicted state, then the backward sweep of the adjoint pair (lambda,
+// Lambda) from its value at the chunk's end, with the exposure-averaged
 // posterior at every measurement and the latent posterior at the test times
-// that fall in the chunk (Algorithm 1)
+// that fall in the chunk
 // ---------------------------------------------------------------------------
-template <class Dm>
-__device__ __forceinline__ void latent_out(const double* m, const double* P, double& mean, double& var) {
-  double mu = 0.0, v = 0.0;
-#pragma unroll
-  for (int t = 0; t < Dm::M; ++t) {
-    mu += m[2 * t];
-#pragma unroll
-    for (int u = 0; u < Dm::M; ++u) v += P[sidx(2 * t, 2 * u, Dm::D)];
-  }
-  mean = mu;
-  var = v;
-}
 
-// posterior of the latent process at a test time between a filtered state
-// (prev, already closed) and the smoothed next event: predict over a, then one
-// RTS step back from the next event over b (open: integrators open over both)
+// latent posterior at a test time between two events: the forward moments
+// (m0, P0) after the earlier event predicted over a, the adjoint pair of the
+// later event (before its update) carried back over b; open: the integrators
+// open over the whole step
 template <class Dm>
-__device__ __forceinline__ void interp_test(const double* pm, const double* pP, const TermConst* tc, const double* coef,
-                                            double a, double b, uint32_t open, const double* ms, const double* Ps,
-                                            double& mean, double& var, bool& ok) {
-  constexpr int D = Dm::D, NP = Dm::NP;
-  if (b == 0.0) {
-    latent_out<Dm>(ms, Ps, mean, var);
-    return;
-  }
+__device__ __forceinline__ void bf_test(const double* m0, const double* P0, const TermConst* tc, const double* coef,
+                                        double a, double b, uint32_t open, const double* lam0, const double* Lam0,
+                                        double& mean, double& var) {
+  constexpr int M = Dm::M, D = Dm::D, NP = Dm::NP;
   double m[D], P[NP];
 #pragma unroll
-  for (int i = 0; i < D; ++i) m[i] = pm[i];
+  for (int i = 0; i < D; ++i) m[i] = m0[i];
 #pragma unroll
-  for (int i = 0; i < NP; ++i) P[i] = pP[i];
-  TermQ tq[Dm::M];
-  discretise<Dm::M>(tc, coef, a, tq);
+  for (int i = 0; i < NP; ++i) P[i] = P0[i];
+  TermQ tq[M];
+  discretise<M>(tc, coef, a, tq);
   predict_mean<Dm>(m, tq, open);
   predict_cov<Dm>(P, tq, open);
-  discretise<Dm::M>(tc, coef, b, tq);
-  ok = rts_step<Dm>(m, P, tq, open, 0u, ms, Ps) && ok;
-  latent_out<Dm>(m, P, mean, var);
+  double l[D], L[NP];
+#pragma unroll
+  for (int i = 0; i < D; ++i) l[i] = lam0[i];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) L[i] = Lam0[i];
+  discretise<M>(tc, coef, b, tq);
+  bf_predict<Dm>(l, L, tq, open);
+  // h = sum of the SHO x components
+  double u[D], hm = 0.0, hu = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    double v = 0.0;
+#pragma unroll
+    for (int t = 0; t < M; ++t) v += P[sidx(i, 2 * t, D)];
+    u[i] = v;
+  }
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    hm += m[2 * t];
+    hu += u[2 * t];
+  }
+  bf_posterior<Dm>(hm, hu, u, l, L, mean, var);
 }
 
 template <int J>
@@ -352,7 +356,7 @@ __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const 
   const int seg = p.seg_order ? p.seg_order[blockIdx.x] : (int)blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t b = p.seg_series[seg];
-  const int32_t nch = p.seg_nch[seg], L = p.seg_len[seg];
+  const int32_t nch = p.seg_nch[seg];
   const int64_t ev0 = p.seg_ev0[seg];
   const bool active = lane < nch;
   const int64_t C = p.n_chunks;
@@ -366,27 +370,18 @@ __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const 
   const double jit2 = jit * jit;
   double* rb = rec + ev0 * F;
   auto ev = [&](int32_t k) { return ev0 + (int64_t)k * WAVE + lane; };
-
-  // forward: store the state after each event's update, before closing
-  double m[D], P[NP];
+  auto load_rec = [&](int32_t k, double* m, double* P) {
 #pragma unroll
-  for (int i = 0; i < D; ++i) m[i] = (i < NX && active) ? bstate[i * C + c] : 0.0;
+    for (int f = 0; f < D; ++f) m[f] = rb[((int64_t)k * F + f) * WAVE + lane];
 #pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int j = i; j < D; ++j) P[sidx(i, j, D)] = (j < NX && active) ? bstate[(NX + sidx(i, j, NX)) * C + c] : 0.0;
-  for (int32_t k = 0; k < len; ++k) {
-    const EvRaw cur = fetch_event(p, ev(k));
-    const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2);
-    TermQ tq[M];
-    discretise<M>(tc, coef, cur.dt, tq);
-    const uint32_t open = ev_open(cur.info);
-    predict_mean<Dm>(m, tq, open);
-    predict_cov<Dm>(P, tq, open);
+    for (int f = 0; f < NP; ++f) P[f] = rb[((int64_t)k * F + D + f) * WAVE + lane];
+  };
+  // the update of one event applied to its predicted moments, then its close
+  auto update_close = [&](const EvRaw& e, double* m, double* P) {
+    const Obs o = make_obs<Dm>(e.info, e.y, e.r, e.invd, jit2);
     double u[D];
     obs_gain<Dm>(P, o, u);
-    const double S = obs_dot<Dm>(u, o) + o.R;
-    const double iS = 1.0 / S;
+    const double iS = 1.0 / (obs_dot<Dm>(u, o) + o.R);
     const double viS = (o.y - obs_dot<Dm>(m, o)) * iS;
 #pragma unroll
     for (int i = 0; i < D; ++i) m[i] = fma(u[i], viS, m[i]);
@@ -396,129 +391,142 @@ __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const 
 #pragma unroll
       for (int j = i; j < D; ++j) P[sidx(i, j, D)] = fma(-ui, u[j], P[sidx(i, j, D)]);
     }
+    close_slot<Dm>(m, P, e.info);
+  };
+
+  // forward: store the predicted moments of each event
+  double m[D], P[NP];
+#pragma unroll
+  for (int i = 0; i < D; ++i) m[i] = (i < NX && active) ? bstate[i * C + c] : 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = i; j < D; ++j) P[sidx(i, j, D)] = (j < NX && active) ? bstate[(NX + sidx(i, j, NX)) * C + c] : 0.0;
+  for (int32_t k = 0; k < len; ++k) {
+    const EvRaw cur = fetch_event(p, ev(k));
+    TermQ tq[M];
+    discretise<M>(tc, coef, cur.dt, tq);
+    const uint32_t open = ev_open(cur.info);
+    predict_mean<Dm>(m, tq, open);
+    predict_cov<Dm>(P, tq, open);
 #pragma unroll
     for (int f = 0; f < D; ++f) rb[((int64_t)k * F + f) * WAVE + lane] = m[f];
 #pragma unroll
     for (int f = 0; f < NP; ++f) rb[((int64_t)k * F + D + f) * WAVE + lane] = P[f];
-    close_slot<Dm>(m, P, cur.info);
+    update_close(cur, m, P);
   }
 
-  // backward
-  bool ok = true;
-  double ms[D], Ps[NP];
+  const int64_t tlo = active ? ts.chunk_t0[c] : 0;
+  int64_t tp = active ? ts.chunk_t0[c + 1] - 1 : -1;
+  // test times after the chunk's last event (only at the end of a series):
+  // prediction from the final filtered state, which holds all the data
+  if (len > 0) {
+    const double tl = p.t[ev(len - 1)];
+    while (tp >= tlo && ts.t[tp] > tl) {
+      double mm[D], PP[NP];
 #pragma unroll
-  for (int i = 0; i < D; ++i) ms[i] = (i < NX && active) ? bsmooth[i * C + c] : 0.0;
+      for (int i = 0; i < D; ++i) mm[i] = m[i];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) PP[i] = P[i];
+      TermQ tqq[M];
+      discretise<M>(tc, coef, ts.t[tp] - tl, tqq);
+      predict_mean<Dm>(mm, tqq, 0u);
+      predict_cov<Dm>(PP, tqq, 0u);
+      double mean = 0.0, var = 0.0;
+#pragma unroll
+      for (int t = 0; t < M; ++t) {
+        mean += mm[2 * t];
+#pragma unroll
+        for (int u = 0; u < M; ++u) var += PP[sidx(2 * t, 2 * u, D)];
+      }
+      const int64_t o = ts.out_index[tp];
+      mean_test[o] = mean;
+      var_test[o] = var;
+      --tp;
+    }
+  }
+
+  // backward: the adjoint pair after the chunk's last event (zero at the end
+  // of a series), carried back through every event
+  double lam[D], Lam[NP];
+#pragma unroll
+  for (int i = 0; i < D; ++i) lam[i] = (i < NX && active) ? bsmooth[i * C + c] : 0.0;
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
-    for (int j = i; j < D; ++j) Ps[sidx(i, j, D)] = (j < NX && active) ? bsmooth[(NX + sidx(i, j, NX)) * C + c] : 0.0;
-  const int64_t tlo = active ? ts.chunk_t0[c] : 0;
-  int64_t tp = active ? ts.chunk_t0[c + 1] - 1 : -1;
-  const bool last_chunk = active && (c + 1 == (int64_t)p.series_chunk0[b] + p.series_nch[b]);
-  double t_next = 0.0;
-  uint32_t open_next = 0u;
-  double dt_next = 0.0;
+    for (int j = i; j < D; ++j) Lam[sidx(i, j, D)] = (j < NX && active) ? bsmooth[(NX + sidx(i, j, NX)) * C + c] : 0.0;
   for (int32_t k = len - 1; k >= 0; --k) {
     const EvRaw cur = fetch_event(p, ev(k));
     const double tk = p.t[ev(k)];
-#pragma unroll
-    for (int f = 0; f < D; ++f) m[f] = rb[((int64_t)k * F + f) * WAVE + lane];
-#pragma unroll
-    for (int f = 0; f < NP; ++f) P[f] = rb[((int64_t)k * F + D + f) * WAVE + lane];
-    // the filtered state after this event, closed
-    double mc[D], Pc[NP];
-#pragma unroll
-    for (int i = 0; i < D; ++i) mc[i] = m[i];
-#pragma unroll
-    for (int i = 0; i < NP; ++i) Pc[i] = P[i];
-    close_slot<Dm>(mc, Pc, cur.info);
-    // test times after this event
-    while (tp >= tlo && ts.t[tp] > tk) {
-      const double tq = ts.t[tp];
-      double mean, var;
-      if (k == len - 1) {
-        // after the last event of the series: prediction from the final state
-        double mm[D], PP[NP];
-#pragma unroll
-        for (int i = 0; i < D; ++i) mm[i] = mc[i];
-#pragma unroll
-        for (int i = 0; i < NP; ++i) PP[i] = Pc[i];
-        TermQ tqq[M];
-        discretise<M>(tc, coef, tq - tk, tqq);
-        predict_mean<Dm>(mm, tqq, 0u);
-        predict_cov<Dm>(PP, tqq, 0u);
-        latent_out<Dm>(mm, PP, mean, var);
-      } else {
-        interp_test<Dm>(mc, Pc, tc, coef, tq - tk, t_next - tq, open_next, ms, Ps, mean, var, ok);
-      }
-      const int64_t o = ts.out_index[tp];
-      mean_test[o] = mean;
-      var_test[o] = var;
-      --tp;
-    }
-    (void)last_chunk;
-    // RTS step back from the next state (the boundary after the last event)
+    bf_close<Dm>(lam, Lam, cur.info);
     {
-      TermQ tq[M];
-      discretise<M>(tc, coef, (k == len - 1) ? 0.0 : dt_next, tq);
-      const uint32_t zmask = (ev_kind(cur.info) == EV_END) ? (1u << ev_slot(cur.info)) : 0u;
-      ok = rts_step<Dm>(m, P, tq, (k == len - 1) ? 0u : open_next, zmask, ms, Ps) && ok;
-    }
-    // posterior at the measurement
-    const uint32_t kind = ev_kind(cur.info);
-    if (kind == EV_END || kind == EV_INSTANT) {
-      const int64_t n = p.meas[ev(k)];
-      double mean = 0.0, var = 0.0;
-      if (kind == EV_END) {
-        const uint32_t j = ev_slot(cur.info);
-#pragma unroll
-        for (int jj = 0; jj < J; ++jj)
-          if ((uint32_t)jj == j) {
-            mean = m[NX + jj] * cur.invd;
-            var = P[sidx(NX + jj, NX + jj, D)] * cur.invd * cur.invd;
-          }
-      } else {
-        latent_out<Dm>(m, P, mean, var);
-      }
-      if (mean_data) mean_data[n] = ok ? mean : __builtin_nan("");
-      if (var_data) var_data[n] = ok ? var : __builtin_nan("");
-    }
-#pragma unroll
-    for (int i = 0; i < D; ++i) ms[i] = m[i];
-#pragma unroll
-    for (int i = 0; i < NP; ++i) Ps[i] = P[i];
-    t_next = tk;
-    open_next = ev_open(cur.info);
-    dt_next = cur.dt;
-  }
-  // test times before the chunk's first event: from the boundary state (or,
-  // before the series' first event, from the prior at the test time)
-  if (active && tp >= tlo) {
-    const bool first = p.chunk_first[c];
-    double pm[D], pP[NP];
-#pragma unroll
-    for (int i = 0; i < D; ++i) pm[i] = (i < NX && !first) ? bstate[i * C + c] : 0.0;
-#pragma unroll
-    for (int i = 0; i < D; ++i)
-#pragma unroll
-      for (int j = i; j < D; ++j) pP[sidx(i, j, D)] = (j < NX && !first) ? bstate[(NX + sidx(i, j, NX)) * C + c] : 0.0;
-    if (first) {
-#pragma unroll
-      for (int t = 0; t < M; ++t) {
-        pP[sidx(2 * t, 2 * t, D)] = tc[t].sigma * tc[t].sigma;
-        pP[sidx(2 * t + 1, 2 * t + 1, D)] = tc[t].sigma * tc[t].sigma;
+      double mp[D], Pp[NP];
+      load_rec(k, mp, Pp);
+      const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2);
+      double u[D];
+      obs_gain<Dm>(Pp, o, u);
+      const double hu = obs_dot<Dm>(u, o), hm = obs_dot<Dm>(mp, o);
+      bf_update<Dm>(lam, Lam, u, o, hu + o.R, o.y - hm);
+      // posterior at the measurement (the exposure average, or the latent
+      // process for an instantaneous one): the same h as the update
+      if (o.has) {
+        double mean, var;
+        bf_posterior<Dm>(hm, hu, u, lam, Lam, mean, var);
+        const int64_t n = p.meas[ev(k)];
+        if (mean_data) mean_data[n] = mean;
+        if (var_data) var_data[n] = var;
       }
     }
-    const double tprev = ts.chunk_tprev[c];
-    while (tp >= tlo) {
-      const double tq = ts.t[tp];
-      double mean, var;
-      interp_test<Dm>(pm, pP, tc, coef, first ? 0.0 : tq - tprev, t_next - tq, open_next, ms, Ps, mean, var, ok);
-      const int64_t o = ts.out_index[tp];
-      mean_test[o] = mean;
-      var_test[o] = var;
-      --tp;
+    // test times between the previous event (or the chunk's start) and this one
+    if (k > 0) {
+      const double tprev = p.t[ev(k - 1)];
+      if (tp >= tlo && ts.t[tp] > tprev) {
+        double mf[D], Pf[NP];
+        load_rec(k - 1, mf, Pf);
+        update_close(fetch_event(p, ev(k - 1)), mf, Pf);
+        while (tp >= tlo && ts.t[tp] > tprev) {
+          const double tq = ts.t[tp];
+          double mean, var;
+          bf_test<Dm>(mf, Pf, tc, coef, tq - tprev, tk - tq, ev_open(cur.info), lam, Lam, mean, var);
+          const int64_t o = ts.out_index[tp];
+          mean_test[o] = mean;
+          var_test[o] = var;
+          --tp;
+        }
+      }
+    } else if (tp >= tlo) {
+      // before the chunk's first event: from the boundary state, or from the
+      // prior before the series' first event
+      const bool first = p.chunk_first[c];
+      double pm[D], pP[NP];
+#pragma unroll
+      for (int i = 0; i < D; ++i) pm[i] = (i < NX && !first) ? bstate[i * C + c] : 0.0;
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = i; j < D; ++j) pP[sidx(i, j, D)] = (j < NX && !first) ? bstate[(NX + sidx(i, j, NX)) * C + c] : 0.0;
+      if (first) {
+#pragma unroll
+        for (int t = 0; t < M; ++t) {
+          pP[sidx(2 * t, 2 * t, D)] = tc[t].sigma * tc[t].sigma;
+          pP[sidx(2 * t + 1, 2 * t + 1, D)] = tc[t].sigma * tc[t].sigma;
+        }
+      }
+      const double tprev = ts.chunk_tprev[c];
+      while (tp >= tlo) {
+        const double tq = ts.t[tp];
+        double mean, var;
+        bf_test<Dm>(pm, pP, tc, coef, first ? 0.0 : tq - tprev, tk - tq, ev_open(cur.info), lam, Lam, mean, var);
+        const int64_t o = ts.out_index[tp];
+        mean_test[o] = mean;
+        var_test[o] = var;
+        --tp;
+      }
     }
+    // back through this event's predict
+    TermQ tq[M];
+    discretise<M>(tc, coef, cur.dt, tq);
+    bf_predict<Dm>(lam, Lam, tq, ev_open(cur.info));
   }
 }
 

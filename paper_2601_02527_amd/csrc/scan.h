@@ -20,7 +20,7 @@ struct ScanWork {
   double* segfut;      // future information after each segment (J packed, then eta)
   double* bstate;      // filtered state at each chunk start
   double* badj;        // adjoint of the state at each chunk end
-  double* bsmooth;     // smoothed state at each chunk end (may be null)
+  double* bsmooth;     // smoother adjoint pair (lambda, Lambda) at each chunk end (may be null)
   double* segll;       // log-likelihood of each segment
   int32_t* segok;      // 1 when every combination of the segment succeeded
 };

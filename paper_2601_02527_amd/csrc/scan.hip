@@ -12,8 +12,9 @@
 //  k_seg_fix    one wavefront per segment: the filtered state at every chunk
 //               boundary, each chunk's log-likelihood contribution, and, for
 //               the gradient and the smoother, the future information at each
-//               chunk's end, from which the adjoint and the smoothed moments
-//               of the boundary state follow.
+//               chunk's end, from which follow the gradient of the future
+//               likelihood with respect to the boundary moments and the
+//               smoother's adjoint pair there.
 //  k_series_finish  sums the per-segment log-likelihoods of each series.
 #include <hip/hip_runtime.h>
 
@@ -256,17 +257,18 @@ __global__ __launch_bounds__(WAVE) void k_seg_fix(DevPlan p, const double* __res
 #pragma unroll
         for (int i = 0; i < N; ++i) ef[i] = en[i];
       }
-      double mb[N], Pb[NP], mh[N], Ph[NP];
-      boundary_adjoint<N>(mn, Pn, Jf, ef, mb, Pb, bsmooth ? mh : nullptr, Ph, ok);
+      double mb[N], Pb[NP], Lb[NP];
+      boundary_adjoint<N>(mn, Pn, Jf, ef, mb, Pb, bsmooth ? Lb : nullptr, ok);
 #pragma unroll
       for (int i = 0; i < N; ++i) badj[(int64_t)i * C + c] = mb[i];
 #pragma unroll
       for (int i = 0; i < NP; ++i) badj[(int64_t)(N + i) * C + c] = Pb[i];
       if (bsmooth) {
+        // the smoother's adjoint pair (lambda, Lambda) after the chunk
 #pragma unroll
-        for (int i = 0; i < N; ++i) bsmooth[(int64_t)i * C + c] = mh[i];
+        for (int i = 0; i < N; ++i) bsmooth[(int64_t)i * C + c] = mb[i];
 #pragma unroll
-        for (int i = 0; i < NP; ++i) bsmooth[(int64_t)(N + i) * C + c] = Ph[i];
+        for (int i = 0; i < NP; ++i) bsmooth[(int64_t)(N + i) * C + c] = Lb[i];
       }
     }
   }

@@ -80,3 +80,30 @@ def test_parameter_regimes(lib):
                          for i in range(b.n_series)])
     out, plan = _run(lib, b, tt, to, chunk_min=3, chunk_target=5)
     _check(b, out, tt, to)
+
+
+def test_long_series_many_segments(lib):
+    """A 45000-exposure series with the mixed-cadence recipe of the 1e5-point
+    smoothing workload (a fast Q=30 term beside a Q=1/sqrt(2) term): under
+    default chunking, and with one-exposure chunks so that the scan over
+    segment totals runs several segments per lane.  The series holds exposures
+    that start within a second of each other, whose integrators are nearly
+    equal: a backward sweep that inverts the predicted covariance loses
+    accuracy there, and errors in the information form of the compositions
+    show up here as non-finite or inaccurate smoothed moments."""
+    b = W.long_100k(n=45000, n_test=4500, T=165.0)
+    s = b.series(0)
+    ref = kalman.smooth(s["ts"], s["te"], s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"], s["jitter"],
+                        t_test=b.t_test)
+    k0 = float(np.sum(np.asarray(s["sigma"]) ** 2))
+    for opt in (dict(), dict(chunk_min=1, chunk_target=1)):
+        out, plan = _run(lib, b, b.t_test, b.test_offsets, **opt)
+        st = plan.stats()
+        if opt:
+            assert st["n_segments"] > 64
+        L, mt, vt, md, vd = ref
+        errs = (np.max(np.abs(out["mean_data"] - md)) / np.sqrt(k0), np.max(np.abs(out["var_data"] - vd)) / k0,
+                np.max(np.abs(out["mean_test"] - mt)) / np.sqrt(k0), np.max(np.abs(out["var_test"] - vt)) / k0)
+        print(opt, st["n_segments"], errs)
+        assert all(np.isfinite(errs)) and max(errs) < TOL, (opt, errs)
+        assert abs(out["loglik"][0] - L) < 1e-9 * abs(L)
