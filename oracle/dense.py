@@ -163,6 +163,29 @@ def loglik(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, K=None):
     return float(-0.5 * y @ alpha - np.sum(np.log(np.diag(cf[0]))) - 0.5 * len(y) * _LOG2PI)
 
 
+def posterior_terms(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=None):
+    """Component-wise latent posterior at t_test (Appendix C, component-wise
+    predictive means and variances): for each term m the cross-covariance
+    K_{m,*} of that term alone with the data, mean K_{m,*}^T K_y^-1 y and
+    variance sigma_m^2 - K_{m,*}^T K_y^-1 K_{m,*}.  Returns (mean, var), each
+    [n_test, M], and the per-term cross-covariances [M][n, n_test]."""
+    sigma, omega0, quality = (np.atleast_1d(np.asarray(a, dtype=np.float64)) for a in (sigma, omega0, quality))
+    K = covariance(ts, te, sigma, omega0, quality)
+    Ky = K + np.diag(np.asarray(yerr) ** 2 + jitter ** 2)
+    cf = cho_factor(Ky, lower=True)
+    alpha = cho_solve(cf, np.asarray(y, dtype=np.float64))
+    M = len(sigma)
+    mean = np.zeros((len(t_test), M))
+    var = np.zeros((len(t_test), M))
+    Ks = []
+    for m in range(M):
+        Km = cross_covariance(t_test, ts, te, sigma[m:m + 1], omega0[m:m + 1], quality[m:m + 1])
+        mean[:, m] = Km.T @ alpha
+        var[:, m] = sigma[m] ** 2 - np.sum(Km * cho_solve(cf, Km), axis=0)
+        Ks.append(Km)
+    return mean, var, Ks
+
+
 def posterior(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=None):
     """(mean_data, var_data, mean_test, var_test): exposure-averaged
     posterior at the data and latent posterior at t_test."""

@@ -25,6 +25,9 @@
  *   - log-likelihood from innovations ............... Sec. 2.4
  *   - integrated RTS smoother ....................... Sec. 3.2.2
  *   - prediction at arbitrary times ................. Sec. 2.5, Algorithm 1
+ *   - component-wise prediction (H^m applied to the
+ *     smoothed state) ............................... Appendix C, component-
+ *                                                     wise predictive means
  *
  * How the discretisation is computed (a method of this file, not the
  * paper's closed forms): per SHO term, in time scaled by omega0 and state
@@ -573,10 +576,21 @@ static void latent(const model_t* md, const state_t* s, double* mean, double* va
   *var = (double)v;
 }
 
+/* posterior of each term's own process x_m (the component-wise prediction:
+ * the latent observation vector restricted to one term), row q of the
+ * [n_test][M] outputs */
+static void latent_terms(const model_t* md, const state_t* s, int64_t q, double* term_mean, double* term_var) {
+  if (!term_mean || !term_var) return;
+  for (int m = 0; m < md->M; ++m) {
+    term_mean[q * md->M + m] = (double)s->m[2 * m];
+    term_var[q * md->M + m] = (double)s->P[2 * m][2 * m];
+  }
+}
+
 int oracle_smooth(int64_t n, const double* ts, const double* te, const double* y, const double* yerr, const int32_t* slot_in,
                   int32_t M, const double* sigma, const double* omega0, const double* quality, double jitter, int64_t n_test,
                   const double* t_test, double* mean_test, double* var_test, double* mean_data, double* var_data,
-                  double* out_hilo) {
+                  double* term_mean, double* term_var, double* out_hilo) {
   model_t md;
   ev_t* ev = NULL;
   int64_t K = 0;
@@ -666,6 +680,7 @@ int oracle_smooth(int64_t n, const double* ts, const double* te, const double* y
       }
       rts_combine(D, Gx, &base, &nxs, &nxp, &out);
       latent(&md, &out, &mean_test[q], &var_test[q]);
+      latent_terms(&md, &out, q, term_mean, term_var);
       continue;
     }
     if (tq > ev[K - 1].t) {
@@ -673,6 +688,7 @@ int oracle_smooth(int64_t n, const double* ts, const double* te, const double* y
       assemble(&md, tq - ev[K - 1].t, A, Qa);
       predict(D, A, Qa, out.m, out.P);
       latent(&md, &out, &mean_test[q], &var_test[q]);
+      latent_terms(&md, &out, q, term_mean, term_var);
       continue;
     }
     /* first event with t >= tq */
@@ -686,6 +702,7 @@ int oracle_smooth(int64_t n, const double* ts, const double* te, const double* y
     }
     if (ev[lo].t == tq) {
       latent(&md, &smo[lo], &mean_test[q], &var_test[q]);
+      latent_terms(&md, &smo[lo], q, term_mean, term_var);
       continue;
     }
     const int64_t nx = lo, pv = lo - 1; /* ev[pv].t < tq < ev[nx].t */
@@ -700,6 +717,7 @@ int oracle_smooth(int64_t n, const double* ts, const double* te, const double* y
     state_t out;
     rts_combine(D, G, &star, &smo[nx], &nxp, &out);
     latent(&md, &out, &mean_test[q], &var_test[q]);
+      latent_terms(&md, &out, q, term_mean, term_var);
   }
   rc = OR_OK;
 done:

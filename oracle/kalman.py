@@ -47,7 +47,7 @@ def lib():
                                         ctypes.c_double, ctypes.c_int32, _dp]
             L.oracle_loglik.restype = ctypes.c_int
             L.oracle_smooth.argtypes = [ctypes.c_int64, _dp, _dp, _dp, _dp, _ip, ctypes.c_int32, _dp, _dp, _dp,
-                                        ctypes.c_double, ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, _dp]
+                                        ctypes.c_double, ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
             L.oracle_smooth.restype = ctypes.c_int
             _lib = L
     return _lib
@@ -114,8 +114,12 @@ def loglik(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, slots=None, extr
     return hi + lo
 
 
-def smooth(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=None, slots=None):
-    """Returns (loglik, mean_test, var_test, mean_data, var_data)."""
+def smooth(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=None, slots=None, terms=False):
+    """Returns (loglik, mean_test, var_test, mean_data, var_data), and with
+    terms=True also the per-term latent posterior at t_test (term_mean,
+    term_var, each [n_test, M]: H^m applied to the smoothed state, Appendix
+    C, component-wise predictive means and variances)."""
+    want_terms = terms
     arrs, terms, sl, slp = _prep(ts, te, y, yerr, sigma, omega0, quality, slots)
     n = len(arrs[0][0])
     tt = np.zeros(0) if t_test is None else np.ascontiguousarray(t_test, dtype=np.float64)
@@ -125,11 +129,15 @@ def smooth(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=None, slo
     vd = np.zeros(n)
     out = np.zeros(2)
     M = len(terms[0][0])
+    tm = np.zeros((len(tt), M))
+    tv = np.zeros((len(tt), M))
     rc = lib().oracle_smooth(n, arrs[0][1], arrs[1][1], arrs[2][1], arrs[3][1], slp, M, terms[0][1], terms[1][1],
                              terms[2][1], float(jitter), len(tt), _d(tt)[1], _d(mt)[1], _d(vt)[1], _d(md)[1], _d(vd)[1],
-                             _d(out)[1])
+                             _d(tm)[1] if want_terms else None, _d(tv)[1] if want_terms else None, _d(out)[1])
     if rc:
         raise OracleError(rc)
+    if want_terms:
+        return out[0] + out[1], mt, vt, md, vd, tm, tv
     return out[0] + out[1], mt, vt, md, vd
 
 

@@ -376,6 +376,73 @@ def test_prediction_far_from_data_reverts_to_prior():
 
 
 # ---------------------------------------------------------------------------
+# component-wise prediction (Appendix C, component-wise predictive means and
+# variances)
+# ---------------------------------------------------------------------------
+
+def test_dense_terms_reconstruct_the_total():
+    """The appendix's reconstruction: the total mean is the sum of the term
+    means, and the total variance is the sum of the term variances minus the
+    cross terms K_{m,*}^T K_y^-1 K_{l,*} over m != l (K_y: data covariance
+    with the noise)."""
+    b = W.random_small_batch(8, B=1, n_lo=40, n_hi=40, M=3, J=2)
+    s = b.series(0)
+    tt = np.linspace(s["ts"].min() - 0.2, s["te"].max() + 0.2, 17)
+    args = (s["ts"], s["te"], s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"], s["jitter"])
+    _, _, mt, vt = dense.posterior(*args, t_test=tt)
+    tm, tv, Ks = dense.posterior_terms(*args, t_test=tt)
+    K = dense.covariance(s["ts"], s["te"], s["sigma"], s["omega0"], s["quality"])
+    Ky = K + np.diag(np.asarray(s["yerr"]) ** 2 + s["jitter"] ** 2)
+    cross = np.zeros(len(tt))
+    for m in range(3):
+        for l in range(3):
+            if m != l:
+                cross += np.sum(Ks[m] * np.linalg.solve(Ky, Ks[l]), axis=0)
+    assert np.max(np.abs(tm.sum(axis=1) - mt)) < 1e-12
+    assert np.max(np.abs(tv.sum(axis=1) - cross - vt)) < 1e-12
+
+
+def test_dense_single_term_equals_total():
+    b = W.random_small_batch(9, B=1, n_lo=30, n_hi=30, M=1, J=2)
+    s = b.series(0)
+    tt = np.linspace(s["ts"].min() - 0.1, s["te"].max() + 0.1, 11)
+    args = (s["ts"], s["te"], s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"], s["jitter"])
+    _, _, mt, vt = dense.posterior(*args, t_test=tt)
+    tm, tv, _ = dense.posterior_terms(*args, t_test=tt)
+    assert np.max(np.abs(tm[:, 0] - mt)) < 1e-13
+    assert np.max(np.abs(tv[:, 0] - vt)) < 1e-13
+
+
+def test_kalman_terms_equal_dense_terms():
+    """H^m applied to the smoothed state (Kalman oracle) against the dense
+    component posterior, with test times before, between, at and after the
+    events, two terms and overlapping exposures."""
+    b = W.random_small_batch(5, B=1, n_lo=30, n_hi=30, M=2, J=3)
+    s = b.series(0)
+    tt = np.concatenate([s["ts"][:4], s["te"][-4:], np.linspace(s["ts"].min() - 0.5, s["te"].max() + 0.5, 23)])
+    args = (s["ts"], s["te"], s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"], s["jitter"])
+    tm, tv, _ = dense.posterior_terms(*args, t_test=tt)
+    out = kalman.smooth(*args, t_test=tt, terms=True)
+    tm2, tv2 = out[5], out[6]
+    assert tm2.shape == (len(tt), 2)
+    assert np.max(np.abs(tm - tm2)) < 1e-9
+    assert np.max(np.abs(tv - tv2)) < 1e-9
+    # the totals are unchanged by asking for the terms
+    L, mt, vt, _, _ = kalman.smooth(*args, t_test=tt)
+    assert np.array_equal(out[1], mt) and np.array_equal(out[2], vt)
+
+
+def test_terms_far_from_data_revert_to_their_priors():
+    b = W.small_multi()
+    s = b.series(0)
+    args = (s["ts"], s["te"], s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"], 0.0)
+    out = kalman.smooth(*args, t_test=np.array([-1e3, 1e3]), terms=True)
+    sig = np.atleast_1d(np.asarray(s["sigma"], dtype=np.float64))
+    assert np.allclose(out[5], 0.0, atol=1e-12)
+    assert np.allclose(out[6], np.broadcast_to(sig ** 2, out[6].shape), rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
 # gradients
 # ---------------------------------------------------------------------------
 
