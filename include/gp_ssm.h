@@ -112,8 +112,8 @@ int gp_ssm_plan_loglik_grad(gp_ssm_plan* plan, int32_t n_terms, const double* si
                             const double* quality, const double* jitter, double* loglik, double* grad, int32_t* status,
                             void* stream);
 
-/* Posterior (RTS smoother, Sec. 3.2.2, and prediction at arbitrary times,
- * Sec. 2.5 Algorithm 1).  test_offsets[B+1] (host or device int64) delimits
+/* Posterior (the RTS smoother's result, Sec. 3.2.2, and prediction at
+ * arbitrary times, Sec. 2.5 Algorithm 1).  test_offsets[B+1] (host or device int64) delimits
  * each series' test times in t_test (device, any order within a series).
  * mean_test/var_test[test_offsets[B]] receive the posterior mean and
  * variance of the latent instantaneous f(t*).  mean_data/var_data[N] (may be
@@ -123,6 +123,19 @@ int gp_ssm_plan_smooth(gp_ssm_plan* plan, int32_t n_terms, const double* sigma, 
                        const double* quality, const double* jitter, const int64_t* test_offsets, const double* t_test,
                        double* mean_test, double* var_test, double* mean_data, double* var_data, double* loglik,
                        int32_t* status, void* stream);
+
+/* The same posterior with, in addition, each SHO term's own latent process
+ * at the test times (Appendix C, component-wise predictive means and
+ * variances: the observation vector restricted to term m, applied to the
+ * smoothed state).  term_mean/term_var[test_offsets[B] * n_terms] (device,
+ * both required when there are test times) hold row i = test time i of
+ * t_test, column m = term m; the row sums of term_mean equal mean_test.
+ * Other arguments as for gp_ssm_plan_smooth. */
+int gp_ssm_plan_smooth_terms(gp_ssm_plan* plan, int32_t n_terms, const double* sigma, const double* omega0,
+                             const double* quality, const double* jitter, const int64_t* test_offsets,
+                             const double* t_test, double* mean_test, double* var_test, double* term_mean,
+                             double* term_var, double* mean_data, double* var_data, double* loglik, int32_t* status,
+                             void* stream);
 
 /* Reference "plain" GPU filter: the same per-event device code, one series at
  * a time, one lane, no time splitting, one launch per series.  Computes the

@@ -27,8 +27,8 @@ ERRORS = {-1: "EINVAL", -2: "EDATA", -3: "EPARAM", -4: "EOVERLAP", -5: "ENUMERIC
 # every symbol include/gp_ssm.h declares
 EXPORTS = [
     "gp_ssm_plan_default_options", "gp_ssm_plan_create", "gp_ssm_plan_destroy", "gp_ssm_plan_get_stats",
-    "gp_ssm_plan_loglik", "gp_ssm_plan_loglik_grad", "gp_ssm_plan_smooth", "gp_ssm_plan_plain_loglik",
-    "gp_ssm_loglik", "gp_ssm_loglik_grad", "gp_ssm_smooth", "gp_ssm_profile_enable", "gp_ssm_profile_reset",
+    "gp_ssm_plan_loglik", "gp_ssm_plan_loglik_grad", "gp_ssm_plan_smooth", "gp_ssm_plan_smooth_terms",
+    "gp_ssm_plan_plain_loglik", "gp_ssm_loglik", "gp_ssm_loglik_grad", "gp_ssm_smooth", "gp_ssm_profile_enable", "gp_ssm_profile_reset",
     "gp_ssm_profile_read", "gp_ssm_last_error", "gp_ssm_version",
 ]
 
@@ -71,6 +71,7 @@ def library():
     L.gp_ssm_plan_loglik.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.gp_ssm_plan_loglik_grad.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
     L.gp_ssm_plan_smooth.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.gp_ssm_plan_smooth_terms.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.gp_ssm_plan_plain_loglik.argtypes = [vp, i64, i64, i32, vp, vp, vp, vp, vp, vp]
     L.gp_ssm_loglik.argtypes = [i64, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.gp_ssm_loglik_grad.argtypes = [i64, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -81,7 +82,8 @@ def library():
     L.gp_ssm_last_error.restype = ctypes.c_char_p
     L.gp_ssm_version.restype = ctypes.c_char_p
     for name in ("gp_ssm_plan_create", "gp_ssm_plan_get_stats", "gp_ssm_plan_loglik", "gp_ssm_plan_loglik_grad",
-                 "gp_ssm_plan_smooth", "gp_ssm_plan_plain_loglik", "gp_ssm_loglik", "gp_ssm_loglik_grad",
+                 "gp_ssm_plan_smooth", "gp_ssm_plan_smooth_terms", "gp_ssm_plan_plain_loglik", "gp_ssm_loglik",
+                 "gp_ssm_loglik_grad",
                  "gp_ssm_smooth", "gp_ssm_profile_enable", "gp_ssm_profile_reset", "gp_ssm_profile_read"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -194,7 +196,10 @@ class Plan:
                                                   _ptr(out), _stream()))
         return out
 
-    def smooth(self, sigma, omega0, quality, jitter, test_offsets, t_test, data=True):
+    def smooth(self, sigma, omega0, quality, jitter, test_offsets, t_test, data=True, terms=False):
+        """Posterior at the data and at the test times; with terms=True also
+        each term's latent posterior at the test times (term_mean, term_var:
+        [n_test, M])."""
         torch = _torch()
         M, s, w, q, j = self._params(sigma, omega0, quality, jitter)
         to = _dev(test_offsets, torch.int64)
@@ -205,9 +210,18 @@ class Plan:
         vd = torch.empty(self.n_meas, dtype=torch.float64, device="cuda") if data else None
         ll = torch.empty(self.n_series, dtype=torch.float64, device="cuda")
         st = torch.empty(self.n_series, dtype=torch.int32, device="cuda")
-        _check(library().gp_ssm_plan_smooth(self._h, M, _ptr(s), _ptr(w), _ptr(q), _ptr(j), _ptr(to), _ptr(tt),
-                                            _ptr(mt), _ptr(vt), _ptr(md), _ptr(vd), _ptr(ll), _ptr(st), _stream()))
-        return dict(mean_test=mt, var_test=vt, mean_data=md, var_data=vd, loglik=ll, status=st)
+        out = dict(mean_test=mt, var_test=vt, mean_data=md, var_data=vd, loglik=ll, status=st)
+        if terms:
+            tm = torch.empty((tt.numel(), M), dtype=torch.float64, device="cuda")
+            tv = torch.empty_like(tm)
+            _check(library().gp_ssm_plan_smooth_terms(self._h, M, _ptr(s), _ptr(w), _ptr(q), _ptr(j), _ptr(to),
+                                                      _ptr(tt), _ptr(mt), _ptr(vt), _ptr(tm), _ptr(tv), _ptr(md),
+                                                      _ptr(vd), _ptr(ll), _ptr(st), _stream()))
+            out.update(term_mean=tm, term_var=tv)
+        else:
+            _check(library().gp_ssm_plan_smooth(self._h, M, _ptr(s), _ptr(w), _ptr(q), _ptr(j), _ptr(to), _ptr(tt),
+                                                _ptr(mt), _ptr(vt), _ptr(md), _ptr(vd), _ptr(ll), _ptr(st), _stream()))
+        return out
 
 
 def _autograd_function():

@@ -529,10 +529,11 @@ int gp_ssm_plan_loglik_grad(gp_ssm_plan* pl, int32_t M, const double* sigma, con
   return 0;
 }
 
-int gp_ssm_plan_smooth(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0, const double* quality,
-                       const double* jitter, const int64_t* test_offsets, const double* t_test, double* mean_test,
-                       double* var_test, double* mean_data, double* var_data, double* loglik, int32_t* status,
-                       void* stream) {
+// the smoother with optional per-term outputs at the test times
+static int plan_smooth(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0, const double* quality,
+                const double* jitter, const int64_t* test_offsets, const double* t_test, double* mean_test,
+                double* var_test, double* term_mean, double* term_var, bool want_terms, double* mean_data,
+                double* var_data, double* loglik, int32_t* status, void* stream) {
   g_err.clear();
   if (!pl) return fail(GP_SSM_EINVAL, "null plan");
   if (!test_offsets) return fail(GP_SSM_EINVAL, "null test_offsets");
@@ -546,6 +547,7 @@ int gp_ssm_plan_smooth(gp_ssm_plan* pl, int32_t M, const double* sigma, const do
     if (to[q + 1] < to[q]) return fail(GP_SSM_EINVAL, "test_offsets not ascending");
   const int64_t T = to[B];
   if (T > 0 && (!t_test || !mean_test || !var_test)) return fail(GP_SSM_EINVAL, "null test arrays");
+  if (want_terms && T > 0 && (!term_mean || !term_var)) return fail(GP_SSM_EINVAL, "null term arrays");
   std::vector<double> tt(T);
   if (int rc = host_copy(t_test, sizeof(double) * T, tt.data(), s)) return rc;
   for (int64_t i = 0; i < T; ++i)
@@ -612,12 +614,31 @@ int gp_ssm_plan_smooth(gp_ssm_plan* pl, int32_t M, const double* sigma, const do
   dt.out_index = pl->tests_idx.as<int64_t>();
   dt.chunk_t0 = pl->tests_c0.as<int64_t>();
   dt.chunk_tprev = pl->tests_before.as<double>();
+  dt.term_mean = want_terms ? term_mean : nullptr;
+  dt.term_var = want_terms ? term_var : nullptr;
   Launch L{s};
   ks.smooth(L, p, pr, pl->bstate.as<double>(), pl->bsmooth.as<double>(), pl->rec.as<double>(), dt, mean_test, var_test,
             mean_data, var_data);
   HIP_TRY(hipGetLastError());
   if (!loglik) HIP_TRY(hipStreamSynchronize(s));  // the temporary log-likelihood buffer is freed on return
   return 0;
+}
+
+int gp_ssm_plan_smooth(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0, const double* quality,
+                       const double* jitter, const int64_t* test_offsets, const double* t_test, double* mean_test,
+                       double* var_test, double* mean_data, double* var_data, double* loglik, int32_t* status,
+                       void* stream) {
+  return plan_smooth(pl, M, sigma, omega0, quality, jitter, test_offsets, t_test, mean_test, var_test, nullptr,
+                     nullptr, false, mean_data, var_data, loglik, status, stream);
+}
+
+int gp_ssm_plan_smooth_terms(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0,
+                             const double* quality, const double* jitter, const int64_t* test_offsets,
+                             const double* t_test, double* mean_test, double* var_test, double* term_mean,
+                             double* term_var, double* mean_data, double* var_data, double* loglik, int32_t* status,
+                             void* stream) {
+  return plan_smooth(pl, M, sigma, omega0, quality, jitter, test_offsets, t_test, mean_test, var_test, term_mean,
+                     term_var, true, mean_data, var_data, loglik, status, stream);
 }
 
 int gp_ssm_plan_plain_loglik(gp_ssm_plan* pl, int64_t first, int64_t count, int32_t M, const double* sigma,

@@ -36,6 +36,8 @@ struct DevTests {
   const int64_t* out_index;   // where each result goes
   const int64_t* chunk_t0;    // first test of each chunk (n_chunks + 1 entries)
   const double* chunk_tprev;  // time of the previous chunk's last event
+  double* term_mean;          // per-term latent posterior [test][term], or null
+  double* term_var;
 };
 
 struct Launch {

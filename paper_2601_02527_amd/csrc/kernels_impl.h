@@ -305,11 +305,13 @@ __global__ __launch_bounds__(WAVE) void k_plain(DevPlan p, DevParams pr, int64_t
 // latent posterior at a test time between two events: the forward moments
 // (m0, P0) after the earlier event predicted over a, the adjoint pair of the
 // later event (before its update) carried back over b; open: the integrators
-// open over the whole step
+// open over the whole step.  With tmean/tvar (a row of M entries) also each
+// term's own process (Appendix C, component-wise predictive means and
+// variances: h = e_{x_m}).
 template <class Dm>
 __device__ __forceinline__ void bf_test(const double* m0, const double* P0, const TermConst* tc, const double* coef,
                                         double a, double b, uint32_t open, const double* lam0, const double* Lam0,
-                                        double& mean, double& var) {
+                                        double& mean, double& var, double* tmean, double* tvar) {
   constexpr int M = Dm::M, D = Dm::D, NP = Dm::NP;
   double m[D], P[NP];
 #pragma unroll
@@ -342,6 +344,15 @@ __device__ __forceinline__ void bf_test(const double* m0, const double* P0, cons
     hu += u[2 * t];
   }
   bf_posterior<Dm>(hm, hu, u, l, L, mean, var);
+  if (tmean) {
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+      double ut[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) ut[i] = P[sidx(i, 2 * t, D)];
+      bf_posterior<Dm>(m[2 * t], ut[2 * t], ut, l, L, tmean[t], tvar[t]);
+    }
+  }
 }
 
 template <int J>
@@ -442,6 +453,13 @@ __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const 
       const int64_t o = ts.out_index[tp];
       mean_test[o] = mean;
       var_test[o] = var;
+      if (ts.term_mean) {
+#pragma unroll
+        for (int t = 0; t < M; ++t) {
+          ts.term_mean[o * M + t] = mm[2 * t];
+          ts.term_var[o * M + t] = PP[sidx(2 * t, 2 * t, D)];
+        }
+      }
       --tp;
     }
   }
@@ -487,8 +505,9 @@ __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const 
         while (tp >= tlo && ts.t[tp] > tprev) {
           const double tq = ts.t[tp];
           double mean, var;
-          bf_test<Dm>(mf, Pf, tc, coef, tq - tprev, tk - tq, ev_open(cur.info), lam, Lam, mean, var);
           const int64_t o = ts.out_index[tp];
+          bf_test<Dm>(mf, Pf, tc, coef, tq - tprev, tk - tq, ev_open(cur.info), lam, Lam, mean, var,
+                      ts.term_mean ? ts.term_mean + o * M : nullptr, ts.term_var ? ts.term_var + o * M : nullptr);
           mean_test[o] = mean;
           var_test[o] = var;
           --tp;
@@ -516,8 +535,9 @@ __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const 
       while (tp >= tlo) {
         const double tq = ts.t[tp];
         double mean, var;
-        bf_test<Dm>(pm, pP, tc, coef, first ? 0.0 : tq - tprev, tk - tq, ev_open(cur.info), lam, Lam, mean, var);
         const int64_t o = ts.out_index[tp];
+        bf_test<Dm>(pm, pP, tc, coef, first ? 0.0 : tq - tprev, tk - tq, ev_open(cur.info), lam, Lam, mean, var,
+                    ts.term_mean ? ts.term_mean + o * M : nullptr, ts.term_var ? ts.term_var + o * M : nullptr);
         mean_test[o] = mean;
         var_test[o] = var;
         --tp;

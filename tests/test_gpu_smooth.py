@@ -15,9 +15,9 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-9
 
 
-def _run(lib, b, t_test, test_offsets, **opt):
+def _run(lib, b, t_test, test_offsets, terms=False, **opt):
     plan = lib.Plan(b.offsets, b.t_start, b.t_end, b.y, b.yerr, **opt)
-    out = plan.smooth(b.sigma, b.omega0, b.quality, b.jitter, test_offsets, t_test)
+    out = plan.smooth(b.sigma, b.omega0, b.quality, b.jitter, test_offsets, t_test, terms=terms)
     return {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}, plan
 
 
@@ -94,16 +94,49 @@ def test_long_series_many_segments(lib):
     b = W.long_100k(n=45000, n_test=4500, T=165.0)
     s = b.series(0)
     ref = kalman.smooth(s["ts"], s["te"], s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"], s["jitter"],
-                        t_test=b.t_test)
+                        t_test=b.t_test, terms=True)
     k0 = float(np.sum(np.asarray(s["sigma"]) ** 2))
     for opt in (dict(), dict(chunk_min=1, chunk_target=1)):
-        out, plan = _run(lib, b, b.t_test, b.test_offsets, **opt)
+        out, plan = _run(lib, b, b.t_test, b.test_offsets, terms=True, **opt)
         st = plan.stats()
         if opt:
             assert st["n_segments"] > 64
-        L, mt, vt, md, vd = ref
+        L, mt, vt, md, vd, tm, tv = ref
         errs = (np.max(np.abs(out["mean_data"] - md)) / np.sqrt(k0), np.max(np.abs(out["var_data"] - vd)) / k0,
-                np.max(np.abs(out["mean_test"] - mt)) / np.sqrt(k0), np.max(np.abs(out["var_test"] - vt)) / k0)
+                np.max(np.abs(out["mean_test"] - mt)) / np.sqrt(k0), np.max(np.abs(out["var_test"] - vt)) / k0,
+                np.max(np.abs(out["term_mean"] - tm)) / np.sqrt(k0), np.max(np.abs(out["term_var"] - tv)) / k0)
         print(opt, st["n_segments"], errs)
         assert all(np.isfinite(errs)) and max(errs) < TOL, (opt, errs)
         assert abs(out["loglik"][0] - L) < 1e-9 * abs(L)
+
+
+@pytest.mark.parametrize("opt", [dict(), dict(chunk_min=1, chunk_target=1), dict(single_chunk=1)])
+def test_component_posteriors(lib, opt):
+    """Each term's own latent posterior at test times before, between, at and
+    after the events (Appendix C, component-wise predictive means and
+    variances) against the oracle, with the totals unchanged and equal to the
+    row sums of the term means."""
+    b = W.random_small_batch(47, B=5, n_lo=3, n_hi=60, M=3, J=3)
+    rng = np.random.default_rng(11)
+    parts = []
+    for i in range(b.n_series):
+        s = b.series(i)
+        lo, hi = s["ts"].min(), s["te"].max()
+        parts.append(np.concatenate([rng.uniform(lo - 0.3, hi + 0.3, 19), s["ts"][:2], s["te"][-2:],
+                                     [lo - 4.0, hi + 4.0]]))
+    to = np.concatenate([[0], np.cumsum([len(p) for p in parts])]).astype(np.int64)
+    tt = np.concatenate(parts)
+    out, plan = _run(lib, b, tt, to, terms=True, **opt)
+    base, _ = _run(lib, b, tt, to, **opt)
+    assert np.array_equal(out["mean_test"], base["mean_test"]) and np.array_equal(out["var_test"], base["var_test"])
+    assert out["term_mean"].shape == (len(tt), 3)
+    for i in range(b.n_series):
+        s = b.series(i)
+        sl = slice(int(to[i]), int(to[i + 1]))
+        args = (s["ts"], s["te"], s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"], s["jitter"])
+        L, mt, vt, md, vd, tm, tv = kalman.smooth(*args, t_test=tt[sl], terms=True)
+        k0 = float(np.sum(np.asarray(s["sigma"]) ** 2))
+        e = (np.max(np.abs(out["term_mean"][sl] - tm)) / np.sqrt(k0), np.max(np.abs(out["term_var"][sl] - tv)) / k0,
+             np.max(np.abs(out["term_mean"][sl].sum(axis=1) - out["mean_test"][sl])) / np.sqrt(k0))
+        print(i, e)
+        assert max(e) < TOL, (i, e)
