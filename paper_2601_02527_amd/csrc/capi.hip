@@ -95,14 +95,14 @@ __global__ void k_prep(int64_t B, int M, const double* __restrict__ sigma, const
   if (j < B) jit[j] = jitter ? jitter[j] : 0.0;
 }
 
-// gradient partials of a series' segments summed: one wavefront per series,
-// lane l takes segments l, l + 64, ..., then a fixed-order wave reduction
+// gradient partials of a series' work waves summed: one wavefront per series,
+// lane l takes waves l, l + 64, ..., then a fixed-order wave reduction
 __global__ __launch_bounds__(WAVE) void k_reduce_grad(DevPlan p, int M, const double* __restrict__ gpart,
                                                       const int32_t* __restrict__ status, double* __restrict__ grad) {
   const int64_t b = blockIdx.x;
   const int lane = threadIdx.x;
-  const int64_t S = p.n_seg;
-  const int32_t s0 = p.series_seg0[b], n = p.series_nseg[b];
+  const int64_t S = p.n_wv;
+  const int32_t s0 = p.series_wv0[b], n = p.series_nwv[b];
   const int G = 3 * M + 1;
   const bool good = status == nullptr || status[b] == 0;
   for (int f = 0; f < G; ++f) {
@@ -198,17 +198,18 @@ struct gp_ssm_plan {
   int device = 0;
   HostPlan host;
   DBuf dt, t, y, r, invd, info, meas;
-  DBuf seg_series, seg_chunk0, seg_nch, seg_len, seg_ev0;
-  DBuf chunk_len, chunk_series, chunk_seg, chunk_first;
-  DBuf series_chunk0, series_nch, series_seg0, series_nseg;
+  DBuf seg_chunk0, seg_nch;
+  DBuf wv_series, wv_nch, wv_len, wv_chunk, wv_ev0;
+  DBuf chunk_len, chunk_series, chunk_wv, chunk_lane, chunk_first;
+  DBuf series_chunk0, series_nch, series_seg0, series_nseg, series_wv0, series_nwv;
   // workspace
   DBuf tc, coef, jit, summ, bstate, badj, bsmooth, gpart, rec, status;
   DBuf pre, suf, segtot, segstate, segfut, segll, segok;
   DBuf tests_t, tests_idx, tests_c0, tests_before;
-  // launch order of the per-segment kernels (most expensive segment first):
-  // written on the host into pinned memory, copied on the call's stream;
-  // order_ev marks the copy so the buffer is not rewritten before it is done
-  DBuf seg_order;
+  // launch order of the work waves (most expensive first): written on the
+  // host into pinned memory, copied on the call's stream; order_ev marks the
+  // copy so the buffer is not rewritten before it is done
+  DBuf wv_order;
   int32_t* order_host = nullptr;
   hipEvent_t order_ev = nullptr;
 
@@ -229,23 +230,29 @@ struct gp_ssm_plan {
     p.invd = invd.as<double>();
     p.info = info.as<uint32_t>();
     p.meas = meas.as<int64_t>();
-    p.seg_series = seg_series.as<int32_t>();
     p.seg_chunk0 = seg_chunk0.as<int32_t>();
     p.seg_nch = seg_nch.as<int32_t>();
-    p.seg_len = seg_len.as<int32_t>();
-    p.seg_ev0 = seg_ev0.as<int64_t>();
+    p.wv_series = wv_series.as<int32_t>();
+    p.wv_nch = wv_nch.as<int32_t>();
+    p.wv_len = wv_len.as<int32_t>();
+    p.wv_chunk = wv_chunk.as<int32_t>();
+    p.wv_ev0 = wv_ev0.as<int64_t>();
     p.chunk_len = chunk_len.as<int32_t>();
     p.chunk_series = chunk_series.as<int32_t>();
-    p.chunk_seg = chunk_seg.as<int32_t>();
+    p.chunk_wv = chunk_wv.as<int32_t>();
+    p.chunk_lane = chunk_lane.as<int32_t>();
     p.chunk_first = chunk_first.as<uint8_t>();
     p.series_chunk0 = series_chunk0.as<int32_t>();
     p.series_nch = series_nch.as<int32_t>();
     p.series_seg0 = series_seg0.as<int32_t>();
     p.series_nseg = series_nseg.as<int32_t>();
-    p.seg_order = seg_order.as<int32_t>();
+    p.series_wv0 = series_wv0.as<int32_t>();
+    p.series_nwv = series_nwv.as<int32_t>();
+    p.wv_order = wv_order.as<int32_t>();
     p.n_series = host.n_series;
     p.n_chunks = host.n_chunks;
     p.n_seg = host.n_seg;
+    p.n_wv = host.n_wv;
     return p;
   }
 };
@@ -262,24 +269,24 @@ int check_device() {
 }
 
 // validates hyperparameters (host copies) and prepares them on the device
-// Launch order of the per-segment kernels.  Two or so wavefronts share each
-// SIMD over a launch, and a segment's cost varies with its series' terms: a
+// Launch order of the work waves.  Two or so wavefronts share each SIMD over a
+// launch, and a wave's cost varies with its series' terms: a
 // wavefront pays for the Taylor branch of a term at a step when any of its
 // lanes needs it, and for the closed-form branch when any lane needs that.
 // With p the fraction of the series' steps below the switch point, the
 // expected cost per step and term is C_SER (1 - (1-p)^64) + C_CLO (1 - p^64)
 // on top of W0 for the filter step; p comes from the series' step-length
-// distribution.  Dispatching the costliest segments first (longest
-// processing time first) evens out the SIMDs' loads.
+// distribution.  Dispatching the costliest waves first (longest processing
+// time first) evens out the SIMDs' loads.
 int set_launch_order(gp_ssm_plan* pl, int32_t M, const double* omega0, const double* quality, hipStream_t s) {
   constexpr double W0 = 4.0, C_SER = 1.0, C_CLO = 1.5;
   const HostPlan& h = pl->host;
-  const int64_t S = h.n_seg;
+  const int64_t S = h.n_wv;
   if (S == 0) return 0;
   if (!pl->order_host) {
     HIP_TRY(hipHostMalloc((void**)&pl->order_host, sizeof(int32_t) * S, hipHostMallocDefault));
     HIP_TRY(hipEventCreateWithFlags(&pl->order_ev, hipEventDisableTiming));
-    if (int rc = pl->seg_order.ensure(sizeof(int32_t) * S)) return rc;
+    if (int rc = pl->wv_order.ensure(sizeof(int32_t) * S)) return rc;
   } else {
     HIP_TRY(hipEventSynchronize(pl->order_ev));
   }
@@ -305,10 +312,10 @@ int set_launch_order(gp_ssm_plan* pl, int32_t M, const double* omega0, const dou
     term_cost[b] = c;
   }
   std::vector<std::pair<double, int32_t>> key(S);
-  for (int64_t q = 0; q < S; ++q) key[q] = {-(double)h.seg_len[q] * term_cost[h.seg_series[q]], (int32_t)q};
+  for (int64_t q = 0; q < S; ++q) key[q] = {-(double)h.wv_len[q] * term_cost[h.wv_series[q]], (int32_t)q};
   std::sort(key.begin(), key.end());
   for (int64_t q = 0; q < S; ++q) pl->order_host[q] = key[q].second;
-  HIP_TRY(hipMemcpyAsync(pl->seg_order.p, pl->order_host, sizeof(int32_t) * S, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(pl->wv_order.p, pl->order_host, sizeof(int32_t) * S, hipMemcpyHostToDevice, s));
   HIP_TRY(hipEventRecord(pl->order_ev, s));
   return 0;
 }
@@ -448,13 +455,15 @@ int gp_ssm_plan_create(int64_t n_series, const int64_t* offsets, const double* t
   HostPlan& h = pl->host;
   if ((rc = upload(pl->dt, h.dt)) || (rc = upload(pl->t, h.t)) || (rc = upload(pl->y, h.y)) || (rc = upload(pl->r, h.r)) ||
       (rc = upload(pl->invd, h.invd)) || (rc = upload(pl->info, h.info)) || (rc = upload(pl->meas, h.meas)) ||
-      (rc = upload(pl->seg_series, h.seg_series)) || (rc = upload(pl->seg_chunk0, h.seg_chunk0)) ||
-      (rc = upload(pl->seg_nch, h.seg_nch)) || (rc = upload(pl->seg_len, h.seg_len)) ||
-      (rc = upload(pl->seg_ev0, h.seg_ev0)) || (rc = upload(pl->chunk_len, h.chunk_len)) ||
-      (rc = upload(pl->chunk_series, h.chunk_series)) || (rc = upload(pl->chunk_seg, h.chunk_seg)) ||
-      (rc = upload(pl->chunk_first, h.chunk_first)) || (rc = upload(pl->series_chunk0, h.series_chunk0)) ||
-      (rc = upload(pl->series_nch, h.series_nch)) || (rc = upload(pl->series_seg0, h.series_seg0)) ||
-      (rc = upload(pl->series_nseg, h.series_nseg))) {
+      (rc = upload(pl->seg_chunk0, h.seg_chunk0)) || (rc = upload(pl->seg_nch, h.seg_nch)) ||
+      (rc = upload(pl->wv_series, h.wv_series)) || (rc = upload(pl->wv_nch, h.wv_nch)) ||
+      (rc = upload(pl->wv_len, h.wv_len)) || (rc = upload(pl->wv_chunk, h.wv_chunk)) ||
+      (rc = upload(pl->wv_ev0, h.wv_ev0)) || (rc = upload(pl->chunk_len, h.chunk_len)) ||
+      (rc = upload(pl->chunk_series, h.chunk_series)) || (rc = upload(pl->chunk_wv, h.chunk_wv)) ||
+      (rc = upload(pl->chunk_lane, h.chunk_lane)) || (rc = upload(pl->chunk_first, h.chunk_first)) ||
+      (rc = upload(pl->series_chunk0, h.series_chunk0)) || (rc = upload(pl->series_nch, h.series_nch)) ||
+      (rc = upload(pl->series_seg0, h.series_seg0)) || (rc = upload(pl->series_nseg, h.series_nseg)) ||
+      (rc = upload(pl->series_wv0, h.series_wv0)) || (rc = upload(pl->series_nwv, h.series_nwv))) {
     delete pl;
     return rc;
   }
@@ -515,7 +524,7 @@ int gp_ssm_plan_loglik_grad(gp_ssm_plan* pl, int32_t M, const double* sigma, con
   const int F = D + D * (D + 1) / 2;
   const int64_t C = pl->host.n_chunks;
   if (int rc = pl->rec.ensure(sizeof(double) * F * std::max<int64_t>(1, pl->host.n_ev_pad))) return rc;
-  if (int rc = pl->gpart.ensure(sizeof(double) * (3 * M + 1) * std::max<int64_t>(1, pl->host.n_seg))) return rc;
+  if (int rc = pl->gpart.ensure(sizeof(double) * (3 * M + 1) * std::max<int64_t>(1, pl->host.n_wv))) return rc;
   const DevPlan p = pl->dev();
   const KernelSet ks = kernel_set(M, pl->host.max_slots);
   Launch L{s};

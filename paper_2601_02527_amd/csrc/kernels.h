@@ -12,14 +12,15 @@ struct DevPlan {
   const double *dt, *t, *y, *r, *invd;
   const uint32_t* info;
   const int64_t* meas;
-  const int32_t *seg_series, *seg_chunk0, *seg_nch, *seg_len;
-  const int64_t* seg_ev0;
-  const int32_t *chunk_len, *chunk_series, *chunk_seg;
+  const int32_t *seg_chunk0, *seg_nch;                    // scan segments
+  const int32_t *wv_series, *wv_nch, *wv_len, *wv_chunk;  // work waves (see plan.h)
+  const int64_t* wv_ev0;
+  const int32_t *chunk_len, *chunk_series, *chunk_wv, *chunk_lane;
   const uint8_t* chunk_first;
-  const int32_t *series_chunk0, *series_nch, *series_seg0, *series_nseg;
-  const int32_t* seg_order;  // launch order of the per-segment kernels (null: natural order)
+  const int32_t *series_chunk0, *series_nch, *series_seg0, *series_nseg, *series_wv0, *series_nwv;
+  const int32_t* wv_order;  // launch order of the work waves (null: natural order)
   int64_t n_series;
-  int32_t n_chunks, n_seg;
+  int32_t n_chunks, n_seg, n_wv;
 };
 
 // hyperparameters prepared on the device: per (series, term) TermConst and the

@@ -100,11 +100,11 @@ template <int J>
 __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, double* __restrict__ summ) {
   using Dm = Dims<M, J>;
   constexpr int NX = Dm::NX, NXP = Dm::NXP;
-  const int seg = p.seg_order ? p.seg_order[blockIdx.x] : (int)blockIdx.x;
+  const int w = p.wv_order ? p.wv_order[blockIdx.x] : (int)blockIdx.x;
   const int lane = threadIdx.x;
-  const int64_t b = p.seg_series[seg];
-  const int32_t nch = p.seg_nch[seg], L = p.seg_len[seg];
-  const int64_t ev0 = p.seg_ev0[seg];
+  const int64_t b = p.wv_series[w];
+  const int32_t nch = p.wv_nch[w], L = p.wv_len[w];
+  const int64_t ev0 = p.wv_ev0[w];
   TermConst tc[M];
   load_terms<Dm>(pr, b, tc);
   __shared__ double lcoef[M * NCOEF];
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, dou
     st.step(tq, cur.info, o);
   }
   if (lane < nch) {
-    const int64_t c = p.seg_chunk0[seg] + lane;
+    const int64_t c = p.wv_chunk[(int64_t)w * WAVE + lane];
     const int64_t C = p.n_chunks;
 #pragma unroll
     for (int i = 0; i < NX; ++i)
@@ -165,14 +165,14 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
   using Dm = Dims<M, J>;
   constexpr int NX = Dm::NX, D = Dm::D, NP = Dm::NP, NXP = Dm::NXP;
   constexpr int F = rec_fields<Dm>();
-  const int seg = p.seg_order ? p.seg_order[blockIdx.x] : (int)blockIdx.x;
+  const int w = p.wv_order ? p.wv_order[blockIdx.x] : (int)blockIdx.x;
   const int lane = threadIdx.x;
-  const int64_t b = p.seg_series[seg];
-  const int32_t nch = p.seg_nch[seg], L = p.seg_len[seg];
-  const int64_t ev0 = p.seg_ev0[seg];
+  const int64_t b = p.wv_series[w];
+  const int32_t nch = p.wv_nch[w], L = p.wv_len[w];
+  const int64_t ev0 = p.wv_ev0[w];
   const bool active = lane < nch;
   const int64_t C = p.n_chunks;
-  const int64_t c = p.seg_chunk0[seg] + (active ? lane : 0);
+  const int64_t c = p.wv_chunk[(int64_t)w * WAVE + (active ? lane : 0)];
   TermConst tc[M];
   load_terms<Dm>(pr, b, tc);
   __shared__ double lcoef[M * 2 * NCOEF];
@@ -230,21 +230,21 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
     for (int t = 0; t < M; ++t)
       acc.s(t) += 2.0 * tc[t].sigma * (Pb[sidx(2 * t, 2 * t, D)] + Pb[sidx(2 * t + 1, 2 * t + 1, D)]);
   }
-  // sum over the segment's lanes (one series), one partial per segment
-  const int64_t S = p.n_seg;
+  // sum over the wave's lanes (one series), one partial per work wave
+  const int64_t S = p.n_wv;
 #pragma unroll
   for (int t = 0; t < M; ++t) {
     const double a0 = wave_sum(active ? acc.s(t) : 0.0);
     const double a1 = wave_sum(active ? acc.w(t) : 0.0);
     const double a2 = wave_sum(active ? acc.q(t) : 0.0);
     if (lane == 0) {
-      gpart[(0 * M + t) * S + seg] = a0;
-      gpart[(1 * M + t) * S + seg] = a1;
-      gpart[(2 * M + t) * S + seg] = a2;
+      gpart[(0 * M + t) * S + w] = a0;
+      gpart[(1 * M + t) * S + w] = a1;
+      gpart[(2 * M + t) * S + w] = a2;
     }
   }
   const double aj = wave_sum(active ? acc.jit() : 0.0);
-  if (lane == 0) gpart[(3 * M) * S + seg] = aj;
+  if (lane == 0) gpart[(3 * M) * S + w] = aj;
   (void)NXP;
   (void)C;
 }
@@ -277,9 +277,8 @@ __global__ __launch_bounds__(WAVE) void k_plain(DevPlan p, DevParams pr, int64_t
   const int32_t c0 = p.series_chunk0[b], nch = p.series_nch[b];
   for (int32_t q = 0; q < nch; ++q) {
     const int32_t c = c0 + q;
-    const int32_t s = p.chunk_seg[c];
-    const int32_t l = c - p.seg_chunk0[s];
-    const int64_t ev0 = p.seg_ev0[s];
+    const int32_t l = p.chunk_lane[c];
+    const int64_t ev0 = p.wv_ev0[p.chunk_wv[c]];
     const int32_t len = p.chunk_len[c];
     for (int32_t k = 0; k < len; ++k) {
       const int64_t e = ev0 + (int64_t)k * WAVE + l;
@@ -364,14 +363,14 @@ __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const 
   using Dm = Dims<M, J>;
   constexpr int NX = Dm::NX, D = Dm::D, NP = Dm::NP;
   constexpr int F = rec_fields<Dm>();
-  const int seg = p.seg_order ? p.seg_order[blockIdx.x] : (int)blockIdx.x;
+  const int w = p.wv_order ? p.wv_order[blockIdx.x] : (int)blockIdx.x;
   const int lane = threadIdx.x;
-  const int64_t b = p.seg_series[seg];
-  const int32_t nch = p.seg_nch[seg];
-  const int64_t ev0 = p.seg_ev0[seg];
+  const int64_t b = p.wv_series[w];
+  const int32_t nch = p.wv_nch[w];
+  const int64_t ev0 = p.wv_ev0[w];
   const bool active = lane < nch;
   const int64_t C = p.n_chunks;
-  const int64_t c = p.seg_chunk0[seg] + (active ? lane : 0);
+  const int64_t c = p.wv_chunk[(int64_t)w * WAVE + (active ? lane : 0)];
   const int32_t len = active ? p.chunk_len[c] : 0;
   TermConst tc[M];
   load_terms<Dm>(pr, b, tc);
@@ -555,17 +554,17 @@ __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const 
 // ---------------------------------------------------------------------------
 template <int J>
 void launch_summaries(const Launch& L, const DevPlan& p, const DevParams& pr, double* summ) {
-  if (p.n_seg == 0) return;
+  if (p.n_wv == 0) return;
   prof_begin("k_summaries", L.stream);
-  hipLaunchKernelGGL(k_summaries<J>, dim3(p.n_seg), dim3(WAVE), 0, L.stream, p, pr, summ);
+  hipLaunchKernelGGL(k_summaries<J>, dim3(p.n_wv), dim3(WAVE), 0, L.stream, p, pr, summ);
   prof_end("k_summaries", L.stream);
 }
 template <int J>
 void launch_adjoint(const Launch& L, const DevPlan& p, const DevParams& pr, const double* bstate, const double* badj,
                     double* rec, double* gpart) {
-  if (p.n_seg == 0) return;
+  if (p.n_wv == 0) return;
   prof_begin("k_adjoint", L.stream);
-  hipLaunchKernelGGL(k_adjoint<J>, dim3(p.n_seg), dim3(WAVE), 0, L.stream, p, pr, bstate, badj, rec, gpart);
+  hipLaunchKernelGGL(k_adjoint<J>, dim3(p.n_wv), dim3(WAVE), 0, L.stream, p, pr, bstate, badj, rec, gpart);
   prof_end("k_adjoint", L.stream);
 }
 template <int J>
@@ -579,9 +578,9 @@ template <int J>
 void launch_smooth(const Launch& L, const DevPlan& p, const DevParams& pr, const double* bstate, const double* bsmooth,
                    double* rec, const DevTests& tests, double* mean_test, double* var_test, double* mean_data,
                    double* var_data) {
-  if (p.n_seg == 0) return;
+  if (p.n_wv == 0) return;
   prof_begin("k_smooth", L.stream);
-  hipLaunchKernelGGL(k_smooth<J>, dim3(p.n_seg), dim3(WAVE), 0, L.stream, p, pr, bstate, bsmooth, rec, tests,
+  hipLaunchKernelGGL(k_smooth<J>, dim3(p.n_wv), dim3(WAVE), 0, L.stream, p, pr, bstate, bsmooth, rec, tests,
                      mean_test, var_test, mean_data, var_data);
   prof_end("k_smooth", L.stream);
 }

@@ -12,11 +12,14 @@
 //    event; events are ordered by time, ends before instantaneous before
 //    starts at equal times;
 //  * chunks: the event sequence is cut after events where no exposure is open
-//    ("quiet" points), once a chunk has reached the target length, so that a
-//    chunk's boundary state is the SHO state alone.
-// Over the batch, runs of up to 64 chunks of one series form a segment (one
-// wavefront, one chunk per lane), and events are stored interleaved so a
-// wavefront reads 64 consecutive values per step.
+//    ("quiet" points), so that a chunk's boundary state is the SHO state
+//    alone; the cuts are the quiet points nearest to an even grid of the
+//    target length, which keeps the chunks of a segment of similar length.
+// Over the batch, runs of up to 64 consecutive chunks of one series form a
+// scan segment (the lanes of one wavefront in the scan kernels).  The
+// per-chunk kernels instead take a series' chunks longest first, 64 to a work
+// wave (one chunk per lane), and events are stored interleaved by work wave so
+// a wavefront reads 64 consecutive values per step.
 #include "plan.h"
 
 #include <algorithm>
@@ -108,23 +111,56 @@ int plan_series(int64_t b, int64_t lo, int64_t hi, const double* ts, const doubl
     if (a.kind != c.kind) return a.kind < c.kind;
     return a.n < c.n;
   });
-  // open sets and quiet-point chunking
+  // open sets and the quiet points (cut positions after which no exposure
+  // is open)
   const int64_t ne = (int64_t)w.ev.size();
   w.open_before.resize(ne);
   w.cuts.clear();
+  std::vector<int64_t> quiet;
   uint32_t open = 0;
-  int64_t start = 0;
   for (int64_t k = 0; k < ne; ++k) {
     w.open_before[k] = open;
     const Ev& e = w.ev[k];
     if (e.kind == K_START) open |= (1u << e.slot);
     if (e.kind == K_END) open &= ~(1u << e.slot);
-    const bool last = (k == ne - 1);
-    if (last || (!single && open == 0 && k + 1 - start >= std::max<int64_t>(Lb, chunk_min))) {
-      w.cuts.push_back(k + 1);
-      start = k + 1;
-    }
+    if (open == 0 && k + 1 < ne) quiet.push_back(k + 1);
   }
+  // chunks: ne / L of them (L the target length, at least chunk_min), each cut
+  // at the quiet point nearest to its place on an even grid, so that chunk
+  // lengths stay close to the mean even where quiet points are sparse (the
+  // lanes of a wavefront all run as long as its longest chunk)
+  const int64_t L = std::max<int64_t>(Lb, chunk_min);
+  const int64_t nc = single ? 1 : std::max<int64_t>(1, ne / L);
+  int64_t prev = 0;
+  for (int64_t i = 1; i < nc; ++i) {
+    const double target = (double)ne * (double)i / (double)nc;
+    // first quiet point at or after the target, and the one before it
+    auto it = std::lower_bound(quiet.begin(), quiet.end(), (int64_t)std::ceil(target));
+    int64_t best = -1;
+    double dbest = 0.0;
+    for (int cand = 0; cand < 2; ++cand) {
+      auto jt = (cand == 0) ? it : it - 1;
+      if (cand == 1 && it == quiet.begin()) continue;
+      if (jt == quiet.end()) continue;
+      const int64_t q = *jt;
+      if (q - prev < chunk_min || ne - q < chunk_min) continue;
+      const double d = std::fabs((double)q - target);
+      if (best < 0 || d < dbest) {
+        best = q;
+        dbest = d;
+      }
+    }
+    if (best < 0) {
+      // nearest admissible quiet point after the previous cut
+      auto kt = std::lower_bound(quiet.begin(), quiet.end(), prev + chunk_min);
+      if (kt == quiet.end() || ne - *kt < chunk_min) break;
+      best = *kt;
+    }
+    if (best <= prev) continue;
+    w.cuts.push_back(best);
+    prev = best;
+  }
+  w.cuts.push_back(ne);
   // step-length histogram in powers of two, then its cumulative fractions
   int64_t cnt[DT_NE] = {};
   for (int64_t k = 1; k < ne; ++k) {
@@ -209,6 +245,8 @@ int build_plan(int64_t n_series, const int64_t* offsets, const double* t_start, 
   P.series_slots.resize(n_series);
   P.series_seg0.resize(n_series);
   P.series_nseg.resize(n_series);
+  P.series_wv0.resize(n_series);
+  P.series_nwv.resize(n_series);
   P.series_nev.resize(n_series);
   std::vector<int64_t> chunk_evstart;  // (series-local start of each chunk)
   for (int64_t b = 0; b < n_series; ++b) {
@@ -235,21 +273,39 @@ int build_plan(int64_t n_series, const int64_t* offsets, const double* t_start, 
     }
     P.series_nch[b] = P.n_chunks - c_first;
     P.series_seg0[b] = P.n_seg;
-    // segments of up to WAVE chunks
+    // scan segments of up to WAVE consecutive chunks
     for (int32_t c = c_first; c < P.n_chunks; c += WAVE) {
-      const int32_t nch = std::min<int32_t>(WAVE, P.n_chunks - c);
-      int32_t L = 0;
-      for (int32_t q = 0; q < nch; ++q) L = std::max(L, P.chunk_len[c + q]);
-      P.seg_series.push_back((int32_t)b);
       P.seg_chunk0.push_back(c);
-      P.seg_nch.push_back(nch);
-      P.seg_len.push_back(L);
-      P.seg_ev0.push_back(P.n_ev_pad);
-      for (int32_t q = 0; q < nch; ++q) P.chunk_seg.push_back(P.n_seg);
-      P.n_ev_pad += (int64_t)L * WAVE;
+      P.seg_nch.push_back(std::min<int32_t>(WAVE, P.n_chunks - c));
       ++P.n_seg;
     }
     P.series_nseg[b] = P.n_seg - P.series_seg0[b];
+    // work waves: the series' chunks longest first, WAVE to a wave
+    std::vector<int32_t> order(P.n_chunks - c_first);
+    for (size_t q = 0; q < order.size(); ++q) order[q] = c_first + (int32_t)q;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t z) { return P.chunk_len[x] > P.chunk_len[z]; });
+    P.series_wv0[b] = P.n_wv;
+    P.chunk_wv.resize(P.n_chunks);
+    P.chunk_lane.resize(P.n_chunks);
+    for (size_t q0 = 0; q0 < order.size(); q0 += WAVE) {
+      const int32_t nch = (int32_t)std::min<size_t>(WAVE, order.size() - q0);
+      P.wv_series.push_back((int32_t)b);
+      P.wv_nch.push_back(nch);
+      P.wv_len.push_back(P.chunk_len[order[q0]]);
+      P.wv_ev0.push_back(P.n_ev_pad);
+      for (int32_t l = 0; l < WAVE; ++l) {
+        const int32_t c = l < nch ? order[q0 + l] : -1;
+        P.wv_chunk.push_back(c);
+        if (c >= 0) {
+          P.chunk_wv[c] = P.n_wv;
+          P.chunk_lane[c] = l;
+        }
+      }
+      P.n_ev_pad += (int64_t)P.chunk_len[order[q0]] * WAVE;
+      ++P.n_wv;
+    }
+    P.series_nwv[b] = P.n_wv - P.series_wv0[b];
   }
   // interleaved event arrays
   P.dt.assign(P.n_ev_pad, 0.0);
@@ -259,20 +315,20 @@ int build_plan(int64_t n_series, const int64_t* offsets, const double* t_start, 
   P.invd.assign(P.n_ev_pad, 0.0);
   P.info.assign(P.n_ev_pad, K_PAD);
   P.meas.assign(P.n_ev_pad, -1);
-  std::atomic<int32_t> nextseg(0);
+  std::atomic<int32_t> nextwv(0);
   auto filler = [&]() {
     for (;;) {
-      const int32_t s = nextseg.fetch_add(1);
-      if (s >= P.n_seg) break;
-      const int32_t b = P.seg_series[s];
+      const int32_t v = nextwv.fetch_add(1);
+      if (v >= P.n_wv) break;
+      const int32_t b = P.wv_series[v];
       const SeriesWork& w = work[b];
-      for (int32_t l = 0; l < P.seg_nch[s]; ++l) {
-        const int32_t c = P.seg_chunk0[s] + l;
+      for (int32_t l = 0; l < P.wv_nch[v]; ++l) {
+        const int32_t c = P.wv_chunk[(int64_t)v * WAVE + l];
         const int64_t e0 = chunk_evstart[c];
         for (int32_t k = 0; k < P.chunk_len[c]; ++k) {
           const int64_t q = e0 + k;
           const Ev& e = w.ev[q];
-          const int64_t at = P.seg_ev0[s] + (int64_t)k * WAVE + l;
+          const int64_t at = P.wv_ev0[v] + (int64_t)k * WAVE + l;
           P.t[at] = e.t;
           P.dt[at] = (q == 0) ? 0.0 : e.t - w.ev[q - 1].t;
           uint32_t info = e.kind | (e.slot >= 0 ? ((uint32_t)e.slot << 2) : 0u) | (w.open_before[q] << 8);
@@ -288,7 +344,7 @@ int build_plan(int64_t n_series, const int64_t* offsets, const double* t_start, 
         }
         // pad the tail of the chunk at its end time
         const double tend = P.chunk_t1[c];
-        for (int32_t k = P.chunk_len[c]; k < P.seg_len[s]; ++k) P.t[P.seg_ev0[s] + (int64_t)k * WAVE + l] = tend;
+        for (int32_t k = P.chunk_len[c]; k < P.wv_len[v]; ++k) P.t[P.wv_ev0[v] + (int64_t)k * WAVE + l] = tend;
       }
     }
   };

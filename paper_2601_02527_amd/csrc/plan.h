@@ -8,7 +8,7 @@
 
 namespace gpssm {
 
-constexpr int WAVE = 64;        // lanes per wavefront; chunks per segment
+constexpr int WAVE = 64;        // lanes per wavefront; chunks per segment and per work wave
 constexpr int MAX_TERMS = 4;
 constexpr int MAX_SLOTS = 4;
 
@@ -30,19 +30,25 @@ struct HostPlan {
   int32_t max_slots = 0;  // largest overlap depth over the batch
   int64_t n_events = 0;   // real events
   int64_t n_ev_pad = 0;   // events in the interleaved layout (with padding)
-  int32_t n_chunks = 0, n_seg = 0, max_chunk_len = 0;
+  int32_t n_chunks = 0, n_seg = 0, n_wv = 0, max_chunk_len = 0;
 
-  // interleaved events: segment s, step k, lane l at seg_ev0[s] + k*WAVE + l
+  // interleaved events: work wave w, step k, lane l at wv_ev0[w] + k*WAVE + l
   std::vector<double> dt, t, y, r, invd;
   std::vector<uint32_t> info;
   std::vector<int64_t> meas;  // global measurement index at end/instantaneous events, else -1
 
-  std::vector<int32_t> seg_series, seg_chunk0, seg_nch, seg_len;
-  std::vector<int64_t> seg_ev0;
-  std::vector<int32_t> chunk_len, chunk_series, chunk_seg;
+  // scan segments: runs of up to WAVE consecutive chunks of one series, whose
+  // summaries the time-parallel scan composes across the lanes of a wavefront
+  std::vector<int32_t> seg_chunk0, seg_nch;
+  // work waves of the per-chunk kernels: up to WAVE chunks of one series taken
+  // in order of length, so that the lanes of a wavefront run similar lengths;
+  // wv_chunk holds WAVE entries per wave (chunk of each lane, -1 if idle)
+  std::vector<int32_t> wv_series, wv_nch, wv_len, wv_chunk;
+  std::vector<int64_t> wv_ev0;
+  std::vector<int32_t> chunk_len, chunk_series, chunk_wv, chunk_lane;
   std::vector<uint8_t> chunk_first;
   std::vector<double> chunk_t0, chunk_t1;  // time of the first / last event of each chunk
-  std::vector<int32_t> series_chunk0, series_nch, series_slots, series_seg0, series_nseg;
+  std::vector<int32_t> series_chunk0, series_nch, series_slots, series_seg0, series_nseg, series_wv0, series_nwv;
   std::vector<int64_t> series_nev;
   std::vector<float> series_dt_cdf;  // n_series * DT_NE, see DT_KMIN
 };
