@@ -131,8 +131,33 @@ int plan_series(int64_t b, int64_t lo, int64_t hi, const double* ts, const doubl
   // lanes of a wavefront all run as long as its longest chunk)
   const int64_t L = std::max<int64_t>(Lb, chunk_min);
   const int64_t nc = single ? 1 : std::max<int64_t>(1, ne / L);
+  // the smallest longest chunk with which nc chunks cover the series: cutting
+  // at the farthest admissible quiet point needs the fewest chunks for a
+  // given longest chunk; no chunk below is made longer than that
+  auto chunks_needed = [&](int64_t lmax) {
+    int64_t at = 0, n = 1;
+    while (ne - at > lmax) {
+      auto it = std::upper_bound(quiet.begin(), quiet.end(), at + lmax);
+      if (it == quiet.begin() || *(it - 1) - at < std::min<int64_t>(chunk_min, lmax)) return ne + 1;
+      at = *(it - 1);
+      ++n;
+    }
+    return n;
+  };
+  int64_t lmax = ne;
+  if (nc > 1) {
+    int64_t lo = (ne + nc - 1) / nc, hi = ne;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (chunks_needed(mid) <= nc)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    lmax = lo;
+  }
   int64_t prev = 0;
-  for (int64_t i = 1; i < nc; ++i) {
+  for (int64_t i = 1; i < nc && ne - prev > lmax; ++i) {
     const double target = (double)ne * (double)i / (double)nc;
     // first quiet point at or after the target, and the one before it
     auto it = std::lower_bound(quiet.begin(), quiet.end(), (int64_t)std::ceil(target));
@@ -156,9 +181,21 @@ int plan_series(int64_t b, int64_t lo, int64_t hi, const double* ts, const doubl
       if (kt == quiet.end() || ne - *kt < chunk_min) break;
       best = *kt;
     }
+    if (best - prev > lmax) {
+      // too long: the farthest quiet point within the bound instead
+      auto kt = std::upper_bound(quiet.begin(), quiet.end(), prev + lmax);
+      if (kt != quiet.begin() && *(kt - 1) > prev) best = *(kt - 1);
+    }
     if (best <= prev) continue;
     w.cuts.push_back(best);
     prev = best;
+  }
+  // whatever the grid left longer than the bound
+  while (ne - prev > lmax) {
+    auto kt = std::upper_bound(quiet.begin(), quiet.end(), prev + lmax);
+    if (kt == quiet.begin() || *(kt - 1) <= prev) break;
+    prev = *(kt - 1);
+    w.cuts.push_back(prev);
   }
   w.cuts.push_back(ne);
   // step-length histogram in powers of two, then its cumulative fractions
