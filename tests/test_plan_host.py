@@ -1,0 +1,170 @@
+"""Host logic of the event planner (no GPU): the planner source is compiled
+with a small driver and its tables are checked against what the method and
+the kernels require.
+
+* every exposure gives a start and an end event (an instantaneous one a
+  single event), in time order, each measurement exactly once;
+* chunks start and end where no exposure is open (the boundary state is the
+  SHO state alone), and within a chunk a slot opens only while closed and
+  closes only while open;
+* scan segments are runs of at most 64 consecutive chunks of one series;
+* every chunk has exactly one lane of one work wave of its own series, the
+  chunks of a wave are in order of length and the wave runs as long as its
+  longest chunk; padding events repeat the chunk's last time and do nothing.
+"""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+WAVE = 64
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    d = tmp_path_factory.mktemp("plan")
+    exe = str(d / "plan_driver")
+    subprocess.check_call(["g++", "-O1", "-std=c++17", "-o", exe, os.path.join(HERE, "plan_driver.cpp"),
+                           os.path.join(ROOT, "paper_2601_02527_amd", "csrc", "plan.cpp"), "-lpthread"])
+    return exe, d
+
+
+def _plan(driver, ts_list, te_list, chunk_min=24, chunk_target=0, single=0, target_chunks=131072):
+    exe, d = driver
+    offs = np.concatenate([[0], np.cumsum([len(x) for x in ts_list])]).astype(np.int64)
+    ts = np.concatenate(ts_list).astype(np.float64)
+    te = np.concatenate(te_list).astype(np.float64)
+    offs.tofile(str(d / "offs.bin"))
+    ts.tofile(str(d / "ts.bin"))
+    te.tofile(str(d / "te.bin"))
+    np.zeros(len(ts)).tofile(str(d / "y.bin"))
+    np.full(len(ts), 0.1).tofile(str(d / "yerr.bin"))
+    out = subprocess.run([exe, str(d), str(chunk_min), str(chunk_target), str(single), str(target_chunks)],
+                         capture_output=True, text=True, check=True).stdout
+    tab = {}
+    for line in out.splitlines():
+        name, *vals = line.split()
+        tab[name] = np.array([float(v) for v in vals])
+    assert tab["rc"][0] == 0
+    n_ev, n_pad, n_ch, n_seg, n_wv, _ = (int(v) for v in tab["scalars"])
+    tab.update(n_ev=n_ev, n_pad=n_pad, n_ch=n_ch, n_seg=n_seg, n_wv=n_wv, offs=offs, ts=ts, te=te)
+    return tab
+
+
+def _check(P):
+    i = lambda k: P[k].astype(np.int64)
+    B = len(P["offs"]) - 1
+    chunk_len, chunk_series, chunk_wv, chunk_lane = i("chunk_len"), i("chunk_series"), i("chunk_wv"), i("chunk_lane")
+    wv_series, wv_nch, wv_len, wv_chunk, wv_ev0 = i("wv_series"), i("wv_nch"), i("wv_len"), i("wv_chunk"), i("wv_ev0")
+    info, meas, t = P["info"].astype(np.int64), i("meas"), P["t"]
+    # layout size
+    assert wv_chunk.size == P["n_wv"] * WAVE
+    assert np.array_equal(wv_ev0, np.concatenate([[0], np.cumsum(wv_len * WAVE)[:-1]]))
+    assert P["n_pad"] == int(np.sum(wv_len)) * WAVE == t.size
+    # series tables
+    seen_meas = []
+    for b in range(B):
+        lo, hi = P["offs"][b], P["offs"][b + 1]
+        n_exp_ev = int(np.sum(np.where(P["te"][lo:hi] > P["ts"][lo:hi], 2, 1)))
+        c0, nc = int(P["series_chunk0"][b]), int(P["series_nch"][b])
+        chunks = np.arange(c0, c0 + nc)
+        assert np.all(chunk_series[chunks] == b)
+        assert int(chunk_len[chunks].sum()) == n_exp_ev
+        assert list(P["chunk_first"][chunks].astype(int)) == [1] + [0] * (nc - 1)
+        # scan segments: consecutive runs of <= 64 chunks covering the series
+        s0, ns = int(P["series_seg0"][b]), int(P["series_nseg"][b])
+        pos = c0
+        for s in range(s0, s0 + ns):
+            assert int(P["seg_chunk0"][s]) == pos and 1 <= int(P["seg_nch"][s]) <= WAVE
+            pos += int(P["seg_nch"][s])
+        assert pos == c0 + nc
+        # work waves of the series
+        w0, nw = int(P["series_wv0"][b]), int(P["series_nwv"][b])
+        assert nw == -(-nc // WAVE)
+        members = []
+        for w in range(w0, w0 + nw):
+            assert wv_series[w] == b
+            lanes = wv_chunk[w * WAVE:(w + 1) * WAVE]
+            k = int(wv_nch[w])
+            assert np.all(lanes[k:] == -1) and np.all(lanes[:k] >= 0)
+            lens = chunk_len[lanes[:k]]
+            assert np.all(np.diff(lens) <= 0) and wv_len[w] == lens[0]
+            members.extend(lanes[:k].tolist())
+        assert sorted(members) == list(chunks)
+        # events of each chunk
+        prev_end = -np.inf
+        for c in chunks:
+            w, l = int(chunk_wv[c]), int(chunk_lane[c])
+            assert wv_chunk[w * WAVE + l] == c
+            at = wv_ev0[w] + np.arange(wv_len[w]) * WAVE + l
+            L = int(chunk_len[c])
+            tt, inf, ms = t[at[:L]], info[at[:L]], meas[at[:L]]
+            assert np.all(np.diff(tt) >= 0) and tt[0] >= prev_end
+            prev_end = tt[-1]
+            kind, slot, open_ = inf & 3, (inf >> 2) & 7, (inf >> 8) & 0xFF
+            assert open_[0] == 0, "chunk does not start at a quiet point"
+            state = 0
+            for q in range(L):
+                assert open_[q] == state
+                if kind[q] == 2:
+                    assert not (state >> slot[q]) & 1
+                    state |= 1 << slot[q]
+                elif kind[q] == 0:
+                    assert (state >> slot[q]) & 1
+                    state &= ~(1 << slot[q])
+                assert kind[q] != 3
+            assert state == 0, "chunk does not end at a quiet point"
+            seen_meas.extend(ms[(kind == 0) | (kind == 1)].tolist())
+            assert np.all(ms[kind == 2] == -1)
+            # padding
+            assert np.all(info[at[L:]] == 3) and np.all(t[at[L:]] == tt[-1])
+    assert sorted(seen_meas) == list(range(int(P["offs"][-1])))
+
+
+def _batch(seed, **kw):
+    b = W.random_small_batch(seed, **kw)
+    return [b.series(i)["ts"] for i in range(b.n_series)], [b.series(i)["te"] for i in range(b.n_series)]
+
+
+@pytest.mark.parametrize("opt", [dict(), dict(chunk_min=1, chunk_target=1), dict(single=1),
+                                 dict(chunk_min=2, chunk_target=3)])
+def test_random_batches(driver, opt):
+    ts, te = _batch(21, B=9, n_lo=1, n_hi=80, J=3)
+    _check(_plan(driver, ts, te, **opt))
+
+
+def test_long_series_several_waves_and_segments(driver):
+    ts, te = _batch(22, B=3, n_lo=2500, n_hi=4000, J=4, T=60.0)
+    P = _plan(driver, ts, te, chunk_min=2, chunk_target=6)
+    assert P["n_wv"] > 3 * 2 and P["n_seg"] > 3 * 2
+    _check(P)
+
+
+def test_edge_series(driver):
+    ts = [np.array([1.0]), np.array([0.0, 0.5, 0.5]), np.array([2.0, 2.0]), np.array([0.0, 0.1, 0.2])]
+    te = [np.array([1.5]), np.array([0.0, 0.5, 0.7]), np.array([2.5, 2.5]), np.array([0.3, 0.25, 0.4])]
+    _check(_plan(driver, ts, te))
+    _check(_plan(driver, ts, te, chunk_min=1, chunk_target=1))
+
+
+def test_balanced_cuts_on_dense_overlaps(driver):
+    """Four busy instruments leave few quiet points: the cuts keep the chunks
+    of a series within a narrow band of lengths."""
+    rng = np.random.default_rng(5)
+    tss, tes = [], []
+    for _ in range(4):
+        d = rng.uniform(20 / 86400, 100 / 86400, 25000)
+        s, e = W.place_slot(rng, 60.0, d)
+        tss.append(s)
+        tes.append(e)
+    ts, te = np.concatenate(tss), np.concatenate(tes)
+    o = np.argsort(ts, kind="stable")
+    P = _plan(driver, [ts[o]], [te[o]], target_chunks=1024)
+    _check(P)
+    L = P["chunk_len"]
+    assert L.max() <= 1.35 * L.mean(), (L.max(), L.mean())
