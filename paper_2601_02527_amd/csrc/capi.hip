@@ -198,13 +198,14 @@ struct gp_ssm_plan {
   int device = 0;
   HostPlan host;
   DBuf dt, t, y, r, invd, info, meas;
-  DBuf seg_chunk0, seg_nch;
+  DBuf seg_chunk0, seg_nch, grp_seg0, grp_nseg, series_grp0, series_ngrp;
   DBuf wv_series, wv_nch, wv_len, wv_chunk, wv_ev0;
   DBuf chunk_len, chunk_series, chunk_wv, chunk_lane, chunk_first;
   DBuf series_chunk0, series_nch, series_seg0, series_nseg, series_wv0, series_nwv;
   // workspace
   DBuf tc, coef, jit, summ, bstate, badj, bsmooth, gpart, rec, status;
   DBuf pre, suf, segtot, segstate, segfut, segll, segok;
+  DBuf pre2, suf2, grptot, grpstate, grpfut;
   DBuf tests_t, tests_idx, tests_c0, tests_before;
   // launch order of the work waves (most expensive first): written on the
   // host into pinned memory, copied on the call's stream; order_ev marks the
@@ -253,6 +254,19 @@ struct gp_ssm_plan {
     p.n_chunks = host.n_chunks;
     p.n_seg = host.n_seg;
     p.n_wv = host.n_wv;
+    return p;
+  }
+
+  // the plan seen by the second scan level: groups of segments in the place
+  // of segments, segments in the place of chunks
+  DevPlan dev_groups() const {
+    DevPlan p = dev();
+    p.seg_chunk0 = grp_seg0.as<int32_t>();
+    p.seg_nch = grp_nseg.as<int32_t>();
+    p.series_seg0 = series_grp0.as<int32_t>();
+    p.series_nseg = series_ngrp.as<int32_t>();
+    p.n_chunks = host.n_seg;
+    p.n_seg = host.n_grp;
     return p;
   }
 };
@@ -395,6 +409,23 @@ int run_forward(gp_ssm_plan* pl, int32_t M, const DevParams& pr, hipStream_t s, 
   w.bsmooth = (back && need_smooth) ? pl->bsmooth.as<double>() : nullptr;
   w.segll = pl->segll.as<double>();
   w.segok = pl->segok.as<int32_t>();
+  w.p2 = nullptr;
+  DevPlan p2;
+  if (pl->host.max_series_nseg > WAVE) {
+    const int64_t G = std::max<int64_t>(1, pl->host.n_grp);
+    if (int rc = pl->pre2.ensure(sizeof(double) * EF * S)) return rc;
+    if (int rc = pl->suf2.ensure(sizeof(double) * EF * S)) return rc;
+    if (int rc = pl->grptot.ensure(sizeof(double) * EF * G)) return rc;
+    if (int rc = pl->grpstate.ensure(sizeof(double) * (NX + NXP) * G)) return rc;
+    if (int rc = pl->grpfut.ensure(sizeof(double) * (NX + NXP) * G)) return rc;
+    p2 = pl->dev_groups();
+    w.p2 = &p2;
+    w.pre2 = pl->pre2.as<double>();
+    w.suf2 = pl->suf2.as<double>();
+    w.grptot = pl->grptot.as<double>();
+    w.grpstate = pl->grpstate.as<double>();
+    w.grpfut = pl->grpfut.as<double>();
+  }
   run_scan(M, s, p, pr, w, loglik, status, back);
   HIP_TRY(hipGetLastError());
   return 0;
@@ -456,6 +487,8 @@ int gp_ssm_plan_create(int64_t n_series, const int64_t* offsets, const double* t
   if ((rc = upload(pl->dt, h.dt)) || (rc = upload(pl->t, h.t)) || (rc = upload(pl->y, h.y)) || (rc = upload(pl->r, h.r)) ||
       (rc = upload(pl->invd, h.invd)) || (rc = upload(pl->info, h.info)) || (rc = upload(pl->meas, h.meas)) ||
       (rc = upload(pl->seg_chunk0, h.seg_chunk0)) || (rc = upload(pl->seg_nch, h.seg_nch)) ||
+      (rc = upload(pl->grp_seg0, h.grp_seg0)) || (rc = upload(pl->grp_nseg, h.grp_nseg)) ||
+      (rc = upload(pl->series_grp0, h.series_grp0)) || (rc = upload(pl->series_ngrp, h.series_ngrp)) ||
       (rc = upload(pl->wv_series, h.wv_series)) || (rc = upload(pl->wv_nch, h.wv_nch)) ||
       (rc = upload(pl->wv_len, h.wv_len)) || (rc = upload(pl->wv_chunk, h.wv_chunk)) ||
       (rc = upload(pl->wv_ev0, h.wv_ev0)) || (rc = upload(pl->chunk_len, h.chunk_len)) ||

@@ -284,6 +284,8 @@ int build_plan(int64_t n_series, const int64_t* offsets, const double* t_start, 
   P.series_nseg.resize(n_series);
   P.series_wv0.resize(n_series);
   P.series_nwv.resize(n_series);
+  P.series_grp0.resize(n_series);
+  P.series_ngrp.resize(n_series);
   P.series_nev.resize(n_series);
   std::vector<int64_t> chunk_evstart;  // (series-local start of each chunk)
   for (int64_t b = 0; b < n_series; ++b) {
@@ -317,6 +319,15 @@ int build_plan(int64_t n_series, const int64_t* offsets, const double* t_start, 
       ++P.n_seg;
     }
     P.series_nseg[b] = P.n_seg - P.series_seg0[b];
+    P.max_series_nseg = std::max(P.max_series_nseg, P.series_nseg[b]);
+    // groups of segments for the second scan level
+    P.series_grp0[b] = P.n_grp;
+    for (int32_t q = 0; q < P.series_nseg[b]; q += WAVE) {
+      P.grp_seg0.push_back(P.series_seg0[b] + q);
+      P.grp_nseg.push_back(std::min<int32_t>(WAVE, P.series_nseg[b] - q));
+      ++P.n_grp;
+    }
+    P.series_ngrp[b] = P.n_grp - P.series_grp0[b];
     // work waves: the series' chunks longest first, WAVE to a wave
     std::vector<int32_t> order(P.n_chunks - c_first);
     for (size_t q = 0; q < order.size(); ++q) order[q] = c_first + (int32_t)q;

@@ -31,6 +31,7 @@ struct HostPlan {
   int64_t n_events = 0;   // real events
   int64_t n_ev_pad = 0;   // events in the interleaved layout (with padding)
   int32_t n_chunks = 0, n_seg = 0, n_wv = 0, max_chunk_len = 0;
+  int32_t n_grp = 0, max_series_nseg = 0;
 
   // interleaved events: work wave w, step k, lane l at wv_ev0[w] + k*WAVE + l
   std::vector<double> dt, t, y, r, invd;
@@ -40,6 +41,9 @@ struct HostPlan {
   // scan segments: runs of up to WAVE consecutive chunks of one series, whose
   // summaries the time-parallel scan composes across the lanes of a wavefront
   std::vector<int32_t> seg_chunk0, seg_nch;
+  // groups of up to WAVE consecutive segments of one series: a second scan
+  // level over the segment totals when a series has more than WAVE segments
+  std::vector<int32_t> grp_seg0, grp_nseg, series_grp0, series_ngrp;
   // work waves of the per-chunk kernels: up to WAVE chunks of one series taken
   // in order of length, so that the lanes of a wavefront run similar lengths;
   // wv_chunk holds WAVE entries per wave (chunk of each lane, -1 if idle)

@@ -23,6 +23,9 @@ struct ScanWork {
   double* bsmooth;     // smoother adjoint pair (lambda, Lambda) at each chunk end (may be null)
   double* segll;       // log-likelihood of each segment
   int32_t* segok;      // 1 when every combination of the segment succeeded
+  // second scan level (null p2: one level), over groups of segments
+  const DevPlan* p2;   // the plan seen by the second level (groups as segments, segments as chunks)
+  double *pre2, *suf2, *grptot, *grpstate, *grpfut;
 };
 
 void run_scan(int M, hipStream_t st, const DevPlan& p, const DevParams& pr, const ScanWork& w, double* loglik,

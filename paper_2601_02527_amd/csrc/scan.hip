@@ -16,6 +16,12 @@
 //               likelihood with respect to the boundary moments and the
 //               smoother's adjoint pair there.
 //  k_series_finish  sums the per-segment log-likelihoods of each series.
+//
+// When a series has more than 64 segments, the segment totals are treated as
+// chunk summaries one level up: k_seg_scan over groups of 64 segments,
+// k_series_scan over the group totals, and k_grp_fix gives the state entering
+// every segment and the information after it, so that no lane walks more than
+// a few totals in sequence.
 #include <hip/hip_runtime.h>
 
 #include "../../include/gp_ssm.h"
@@ -302,6 +308,61 @@ __global__ __launch_bounds__(WAVE) void k_series_finish(DevPlan p, const double*
   }
 }
 
+// second scan level: from the state entering each group of segments and the
+// information after it (grpstate, grpfut), and the prefixes and suffixes of
+// the segment totals within the group (pre2, suf2), the state entering every
+// segment and the information after it.  p2 sees groups as segments and
+// segments as chunks; one wavefront per group, one segment per lane.
+template <int N>
+__global__ __launch_bounds__(WAVE) void k_grp_fix(DevPlan p2, const double* __restrict__ pre2,
+                                                  const double* __restrict__ suf2, const double* __restrict__ grpstate,
+                                                  const double* __restrict__ grpfut, double* __restrict__ segstate,
+                                                  double* __restrict__ segfut, int want_back) {
+  constexpr int NP = N * (N + 1) / 2;
+  const int g = blockIdx.x, lane = threadIdx.x;
+  const int32_t n = p2.seg_nch[g];
+  if (lane >= n) return;
+  const int64_t S = p2.n_chunks, G = p2.n_seg;
+  const int64_t s = p2.seg_chunk0[g] + lane;
+  bool ok = true;
+  double m[N], P[NP];
+#pragma unroll
+  for (int i = 0; i < N; ++i) m[i] = grpstate[(int64_t)i * G + g];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) P[i] = grpstate[(int64_t)(N + i) * G + g];
+  if (lane > 0) {
+    double mn[N], Pn[NP];
+    combine_forward<N>(m, P, [&](int f) { return f == sum_c0(N) ? 0.0 : pre2[(int64_t)f * S + s - 1]; }, mn, Pn, ok);
+#pragma unroll
+    for (int i = 0; i < N; ++i) m[i] = mn[i];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) P[i] = Pn[i];
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) segstate[(int64_t)i * S + s] = m[i];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) segstate[(int64_t)(N + i) * S + s] = P[i];
+  if (!want_back) return;
+  double Jf[NP], ef[N];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) Jf[i] = grpfut[(int64_t)i * G + g];
+#pragma unroll
+  for (int i = 0; i < N; ++i) ef[i] = grpfut[(int64_t)(NP + i) * G + g];
+  if (lane + 1 < n) {
+    double Jn[NP], en[N];
+    future_step<N>([&](int f) { return suf2[(int64_t)f * S + s + 1]; }, Jf, ef, Jn, en, ok);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) Jf[i] = Jn[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) ef[i] = en[i];
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) segfut[(int64_t)i * S + s] = Jf[i];
+#pragma unroll
+  for (int i = 0; i < N; ++i) segfut[(int64_t)(NP + i) * S + s] = ef[i];
+  (void)ok;  // a failed combination leaves non-finite states, caught by the segment's check
+}
+
 template <int N>
 void run_scan_n(hipStream_t st, const DevPlan& p, const DevParams& pr, const ScanWork& w, double* loglik,
                 int32_t* status, int back) {
@@ -309,10 +370,28 @@ void run_scan_n(hipStream_t st, const DevPlan& p, const DevParams& pr, const Sca
   prof_begin("k_seg_scan", st);
   hipLaunchKernelGGL(k_seg_scan<N>, dim3(p.n_seg), dim3(WAVE), 0, st, p, w.summ, w.pre, w.suf, w.segtot, back);
   prof_end("k_seg_scan", st);
-  prof_begin("k_series_scan", st);
-  hipLaunchKernelGGL(k_series_scan<N>, dim3((unsigned)p.n_series), dim3(WAVE), 0, st, p, pr, w.segtot, w.segstate,
-                     w.segfut, back);
-  prof_end("k_series_scan", st);
+  if (w.p2) {
+    // series with more than WAVE segments: the segment totals are scanned in
+    // groups of WAVE like the chunk summaries, the group totals per series
+    const DevPlan& p2 = *w.p2;
+    prof_begin("k_grp_scan", st);
+    hipLaunchKernelGGL(k_seg_scan<N>, dim3(p2.n_seg), dim3(WAVE), 0, st, p2, w.segtot, w.pre2, w.suf2, w.grptot,
+                       back);
+    prof_end("k_grp_scan", st);
+    prof_begin("k_series_scan", st);
+    hipLaunchKernelGGL(k_series_scan<N>, dim3((unsigned)p2.n_series), dim3(WAVE), 0, st, p2, pr, w.grptot,
+                       w.grpstate, w.grpfut, back);
+    prof_end("k_series_scan", st);
+    prof_begin("k_grp_fix", st);
+    hipLaunchKernelGGL(k_grp_fix<N>, dim3(p2.n_seg), dim3(WAVE), 0, st, p2, w.pre2, w.suf2, w.grpstate, w.grpfut,
+                       w.segstate, w.segfut, back);
+    prof_end("k_grp_fix", st);
+  } else {
+    prof_begin("k_series_scan", st);
+    hipLaunchKernelGGL(k_series_scan<N>, dim3((unsigned)p.n_series), dim3(WAVE), 0, st, p, pr, w.segtot, w.segstate,
+                       w.segfut, back);
+    prof_end("k_series_scan", st);
+  }
   prof_begin("k_seg_fix", st);
   hipLaunchKernelGGL(k_seg_fix<N>, dim3(p.n_seg), dim3(WAVE), 0, st, p, w.summ, w.pre, w.suf, w.segstate, w.segfut,
                      w.bstate, w.badj, w.bsmooth, w.segll, w.segok, back);

@@ -68,5 +68,9 @@ int main(int argc, char** argv) {
   put("series_wv0", P.series_wv0);
   put("series_nwv", P.series_nwv);
   put("series_slots", P.series_slots);
+  put("grp_seg0", P.grp_seg0);
+  put("grp_nseg", P.grp_nseg);
+  put("series_grp0", P.series_grp0);
+  put("series_ngrp", P.series_ngrp);
   return 0;
 }

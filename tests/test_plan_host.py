@@ -7,7 +7,9 @@ the kernels require.
 * chunks start and end where no exposure is open (the boundary state is the
   SHO state alone), and within a chunk a slot opens only while closed and
   closes only while open;
-* scan segments are runs of at most 64 consecutive chunks of one series;
+* scan segments are runs of at most 64 consecutive chunks of one series,
+  and groups of segments (the second scan level) runs of at most 64
+  consecutive segments;
 * every chunk has exactly one lane of one work wave of its own series, the
   chunks of a wave are in order of length and the wave runs as long as its
   longest chunk; padding events repeat the chunk's last time and do nothing.
@@ -83,6 +85,14 @@ def _check(P):
             assert int(P["seg_chunk0"][s]) == pos and 1 <= int(P["seg_nch"][s]) <= WAVE
             pos += int(P["seg_nch"][s])
         assert pos == c0 + nc
+        # groups of segments (second scan level): consecutive runs of <= 64
+        g0, ng = int(P["series_grp0"][b]), int(P["series_ngrp"][b])
+        assert ng == -(-ns // WAVE)
+        pos = s0
+        for g in range(g0, g0 + ng):
+            assert int(P["grp_seg0"][g]) == pos and 1 <= int(P["grp_nseg"][g]) <= WAVE
+            pos += int(P["grp_nseg"][g])
+        assert pos == s0 + ns
         # work waves of the series
         w0, nw = int(P["series_wv0"][b]), int(P["series_nwv"][b])
         assert nw == -(-nc // WAVE)
