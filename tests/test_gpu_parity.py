@@ -218,3 +218,25 @@ def test_long_series_multi_level_scan(lib):
             gfd = kalman.loglik_grad_fd(s["ts"], s["te"], s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"],
                                         s["jitter"])
             assert _grad_err(g.cpu().numpy()[1], gfd) < GRAD_TOL
+
+
+def test_two_level_scan_with_several_totals_per_lane(lib):
+    """A 300000-exposure single-instrument series cut at every quiet point:
+    more than 4096 segments, so the second scan level runs over more than 64
+    groups and each lane of the series-level scan walks several group
+    totals.  Log-likelihood against the oracle; the gradient against that of
+    the default chunking, whose scan has a different structure."""
+    b = W.random_small_batch(91, B=1, n_lo=300000, n_hi=300000, M=1, J=1, T=30000.0)
+    ref = _oracle_ll(b)
+    plan = _plan(lib, b, chunk_min=1, chunk_target=1)
+    st = plan.stats()
+    assert st["n_segments"] > 64 * 64, st
+    ll, g = plan.loglik_grad(b.sigma, b.omega0, b.quality, b.jitter)
+    ll1 = plan.loglik(b.sigma, b.omega0, b.quality, b.jitter).cpu().numpy()
+    ll, g = ll.cpu().numpy(), g.cpu().numpy()
+    plan0 = _plan(lib, b)
+    ll0, g0 = plan0.loglik_grad(b.sigma, b.omega0, b.quality, b.jitter)
+    ll0, g0 = ll0.cpu().numpy(), g0.cpu().numpy()
+    print(st, plan0.stats(), _rel(ll, ref), _rel(ll0, ref), _grad_err(g[0], g0[0]))
+    assert np.all(_rel(ll, ref) < LL_TOL) and np.all(_rel(ll1, ref) < LL_TOL) and np.all(_rel(ll0, ref) < LL_TOL)
+    assert _grad_err(g[0], g0[0]) < GRAD_TOL
