@@ -75,6 +75,10 @@ typedef struct {
   int32_t threads;       /* host threads used to build the plan; 0 = all */
 } gp_ssm_plan_options;
 
+/* n_events_padded: events in the interleaved device layout, the real ones and
+ * the no-op padding of chunks shorter than the longest of their wavefront;
+ * n_segments: runs of up to 64 consecutive chunks combined by one wavefront
+ * of the time-parallel scan. */
 typedef struct {
   int64_t n_series, n_meas, n_events, n_events_padded;
   int32_t n_chunks, n_segments, max_slots, max_chunk_len;

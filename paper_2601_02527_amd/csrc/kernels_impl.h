@@ -1,13 +1,13 @@
 // Kernels for one number of SHO terms (GPSSM_M, set by the including file)
 // and every slot count J = 1..MAX_SLOTS.
 //
-// Work mapping: one wavefront per segment (up to 64 consecutive chunks of one
-// series, one chunk per lane).  All lanes of a wavefront share the series, so
-// its hyperparameters and Taylor tables are wavefront-uniform (scalar loads);
-// events are stored interleaved so each step of the wavefront reads 64
-// consecutive values.  Lanes whose chunk is shorter than the segment's
-// longest read padding events (zero step, no measurement), which leave the
-// state unchanged.
+// Work mapping: one wavefront per work wave (up to 64 chunks of one series of
+// similar length, one chunk per lane, found through the plan's wv_chunk).
+// All lanes of a wavefront share the series, so its hyperparameters and
+// Taylor tables are wavefront-uniform; events are stored interleaved so each
+// step of the wavefront reads 64 consecutive values.  Lanes whose chunk is
+// shorter than the wave's longest read padding events (zero step, no
+// measurement), which leave the state unchanged.
 #pragma once
 
 #include "kernels.h"
