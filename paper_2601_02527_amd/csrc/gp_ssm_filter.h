@@ -892,10 +892,11 @@ GPD void discretise(const TermConst* tc, const double* coef, double dt, TermQ* t
   }
 }
 
-// with the beta-derivatives of the base functions (db[t*6 + f]); the tables
-// of term t (values, then beta-derivatives) start at coef + t * 2 NCOEF
-template <int M, class Acc = DiscFull>
-GPD void discretise_dual(const TermConst* tc, const double* coef, double dt, double* db, TermQ* tq) {
+// with the beta-derivatives of the base functions (db[t*6 + f], a register
+// array or a LaneLds view); the tables of term t (values, then
+// beta-derivatives) start at coef + t * 2 NCOEF
+template <int M, class Acc = DiscFull, class DB>
+GPD void discretise_dual(const TermConst* tc, const double* coef, double dt, DB&& db, TermQ* tq) {
 #pragma unroll
   for (int t = 0; t < M; ++t) {
     const double x = tc[t].w0 * dt;
@@ -926,14 +927,20 @@ GPD void discretise_dual(const TermConst* tc, const double* coef, double dt, dou
 // with respect to the state after the step, on exit with respect to (m, P).
 // The predicted moments are not formed: the gain u = (A P A^T + Q) h is
 // computed as A (P (A^T h)) + Q h, and (A P) one column at a time.
-template <class Dm>
+// DBL: the beta-derivatives of the base functions, needed only at the end of
+// the step, wait in the lane's LDS slots dbl instead of registers.
+template <class Dm, bool DBL = false>
 GPD void adjoint_step(const double* m, const double* P, double* mb, double* Pb, const TermConst* tc, const double* coef,
-                      double dt, uint32_t info, const Obs& o, double jit, const GradAcc<Dm::M>& acc) {
+                      double dt, uint32_t info, const Obs& o, double jit, const GradAcc<Dm::M>& acc,
+                      LaneLds dbl = LaneLds{nullptr}) {
   constexpr int M = Dm::M, J = Dm::J, NX = Dm::NX, D = Dm::D;
   const uint32_t open = ev_open(info);
-  double db[6 * M];
+  double dbr[DBL ? 1 : 6 * M];
   TermQ tq[M];
-  discretise_dual<M, DiscGrad>(tc, coef, dt, db, tq);
+  if constexpr (DBL)
+    discretise_dual<M, DiscGrad>(tc, coef, dt, dbl, tq);
+  else
+    discretise_dual<M, DiscGrad>(tc, coef, dt, dbr, tq);
   double oj[J > 0 ? J : 1];
 #pragma unroll
   for (int j = 0; j < J; ++j) oj[j] = ((open >> j) & 1u) ? 1.0 : 0.0;
@@ -1090,7 +1097,15 @@ GPD void adjoint_step(const double* m, const double* P, double* mb, double* Pb, 
 #pragma unroll
       for (int j = 0; j < J; ++j) zz = fma(oj[i] * oj[j], Pb[sidx(NX + i, NX + j, D)], zz);
     w[10] = zz;
-    term_backprop(tc[t], tq[t], db + 6 * t, dt, w, acc.s(t), acc.w(t), acc.q(t));
+    double d6[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      if constexpr (DBL)
+        d6[f] = dbl[6 * t + f];
+      else
+        d6[f] = dbr[6 * t + f];
+    }
+    term_backprop(tc[t], tq[t], d6, dt, w, acc.s(t), acc.w(t), acc.q(t));
   }
 
   // adjoint to the state before the predict

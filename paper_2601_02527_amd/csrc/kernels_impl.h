@@ -193,10 +193,12 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
   for (int32_t k = 0; k < L; ++k) {
     const EvRaw cur = nxt;
     if (k + 1 < L) nxt = fetch_event(p, ev0 + (int64_t)(k + 1) * WAVE + lane);
+    // the records come back long after they have left the caches: streaming
+    // (non-temporal) stores
 #pragma unroll
-    for (int f = 0; f < D; ++f) rb[((int64_t)k * F + f) * WAVE + lane] = m[f];
+    for (int f = 0; f < D; ++f) __builtin_nontemporal_store(m[f], &rb[((int64_t)k * F + f) * WAVE + lane]);
 #pragma unroll
-    for (int f = 0; f < NP; ++f) rb[((int64_t)k * F + D + f) * WAVE + lane] = P[f];
+    for (int f = 0; f < NP; ++f) __builtin_nontemporal_store(P[f], &rb[((int64_t)k * F + D + f) * WAVE + lane]);
     const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2);
     TermQ tq[M];
     discretise<M, DiscGrad, 2 * NCOEF>(tc, coef, cur.dt, tq);
@@ -213,6 +215,10 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
   __shared__ double lacc[(3 * M + 1) * WAVE];
   const GradAcc<M> acc{lacc + lane};
   acc.init();
+  // with four open exposures the step's registers spill; the beta-derivatives
+  // then wait in LDS (9 KB at M = 3)
+  constexpr bool DBL = J >= 4;
+  __shared__ double ldb[DBL ? 6 * M * WAVE : 1];
   nxt = fetch_event(p, ev0 + (int64_t)(L - 1) * WAVE + lane);
   for (int32_t k = L - 1; k >= 0; --k) {
     const EvRaw cur = nxt;
@@ -222,7 +228,7 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
 #pragma unroll
     for (int f = 0; f < NP; ++f) P[f] = rb[((int64_t)k * F + D + f) * WAVE + lane];
     const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2);
-    adjoint_step<Dm>(m, P, mb, Pb, tc, coef, cur.dt, cur.info, o, jit, acc);
+    adjoint_step<Dm, DBL>(m, P, mb, Pb, tc, coef, cur.dt, cur.info, o, jit, acc, LaneLds{ldb + lane});
   }
   if (active && p.chunk_first[c]) {
     // prior of the SHO states: sigma_t^2 I in scaled coordinates
@@ -420,9 +426,9 @@ __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const 
     predict_mean<Dm>(m, tq, open);
     predict_cov<Dm>(P, tq, open);
 #pragma unroll
-    for (int f = 0; f < D; ++f) rb[((int64_t)k * F + f) * WAVE + lane] = m[f];
+    for (int f = 0; f < D; ++f) __builtin_nontemporal_store(m[f], &rb[((int64_t)k * F + f) * WAVE + lane]);
 #pragma unroll
-    for (int f = 0; f < NP; ++f) rb[((int64_t)k * F + D + f) * WAVE + lane] = P[f];
+    for (int f = 0; f < NP; ++f) __builtin_nontemporal_store(P[f], &rb[((int64_t)k * F + D + f) * WAVE + lane]);
     update_close(cur, m, P);
   }
 
