@@ -194,7 +194,7 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
     const EvRaw cur = nxt;
     if (k + 1 < L) nxt = fetch_event(p, ev0 + (int64_t)(k + 1) * WAVE + lane);
     // the records come back long after they have left the caches: streaming
-    // (non-temporal) stores
+    // (non-temporal) stores here and loads in the backward sweep
 #pragma unroll
     for (int f = 0; f < D; ++f) __builtin_nontemporal_store(m[f], &rb[((int64_t)k * F + f) * WAVE + lane]);
 #pragma unroll
@@ -224,9 +224,9 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
     const EvRaw cur = nxt;
     if (k > 0) nxt = fetch_event(p, ev0 + (int64_t)(k - 1) * WAVE + lane);
 #pragma unroll
-    for (int f = 0; f < D; ++f) m[f] = rb[((int64_t)k * F + f) * WAVE + lane];
+    for (int f = 0; f < D; ++f) m[f] = __builtin_nontemporal_load(&rb[((int64_t)k * F + f) * WAVE + lane]);
 #pragma unroll
-    for (int f = 0; f < NP; ++f) P[f] = rb[((int64_t)k * F + D + f) * WAVE + lane];
+    for (int f = 0; f < NP; ++f) P[f] = __builtin_nontemporal_load(&rb[((int64_t)k * F + D + f) * WAVE + lane]);
     const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2);
     adjoint_step<Dm, DBL>(m, P, mb, Pb, tc, coef, cur.dt, cur.info, o, jit, acc, LaneLds{ldb + lane});
   }
@@ -425,10 +425,12 @@ __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const 
     const uint32_t open = ev_open(cur.info);
     predict_mean<Dm>(m, tq, open);
     predict_cov<Dm>(P, tq, open);
+    // ordinary stores: a smoothed series' records (tens of MB) can stay in
+    // the last-level cache until the backward sweep reads them
 #pragma unroll
-    for (int f = 0; f < D; ++f) __builtin_nontemporal_store(m[f], &rb[((int64_t)k * F + f) * WAVE + lane]);
+    for (int f = 0; f < D; ++f) rb[((int64_t)k * F + f) * WAVE + lane] = m[f];
 #pragma unroll
-    for (int f = 0; f < NP; ++f) __builtin_nontemporal_store(P[f], &rb[((int64_t)k * F + D + f) * WAVE + lane]);
+    for (int f = 0; f < NP; ++f) rb[((int64_t)k * F + D + f) * WAVE + lane] = P[f];
     update_close(cur, m, P);
   }
 
