@@ -150,10 +150,15 @@ def test_errors(lib):
     assert e.value.code == -4
 
 
-@pytest.mark.parametrize("M,J", [(1, 1), (2, 2), (2, 3), (3, 3)])
-def test_gradient_matches_oracle(lib, M, J):
-    b = W.random_small_batch(300 + 10 * M + J, B=6, n_lo=5, n_hi=60, M=M, J=J)
+@pytest.mark.parametrize("M,J,T", [(1, 1, 2.0), (2, 2, 2.0), (2, 3, 2.0), (3, 3, 2.0), (3, 4, 0.4), (4, 2, 2.0),
+                                   (4, 4, 0.4)])
+def test_gradient_matches_oracle(lib, M, J, T):
+    """Each slot count's kernel (the batch reaches overlap depth J; with four
+    the adjoint step keeps part of its state in LDS) against central
+    differences of the oracle."""
+    b = W.random_small_batch(300 + 10 * M + J, B=6, n_lo=5, n_hi=60, M=M, J=J, T=T)
     plan = _plan(lib, b, chunk_min=4, chunk_target=9)
+    assert plan.stats()["max_slots"] == J
     ll, g = plan.loglik_grad(b.sigma, b.omega0, b.quality, b.jitter)
     ll = ll.cpu().numpy()
     g = g.cpu().numpy()
