@@ -140,3 +140,30 @@ def test_component_posteriors(lib, opt):
              np.max(np.abs(out["term_mean"][sl].sum(axis=1) - out["mean_test"][sl])) / np.sqrt(k0))
         print(i, e)
         assert max(e) < TOL, (i, e)
+
+
+@pytest.mark.parametrize("M,J,T", [(3, 4, 0.4), (4, 2, 2.0), (4, 4, 0.4)])
+def test_four_slots_and_four_terms(lib, M, J, T):
+    """The smoother's kernels for four overlapping exposures and for four terms
+    (dense batches reach the overlap depth they name), total and per-term
+    posteriors against the oracle."""
+    b = W.random_small_batch(70 + 10 * M + J, B=4, n_lo=10, n_hi=50, M=M, J=J, T=T)
+    rng = np.random.default_rng(17)
+    parts = []
+    for i in range(b.n_series):
+        s = b.series(i)
+        lo, hi = s["ts"].min(), s["te"].max()
+        parts.append(np.concatenate([rng.uniform(lo - 0.05, hi + 0.05, 15), s["te"][:2]]))
+    to = np.concatenate([[0], np.cumsum([len(p) for p in parts])]).astype(np.int64)
+    tt = np.concatenate(parts)
+    out, plan = _run(lib, b, tt, to, terms=True, chunk_min=3, chunk_target=5)
+    assert plan.stats()["max_slots"] == J
+    _check(b, out, tt, to)
+    for i in range(b.n_series):
+        s = b.series(i)
+        sl = slice(int(to[i]), int(to[i + 1]))
+        *_, tm, tv = kalman.smooth(s["ts"], s["te"], s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"],
+                                   s["jitter"], t_test=tt[sl], terms=True)
+        k0 = float(np.sum(np.asarray(s["sigma"]) ** 2))
+        assert np.max(np.abs(out["term_mean"][sl] - tm)) < TOL * np.sqrt(k0)
+        assert np.max(np.abs(out["term_var"][sl] - tv)) < TOL * k0
