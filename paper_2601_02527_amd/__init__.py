@@ -224,6 +224,59 @@ class Plan:
         return out
 
 
+def _one_shot_inputs(offsets, t_start, t_end, y, yerr, sigma, omega0, quality, jitter):
+    torch = _torch()
+    off = _dev(offsets, torch.int64)
+    B = off.numel() - 1
+    sigma = _dev(sigma).reshape(B, -1)
+    M = sigma.shape[1]
+    arrs = [_dev(a) for a in (t_start, t_end, y, yerr)]
+    omega0 = _dev(omega0).reshape(B, M)
+    quality = _dev(quality).reshape(B, M)
+    jit = None if jitter is None else _dev(jitter).reshape(B)
+    return B, M, off, arrs, sigma, omega0, quality, jit
+
+
+def loglik(offsets, t_start, t_end, y, yerr, sigma, omega0, quality, jitter=None):
+    """One-shot log-likelihood (gp_ssm_loglik: plan, run, destroy)."""
+    torch = _torch()
+    B, M, off, (ts, te, yy, ye), s, w, q, j = _one_shot_inputs(offsets, t_start, t_end, y, yerr, sigma, omega0,
+                                                               quality, jitter)
+    ll = torch.empty(B, dtype=torch.float64, device="cuda")
+    _check(library().gp_ssm_loglik(B, _ptr(off), _ptr(ts), _ptr(te), _ptr(yy), _ptr(ye), M, _ptr(s), _ptr(w), _ptr(q),
+                                   _ptr(j), _ptr(ll), None, _stream()))
+    return ll
+
+
+def loglik_grad(offsets, t_start, t_end, y, yerr, sigma, omega0, quality, jitter=None):
+    """One-shot log-likelihood and gradient (gp_ssm_loglik_grad)."""
+    torch = _torch()
+    B, M, off, (ts, te, yy, ye), s, w, q, j = _one_shot_inputs(offsets, t_start, t_end, y, yerr, sigma, omega0,
+                                                               quality, jitter)
+    ll = torch.empty(B, dtype=torch.float64, device="cuda")
+    g = torch.empty((B, 3 * M + 1), dtype=torch.float64, device="cuda")
+    _check(library().gp_ssm_loglik_grad(B, _ptr(off), _ptr(ts), _ptr(te), _ptr(yy), _ptr(ye), M, _ptr(s), _ptr(w),
+                                        _ptr(q), _ptr(j), _ptr(ll), _ptr(g), None, _stream()))
+    return ll, g
+
+
+def smooth(offsets, t_start, t_end, y, yerr, sigma, omega0, quality, jitter, test_offsets, t_test, data=True):
+    """One-shot posterior (gp_ssm_smooth)."""
+    torch = _torch()
+    B, M, off, (ts, te, yy, ye), s, w, q, j = _one_shot_inputs(offsets, t_start, t_end, y, yerr, sigma, omega0,
+                                                               quality, jitter)
+    to = _dev(test_offsets, torch.int64)
+    tt = _dev(t_test)
+    mt, vt = torch.empty_like(tt), torch.empty_like(tt)
+    md = torch.empty(ts.numel(), dtype=torch.float64, device="cuda") if data else None
+    vd = torch.empty(ts.numel(), dtype=torch.float64, device="cuda") if data else None
+    st = torch.empty(B, dtype=torch.int32, device="cuda")
+    _check(library().gp_ssm_smooth(B, _ptr(off), _ptr(ts), _ptr(te), _ptr(yy), _ptr(ye), M, _ptr(s), _ptr(w), _ptr(q),
+                                   _ptr(j), _ptr(to), _ptr(tt), _ptr(mt), _ptr(vt), _ptr(md), _ptr(vd), _ptr(st),
+                                   _stream()))
+    return dict(mean_test=mt, var_test=vt, mean_data=md, var_data=vd, status=st)
+
+
 def _autograd_function():
     torch = _torch()
 

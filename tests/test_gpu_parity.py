@@ -245,3 +245,25 @@ def test_two_level_scan_with_several_totals_per_lane(lib):
     print(st, plan0.stats(), _rel(ll, ref), _rel(ll0, ref), _grad_err(g[0], g0[0]))
     assert np.all(_rel(ll, ref) < LL_TOL) and np.all(_rel(ll1, ref) < LL_TOL) and np.all(_rel(ll0, ref) < LL_TOL)
     assert _grad_err(g[0], g0[0]) < GRAD_TOL
+
+
+def test_one_shot_entry_points(lib):
+    """gp_ssm_loglik, gp_ssm_loglik_grad and gp_ssm_smooth (plan, run, destroy
+    in one call) give the plan path's results bit for bit, and the oracle's."""
+    b = W.random_small_batch(33, B=5, n_lo=3, n_hi=50, M=2, J=3)
+    inputs = (b.offsets, b.t_start, b.t_end, b.y, b.yerr, b.sigma, b.omega0, b.quality, b.jitter)
+    plan = _plan(lib, b)
+    ll_p, g_p = plan.loglik_grad(b.sigma, b.omega0, b.quality, b.jitter)
+    ll1 = lib.loglik(*inputs).cpu().numpy()
+    ll2, g2 = lib.loglik_grad(*inputs)
+    assert np.array_equal(ll1, ll_p.cpu().numpy()) and np.array_equal(ll2.cpu().numpy(), ll_p.cpu().numpy())
+    assert np.array_equal(g2.cpu().numpy(), g_p.cpu().numpy())
+    assert np.all(_rel(ll1, _oracle_ll(b)) < LL_TOL)
+    tt = np.concatenate([np.linspace(b.series(i)["ts"].min() - 0.1, b.series(i)["te"].max() + 0.1, 9)
+                         for i in range(b.n_series)])
+    to = np.arange(b.n_series + 1, dtype=np.int64) * 9
+    o1 = lib.smooth(*inputs, to, tt)
+    o2 = plan.smooth(b.sigma, b.omega0, b.quality, b.jitter, to, tt)
+    for k in ("mean_test", "var_test", "mean_data", "var_data"):
+        assert np.array_equal(o1[k].cpu().numpy(), o2[k].cpu().numpy()), k
+    assert np.all(o1["status"].cpu().numpy() == 0)
