@@ -107,7 +107,7 @@ def _timed(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
-def run_legs(gp, steps=3, warmup=1):
+def run_legs(gp, steps=3, warmup=1, which=("C3", "C2", "C5")):
     """The other configurations of the hot path, each on one GPU:
     C3 (4096 series of 1e3..5e4 exposures, M = 2: batched launch),
     C5 (one series of 1e7 exposures, M = 3, J = 4: time-parallel scan) with the
@@ -126,7 +126,17 @@ def run_legs(gp, steps=3, warmup=1):
         gp.profile_enable(False)
         return {k: round(v[1] / max(1, v[0]), 4) for k, v in p.items()}
 
-    # C3
+    if "C3" in which:
+        _leg_c3(gp, legs, dev, prof_run, steps, warmup)
+    if "C2" in which:
+        _leg_c2(gp, legs, dev, prof_run, steps, warmup)
+    if "C5" in which:
+        _leg_c5(gp, legs, dev, prof_run, steps, warmup)
+    return legs
+
+
+def _leg_c3(gp, legs, dev, prof_run, steps, warmup):
+    import torch
     t0 = time.perf_counter()
     b = W.batch_4096()
     gen = time.perf_counter() - t0
@@ -148,7 +158,9 @@ def run_legs(gp, steps=3, warmup=1):
     del plan, b, a
     torch.cuda.empty_cache()
 
-    # C2: smoother first (its plain-filter rate also projects C5)
+
+def _leg_c2(gp, legs, dev, prof_run, steps, warmup):
+    import torch
     b = W.long_100k()
     plan = gp.Plan(b.offsets, b.t_start, b.t_end, b.y, b.yerr)
     a = (dev(b.sigma), dev(b.omega0), dev(b.quality), dev(b.jitter))
@@ -169,7 +181,9 @@ def run_legs(gp, steps=3, warmup=1):
     del plan, b, a
     torch.cuda.empty_cache()
 
-    # C5
+
+def _leg_c5(gp, legs, dev, prof_run, steps, warmup):
+    import torch
     t0 = time.perf_counter()
     b = W.long_1e7()
     gen = time.perf_counter() - t0
@@ -197,7 +211,6 @@ def run_legs(gp, steps=3, warmup=1):
     print(f"[bench] C5 {legs['C5_long_1e7']}", file=sys.stderr, flush=True)
     del plan, sub, b, a
     torch.cuda.empty_cache()
-    return legs
 
 
 def cpu_oracle_baseline(batch, n_series, threads):
@@ -230,6 +243,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-legs", action="store_true", help="skip the C2, C3 and C5 configurations")
+    ap.add_argument("--leg", choices=["C2", "C3", "C5"],
+                    help="run only this configuration (for profiling) and print its figures as JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 1 GiB (10 times), to scale HBM byte counters")
     args = ap.parse_args()
@@ -245,6 +260,11 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(1)
+
+    if args.leg:
+        legs = run_legs(gp, steps=args.steps, warmup=args.warmup, which=(args.leg,))
+        print(json.dumps({"legs": legs}))
+        return
 
     if args.copy_calibration:
         n = (1 << 30) // 8
