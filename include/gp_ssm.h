@@ -2,7 +2,8 @@
  * gp_ssm -- exact O(N) Gaussian-process likelihood, gradient and posterior for
  * exposure-integrated, possibly overlapping measurements of a sum of SHO
  * (stochastically driven damped harmonic oscillator) processes, computed by a
- * Kalman filter / RTS smoother over the augmented state-space model of
+ * Kalman filter and smoother (the RTS posterior, in adjoint form) over the
+ * augmented state-space model of
  * "Scalable Gaussian Processes for Integrated and Overlapping Measurements via
  * Augmented State-Space Models" (Sec. 3.2: an integrator state per instrument,
  * reset when an exposure opens and read out when it closes), on AMD MI355X
