@@ -375,6 +375,35 @@ def test_prediction_far_from_data_reverts_to_prior():
     assert np.allclose(vt, np.sum(np.asarray(s["sigma"]) ** 2), rtol=1e-12)
 
 
+def test_smoother_accuracy_near_coincident_starts():
+    """The oracle's smoother (the RTS recursion of Sec. 3.2.2, long double)
+    inverts the predicted covariance, which is nearly singular where two
+    exposures start 3 ms apart: against the dense posterior (Sec. 2.1) its
+    smoothed variances just before the pair stay within 1e-6 of the prior
+    variance, and away from it within 1e-12 -- the accuracy the full-size
+    smoother comparison allows for."""
+    rng = np.random.default_rng(3)
+    s1, e1 = W.place_slot(rng, 1.0, rng.uniform(5, 15, 30) / 1440.0)
+    s2, e2 = W.place_slot(rng, 1.0, rng.uniform(5, 15, 30) / 1440.0)
+    j = int(np.argmin(np.abs(s2 - s1[15])))
+    length = e2[j] - s2[j]
+    s2[j] = s1[15] + 3e-3 / 86400.0
+    e2[j] = s2[j] + length
+    ts, te = np.concatenate([s1, s2]), np.concatenate([e1, e2])
+    o = np.argsort(ts, kind="stable")
+    ts, te = ts[o], te[o]
+    sig, w0, q = [1.0, 0.5], [2 * np.pi / 0.2, 2 * np.pi * 1440 / 5], [1 / np.sqrt(2), 30.0]
+    yerr = np.full(len(ts), 0.2)
+    y = rng.normal(size=len(ts)) * 0.5
+    _, vd_dense, _, _ = dense.posterior(ts, te, y, yerr, sig, w0, q, 0.0)
+    _, _, _, _, vd = kalman.smooth(ts, te, y, yerr, sig, w0, q, 0.0)
+    err = np.abs(vd - vd_dense) / 1.25
+    p = int(np.argmin(np.diff(ts)))
+    assert np.diff(ts)[p] * 86400.0 < 0.01
+    away = np.r_[err[:p - 12], err[p + 3:]]
+    assert err.max() < 1e-6 and away.max() < 1e-12, (err.max(), away.max())
+
+
 # ---------------------------------------------------------------------------
 # component-wise prediction (Appendix C, component-wise predictive means and
 # variances)
