@@ -48,13 +48,24 @@ def algorithmic_flops_per_point(M, J):
 
 def algorithmic_bytes_per_point(M, J, grad):
     """Inputs in event order read per pass (t_start, t_end, y, yerr and the
-    slot byte: 33 B); the gradient reads them twice and writes/reads the
-    per-event filter state it recomputes from."""
+    slot byte: 33 B per measurement); the gradient reads them twice.  The
+    per-chunk boundary states are counted separately (see chunk_bytes)."""
+    return 33.0 * (2 if grad else 1)
+
+
+def chunk_bytes(M, n_chunks):
+    """Per-chunk checkpoint traffic of a loglik + gradient step: the filtered
+    SHO state at each chunk start and the adjoint at each chunk end (2M + the
+    packed 2M x 2M covariance each), written by the scan and read back."""
+    NX = 2 * M
+    return 2 * 2 * (NX + NX * (NX + 1) // 2) * 8 * n_chunks
+
+
+def record_bytes(M, J, n_events_padded):
+    """Per-event filter states the adjoint kernel writes and reads back (its
+    recomputation buffer): D + D(D+1)/2 doubles per event, each way."""
     D = 2 * M + J
-    base = 33.0
-    if not grad:
-        return base
-    return 2 * base + 2 * 2 * (D + D * (D + 1) / 2) * 8
+    return 2 * (D + D * (D + 1) // 2) * 8 * n_events_padded
 
 
 def kernel_source_fingerprint():
@@ -96,6 +107,7 @@ def measured_traffic(kernel, workload):
 
 
 def _timed(fn, steps, warmup):
+    """Mean seconds per call over `steps` calls after `warmup` untimed ones."""
     import torch
     for _ in range(warmup):
         fn()
@@ -105,6 +117,24 @@ def _timed(fn, steps, warmup):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
+
+
+def _median_replay(fn, n):
+    """Median seconds of n calls, each synchronised on its own."""
+    import torch
+    ts = []
+    for _ in range(n):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def _plan_memory(plan):
+    st = plan.stats()
+    return {"device_bytes": st["device_bytes"], "record_bytes": st["record_bytes"]}
 
 
 def run_legs(gp, steps=3, warmup=1, which=("C3", "C2", "C5")):
@@ -153,7 +183,9 @@ def _leg_c3(gp, legs, dev, prof_run, steps, warmup):
         "series": b.n_series, "points": pts, "terms": b.n_terms, "slots": plan.stats()["max_slots"],
         "loglik_grad_ms": tg * 1e3, "loglik_grad_points_per_s": pts / tg,
         "loglik_ms": tl * 1e3, "loglik_points_per_s": pts / tl, "nan_series": int(torch.isnan(ll).sum().item()),
-        "kernels_ms": prof_run(lambda: plan.loglik_grad(*a)), "plan_s": tp, "generate_s": gen}
+        "loglik_grad_median_replay_ms": _median_replay(lambda: plan.loglik_grad(*a), 5) * 1e3,
+        "kernels_ms": prof_run(lambda: plan.loglik_grad(*a)), "plan_s": tp, "generate_s": gen,
+        "device_memory": _plan_memory(plan)}
     print(f"[bench] C3 {legs['C3_batch_4096']}", file=sys.stderr, flush=True)
     del plan, b, a
     torch.cuda.empty_cache()
@@ -176,7 +208,7 @@ def _leg_c2(gp, legs, dev, prof_run, steps, warmup):
         "loglik_ms": tl * 1e3,
         "plain_gpu_filter_ms": tplain * 1e3,
         "finite": bool(torch.isfinite(out["mean_test"]).all().item() and torch.isfinite(out["var_test"]).all().item()),
-        "kernels_ms": prof_run(lambda: plan.smooth(*a, to, tt))}
+        "kernels_ms": prof_run(lambda: plan.smooth(*a, to, tt)), "device_memory": _plan_memory(plan)}
     print(f"[bench] C2 {legs['C2_long_100k_smooth']}", file=sys.stderr, flush=True)
     del plan, b, a
     torch.cuda.empty_cache()
@@ -207,7 +239,9 @@ def _leg_c5(gp, legs, dev, prof_run, steps, warmup):
         "segments": st["n_segments"], "loglik_ms": tl * 1e3, "loglik_grad_ms": tg * 1e3,
         "plain_gpu_filter_projected_ms": proj * 1e3, "plain_gpu_filter_measured": f"{nsub} exposures in {tsub * 1e3:.1f} ms",
         "scan_speedup_vs_plain": proj / tl, "loglik_finite": bool(torch.isfinite(ll).all().item()),
-        "kernels_ms": prof_run(lambda: plan.loglik_grad(*a)), "plan_s": tp, "generate_s": gen}
+        "loglik_grad_median_replay_ms": _median_replay(lambda: plan.loglik_grad(*a), 5) * 1e3,
+        "kernels_ms": prof_run(lambda: plan.loglik_grad(*a)), "plan_s": tp, "generate_s": gen,
+        "device_memory": _plan_memory(plan)}
     print(f"[bench] C5 {legs['C5_long_1e7']}", file=sys.stderr, flush=True)
     del plan, sub, b, a
     torch.cuda.empty_cache()
@@ -239,7 +273,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="grad_1024", choices=["grad_1024", "batch_4096"])
     ap.add_argument("--plain-sample", type=int, default=4)
-    ap.add_argument("--cpu-sample", type=int, default=0, help="series for the CPU oracle (0 = one per core)")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="series for the CPU oracle (0 = one per thread)")
+    ap.add_argument("--cpu-threads", type=int, default=16,
+                    help="threads for the CPU oracle (at most the visible host cores)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-legs", action="store_true", help="skip the C2, C3 and C5 configurations")
@@ -295,38 +331,42 @@ def main():
     dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda")
     sig, w0, q, jit = dev(batch.sigma), dev(batch.omega0), dev(batch.quality), dev(batch.jitter)
 
-    # warmup
+    # warmup (the first call captures the step in a graph)
     for _ in range(args.warmup):
         ll, g = plan.loglik_grad(sig, w0, q, jit)
     torch.cuda.synchronize()
     print("[bench] warmup done", file=sys.stderr, flush=True)
 
-    # timed region: loglik + gradient, kernel durations from HIP events
-    gp.profile_enable(True)
-    gp.profile_reset()
+    # timed region: K steps of loglik + gradient, replayed from the graph
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ll, g = plan.loglik_grad(sig, w0, q, jit)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    prof = gp.profile_read()
-    gp.profile_enable(False)
     ms_step = elapsed / args.steps * 1e3
     value = points * args.steps / elapsed
     bad = int(torch.isnan(ll).sum().item())
-    print(f"[bench] loglik+grad {ms_step:.3f} ms/step, {value:.4g} points/s, nan={bad}", file=sys.stderr, flush=True)
-    print(f"[bench] kernels {prof}", file=sys.stderr, flush=True)
+    med_ms = _median_replay(lambda: plan.loglik_grad(sig, w0, q, jit), max(5, args.steps)) * 1e3
+    print(f"[bench] loglik+grad {ms_step:.3f} ms/step (median of replays {med_ms:.3f}), {value:.4g} points/s, "
+          f"nan={bad}", file=sys.stderr, flush=True)
 
-    # log-likelihood alone (batched)
-    for _ in range(args.warmup):
-        plan.loglik(sig, w0, q, jit)
+    # the same K steps launched kernel by kernel, each kernel bracketed by HIP
+    # events on the launch stream: per-kernel durations for the roofline
+    gp.profile_enable(True)
+    gp.profile_reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        plan.loglik(sig, w0, q, jit)
+        plan.loglik_grad(sig, w0, q, jit)
     torch.cuda.synchronize()
-    ms_ll = (time.perf_counter() - t0) / args.steps * 1e3
+    ms_step_direct = (time.perf_counter() - t0) / args.steps * 1e3
+    prof = gp.profile_read()
+    gp.profile_enable(False)
+    print(f"[bench] kernels {prof}", file=sys.stderr, flush=True)
+
+    # log-likelihood alone (batched)
+    ms_ll = _timed(lambda: plan.loglik(sig, w0, q, jit), args.steps, args.warmup) * 1e3
 
     # plain one-series-at-a-time GPU filter on a sample
     plain = None
@@ -352,34 +392,45 @@ def main():
     dom = max(prof.items(), key=lambda kv: kv[1][1])[0] if prof else None
     roof = None
     if dom is not None:
+        # the kernel's work over the whole batch (all its launches of a step:
+        # one, unless its per-event records exceed the plan's budget and it
+        # runs in rounds)
         flops_per_launch = {"k_adjoint": (grad_pt - fwd_pt) * points, "k_summaries": fwd_pt * points}.get(dom)
-        avg_s = kern[dom]["avg_ms"] * 1e-3
+        launches = prof[dom][0] / args.steps
+        step_ms = prof[dom][1] / args.steps
         if flops_per_launch is not None:
-            ach = flops_per_launch / avg_s / 1e12
+            ach = flops_per_launch / (step_ms * 1e-3) / 1e12
             tr = measured_traffic(dom, args.workload)
             roof = {"bound": "alu", "kernel": dom, "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS,
                     "traffic": tr["bytes"] if tr else None, "traffic_detail": tr,
-                    "avg_ms": kern[dom]["avg_ms"], "flops_per_launch": flops_per_launch}
+                    "avg_ms": step_ms, "launches_per_step": launches, "flops_per_launch": flops_per_launch,
+                    "timing": f"HIP events on the launch stream over {args.steps} steps launched kernel by kernel"}
     step_flops = grad_pt * points
+    alg_bytes = algorithmic_bytes_per_point(M, J, True) * points + chunk_bytes(M, st["n_chunks"])
+    rec = record_bytes(M, J, st["n_events_padded"])
     step_roof = {"achieved_tflops": step_flops / (ms_step * 1e-3) / 1e12,
                  "frac_fp64": step_flops / (ms_step * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
-                 "hbm_gbs": algorithmic_bytes_per_point(M, J, True) * points / (ms_step * 1e-3) / 1e9}
+                 "algorithmic_bytes": alg_bytes, "hbm_gbs_algorithmic": alg_bytes / (ms_step * 1e-3) / 1e9,
+                 "record_bytes_overhead": rec, "hbm_gbs_with_records": (alg_bytes + rec) / (ms_step * 1e-3) / 1e9}
 
-    # CPU oracle on the host cores
+    # CPU oracle on the host cores, and on one core
     cpu = None
     if not args.no_cpu:
         try:
-            cores = len(os.sched_getaffinity(0))
+            nproc = len(os.sched_getaffinity(0))
         except Exception:
-            cores = os.cpu_count() or 1
-        cores = max(1, min(cores, 16))
-        ns = args.cpu_sample or cores
-        rate, secs, pts = cpu_oracle_baseline(batch, ns, cores)
-        cpu = {"value": rate, "unit": "series-points/s", "cores": cores, "kind": "oracle",
+            nproc = os.cpu_count() or 1
+        threads = max(1, min(nproc, args.cpu_threads))
+        ns = args.cpu_sample or threads
+        rate, secs, pts = cpu_oracle_baseline(batch, ns, threads)
+        rate1, secs1, pts1 = cpu_oracle_baseline(batch, 1, 1)
+        cpu = {"value": rate, "unit": "series-points/s", "cores": threads, "kind": "oracle", "nproc": nproc,
+               "one_core_value": rate1,
                "sample": f"first {ns} series of the workload at full length ({pts} points): long-double sequential "
                          f"Kalman filter log-likelihood + central-difference gradient (21 evaluations), "
-                         f"one series per thread, {secs:.1f}s"}
+                         f"one series per thread on {threads} threads ({nproc} host cores visible), {secs:.1f}s; "
+                         f"one core: series 0 ({pts1} points) in {secs1:.1f}s"}
         print(f"[bench] cpu {cpu}", file=sys.stderr, flush=True)
 
     legs = None
@@ -408,6 +459,10 @@ def main():
         "loglik_only_points_per_s": points / (ms_ll * 1e-3),
         "plain_gpu": plain,
         "plan_seconds": t_plan,
+        "median_replay_ms": med_ms,
+        "ms_per_step_kernel_by_kernel": ms_step_direct,
+        "timing": "graph replays of the captured step; value and ms_per_step over the K timed steps",
+        "device_memory": _plan_memory(plan),
         "kernels": kern,
         "step_roofline": step_roof,
         "algorithmic_flops_per_point": {"fwd": fwd_pt, "fwd_grad": grad_pt},

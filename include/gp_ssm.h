@@ -21,24 +21,37 @@
  *  - A batch holds B independent series.  offsets[B+1] (int64, ascending,
  *    offsets[0] = 0) delimits each series' measurements in the flat arrays
  *    t_start, t_end, y, yerr (length offsets[B]).  Within a series t_start
- *    must be non-decreasing; t_end >= t_start; yerr >= 0; all finite.
+ *    must be non-decreasing; t_end >= t_start; yerr >= 0; all finite.  A
+ *    series may be empty: its log-likelihood is 0, its gradient 0 and its
+ *    posterior at any test time the prior.
  *  - Hyperparameters are series-major: sigma[b*M + m], omega0[b*M + m],
  *    quality[b*M + m] (all > 0, finite), jitter[b] (>= 0) or NULL for zero.
- *  - Every array argument is a DEVICE pointer (hipMalloc'd or managed) unless
- *    stated otherwise; the caller owns all buffers.  `stream` is a
- *    hipStream_t (NULL = the default stream); kernels are enqueued on it and
- *    outputs are valid once it has synchronised.  Functions that need host
- *    copies of their inputs (plan creation, hyperparameter validation)
- *    synchronise with `stream` first.
+ *    They may be device or host arrays (host arrays are copied on the
+ *    stream).  Output arrays must be device memory (hipMalloc'd or managed);
+ *    so must every other array argument unless stated otherwise.  The
+ *    caller owns all buffers.  `stream` is a hipStream_t (NULL = the
+ *    default stream); kernels are enqueued on it and outputs are valid once
+ *    it has synchronised.  Plan creation and the smoother read some inputs
+ *    on the host (the data, test times) and synchronise with `stream` to do
+ *    so; gp_ssm_plan_loglik and gp_ssm_plan_loglik_grad do not: they only
+ *    enqueue work, replayed from a graph the plan captures on its first such
+ *    call (again after its workspace grows).  Calls on one plan share its
+ *    workspace and must be issued on one stream, or ordered by the caller.
  *  - At most GP_SSM_MAX_TERMS terms and GP_SSM_MAX_SLOTS simultaneously open
  *    exposures per series (the overlap depth; instrument labels are assigned
  *    internally, Sec. 3.2.3).
  *  - Return value: 0 on success, else a negative GP_SSM_E* code with a
- *    message from gp_ssm_last_error().  Arguments are validated before any
- *    device work.  Per-series status[b] (int32, may be NULL) receives 0 or
+ *    message from gp_ssm_last_error().  Pointers, sizes and the data are
+ *    validated on the host before any device work.  The hyperparameters are
+ *    validated on the device, per series, before any other kernel reads
+ *    them: per-series status[b] (int32, may be NULL) receives 0,
+ *    GP_SSM_EPARAM for a series whose hyperparameters are out of range, or
  *    GP_SSM_ENUMERIC for a series whose likelihood is not finite (a
- *    non-positive innovation variance or a singular summary); its outputs
- *    are then NaN and other series are unaffected.
+ *    non-positive innovation variance, an overflow or a singular summary);
+ *    the outputs of such a series are NaN and other series are unaffected.
+ *    The plan forms return 0 in that case (they do not wait for the device);
+ *    the one-shot forms, which do, return GP_SSM_EPARAM or GP_SSM_ENUMERIC
+ *    when any series failed.
  */
 #ifndef GP_SSM_H
 #define GP_SSM_H
@@ -74,15 +87,27 @@ typedef struct {
   int64_t target_chunks; /* wanted number of chunks when deriving (default 131072) */
   int32_t single_chunk;  /* 1 = never split a series in time */
   int32_t threads;       /* host threads used to build the plan; 0 = all */
+  /* device bytes for the per-event filter states that the gradient and the
+   * smoother keep between their forward and backward sweeps (default
+   * 32 GiB; <= 0 = default).  Past it they run in rounds of work waves that
+   * reuse one buffer (at least one slot per workgroup the GPU holds at once),
+   * so memory stays bounded whatever the size of the batch. */
+  int64_t record_budget;
 } gp_ssm_plan_options;
 
 /* n_events_padded: events in the interleaved device layout, the real ones and
  * the no-op padding of chunks shorter than the longest of their wavefront;
  * n_segments: runs of up to 64 consecutive chunks combined by one wavefront
- * of the time-parallel scan. */
+ * of the time-parallel scan; device_bytes: device memory the plan holds now
+ * (its event layout and tables, and the workspace its calls have grown);
+ * record_bytes: the part of it that holds per-event filter states for the
+ * backward passes (one slot per resident workgroup, bounded by the number of
+ * workgroups the GPU runs at once times the longest work wave, not by the
+ * size of the batch). */
 typedef struct {
   int64_t n_series, n_meas, n_events, n_events_padded;
   int32_t n_chunks, n_segments, max_slots, max_chunk_len;
+  int64_t device_bytes, record_bytes;
 } gp_ssm_plan_stats;
 
 /* Fills *opt with the defaults. */
@@ -150,14 +175,27 @@ int gp_ssm_plan_plain_loglik(gp_ssm_plan* plan, int64_t first, int64_t count, in
                              const double* omega0, const double* quality, const double* jitter, double* loglik,
                              void* stream);
 
-/* One-shot forms: build a plan with default options, run, destroy. */
+/* One-shot forms: build a plan with default options, run it once, wait for
+ * `stream`, destroy the plan.  Same arguments and outputs as the plan forms;
+ * they return GP_SSM_EPARAM or GP_SSM_ENUMERIC when any series failed
+ * (status[b] says which; status may be NULL).
+ *
+ * gp_ssm_loglik: the marginal log-likelihood of each series (the Gaussian
+ * likelihood of Sec. 2.4, evaluated by the Kalman filter over the augmented
+ * model of Sec. 3.2 with the per-event update of Sec. 3.2.2). */
 int gp_ssm_loglik(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end, const double* y,
                   const double* yerr, int32_t n_terms, const double* sigma, const double* omega0, const double* quality,
                   const double* jitter, double* loglik, int32_t* status, void* stream);
+/* gp_ssm_loglik_grad: the same log-likelihood and its gradient with respect
+ * to every term's (sigma, omega0, Q) (Appendix B parameterisation) and the
+ * jitter, grad[b*(3M+1) + k] ordered as for gp_ssm_plan_loglik_grad. */
 int gp_ssm_loglik_grad(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end,
                        const double* y, const double* yerr, int32_t n_terms, const double* sigma, const double* omega0,
                        const double* quality, const double* jitter, double* loglik, double* grad, int32_t* status,
                        void* stream);
+/* gp_ssm_smooth: the posterior of Sec. 3.2.2 (the smoother over the
+ * augmented model) at the data and, by the interpolation of Sec. 2.5
+ * Algorithm 1, at the test times; arguments as for gp_ssm_plan_smooth. */
 int gp_ssm_smooth(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end,
                   const double* y, const double* yerr, int32_t n_terms, const double* sigma, const double* omega0,
                   const double* quality, const double* jitter, const int64_t* test_offsets, const double* t_test,

@@ -41,13 +41,14 @@ class GpSsmError(RuntimeError):
 
 class PlanOptions(ctypes.Structure):
     _fields_ = [("chunk_min", ctypes.c_int32), ("chunk_target", ctypes.c_int32), ("target_chunks", ctypes.c_int64),
-                ("single_chunk", ctypes.c_int32), ("threads", ctypes.c_int32)]
+                ("single_chunk", ctypes.c_int32), ("threads", ctypes.c_int32), ("record_budget", ctypes.c_int64)]
 
 
 class PlanStats(ctypes.Structure):
     _fields_ = [("n_series", ctypes.c_int64), ("n_meas", ctypes.c_int64), ("n_events", ctypes.c_int64),
                 ("n_events_padded", ctypes.c_int64), ("n_chunks", ctypes.c_int32), ("n_segments", ctypes.c_int32),
-                ("max_slots", ctypes.c_int32), ("max_chunk_len", ctypes.c_int32)]
+                ("max_slots", ctypes.c_int32), ("max_chunk_len", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64), ("record_bytes", ctypes.c_int64)]
 
 
 _lib = None
@@ -93,6 +94,19 @@ def library():
 def _check(rc):
     if rc != 0:
         raise GpSsmError(rc, library().gp_ssm_last_error().decode())
+
+
+def check_status(status):
+    """Raises GpSsmError (EPARAM before ENUMERIC) if any series' status is not
+    0; waits for the device."""
+    st = status.cpu().numpy()
+    for code in (-3, -5):
+        bad = np.flatnonzero(st == code)
+        if bad.size:
+            raise GpSsmError(code, f"{bad.size} series (first {int(bad[0])})")
+    bad = np.flatnonzero(st != 0)
+    if bad.size:
+        raise GpSsmError(int(st[bad[0]]), f"{bad.size} series (first {int(bad[0])})")
 
 
 def _torch():
@@ -168,16 +182,23 @@ class Plan:
         jit = None if jitter is None else _dev(jitter).reshape(self.n_series)
         return M, sigma, omega0, quality, jit
 
-    def loglik(self, sigma, omega0, quality, jitter=None, status=False):
+    def loglik(self, sigma, omega0, quality, jitter=None, status=False, check=False):
+        """Log-likelihood of every series [B].  status=True also returns the
+        per-series status; check=True waits and raises if any series failed
+        (a failed series' outputs are NaN either way)."""
         torch = _torch()
         M, s, w, q, j = self._params(sigma, omega0, quality, jitter)
         out = torch.empty(self.n_series, dtype=torch.float64, device="cuda")
         st = torch.empty(self.n_series, dtype=torch.int32, device="cuda")
         _check(library().gp_ssm_plan_loglik(self._h, M, _ptr(s), _ptr(w), _ptr(q), _ptr(j), _ptr(out), _ptr(st),
                                             _stream()))
+        if check:
+            check_status(st)
         return (out, st) if status else out
 
-    def loglik_grad(self, sigma, omega0, quality, jitter=None, status=False):
+    def loglik_grad(self, sigma, omega0, quality, jitter=None, status=False, check=False):
+        """Log-likelihood [B] and gradient [B, 3M+1] (d/d sigma_1..M,
+        omega0_1..M, Q_1..M, jitter); status and check as for loglik."""
         torch = _torch()
         M, s, w, q, j = self._params(sigma, omega0, quality, jitter)
         out = torch.empty(self.n_series, dtype=torch.float64, device="cuda")
@@ -185,6 +206,8 @@ class Plan:
         st = torch.empty(self.n_series, dtype=torch.int32, device="cuda")
         _check(library().gp_ssm_plan_loglik_grad(self._h, M, _ptr(s), _ptr(w), _ptr(q), _ptr(j), _ptr(out), _ptr(g),
                                                  _ptr(st), _stream()))
+        if check:
+            check_status(st)
         return (out, g, st) if status else (out, g)
 
     def plain_loglik(self, sigma, omega0, quality, jitter=None, first=0, count=None):

@@ -1,11 +1,13 @@
 // C-ABI of the library (declared in include/gp_ssm.h): plans, workspace,
-// hyperparameter preparation, the cross-chunk combination and the dispatch of
-// the per-(terms, slots) kernels.
+// hyperparameter validation and preparation on the device, the launch order
+// of the work waves, the capture of a whole step in a graph, and the dispatch
+// of the per-(terms, slots) kernels.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -79,38 +81,163 @@ void prof_flush() {
 // ---------------------------------------------------------------------------
 // small kernels that do not depend on the slot count
 // ---------------------------------------------------------------------------
-__global__ void k_prep(int64_t B, int M, const double* __restrict__ sigma, const double* __restrict__ omega0,
-                       const double* __restrict__ quality, const double* __restrict__ jitter, TermConst* __restrict__ tc,
-                       double* __restrict__ coef, double* __restrict__ jit) {
-  // one thread per (series, term, series interval)
+__device__ __forceinline__ bool param_ok(double v) { return v > 0.0 && isfinite(v); }
+
+// hyperparameters of series b valid: sigma, omega0, Q > 0 and finite for every
+// term, jitter >= 0 and finite (or absent)
+__device__ __forceinline__ bool series_params_ok(const CallArgs& a, int64_t b, int M) {
+  bool ok = true;
+  for (int t = 0; t < M; ++t) {
+    const int64_t i = b * M + t;
+    ok = ok && param_ok(a.sigma[i]) && param_ok(a.omega0[i]) && param_ok(a.quality[i]);
+  }
+  if (a.jitter) ok = ok && a.jitter[b] >= 0.0 && isfinite(a.jitter[b]);
+  return ok;
+}
+
+// Validates the hyperparameters and prepares them: per (series, term) the
+// step constants and the Taylor tables of one series interval per thread,
+// per series the jitter and the validation flag.  A series that fails
+// validation is prepared with sigma = omega0 = Q = 1 and jitter 0, so that
+// every kernel runs on finite, in-range values; its outputs are set to NaN
+// and its status to GP_SSM_EPARAM where they are written.
+__global__ void k_prep(int64_t B, int M, const CallArgs* __restrict__ args, TermConst* __restrict__ tc,
+                       double* __restrict__ coef, double* __restrict__ jit, int32_t* __restrict__ bad) {
+  const CallArgs a = *args;
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j < B * M * NI) {
     const int64_t i = j / NI;
     const int iv = (int)(j - i * NI);
-    const TermConst t = make_term(sigma[i], omega0[i], quality[i]);
+    const bool ok = series_params_ok(a, i / M, M);
+    const TermConst t = ok ? make_term(a.sigma[i], a.omega0[i], a.quality[i]) : make_term(1.0, 1.0, 1.0);
     if (iv == 0) tc[i] = t;
     double* c = coef + i * 2 * NCOEF + iv * ISTRIDE;
     series_interval_table(t.beta, interval_centre(iv, t.b1ser, t.wser), c, c + NCOEF);
   }
-  if (j < B) jit[j] = jitter ? jitter[j] : 0.0;
+  if (j < B) {
+    const bool ok = series_params_ok(a, j, M);
+    jit[j] = (ok && a.jitter) ? a.jitter[j] : 0.0;
+    bad[j] = ok ? 0 : 1;
+  }
+}
+
+// Launch order of the work waves, computed on the device each call (it
+// depends on the hyperparameters).  A wave's cost varies with its series'
+// terms: a wavefront pays for the Taylor branch of a term at a step when any
+// of its lanes needs it, and for the closed-form branch when any lane needs
+// that.  With p the fraction of the series' steps below the switch point, the
+// expected cost per step and term is C_SER (1 - (1-p)^64) + C_CLO (1 - p^64)
+// on top of W0 for the filter step; p comes from the series' step-length
+// distribution (the plan's cumulative histogram over powers of two).
+// Dispatching the costliest waves first (longest processing time first)
+// evens out the SIMDs' loads.  One workgroup sorts the waves by a key of
+// 64 levels per octave of cost (counting sort; the order within a level is
+// arbitrary, and results do not depend on the order).
+constexpr int ORDER_THREADS = 1024;
+constexpr int ORDER_NB = 4096;
+
+__device__ __forceinline__ int order_key(const DevPlan& p, int M, const TermConst* __restrict__ tc,
+                                         const float* __restrict__ cdf_all, int32_t w) {
+  constexpr double W0 = 4.0, C_SER = 1.0, C_CLO = 1.5;
+  const int64_t b = p.wv_series[w];
+  const float* cdf = cdf_all + b * DT_NE;
+  double c = W0;
+  for (int t = 0; t < M; ++t) {
+    const TermConst& q = tc[b * M + t];
+    const double thr = XSER / fmax(1.0, q.beta) / q.w0;  // steps with dt <= thr take the series
+    int ex;
+    const double fr = frexp(thr, &ex);  // thr = fr 2^ex, fr in [0.5, 1)
+    const int k = ex - DT_KMIN;
+    double pr;
+    if (k <= 0)
+      pr = cdf[0];
+    else if (k >= DT_NE)
+      pr = 1.0;
+    else  // linear in log2(dt) between the edges 2^(ex-1) and 2^ex
+      pr = cdf[k - 1] + (cdf[k] - cdf[k - 1]) * (log2(fr) + 1.0);
+    c += C_SER * (1.0 - pow(1.0 - pr, (double)WAVE)) + C_CLO * (1.0 - pow(pr, (double)WAVE));
+  }
+  const double cost = (double)p.wv_len[w] * c;
+  const int lvl = (int)(log2(fmax(cost, 1.0)) * 64.0);
+  return ORDER_NB - 1 - min(max(lvl, 0), ORDER_NB - 1);  // costliest first
+}
+
+__global__ __launch_bounds__(ORDER_THREADS) void k_order(DevPlan p, int M, const TermConst* __restrict__ tc,
+                                                         const float* __restrict__ cdf, int32_t* __restrict__ order) {
+  __shared__ int32_t hist[ORDER_NB];
+  __shared__ int32_t part[ORDER_THREADS];
+  constexpr int PER = ORDER_NB / ORDER_THREADS;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < ORDER_NB; i += ORDER_THREADS) hist[i] = 0;
+  __syncthreads();
+  for (int32_t w = tid; w < p.n_wv; w += ORDER_THREADS) atomicAdd(&hist[order_key(p, M, tc, cdf, w)], 1);
+  __syncthreads();
+  // exclusive prefix sum of the histogram: PER bins per thread, then a scan
+  // of the per-thread sums
+  int32_t loc = 0;
+  for (int i = 0; i < PER; ++i) loc += hist[tid * PER + i];
+  part[tid] = loc;
+  __syncthreads();
+  for (int d = 1; d < ORDER_THREADS; d <<= 1) {
+    const int32_t v = tid >= d ? part[tid - d] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int32_t run = part[tid] - loc;
+  for (int i = 0; i < PER; ++i) {
+    const int32_t h = hist[tid * PER + i];
+    hist[tid * PER + i] = run;
+    run += h;
+  }
+  __syncthreads();
+  for (int32_t w = tid; w < p.n_wv; w += ORDER_THREADS) {
+    const int32_t at = atomicAdd(&hist[order_key(p, M, tc, cdf, w)], 1);
+    order[at] = w;
+  }
 }
 
 // gradient partials of a series' work waves summed: one wavefront per series,
-// lane l takes waves l, l + 64, ..., then a fixed-order wave reduction
+// lane l takes waves l, l + 64, ..., then a fixed-order wave reduction; NaN for
+// a series whose status is not 0
 __global__ __launch_bounds__(WAVE) void k_reduce_grad(DevPlan p, int M, const double* __restrict__ gpart,
-                                                      const int32_t* __restrict__ status, double* __restrict__ grad) {
+                                                      const CallArgs* __restrict__ args) {
   const int64_t b = blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t S = p.n_wv;
   const int32_t s0 = p.series_wv0[b], n = p.series_nwv[b];
   const int G = 3 * M + 1;
-  const bool good = status == nullptr || status[b] == 0;
+  double* const grad = args->grad;
+  const bool good = args->status[b] == 0;
   for (int f = 0; f < G; ++f) {
     double s = 0.0;
     for (int32_t q = lane; q < n; q += WAVE) s += gpart[(int64_t)f * S + s0 + q];
     s = wave_sum(s);
     if (lane == 0) grad[b * G + f] = (good && isfinite(s)) ? s : __builtin_nan("");
   }
+}
+
+// test times of series without measurements: the prior (mean 0, variance
+// sum_m sigma_m^2, each term's own variance sigma_m^2)
+__global__ void k_prior_tests(int64_t n, const int64_t* __restrict__ idx, const int32_t* __restrict__ series, int M,
+                              const TermConst* __restrict__ tc, const int32_t* __restrict__ bad,
+                              double* __restrict__ mean_test, double* __restrict__ var_test,
+                              double* __restrict__ term_mean, double* __restrict__ term_var) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t o = idx[i], b = series[i];
+  const double poison = bad[b] ? __builtin_nan("") : 0.0;
+  double v = 0.0;
+  for (int t = 0; t < M; ++t) {
+    const double s2 = tc[b * M + t].sigma * tc[b * M + t].sigma;
+    v += s2;
+    if (term_mean) {
+      term_mean[o * M + t] = poison;
+      term_var[o * M + t] = s2 + poison;
+    }
+  }
+  mean_test[o] = poison;
+  var_test[o] = v + poison;
 }
 
 KernelSet kernel_set(int M, int J) {
@@ -126,9 +253,13 @@ KernelSet kernel_set(int M, int J) {
 // ---------------------------------------------------------------------------
 // device buffers
 // ---------------------------------------------------------------------------
+// Every (re)allocation bumps *gen, the generation of the plan's workspace: a
+// captured graph holds buffer addresses and is captured again when the
+// generation it was captured at is no longer current.
 struct DBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  uint64_t* gen = nullptr;
   ~DBuf() {
     if (p) (void)hipFree(p);
   }
@@ -137,7 +268,11 @@ struct DBuf {
     if (p) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
-    if (hipMalloc(&p, n) != hipSuccess) return fail(GP_SSM_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+    if (gen) ++*gen;
+    if (hipMalloc(&p, n) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(GP_SSM_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+    }
     bytes = n;
     return 0;
   }
@@ -154,22 +289,33 @@ int upload(DBuf& d, const std::vector<T>& v) {
   return 0;
 }
 
+// true for memory a kernel can read and write (device or managed)
+bool device_memory(const void* ptr) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
 int host_copy(const void* src, size_t bytes, void* dst, hipStream_t s) {
   if (bytes == 0) return 0;
-  hipPointerAttribute_t attr;
-  bool device = false;
-  if (hipPointerGetAttributes(&attr, src) == hipSuccess) {
-    device = (attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged);
-  } else {
-    (void)hipGetLastError();
-  }
-  if (device) {
+  if (device_memory(src)) {
     HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
   } else {
     std::memcpy(dst, src, bytes);
   }
   return 0;
+}
+
+bool graphs_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("GP_SSM_GRAPH");
+    return !(e && e[0] == '0');
+  }();
+  return on;
 }
 
 }  // namespace
@@ -194,32 +340,70 @@ void prof_end(const char* name, hipStream_t s) {
 }
 }  // namespace gpssm
 
+namespace {
+enum StepKind { STEP_LOGLIK = 0, STEP_GRAD = 1 };
+constexpr int64_t DEFAULT_RECORD_BUDGET = int64_t(32) << 30;
+constexpr int ARG_RING = 16;
+}  // namespace
+
 struct gp_ssm_plan {
   int device = 0;
+  int n_cu = 1;
+  int64_t record_budget = 0;  // bytes of per-event records before the backward kernels run in rounds
+  uint64_t gen = 0;  // workspace generation (see DBuf)
   HostPlan host;
   DBuf dt, t, y, r, invd, info, meas;
   DBuf seg_chunk0, seg_nch, grp_seg0, grp_nseg, series_grp0, series_ngrp;
   DBuf wv_series, wv_nch, wv_len, wv_chunk, wv_ev0;
   DBuf chunk_len, chunk_series, chunk_wv, chunk_lane, chunk_first;
-  DBuf series_chunk0, series_nch, series_seg0, series_nseg, series_wv0, series_nwv;
+  DBuf series_chunk0, series_nch, series_seg0, series_nseg, series_wv0, series_nwv, series_dt_cdf;
   // workspace
-  DBuf tc, coef, jit, summ, bstate, badj, bsmooth, gpart, rec, status;
+  DBuf tc, coef, jit, pbad, summ, bstate, badj, bsmooth, gpart, rec, status, llbuf, stage;
   DBuf pre, suf, segtot, segstate, segfut, segll, segok;
   DBuf pre2, suf2, grptot, grpstate, grpfut;
-  DBuf tests_t, tests_idx, tests_c0, tests_before;
-  // launch order of the work waves (most expensive first): written on the
-  // host into pinned memory, copied on the call's stream; order_ev marks the
-  // copy so the buffer is not rewritten before it is done
-  DBuf wv_order;
-  int32_t* order_host = nullptr;
-  hipEvent_t order_ev = nullptr;
+  DBuf tests_t, tests_idx, tests_c0, tests_before, prior_idx, prior_series;
+  DBuf wv_order, args;
+  // the call's pointers go to `args` on the call's stream from a ring of
+  // pinned host slots; an event per slot marks when its copy has been done
+  CallArgs* args_host = nullptr;
+  hipEvent_t args_ev[ARG_RING] = {};
+  int args_next = 0;
+  // one captured step per (kind, number of terms)
+  struct Graph {
+    hipGraphExec_t exec = nullptr;
+    uint64_t gen = 0;
+  };
+  std::map<int, Graph> graphs;
+  hipStream_t cap = nullptr;
 
+  std::vector<DBuf*> workspace() {
+    return {&tc,       &coef,   &jit,     &pbad,      &summ,      &bstate,    &badj,         &bsmooth,
+            &gpart,    &rec,    &status,  &llbuf,     &stage,     &pre,       &suf,          &segtot,
+            &segstate, &segfut, &segll,   &segok,     &pre2,      &suf2,      &grptot,       &grpstate,
+            &grpfut,   &wv_order, &args,  &tests_t,   &tests_idx, &tests_c0,  &tests_before,
+            &prior_idx, &prior_series};
+  }
+  std::vector<const DBuf*> all_buffers() const {
+    auto* self = const_cast<gp_ssm_plan*>(this);
+    std::vector<const DBuf*> v = {&dt, &t, &y, &r, &invd, &info, &meas, &seg_chunk0, &seg_nch, &grp_seg0, &grp_nseg,
+                                  &series_grp0, &series_ngrp, &wv_series, &wv_nch, &wv_len, &wv_chunk, &wv_ev0,
+                                  &chunk_len, &chunk_series, &chunk_wv, &chunk_lane, &chunk_first, &series_chunk0,
+                                  &series_nch, &series_seg0, &series_nseg, &series_wv0, &series_nwv, &series_dt_cdf};
+    for (DBuf* d : self->workspace()) v.push_back(d);
+    return v;
+  }
+
+  gp_ssm_plan() {
+    for (DBuf* d : workspace()) d->gen = &gen;
+  }
   ~gp_ssm_plan() {
-    if (order_ev) {
-      (void)hipEventSynchronize(order_ev);
-      (void)hipEventDestroy(order_ev);
-    }
-    if (order_host) (void)hipHostFree(order_host);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : graphs)
+      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (cap) (void)hipStreamDestroy(cap);
+    for (hipEvent_t& e : args_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (args_host) (void)hipHostFree(args_host);
   }
 
   DevPlan dev() const {
@@ -269,6 +453,17 @@ struct gp_ssm_plan {
     p.n_seg = host.n_grp;
     return p;
   }
+
+  DevParams params() const {
+    DevParams pr;
+    pr.tc = tc.as<TermConst>();
+    pr.coef = coef.as<double>();
+    pr.jit = jit.as<double>();
+    pr.bad = pbad.as<int32_t>();
+    return pr;
+  }
+
+  const CallArgs* dargs() const { return args.as<CallArgs>(); }
 };
 
 namespace {
@@ -282,121 +477,146 @@ int check_device() {
   return 0;
 }
 
-// validates hyperparameters (host copies) and prepares them on the device
-// Launch order of the work waves.  Two or so wavefronts share each SIMD over a
-// launch, and a wave's cost varies with its series' terms: a
-// wavefront pays for the Taylor branch of a term at a step when any of its
-// lanes needs it, and for the closed-form branch when any lane needs that.
-// With p the fraction of the series' steps below the switch point, the
-// expected cost per step and term is C_SER (1 - (1-p)^64) + C_CLO (1 - p^64)
-// on top of W0 for the filter step; p comes from the series' step-length
-// distribution.  Dispatching the costliest waves first (longest processing
-// time first) evens out the SIMDs' loads.
-int set_launch_order(gp_ssm_plan* pl, int32_t M, const double* omega0, const double* quality, hipStream_t s) {
-  constexpr double W0 = 4.0, C_SER = 1.0, C_CLO = 1.5;
-  const HostPlan& h = pl->host;
-  const int64_t S = h.n_wv;
-  if (S == 0) return 0;
-  if (!pl->order_host) {
-    HIP_TRY(hipHostMalloc((void**)&pl->order_host, sizeof(int32_t) * S, hipHostMallocDefault));
-    HIP_TRY(hipEventCreateWithFlags(&pl->order_ev, hipEventDisableTiming));
-    if (int rc = pl->wv_order.ensure(sizeof(int32_t) * S)) return rc;
-  } else {
-    HIP_TRY(hipEventSynchronize(pl->order_ev));
-  }
-  std::vector<double> term_cost(h.n_series);
-  for (int64_t b = 0; b < h.n_series; ++b) {
-    const float* cdf = h.series_dt_cdf.data() + b * DT_NE;
-    double c = W0;
-    for (int t = 0; t < M; ++t) {
-      const double w0 = omega0[b * M + t], beta = 0.5 / quality[b * M + t];
-      const double thr = XSER / std::max(1.0, beta) / w0;  // steps with dt <= thr take the series
-      int ex;
-      const double fr = std::frexp(thr, &ex);  // thr = fr 2^ex, fr in [0.5, 1)
-      const int k = ex - DT_KMIN;
-      double p;
-      if (k <= 0)
-        p = cdf[0];
-      else if (k >= DT_NE)
-        p = 1.0;
-      else  // linear in log2(dt) between the edges 2^(ex-1) and 2^ex
-        p = cdf[k - 1] + (cdf[k] - cdf[k - 1]) * (std::log2(fr) + 1.0);
-      c += C_SER * (1.0 - std::pow(1.0 - p, WAVE)) + C_CLO * (1.0 - std::pow(p, WAVE));
-    }
-    term_cost[b] = c;
-  }
-  std::vector<std::pair<double, int32_t>> key(S);
-  for (int64_t q = 0; q < S; ++q) key[q] = {-(double)h.wv_len[q] * term_cost[h.wv_series[q]], (int32_t)q};
-  std::sort(key.begin(), key.end());
-  for (int64_t q = 0; q < S; ++q) pl->order_host[q] = key[q].second;
-  HIP_TRY(hipMemcpyAsync(pl->wv_order.p, pl->order_host, sizeof(int32_t) * S, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipEventRecord(pl->order_ev, s));
-  return 0;
-}
-
-int prepare_params(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0, const double* quality,
-                   const double* jitter, hipStream_t s, DevParams& pr) {
+// ---------------------------------------------------------------------------
+// per-call arguments
+// ---------------------------------------------------------------------------
+// Checks the call's pointers and sends them to the plan's argument block on
+// the call's stream.  Hyperparameters in host memory are first copied into
+// the plan's staging buffer; outputs must be device memory.
+int put_args(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0, const double* quality,
+             const double* jitter, double* loglik, double* grad, int32_t* status, hipStream_t s) {
   if (!pl) return fail(GP_SSM_EINVAL, "null plan");
   if (M < 1 || M > GP_SSM_MAX_TERMS) return fail(GP_SSM_EINVAL, "n_terms out of range");
   if (!sigma || !omega0 || !quality) return fail(GP_SSM_EINVAL, "null hyperparameter pointer");
   const int64_t B = pl->host.n_series;
-  std::vector<double> h(3 * B * M + B);
-  if (int rc = host_copy(sigma, sizeof(double) * B * M, h.data(), s)) return rc;
-  if (int rc = host_copy(omega0, sizeof(double) * B * M, h.data() + B * M, s)) return rc;
-  if (int rc = host_copy(quality, sizeof(double) * B * M, h.data() + 2 * B * M, s)) return rc;
-  if (jitter) {
-    if (int rc = host_copy(jitter, sizeof(double) * B, h.data() + 3 * B * M, s)) return rc;
+  if ((loglik && !device_memory(loglik)) || (grad && !device_memory(grad)) || (status && !device_memory(status)))
+    return fail(GP_SSM_EINVAL, "output arrays must be device memory");
+  CallArgs a{sigma, omega0, quality, jitter, loglik, grad, status};
+  const bool host_in = !device_memory(sigma) || !device_memory(omega0) || !device_memory(quality) ||
+                       (jitter && !device_memory(jitter));
+  if (host_in) {
+    // host hyperparameters: staged through device memory (the copies are
+    // ordered on the stream before the kernels that read them)
+    if (int rc = pl->stage.ensure(sizeof(double) * (3 * B * M + B))) return rc;
+    double* d = pl->stage.as<double>();
+    const double* src[4] = {sigma, omega0, quality, jitter};
+    const int64_t cnt[4] = {B * M, B * M, B * M, B};
+    double* dst[4] = {d, d + B * M, d + 2 * B * M, d + 3 * B * M};
+    for (int k = 0; k < 4; ++k) {
+      if (!src[k]) continue;
+      HIP_TRY(hipMemcpyAsync(dst[k], src[k], sizeof(double) * cnt[k],
+                             device_memory(src[k]) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    }
+    a.sigma = dst[0];
+    a.omega0 = dst[1];
+    a.quality = dst[2];
+    a.jitter = jitter ? dst[3] : nullptr;
   }
-  for (int64_t i = 0; i < 3 * B * M; ++i)
-    if (!(h[i] > 0) || !std::isfinite(h[i]))
-      return fail(GP_SSM_EPARAM, "sigma, omega0 and Q must be positive and finite (entry " + std::to_string(i % (B * M)) + ")");
-  if (jitter)
-    for (int64_t b = 0; b < B; ++b)
-      if (!(h[3 * B * M + b] >= 0) || !std::isfinite(h[3 * B * M + b]))
-        return fail(GP_SSM_EPARAM, "jitter must be >= 0 and finite (series " + std::to_string(b) + ")");
-  if (int rc = set_launch_order(pl, M, h.data() + B * M, h.data() + 2 * B * M, s)) return rc;
-  if (int rc = pl->tc.ensure(sizeof(TermConst) * B * M)) return rc;
-  if (int rc = pl->coef.ensure(sizeof(double) * B * M * 2 * NCOEF)) return rc;
-  if (int rc = pl->jit.ensure(sizeof(double) * B)) return rc;
-  const int threads = 256;
-  const int64_t n = std::max<int64_t>(B * M * NI, B);
-  prof_begin("k_prep", s);
-  hipLaunchKernelGGL(k_prep, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0, s, B, M, sigma, omega0,
-                     quality, jitter, pl->tc.as<TermConst>(), pl->coef.as<double>(), pl->jit.as<double>());
-  prof_end("k_prep", s);
-  HIP_TRY(hipGetLastError());
-  pr.tc = pl->tc.as<TermConst>();
-  pr.coef = pl->coef.as<double>();
-  pr.jit = pl->jit.as<double>();
+  if (!pl->args_host) {
+    HIP_TRY(hipHostMalloc((void**)&pl->args_host, sizeof(CallArgs) * ARG_RING, hipHostMallocDefault));
+    for (hipEvent_t& e : pl->args_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  if (int rc = pl->args.ensure(sizeof(CallArgs))) return rc;
+  const int k = pl->args_next;
+  pl->args_next = (k + 1) % ARG_RING;
+  HIP_TRY(hipEventSynchronize(pl->args_ev[k]));  // the slot's previous copy is done
+  pl->args_host[k] = a;
+  HIP_TRY(hipMemcpyAsync(pl->args.p, &pl->args_host[k], sizeof(CallArgs), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(pl->args_ev[k], s));
   return 0;
 }
 
-int run_forward(gp_ssm_plan* pl, int32_t M, const DevParams& pr, hipStream_t s, double* loglik, int32_t* status,
-                int back, bool need_smooth) {
+// ---------------------------------------------------------------------------
+// workspace (allocated before any launch, so that a captured step never
+// allocates) and the launches of one step
+// ---------------------------------------------------------------------------
+int record_slots(gp_ssm_plan* pl, int32_t M, bool smooth, RecSlots& rs) {
+  const KernelSet ks = kernel_set(M, pl->host.max_slots);
+  const int NX = 2 * M;
+  const int J = std::max(1, pl->host.max_slots);
+  const int D = NX + J;
+  const int F = D + D * (D + 1) / 2;
+  const int64_t n_wv = std::max<int64_t>(1, pl->host.n_wv);
+  const int64_t whole = sizeof(double) * F * std::max<int64_t>(1, pl->host.n_ev_pad);
+  if (whole <= pl->record_budget) {
+    // every work wave at its own place in the event layout, one launch
+    rs.grid = (int32_t)n_wv;
+    rs.slot = 0;
+    if (int rc = pl->rec.ensure(whole)) return rc;
+  } else {
+    // rounds of work waves, one slot per workgroup of a round: at least the
+    // workgroups the GPU holds at once, more if the budget allows
+    const int occ = smooth ? ks.smooth_occupancy() : ks.adjoint_occupancy();
+    rs.slot = (int64_t)std::max(1, pl->host.max_chunk_len) * WAVE * F;
+    const int64_t fit = pl->record_budget / (int64_t)(sizeof(double) * rs.slot);
+    rs.grid = (int32_t)std::min<int64_t>(n_wv, std::max<int64_t>((int64_t)occ * pl->n_cu, fit));
+    if (int rc = pl->rec.ensure(sizeof(double) * rs.slot * rs.grid)) return rc;
+  }
+  rs.base = pl->rec.as<double>();
+  rs.first = 0;
+  return 0;
+}
+
+int reserve(gp_ssm_plan* pl, int32_t M, int back, bool smooth) {
+  const HostPlan& h = pl->host;
+  const int64_t B = h.n_series;
   const int NX = 2 * M;
   const int NXP = NX * (NX + 1) / 2;
-  const int64_t C = std::max<int64_t>(1, pl->host.n_chunks);
-  const int64_t S = std::max<int64_t>(1, pl->host.n_seg);
+  const int64_t C = std::max<int64_t>(1, h.n_chunks);
+  const int64_t S = std::max<int64_t>(1, h.n_seg);
   const int EF = elem_fields(NX);
-  if (int rc = pl->summ.ensure(sizeof(double) * summary_size(NX) * C)) return rc;
-  if (int rc = pl->bstate.ensure(sizeof(double) * (NX + NXP) * C)) return rc;
-  if (int rc = pl->pre.ensure(sizeof(double) * EF * C)) return rc;
-  if (int rc = pl->suf.ensure(sizeof(double) * EF * C)) return rc;
-  if (int rc = pl->segtot.ensure(sizeof(double) * EF * S)) return rc;
-  if (int rc = pl->segstate.ensure(sizeof(double) * (NX + NXP) * S)) return rc;
-  if (int rc = pl->segfut.ensure(sizeof(double) * (NX + NXP) * S)) return rc;
-  if (int rc = pl->segll.ensure(sizeof(double) * S)) return rc;
-  if (int rc = pl->segok.ensure(sizeof(int32_t) * S)) return rc;
-  if (back) {
-    if (int rc = pl->badj.ensure(sizeof(double) * (NX + NXP) * C)) return rc;
-    if (need_smooth)
-      if (int rc = pl->bsmooth.ensure(sizeof(double) * (NX + NXP) * C)) return rc;
+  int rc = 0;
+  if ((rc = pl->tc.ensure(sizeof(TermConst) * B * M)) || (rc = pl->coef.ensure(sizeof(double) * B * M * 2 * NCOEF)) ||
+      (rc = pl->jit.ensure(sizeof(double) * B)) || (rc = pl->pbad.ensure(sizeof(int32_t) * B)) ||
+      (rc = pl->wv_order.ensure(sizeof(int32_t) * std::max<int64_t>(1, h.n_wv))) ||
+      (rc = pl->args.ensure(sizeof(CallArgs))) ||
+      (rc = pl->summ.ensure(sizeof(double) * summary_size(NX) * C)) ||
+      (rc = pl->bstate.ensure(sizeof(double) * (NX + NXP) * C)) || (rc = pl->pre.ensure(sizeof(double) * EF * C)) ||
+      (rc = pl->suf.ensure(sizeof(double) * EF * C)) || (rc = pl->segtot.ensure(sizeof(double) * EF * S)) ||
+      (rc = pl->segstate.ensure(sizeof(double) * (NX + NXP) * S)) ||
+      (rc = pl->segfut.ensure(sizeof(double) * (NX + NXP) * S)) || (rc = pl->segll.ensure(sizeof(double) * S)) ||
+      (rc = pl->segok.ensure(sizeof(int32_t) * S)) || (rc = pl->status.ensure(sizeof(int32_t) * B)) ||
+      (rc = pl->llbuf.ensure(sizeof(double) * B)))
+    return rc;
+  if (h.max_series_nseg > WAVE) {
+    const int64_t G = std::max<int64_t>(1, h.n_grp);
+    if ((rc = pl->pre2.ensure(sizeof(double) * EF * S)) || (rc = pl->suf2.ensure(sizeof(double) * EF * S)) ||
+        (rc = pl->grptot.ensure(sizeof(double) * EF * G)) ||
+        (rc = pl->grpstate.ensure(sizeof(double) * (NX + NXP) * G)) ||
+        (rc = pl->grpfut.ensure(sizeof(double) * (NX + NXP) * G)))
+      return rc;
   }
+  if (back) {
+    if ((rc = pl->badj.ensure(sizeof(double) * (NX + NXP) * C))) return rc;
+    if (smooth && (rc = pl->bsmooth.ensure(sizeof(double) * (NX + NXP) * C))) return rc;
+    if (!smooth && (rc = pl->gpart.ensure(sizeof(double) * (3 * M + 1) * std::max<int64_t>(1, h.n_wv)))) return rc;
+    RecSlots rs;
+    if ((rc = record_slots(pl, M, smooth, rs))) return rc;
+  }
+  return 0;
+}
+
+// validation, preparation and launch order of the hyperparameters
+void enqueue_prep(gp_ssm_plan* pl, int32_t M, hipStream_t s) {
+  const int64_t B = pl->host.n_series;
+  const int threads = 256;
+  const int64_t n = std::max<int64_t>(B * M * NI, B);
+  prof_begin("k_prep", s);
+  hipLaunchKernelGGL(k_prep, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0, s, B, M, pl->dargs(),
+                     pl->tc.as<TermConst>(), pl->coef.as<double>(), pl->jit.as<double>(), pl->pbad.as<int32_t>());
+  prof_end("k_prep", s);
+  prof_begin("k_order", s);
+  hipLaunchKernelGGL(k_order, dim3(1), dim3(ORDER_THREADS), 0, s, pl->dev(), M, pl->tc.as<TermConst>(),
+                     pl->series_dt_cdf.as<float>(), pl->wv_order.as<int32_t>());
+  prof_end("k_order", s);
+}
+
+void enqueue_forward(gp_ssm_plan* pl, int32_t M, hipStream_t s, int back, bool need_smooth) {
   const DevPlan p = pl->dev();
+  const DevParams pr = pl->params();
   const KernelSet ks = kernel_set(M, pl->host.max_slots);
   Launch L{s};
   ks.summaries(L, p, pr, pl->summ.as<double>());
-  HIP_TRY(hipGetLastError());
   ScanWork w;
   w.summ = pl->summ.as<double>();
   w.pre = pl->pre.as<double>();
@@ -412,12 +632,6 @@ int run_forward(gp_ssm_plan* pl, int32_t M, const DevParams& pr, hipStream_t s, 
   w.p2 = nullptr;
   DevPlan p2;
   if (pl->host.max_series_nseg > WAVE) {
-    const int64_t G = std::max<int64_t>(1, pl->host.n_grp);
-    if (int rc = pl->pre2.ensure(sizeof(double) * EF * S)) return rc;
-    if (int rc = pl->suf2.ensure(sizeof(double) * EF * S)) return rc;
-    if (int rc = pl->grptot.ensure(sizeof(double) * EF * G)) return rc;
-    if (int rc = pl->grpstate.ensure(sizeof(double) * (NX + NXP) * G)) return rc;
-    if (int rc = pl->grpfut.ensure(sizeof(double) * (NX + NXP) * G)) return rc;
     p2 = pl->dev_groups();
     w.p2 = &p2;
     w.pre2 = pl->pre2.as<double>();
@@ -426,8 +640,81 @@ int run_forward(gp_ssm_plan* pl, int32_t M, const DevParams& pr, hipStream_t s, 
     w.grpstate = pl->grpstate.as<double>();
     w.grpfut = pl->grpfut.as<double>();
   }
-  run_scan(M, s, p, pr, w, loglik, status, back);
-  HIP_TRY(hipGetLastError());
+  run_scan(M, s, p, pr, w, pl->dargs(), back);
+}
+
+void enqueue_grad_tail(gp_ssm_plan* pl, int32_t M, hipStream_t s) {
+  const DevPlan p = pl->dev();
+  const KernelSet ks = kernel_set(M, pl->host.max_slots);
+  RecSlots rs;
+  (void)record_slots(pl, M, false, rs);  // reserved: no allocation here
+  Launch L{s};
+  ks.adjoint(L, p, pl->params(), pl->bstate.as<double>(), pl->badj.as<double>(), rs, pl->gpart.as<double>());
+  prof_begin("k_reduce_grad", s);
+  hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)pl->host.n_series), dim3(WAVE), 0, s, p, M,
+                     pl->gpart.as<double>(), pl->dargs());
+  prof_end("k_reduce_grad", s);
+}
+
+void enqueue_step(gp_ssm_plan* pl, int32_t M, int kind, hipStream_t s) {
+  enqueue_prep(pl, M, s);
+  enqueue_forward(pl, M, s, kind == STEP_GRAD, false);
+  if (kind == STEP_GRAD) enqueue_grad_tail(pl, M, s);
+}
+
+// One step (log-likelihood, or with its gradient) after put_args: replayed
+// from a graph captured once per (plan, kind, number of terms) and workspace
+// generation, or launched kernel by kernel while kernel timing is on (its
+// events are per launch) or graphs are switched off (GP_SSM_GRAPH=0).
+int run_step(gp_ssm_plan* pl, int32_t M, int kind, hipStream_t s) {
+  if (int rc = reserve(pl, M, kind == STEP_GRAD, false)) return rc;
+  if (g_prof.on || !graphs_enabled()) {
+    enqueue_step(pl, M, kind, s);
+    HIP_TRY(hipGetLastError());
+    return 0;
+  }
+  auto& g = pl->graphs[kind * 16 + M];
+  if (!g.exec || g.gen != pl->gen) {
+    if (g.exec) {
+      HIP_TRY(hipGraphExecDestroy(g.exec));
+      g.exec = nullptr;
+    }
+    if (!pl->cap) HIP_TRY(hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
+    enqueue_step(pl, M, kind, pl->cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t e1 = hipStreamEndCapture(pl->cap, &graph);
+    if (e1 != hipSuccess || !graph) return fail(GP_SSM_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(e1));
+    const hipError_t e2 = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) {
+      g.exec = nullptr;
+      return fail(GP_SSM_EDEVICE, std::string("graph instantiation failed: ") + hipGetErrorString(e2));
+    }
+    g.gen = pl->gen;
+  }
+  HIP_TRY(hipGraphLaunch(g.exec, s));
+  return 0;
+}
+
+// waits for the stream and turns the per-series status into a return code
+int sync_status(gp_ssm_plan* pl, const int32_t* status, hipStream_t s) {
+  HIP_TRY(hipStreamSynchronize(s));
+  const int64_t B = pl->host.n_series;
+  std::vector<int32_t> st(B);
+  HIP_TRY(hipMemcpy(st.data(), status, sizeof(int32_t) * B, hipMemcpyDeviceToHost));
+  int64_t nbad = 0, nparam = 0, first = -1;
+  for (int64_t b = 0; b < B; ++b)
+    if (st[b] != 0) {
+      ++nbad;
+      if (st[b] == GP_SSM_EPARAM) ++nparam;
+      if (first < 0) first = b;
+    }
+  if (nparam) return fail(GP_SSM_EPARAM, "sigma, omega0 and Q must be positive and finite, jitter >= 0 and finite (" +
+                                             std::to_string(nparam) + " series, first " + std::to_string(first) + ")");
+  if (nbad)
+    return fail(GP_SSM_ENUMERIC, "non-finite result in " + std::to_string(nbad) + " series (first " +
+                                     std::to_string(first) + ")");
   return 0;
 }
 
@@ -443,6 +730,7 @@ void gp_ssm_plan_default_options(gp_ssm_plan_options* opt) {
   opt->target_chunks = d.target_chunks;
   opt->single_chunk = d.single_chunk;
   opt->threads = d.threads;
+  opt->record_budget = DEFAULT_RECORD_BUDGET;
 }
 
 int gp_ssm_plan_create(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end,
@@ -452,7 +740,7 @@ int gp_ssm_plan_create(int64_t n_series, const int64_t* offsets, const double* t
   if (!out) return fail(GP_SSM_EINVAL, "null output pointer");
   *out = nullptr;
   if (n_series < 1) return fail(GP_SSM_EINVAL, "n_series < 1");
-  if (!offsets || !t_start || !t_end || !y || !yerr) return fail(GP_SSM_EINVAL, "null input pointer");
+  if (!offsets) return fail(GP_SSM_EINVAL, "null offsets");
   if (int rc = check_device()) return rc;
   hipStream_t s = (hipStream_t)stream;
   std::vector<int64_t> off(n_series + 1);
@@ -461,6 +749,7 @@ int gp_ssm_plan_create(int64_t n_series, const int64_t* offsets, const double* t
   for (int64_t b = 0; b < n_series; ++b)
     if (off[b + 1] < off[b]) return fail(GP_SSM_EINVAL, "offsets not ascending");
   const int64_t N = off[n_series];
+  if (N > 0 && (!t_start || !t_end || !y || !yerr)) return fail(GP_SSM_EINVAL, "null input pointer");
   std::vector<double> ts(N), te(N), yy(N), ye(N);
   if (int rc = host_copy(t_start, sizeof(double) * N, ts.data(), s)) return rc;
   if (int rc = host_copy(t_end, sizeof(double) * N, te.data(), s)) return rc;
@@ -482,7 +771,13 @@ int gp_ssm_plan_create(int64_t n_series, const int64_t* offsets, const double* t
     delete pl;
     return fail(rc, err);
   }
+  pl->record_budget = (opt && opt->record_budget > 0) ? opt->record_budget : DEFAULT_RECORD_BUDGET;
   (void)hipGetDevice(&pl->device);
+  if (hipDeviceGetAttribute(&pl->n_cu, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess ||
+      pl->n_cu < 1) {
+    (void)hipGetLastError();
+    pl->n_cu = 1;
+  }
   HostPlan& h = pl->host;
   if ((rc = upload(pl->dt, h.dt)) || (rc = upload(pl->t, h.t)) || (rc = upload(pl->y, h.y)) || (rc = upload(pl->r, h.r)) ||
       (rc = upload(pl->invd, h.invd)) || (rc = upload(pl->info, h.info)) || (rc = upload(pl->meas, h.meas)) ||
@@ -496,7 +791,8 @@ int gp_ssm_plan_create(int64_t n_series, const int64_t* offsets, const double* t
       (rc = upload(pl->chunk_lane, h.chunk_lane)) || (rc = upload(pl->chunk_first, h.chunk_first)) ||
       (rc = upload(pl->series_chunk0, h.series_chunk0)) || (rc = upload(pl->series_nch, h.series_nch)) ||
       (rc = upload(pl->series_seg0, h.series_seg0)) || (rc = upload(pl->series_nseg, h.series_nseg)) ||
-      (rc = upload(pl->series_wv0, h.series_wv0)) || (rc = upload(pl->series_nwv, h.series_nwv))) {
+      (rc = upload(pl->series_wv0, h.series_wv0)) || (rc = upload(pl->series_nwv, h.series_nwv)) ||
+      (rc = upload(pl->series_dt_cdf, h.series_dt_cdf))) {
     delete pl;
     return rc;
   }
@@ -523,6 +819,9 @@ int gp_ssm_plan_get_stats(const gp_ssm_plan* pl, gp_ssm_plan_stats* out) {
   out->n_segments = pl->host.n_seg;
   out->max_slots = pl->host.max_slots;
   out->max_chunk_len = pl->host.max_chunk_len;
+  out->device_bytes = 0;
+  for (const DBuf* d : pl->all_buffers()) out->device_bytes += (int64_t)d->bytes;
+  out->record_bytes = (int64_t)pl->rec.bytes;
   return 0;
 }
 
@@ -531,9 +830,8 @@ int gp_ssm_plan_loglik(gp_ssm_plan* pl, int32_t M, const double* sigma, const do
   g_err.clear();
   if (!loglik) return fail(GP_SSM_EINVAL, "null loglik");
   hipStream_t s = (hipStream_t)stream;
-  DevParams pr;
-  if (int rc = prepare_params(pl, M, sigma, omega0, quality, jitter, s, pr)) return rc;
-  return run_forward(pl, M, pr, s, loglik, status, 0, false);
+  if (int rc = put_args(pl, M, sigma, omega0, quality, jitter, loglik, nullptr, status, s)) return rc;
+  return run_step(pl, M, STEP_LOGLIK, s);
 }
 
 int gp_ssm_plan_loglik_grad(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0,
@@ -541,41 +839,21 @@ int gp_ssm_plan_loglik_grad(gp_ssm_plan* pl, int32_t M, const double* sigma, con
                             int32_t* status, void* stream) {
   g_err.clear();
   if (!loglik || !grad) return fail(GP_SSM_EINVAL, "null output");
+  if (!pl) return fail(GP_SSM_EINVAL, "null plan");
   hipStream_t s = (hipStream_t)stream;
-  DevParams pr;
-  if (int rc = prepare_params(pl, M, sigma, omega0, quality, jitter, s, pr)) return rc;
-  const int64_t B = pl->host.n_series;
-  int32_t* st = status;
-  if (!st) {
-    if (int rc = pl->status.ensure(sizeof(int32_t) * B)) return rc;
-    st = pl->status.as<int32_t>();
-  }
-  if (int rc = run_forward(pl, M, pr, s, loglik, st, 1, false)) return rc;
-  const int NX = 2 * M;
-  const int J = std::max(1, pl->host.max_slots);
-  const int D = NX + J;
-  const int F = D + D * (D + 1) / 2;
-  const int64_t C = pl->host.n_chunks;
-  if (int rc = pl->rec.ensure(sizeof(double) * F * std::max<int64_t>(1, pl->host.n_ev_pad))) return rc;
-  if (int rc = pl->gpart.ensure(sizeof(double) * (3 * M + 1) * std::max<int64_t>(1, pl->host.n_wv))) return rc;
-  const DevPlan p = pl->dev();
-  const KernelSet ks = kernel_set(M, pl->host.max_slots);
-  Launch L{s};
-  ks.adjoint(L, p, pr, pl->bstate.as<double>(), pl->badj.as<double>(), pl->rec.as<double>(), pl->gpart.as<double>());
-  HIP_TRY(hipGetLastError());
-  prof_begin("k_reduce_grad", s);
-  hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)B), dim3(WAVE), 0, s, p, M, pl->gpart.as<double>(), st,
-                     grad);
-  prof_end("k_reduce_grad", s);
-  HIP_TRY(hipGetLastError());
-  return 0;
+  // the gradient reduction reads every series' status: the plan's own array
+  // when the caller passes none
+  if (int rc = pl->status.ensure(sizeof(int32_t) * pl->host.n_series)) return rc;
+  int32_t* st = status ? status : pl->status.as<int32_t>();
+  if (int rc = put_args(pl, M, sigma, omega0, quality, jitter, loglik, grad, st, s)) return rc;
+  return run_step(pl, M, STEP_GRAD, s);
 }
 
 // the smoother with optional per-term outputs at the test times
 static int plan_smooth(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0, const double* quality,
-                const double* jitter, const int64_t* test_offsets, const double* t_test, double* mean_test,
-                double* var_test, double* term_mean, double* term_var, bool want_terms, double* mean_data,
-                double* var_data, double* loglik, int32_t* status, void* stream) {
+                       const double* jitter, const int64_t* test_offsets, const double* t_test, double* mean_test,
+                       double* var_test, double* term_mean, double* term_var, bool want_terms, double* mean_data,
+                       double* var_data, double* loglik, int32_t* status, void* stream) {
   g_err.clear();
   if (!pl) return fail(GP_SSM_EINVAL, "null plan");
   if (!test_offsets) return fail(GP_SSM_EINVAL, "null test_offsets");
@@ -590,18 +868,28 @@ static int plan_smooth(gp_ssm_plan* pl, int32_t M, const double* sigma, const do
   const int64_t T = to[B];
   if (T > 0 && (!t_test || !mean_test || !var_test)) return fail(GP_SSM_EINVAL, "null test arrays");
   if (want_terms && T > 0 && (!term_mean || !term_var)) return fail(GP_SSM_EINVAL, "null term arrays");
+  for (const void* o : {(const void*)mean_test, (const void*)var_test, (const void*)term_mean, (const void*)term_var,
+                        (const void*)mean_data, (const void*)var_data})
+    if (o && !device_memory(o)) return fail(GP_SSM_EINVAL, "output arrays must be device memory");
   std::vector<double> tt(T);
   if (int rc = host_copy(t_test, sizeof(double) * T, tt.data(), s)) return rc;
   for (int64_t i = 0; i < T; ++i)
     if (!std::isfinite(tt[i])) return fail(GP_SSM_EDATA, "non-finite test time");
-  // assign each test time to the chunk whose event interval holds it
+  // assign each test time to the chunk whose event interval holds it; test
+  // times of a series without measurements take the prior
   const int64_t C = h.n_chunks;
   std::vector<int32_t> owner(T);
-  std::vector<int64_t> cnt(C + 1, 0);
+  std::vector<int64_t> cnt(C + 1, 0), prior_idx;
+  std::vector<int32_t> prior_series;
   for (int64_t q = 0; q < B; ++q) {
     const int32_t c0 = h.series_chunk0[q], n = h.series_nch[q];
-    if (to[q + 1] > to[q] && n == 0) return fail(GP_SSM_EINVAL, "test times for a series without measurements");
     for (int64_t i = to[q]; i < to[q + 1]; ++i) {
+      if (n == 0) {
+        owner[i] = -1;
+        prior_idx.push_back(i);
+        prior_series.push_back((int32_t)q);
+        continue;
+      }
       int32_t lo = c0, hi = c0 + n - 1;
       while (lo < hi) {
         const int32_t mid = (lo + hi) / 2;
@@ -616,41 +904,36 @@ static int plan_smooth(gp_ssm_plan* pl, int32_t M, const double* sigma, const do
   }
   std::vector<int64_t> c0v(C + 1, 0);
   for (int64_t c = 0; c < C; ++c) c0v[c + 1] = c0v[c] + cnt[c + 1];
-  std::vector<int64_t> fillp(c0v.begin(), c0v.end() - 1), idx(T);
-  for (int64_t i = 0; i < T; ++i) idx[fillp[owner[i]]++] = i;
-  std::vector<double> tsort(T);
+  std::vector<int64_t> fillp(c0v.begin(), c0v.end() - 1), idx(std::max<int64_t>(0, c0v[C]));
+  for (int64_t i = 0; i < T; ++i)
+    if (owner[i] >= 0) idx[fillp[owner[i]]++] = i;
   for (int64_t c = 0; c < C; ++c) {
     std::stable_sort(idx.begin() + c0v[c], idx.begin() + c0v[c + 1], [&](int64_t x, int64_t y) { return tt[x] < tt[y]; });
   }
-  for (int64_t i = 0; i < T; ++i) tsort[i] = tt[idx[i]];
+  std::vector<double> tsort(idx.size());
+  for (size_t i = 0; i < idx.size(); ++i) tsort[i] = tt[idx[i]];
   std::vector<double> tprev(std::max<int64_t>(1, C), 0.0);
   for (int64_t c = 0; c < C; ++c) tprev[c] = h.chunk_first[c] ? 0.0 : h.chunk_t1[c - 1];
+  // the smoother is not captured: make sure no earlier call still reads the
+  // test tables before they are replaced
+  HIP_TRY(hipStreamSynchronize(s));
   if (int rc = upload(pl->tests_t, tsort)) return rc;
   if (int rc = upload(pl->tests_idx, idx)) return rc;
   if (int rc = upload(pl->tests_c0, c0v)) return rc;
   if (int rc = upload(pl->tests_before, tprev)) return rc;
+  if (int rc = upload(pl->prior_idx, prior_idx)) return rc;
+  if (int rc = upload(pl->prior_series, prior_series)) return rc;
 
-  DevParams pr;
-  if (int rc = prepare_params(pl, M, sigma, omega0, quality, jitter, s, pr)) return rc;
-  int32_t* st = status;
-  if (!st) {
-    if (int rc = pl->status.ensure(sizeof(int32_t) * B)) return rc;
-    st = pl->status.as<int32_t>();
-  }
-  double* ll = loglik;
-  DBuf tmpll;
-  if (!ll) {
-    if (int rc = tmpll.ensure(sizeof(double) * B)) return rc;
-    ll = tmpll.as<double>();
-  }
-  if (int rc = run_forward(pl, M, pr, s, ll, st, 1, true)) return rc;
-  const int NX = 2 * M;
-  const int J = std::max(1, h.max_slots);
-  const int D = NX + J;
-  const int F = D + D * (D + 1) / 2;
-  if (int rc = pl->rec.ensure(sizeof(double) * F * std::max<int64_t>(1, h.n_ev_pad))) return rc;
+  if (int rc = reserve(pl, M, 1, true)) return rc;
+  int32_t* st = status ? status : pl->status.as<int32_t>();
+  double* ll = loglik ? loglik : pl->llbuf.as<double>();
+  if (int rc = put_args(pl, M, sigma, omega0, quality, jitter, ll, nullptr, st, s)) return rc;
+  enqueue_prep(pl, M, s);
+  enqueue_forward(pl, M, s, 1, true);
   const DevPlan p = pl->dev();
   const KernelSet ks = kernel_set(M, h.max_slots);
+  RecSlots rs;
+  if (int rc = record_slots(pl, M, true, rs)) return rc;
   DevTests dt;
   dt.t = pl->tests_t.as<double>();
   dt.out_index = pl->tests_idx.as<int64_t>();
@@ -659,10 +942,15 @@ static int plan_smooth(gp_ssm_plan* pl, int32_t M, const double* sigma, const do
   dt.term_mean = want_terms ? term_mean : nullptr;
   dt.term_var = want_terms ? term_var : nullptr;
   Launch L{s};
-  ks.smooth(L, p, pr, pl->bstate.as<double>(), pl->bsmooth.as<double>(), pl->rec.as<double>(), dt, mean_test, var_test,
+  ks.smooth(L, p, pl->params(), pl->bstate.as<double>(), pl->bsmooth.as<double>(), rs, dt, mean_test, var_test,
             mean_data, var_data);
+  if (!prior_idx.empty()) {
+    const int64_t n = (int64_t)prior_idx.size();
+    hipLaunchKernelGGL(k_prior_tests, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                       pl->prior_idx.as<int64_t>(), pl->prior_series.as<int32_t>(), M, pl->tc.as<TermConst>(),
+                       pl->pbad.as<int32_t>(), mean_test, var_test, dt.term_mean, dt.term_var);
+  }
   HIP_TRY(hipGetLastError());
-  if (!loglik) HIP_TRY(hipStreamSynchronize(s));  // the temporary log-likelihood buffer is freed on return
   return 0;
 }
 
@@ -691,18 +979,21 @@ int gp_ssm_plan_plain_loglik(gp_ssm_plan* pl, int64_t first, int64_t count, int3
   if (!pl) return fail(GP_SSM_EINVAL, "null plan");
   if (first < 0 || count < 0 || first + count > pl->host.n_series) return fail(GP_SSM_EINVAL, "series range");
   hipStream_t s = (hipStream_t)stream;
-  DevParams pr;
-  if (int rc = prepare_params(pl, M, sigma, omega0, quality, jitter, s, pr)) return rc;
+  if (int rc = reserve(pl, M, 0, false)) return rc;
+  if (int rc = put_args(pl, M, sigma, omega0, quality, jitter, loglik, nullptr, nullptr, s)) return rc;
+  enqueue_prep(pl, M, s);
   const DevPlan p = pl->dev();
   const KernelSet ks = kernel_set(M, pl->host.max_slots);
   Launch L{s};
   for (int64_t b = first; b < first + count; ++b) {
-    ks.plain(L, p, pr, b, loglik);
+    ks.plain(L, p, pl->params(), b, loglik);
     HIP_TRY(hipGetLastError());
   }
   return 0;
 }
 
+// One-shot forms: plan with default options, run, wait, destroy.  They return
+// GP_SSM_EPARAM or GP_SSM_ENUMERIC when any series failed (its outputs NaN).
 static int one_shot_plan(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end,
                          const double* y, const double* yerr, void* stream, gp_ssm_plan** pl) {
   return gp_ssm_plan_create(n_series, offsets, t_start, t_end, y, yerr, nullptr, stream, pl);
@@ -713,8 +1004,10 @@ int gp_ssm_loglik(int64_t n_series, const int64_t* offsets, const double* t_star
                   const double* jitter, double* loglik, int32_t* status, void* stream) {
   gp_ssm_plan* pl = nullptr;
   if (int rc = one_shot_plan(n_series, offsets, t_start, t_end, y, yerr, stream, &pl)) return rc;
-  int rc = gp_ssm_plan_loglik(pl, n_terms, sigma, omega0, quality, jitter, loglik, status, stream);
-  if (rc == 0 && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = fail(GP_SSM_EDEVICE, "stream sync failed");
+  int rc = pl->status.ensure(sizeof(int32_t) * n_series);
+  int32_t* st = status ? status : pl->status.as<int32_t>();
+  if (rc == 0) rc = gp_ssm_plan_loglik(pl, n_terms, sigma, omega0, quality, jitter, loglik, st, stream);
+  if (rc == 0) rc = sync_status(pl, st, (hipStream_t)stream);
   gp_ssm_plan_destroy(pl);
   return rc;
 }
@@ -725,8 +1018,10 @@ int gp_ssm_loglik_grad(int64_t n_series, const int64_t* offsets, const double* t
                        void* stream) {
   gp_ssm_plan* pl = nullptr;
   if (int rc = one_shot_plan(n_series, offsets, t_start, t_end, y, yerr, stream, &pl)) return rc;
-  int rc = gp_ssm_plan_loglik_grad(pl, n_terms, sigma, omega0, quality, jitter, loglik, grad, status, stream);
-  if (rc == 0 && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = fail(GP_SSM_EDEVICE, "stream sync failed");
+  int rc = pl->status.ensure(sizeof(int32_t) * n_series);
+  int32_t* st = status ? status : pl->status.as<int32_t>();
+  if (rc == 0) rc = gp_ssm_plan_loglik_grad(pl, n_terms, sigma, omega0, quality, jitter, loglik, grad, st, stream);
+  if (rc == 0) rc = sync_status(pl, st, (hipStream_t)stream);
   gp_ssm_plan_destroy(pl);
   return rc;
 }
@@ -738,9 +1033,12 @@ int gp_ssm_smooth(int64_t n_series, const int64_t* offsets, const double* t_star
                   void* stream) {
   gp_ssm_plan* pl = nullptr;
   if (int rc = one_shot_plan(n_series, offsets, t_start, t_end, y, yerr, stream, &pl)) return rc;
-  int rc = gp_ssm_plan_smooth(pl, n_terms, sigma, omega0, quality, jitter, test_offsets, t_test, mean_test, var_test,
-                              mean_data, var_data, nullptr, status, stream);
-  if (rc == 0 && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = fail(GP_SSM_EDEVICE, "stream sync failed");
+  int rc = pl->status.ensure(sizeof(int32_t) * n_series);
+  int32_t* st = status ? status : pl->status.as<int32_t>();
+  if (rc == 0)
+    rc = gp_ssm_plan_smooth(pl, n_terms, sigma, omega0, quality, jitter, test_offsets, t_test, mean_test, var_test,
+                            mean_data, var_data, nullptr, st, stream);
+  if (rc == 0) rc = sync_status(pl, st, (hipStream_t)stream);
   gp_ssm_plan_destroy(pl);
   return rc;
 }

@@ -24,12 +24,26 @@ struct DevPlan {
 };
 
 // hyperparameters prepared on the device: per (series, term) TermConst and the
-// Taylor coefficients followed by their beta-derivatives (2*NCOEF doubles)
+// Taylor coefficients followed by their beta-derivatives (2*NCOEF doubles);
+// bad[b] = 1 when series b's hyperparameters failed validation (its constants
+// are then those of sigma = omega0 = Q = 1, jitter 0, and its outputs NaN)
 struct DevParams {
   const TermConst* tc;
   const double* coef;
   const double* jit;
+  const int32_t* bad;
 };
+
+// the caller's pointers of one call, read by the kernels from device memory
+// (written there on the call's stream before the kernels), so that a captured
+// sequence of launches serves every later call with other buffers
+struct CallArgs {
+  const double *sigma, *omega0, *quality, *jitter;
+  double *loglik, *grad;
+  int32_t* status;
+};
+
+
 
 // test-time work of the smoother, assigned to chunks on the host
 struct DevTests {
@@ -45,15 +59,37 @@ struct Launch {
   hipStream_t stream;
 };
 
+// Per-event record buffer of the backward kernels (k_adjoint, k_smooth).
+// Within the plan's record budget every work wave keeps its records at its
+// own place in the event layout (slot = 0, one launch over all waves).
+// Beyond it the buffer holds `grid` slots of `slot` doubles (the longest work
+// wave's events x 64 lanes x fields), and the kernels run in rounds of at
+// most `grid` work waves taken in launch order, workgroup i of the round
+// starting at entry `first` using slot i; memory is then bounded by the
+// budget (at least the workgroups the GPU holds at once), not by the batch.
+struct RecSlots {
+  double* base;
+  int64_t slot;
+  int32_t grid;
+  int32_t first;
+  // the records of the work wave whose events start at ev0 (F fields each)
+  __device__ __forceinline__ double* records(int64_t ev0, int F) const {
+    return slot ? base + (int64_t)blockIdx.x * slot : base + ev0 * F;
+  }
+};
+
 // per-(M, J) kernel launchers
 struct KernelSet {
   void (*summaries)(const Launch&, const DevPlan&, const DevParams&, double* summ);
   void (*adjoint)(const Launch&, const DevPlan&, const DevParams&, const double* bstate, const double* badj,
-                  double* rec, double* gpart);
+                  const RecSlots& rec, double* gpart);
   void (*plain)(const Launch&, const DevPlan&, const DevParams&, int64_t series, double* loglik);
   void (*smooth)(const Launch&, const DevPlan&, const DevParams&, const double* bstate, const double* bsmooth,
-                 double* rec, const DevTests& tests, double* mean_test, double* var_test, double* mean_data,
+                 const RecSlots& rec, const DevTests& tests, double* mean_test, double* var_test, double* mean_data,
                  double* var_data);
+  // workgroups of k_adjoint / k_smooth resident at once on one compute unit
+  int (*adjoint_occupancy)();
+  int (*smooth_occupancy)();
 };
 
 KernelSet kernels_m1(int J);

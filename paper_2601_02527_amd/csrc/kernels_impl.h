@@ -158,101 +158,105 @@ __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, dou
 // gradient: plain forward from the boundary state (storing the state before
 // every event), then the adjoint backward from the boundary adjoint
 // ---------------------------------------------------------------------------
+// one work wave per workgroup: entry rs.first + blockIdx.x of the launch
+// order; the per-event states of the wave live in the workgroup's record slot
 template <int J>
 __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const double* __restrict__ bstate,
-                                                  const double* __restrict__ badj, double* __restrict__ rec,
+                                                  const double* __restrict__ badj, RecSlots rs,
                                                   double* __restrict__ gpart) {
   using Dm = Dims<M, J>;
-  constexpr int NX = Dm::NX, D = Dm::D, NP = Dm::NP, NXP = Dm::NXP;
+  constexpr int NX = Dm::NX, D = Dm::D, NP = Dm::NP;
   constexpr int F = rec_fields<Dm>();
-  const int w = p.wv_order ? p.wv_order[blockIdx.x] : (int)blockIdx.x;
   const int lane = threadIdx.x;
-  const int64_t b = p.wv_series[w];
-  const int32_t nch = p.wv_nch[w], L = p.wv_len[w];
-  const int64_t ev0 = p.wv_ev0[w];
-  const bool active = lane < nch;
   const int64_t C = p.n_chunks;
-  const int64_t c = p.wv_chunk[(int64_t)w * WAVE + (active ? lane : 0)];
-  TermConst tc[M];
-  load_terms<Dm>(pr, b, tc);
   __shared__ double lcoef[M * 2 * NCOEF];
-  const double* coef = stage_coef<Dm, true>(pr, b, lcoef);
-  const double jit = pr.jit[b];
-  const double jit2 = jit * jit;
-  double* rb = rec + ev0 * F;
-
-  double m[D], P[NP];
-#pragma unroll
-  for (int i = 0; i < D; ++i) m[i] = (i < NX && active) ? bstate[i * C + c] : 0.0;
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int j = i; j < D; ++j) P[sidx(i, j, D)] = (j < NX && active) ? bstate[(NX + sidx(i, j, NX)) * C + c] : 0.0;
-
-  EvRaw nxt = fetch_event(p, ev0 + lane);
-  for (int32_t k = 0; k < L; ++k) {
-    const EvRaw cur = nxt;
-    if (k + 1 < L) nxt = fetch_event(p, ev0 + (int64_t)(k + 1) * WAVE + lane);
-    // the records come back long after they have left the caches: streaming
-    // (non-temporal) stores here and loads in the backward sweep
-#pragma unroll
-    for (int f = 0; f < D; ++f) __builtin_nontemporal_store(m[f], &rb[((int64_t)k * F + f) * WAVE + lane]);
-#pragma unroll
-    for (int f = 0; f < NP; ++f) __builtin_nontemporal_store(P[f], &rb[((int64_t)k * F + D + f) * WAVE + lane]);
-    const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2);
-    TermQ tq[M];
-    discretise<M, DiscGrad, 2 * NCOEF>(tc, coef, cur.dt, tq);
-    plain_step<Dm, false>(m, P, tq, cur.info, o);
-  }
-
-  double mb[D], Pb[NP];
-#pragma unroll
-  for (int i = 0; i < D; ++i) mb[i] = (i < NX && active) ? badj[i * C + c] : 0.0;
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int j = i; j < D; ++j) Pb[sidx(i, j, D)] = (j < NX && active) ? badj[(NX + sidx(i, j, NX)) * C + c] : 0.0;
   __shared__ double lacc[(3 * M + 1) * WAVE];
-  const GradAcc<M> acc{lacc + lane};
-  acc.init();
   // with four open exposures the step's registers spill; the beta-derivatives
   // then wait in LDS (9 KB at M = 3)
   constexpr bool DBL = J >= 4;
   __shared__ double ldb[DBL ? 6 * M * WAVE : 1];
-  nxt = fetch_event(p, ev0 + (int64_t)(L - 1) * WAVE + lane);
-  for (int32_t k = L - 1; k >= 0; --k) {
-    const EvRaw cur = nxt;
-    if (k > 0) nxt = fetch_event(p, ev0 + (int64_t)(k - 1) * WAVE + lane);
+  {
+    const int32_t qi = rs.first + (int32_t)blockIdx.x;
+    const int w = p.wv_order ? p.wv_order[qi] : qi;
+    const int64_t b = p.wv_series[w];
+    const int32_t nch = p.wv_nch[w], L = p.wv_len[w];
+    const int64_t ev0 = p.wv_ev0[w];
+    double* const rb = rs.records(ev0, F);
+    const bool active = lane < nch;
+    const int64_t c = p.wv_chunk[(int64_t)w * WAVE + (active ? lane : 0)];
+    TermConst tc[M];
+    load_terms<Dm>(pr, b, tc);
+    const double* coef = stage_coef<Dm, true>(pr, b, lcoef);
+    const double jit = pr.jit[b];
+    const double jit2 = jit * jit;
+
+    double m[D], P[NP];
 #pragma unroll
-    for (int f = 0; f < D; ++f) m[f] = __builtin_nontemporal_load(&rb[((int64_t)k * F + f) * WAVE + lane]);
+    for (int i = 0; i < D; ++i) m[i] = (i < NX && active) ? bstate[i * C + c] : 0.0;
 #pragma unroll
-    for (int f = 0; f < NP; ++f) P[f] = __builtin_nontemporal_load(&rb[((int64_t)k * F + D + f) * WAVE + lane]);
-    const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2);
-    adjoint_step<Dm, DBL>(m, P, mb, Pb, tc, coef, cur.dt, cur.info, o, jit, acc, LaneLds{ldb + lane});
-  }
-  if (active && p.chunk_first[c]) {
-    // prior of the SHO states: sigma_t^2 I in scaled coordinates
+    for (int i = 0; i < D; ++i)
 #pragma unroll
-    for (int t = 0; t < M; ++t)
-      acc.s(t) += 2.0 * tc[t].sigma * (Pb[sidx(2 * t, 2 * t, D)] + Pb[sidx(2 * t + 1, 2 * t + 1, D)]);
-  }
-  // sum over the wave's lanes (one series), one partial per work wave
-  const int64_t S = p.n_wv;
+      for (int j = i; j < D; ++j) P[sidx(i, j, D)] = (j < NX && active) ? bstate[(NX + sidx(i, j, NX)) * C + c] : 0.0;
+
+    EvRaw nxt = fetch_event(p, ev0 + lane);
+    for (int32_t k = 0; k < L; ++k) {
+      const EvRaw cur = nxt;
+      if (k + 1 < L) nxt = fetch_event(p, ev0 + (int64_t)(k + 1) * WAVE + lane);
+      // the records come back after the rest of the wave's forward sweep has
+      // gone through the caches: streaming (non-temporal) stores here and
+      // loads in the backward sweep
 #pragma unroll
-  for (int t = 0; t < M; ++t) {
-    const double a0 = wave_sum(active ? acc.s(t) : 0.0);
-    const double a1 = wave_sum(active ? acc.w(t) : 0.0);
-    const double a2 = wave_sum(active ? acc.q(t) : 0.0);
-    if (lane == 0) {
-      gpart[(0 * M + t) * S + w] = a0;
-      gpart[(1 * M + t) * S + w] = a1;
-      gpart[(2 * M + t) * S + w] = a2;
+      for (int f = 0; f < D; ++f) __builtin_nontemporal_store(m[f], &rb[((int64_t)k * F + f) * WAVE + lane]);
+#pragma unroll
+      for (int f = 0; f < NP; ++f) __builtin_nontemporal_store(P[f], &rb[((int64_t)k * F + D + f) * WAVE + lane]);
+      const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2);
+      TermQ tq[M];
+      discretise<M, DiscGrad, 2 * NCOEF>(tc, coef, cur.dt, tq);
+      plain_step<Dm, false>(m, P, tq, cur.info, o);
     }
+
+    double mb[D], Pb[NP];
+#pragma unroll
+    for (int i = 0; i < D; ++i) mb[i] = (i < NX && active) ? badj[i * C + c] : 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = i; j < D; ++j) Pb[sidx(i, j, D)] = (j < NX && active) ? badj[(NX + sidx(i, j, NX)) * C + c] : 0.0;
+    const GradAcc<M> acc{lacc + lane};
+    acc.init();
+    nxt = fetch_event(p, ev0 + (int64_t)(L - 1) * WAVE + lane);
+    for (int32_t k = L - 1; k >= 0; --k) {
+      const EvRaw cur = nxt;
+      if (k > 0) nxt = fetch_event(p, ev0 + (int64_t)(k - 1) * WAVE + lane);
+#pragma unroll
+      for (int f = 0; f < D; ++f) m[f] = __builtin_nontemporal_load(&rb[((int64_t)k * F + f) * WAVE + lane]);
+#pragma unroll
+      for (int f = 0; f < NP; ++f) P[f] = __builtin_nontemporal_load(&rb[((int64_t)k * F + D + f) * WAVE + lane]);
+      const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2);
+      adjoint_step<Dm, DBL>(m, P, mb, Pb, tc, coef, cur.dt, cur.info, o, jit, acc, LaneLds{ldb + lane});
+    }
+    if (active && p.chunk_first[c]) {
+      // prior of the SHO states: sigma_t^2 I in scaled coordinates
+#pragma unroll
+      for (int t = 0; t < M; ++t)
+        acc.s(t) += 2.0 * tc[t].sigma * (Pb[sidx(2 * t, 2 * t, D)] + Pb[sidx(2 * t + 1, 2 * t + 1, D)]);
+    }
+    // sum over the wave's lanes (one series), one partial per work wave
+    const int64_t S = p.n_wv;
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+      const double a0 = wave_sum(active ? acc.s(t) : 0.0);
+      const double a1 = wave_sum(active ? acc.w(t) : 0.0);
+      const double a2 = wave_sum(active ? acc.q(t) : 0.0);
+      if (lane == 0) {
+        gpart[(0 * M + t) * S + w] = a0;
+        gpart[(1 * M + t) * S + w] = a1;
+        gpart[(2 * M + t) * S + w] = a2;
+      }
+    }
+    const double aj = wave_sum(active ? acc.jit() : 0.0);
+    if (lane == 0) gpart[(3 * M) * S + w] = aj;
   }
-  const double aj = wave_sum(active ? acc.jit() : 0.0);
-  if (lane == 0) gpart[(3 * M) * S + w] = aj;
-  (void)NXP;
-  (void)C;
 }
 
 // ---------------------------------------------------------------------------
@@ -296,7 +300,7 @@ __global__ __launch_bounds__(WAVE) void k_plain(DevPlan p, DevParams pr, int64_t
       ll += plain_step<Dm>(m, P, tq, info, o);
     }
   }
-  loglik[b] = ll;
+  loglik[b] = pr.bad[b] ? __builtin_nan("") : ll;
 }
 
 // ---------------------------------------------------------------------------
@@ -360,16 +364,25 @@ __device__ __forceinline__ void bf_test(const double* m0, const double* P0, cons
   }
 }
 
+// adds NaN (poison) or 0 to test time o's per-term outputs, if wanted
+__device__ __forceinline__ void poison_terms(const DevTests& ts, int64_t o, double poison) {
+  if (!ts.term_mean) return;
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    ts.term_mean[o * M + t] += poison;
+    ts.term_var[o * M + t] += poison;
+  }
+}
+
 template <int J>
-__global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const double* __restrict__ bstate,
-                                                 const double* __restrict__ bsmooth, double* __restrict__ rec,
-                                                 DevTests ts, double* __restrict__ mean_test,
-                                                 double* __restrict__ var_test, double* __restrict__ mean_data,
-                                                 double* __restrict__ var_data) {
+__device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& pr, const double* __restrict__ bstate,
+                                            const double* __restrict__ bsmooth, double* __restrict__ rb, int w,
+                                            double* lcoef, const DevTests& ts, double* __restrict__ mean_test,
+                                            double* __restrict__ var_test, double* __restrict__ mean_data,
+                                            double* __restrict__ var_data) {
   using Dm = Dims<M, J>;
   constexpr int NX = Dm::NX, D = Dm::D, NP = Dm::NP;
   constexpr int F = rec_fields<Dm>();
-  const int w = p.wv_order ? p.wv_order[blockIdx.x] : (int)blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t b = p.wv_series[w];
   const int32_t nch = p.wv_nch[w];
@@ -380,11 +393,11 @@ __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const 
   const int32_t len = active ? p.chunk_len[c] : 0;
   TermConst tc[M];
   load_terms<Dm>(pr, b, tc);
-  __shared__ double lcoef[M * NCOEF];
   const double* coef = stage_coef<Dm, false>(pr, b, lcoef);
   const double jit = pr.jit[b];
   const double jit2 = jit * jit;
-  double* rb = rec + ev0 * F;
+  // a series whose hyperparameters failed validation gets NaN outputs
+  const double poison = pr.bad[b] ? __builtin_nan("") : 0.0;
   auto ev = [&](int32_t k) { return ev0 + (int64_t)k * WAVE + lane; };
   auto load_rec = [&](int32_t k, double* m, double* P) {
 #pragma unroll
@@ -458,13 +471,13 @@ __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const 
         for (int u = 0; u < M; ++u) var += PP[sidx(2 * t, 2 * u, D)];
       }
       const int64_t o = ts.out_index[tp];
-      mean_test[o] = mean;
-      var_test[o] = var;
+      mean_test[o] = mean + poison;
+      var_test[o] = var + poison;
       if (ts.term_mean) {
 #pragma unroll
         for (int t = 0; t < M; ++t) {
-          ts.term_mean[o * M + t] = mm[2 * t];
-          ts.term_var[o * M + t] = PP[sidx(2 * t, 2 * t, D)];
+          ts.term_mean[o * M + t] = mm[2 * t] + poison;
+          ts.term_var[o * M + t] = PP[sidx(2 * t, 2 * t, D)] + poison;
         }
       }
       --tp;
@@ -498,8 +511,8 @@ __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const 
         double mean, var;
         bf_posterior<Dm>(hm, hu, u, lam, Lam, mean, var);
         const int64_t n = p.meas[ev(k)];
-        if (mean_data) mean_data[n] = mean;
-        if (var_data) var_data[n] = var;
+        if (mean_data) mean_data[n] = mean + poison;
+        if (var_data) var_data[n] = var + poison;
       }
     }
     // test times between the previous event (or the chunk's start) and this one
@@ -515,8 +528,9 @@ __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const 
           const int64_t o = ts.out_index[tp];
           bf_test<Dm>(mf, Pf, tc, coef, tq - tprev, tk - tq, ev_open(cur.info), lam, Lam, mean, var,
                       ts.term_mean ? ts.term_mean + o * M : nullptr, ts.term_var ? ts.term_var + o * M : nullptr);
-          mean_test[o] = mean;
-          var_test[o] = var;
+          poison_terms(ts, o, poison);
+          mean_test[o] = mean + poison;
+          var_test[o] = var + poison;
           --tp;
         }
       }
@@ -545,8 +559,9 @@ __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const 
         const int64_t o = ts.out_index[tp];
         bf_test<Dm>(pm, pP, tc, coef, first ? 0.0 : tq - tprev, tk - tq, ev_open(cur.info), lam, Lam, mean, var,
                     ts.term_mean ? ts.term_mean + o * M : nullptr, ts.term_var ? ts.term_var + o * M : nullptr);
-        mean_test[o] = mean;
-        var_test[o] = var;
+        poison_terms(ts, o, poison);
+        mean_test[o] = mean + poison;
+        var_test[o] = var + poison;
         --tp;
       }
     }
@@ -555,6 +570,18 @@ __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const 
     discretise<M>(tc, coef, cur.dt, tq);
     bf_predict<Dm>(lam, Lam, tq, ev_open(cur.info));
   }
+}
+
+template <int J>
+__global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const double* __restrict__ bstate,
+                                                 const double* __restrict__ bsmooth, RecSlots rs, DevTests ts,
+                                                 double* __restrict__ mean_test, double* __restrict__ var_test,
+                                                 double* __restrict__ mean_data, double* __restrict__ var_data) {
+  __shared__ double lcoef[M * NCOEF];
+  const int32_t qi = rs.first + (int32_t)blockIdx.x;
+  const int w = p.wv_order ? p.wv_order[qi] : qi;
+  double* const rb = rs.records(p.wv_ev0[w], rec_fields<Dims<M, J>>());
+  smooth_wave<J>(p, pr, bstate, bsmooth, rb, w, lcoef, ts, mean_test, var_test, mean_data, var_data);
 }
 
 // ---------------------------------------------------------------------------
@@ -569,11 +596,17 @@ void launch_summaries(const Launch& L, const DevPlan& p, const DevParams& pr, do
 }
 template <int J>
 void launch_adjoint(const Launch& L, const DevPlan& p, const DevParams& pr, const double* bstate, const double* badj,
-                    double* rec, double* gpart) {
-  if (p.n_wv == 0) return;
-  prof_begin("k_adjoint", L.stream);
-  hipLaunchKernelGGL(k_adjoint<J>, dim3(p.n_wv), dim3(WAVE), 0, L.stream, p, pr, bstate, badj, rec, gpart);
-  prof_end("k_adjoint", L.stream);
+                    const RecSlots& rec, double* gpart) {
+  // rounds of at most rec.grid work waves in launch order, one record slot
+  // per workgroup of a round
+  for (int32_t first = 0; first < p.n_wv; first += rec.grid) {
+    RecSlots r = rec;
+    r.first = first;
+    prof_begin("k_adjoint", L.stream);
+    hipLaunchKernelGGL(k_adjoint<J>, dim3(std::min(rec.grid, p.n_wv - first)), dim3(WAVE), 0, L.stream, p, pr,
+                       bstate, badj, r, gpart);
+    prof_end("k_adjoint", L.stream);
+  }
 }
 template <int J>
 void launch_plain(const Launch& L, const DevPlan& p, const DevParams& pr, int64_t series, double* loglik) {
@@ -584,13 +617,36 @@ void launch_plain(const Launch& L, const DevPlan& p, const DevParams& pr, int64_
 
 template <int J>
 void launch_smooth(const Launch& L, const DevPlan& p, const DevParams& pr, const double* bstate, const double* bsmooth,
-                   double* rec, const DevTests& tests, double* mean_test, double* var_test, double* mean_data,
+                   const RecSlots& rec, const DevTests& tests, double* mean_test, double* var_test, double* mean_data,
                    double* var_data) {
-  if (p.n_wv == 0) return;
-  prof_begin("k_smooth", L.stream);
-  hipLaunchKernelGGL(k_smooth<J>, dim3(p.n_wv), dim3(WAVE), 0, L.stream, p, pr, bstate, bsmooth, rec, tests,
-                     mean_test, var_test, mean_data, var_data);
-  prof_end("k_smooth", L.stream);
+  for (int32_t first = 0; first < p.n_wv; first += rec.grid) {
+    RecSlots r = rec;
+    r.first = first;
+    prof_begin("k_smooth", L.stream);
+    hipLaunchKernelGGL(k_smooth<J>, dim3(std::min(rec.grid, p.n_wv - first)), dim3(WAVE), 0, L.stream, p, pr,
+                       bstate, bsmooth, r, tests, mean_test, var_test, mean_data, var_data);
+    prof_end("k_smooth", L.stream);
+  }
+}
+
+template <class K>
+int occupancy(K kernel) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, WAVE, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return n > 0 ? n : 1;
+}
+template <int J>
+int adjoint_occupancy() {
+  static const int n = occupancy(k_adjoint<J>);
+  return n;
+}
+template <int J>
+int smooth_occupancy() {
+  static const int n = occupancy(k_smooth<J>);
+  return n;
 }
 
 template <int J>
@@ -600,6 +656,8 @@ KernelSet make_set() {
   k.adjoint = &launch_adjoint<J>;
   k.plain = &launch_plain<J>;
   k.smooth = &launch_smooth<J>;
+  k.adjoint_occupancy = &adjoint_occupancy<J>;
+  k.smooth_occupancy = &smooth_occupancy<J>;
   return k;
 }
 

@@ -197,7 +197,8 @@ int plan_series(int64_t b, int64_t lo, int64_t hi, const double* ts, const doubl
     prev = *(kt - 1);
     w.cuts.push_back(prev);
   }
-  w.cuts.push_back(ne);
+  // a series without measurements has no chunk (its log-likelihood is 0)
+  if (ne > 0) w.cuts.push_back(ne);
   // step-length histogram in powers of two, then its cumulative fractions
   int64_t cnt[DT_NE] = {};
   for (int64_t k = 1; k < ne; ++k) {

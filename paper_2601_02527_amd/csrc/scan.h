@@ -28,7 +28,8 @@ struct ScanWork {
   double *pre2, *suf2, *grptot, *grpstate, *grpfut;
 };
 
-void run_scan(int M, hipStream_t st, const DevPlan& p, const DevParams& pr, const ScanWork& w, double* loglik,
-              int32_t* status, int back);
+// loglik and status of the call are read from args (device memory)
+void run_scan(int M, hipStream_t st, const DevPlan& p, const DevParams& pr, const ScanWork& w, const CallArgs* args,
+              int back);
 
 }  // namespace gpssm

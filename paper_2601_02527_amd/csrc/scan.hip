@@ -287,10 +287,12 @@ __global__ __launch_bounds__(WAVE) void k_seg_fix(DevPlan p, const double* __res
 }
 
 // one wavefront per series: lane l sums segments l, l + 64, ..., then a
-// fixed-order wave reduction (the same result on every run)
-__global__ __launch_bounds__(WAVE) void k_series_finish(DevPlan p, const double* __restrict__ segll,
-                                                        const int32_t* __restrict__ segok, double* __restrict__ loglik,
-                                                        int32_t* __restrict__ status) {
+// fixed-order wave reduction (the same result on every run).  The outputs go
+// to the call's loglik and status (either may be null); a series whose
+// hyperparameters failed validation gets NaN and GP_SSM_EPARAM.
+__global__ __launch_bounds__(WAVE) void k_series_finish(DevPlan p, DevParams pr, const double* __restrict__ segll,
+                                                        const int32_t* __restrict__ segok,
+                                                        const CallArgs* __restrict__ args) {
   const int64_t b = blockIdx.x;
   const int lane = threadIdx.x;
   const int32_t s0 = p.series_seg0[b], ns = p.series_nseg[b];
@@ -303,8 +305,11 @@ __global__ __launch_bounds__(WAVE) void k_series_finish(DevPlan p, const double*
   ll = wave_sum(ll);
   const bool good = !__any(bad) && isfinite(ll);
   if (lane == 0) {
-    if (loglik) loglik[b] = good ? ll : __builtin_nan("");
-    if (status) status[b] = good ? 0 : GP_SSM_ENUMERIC;
+    const bool pbad = pr.bad[b] != 0;
+    double* const loglik = args->loglik;
+    int32_t* const status = args->status;
+    if (loglik) loglik[b] = (good && !pbad) ? ll : __builtin_nan("");
+    if (status) status[b] = pbad ? GP_SSM_EPARAM : (good ? 0 : GP_SSM_ENUMERIC);
   }
 }
 
@@ -364,9 +369,21 @@ __global__ __launch_bounds__(WAVE) void k_grp_fix(DevPlan p2, const double* __re
 }
 
 template <int N>
-void run_scan_n(hipStream_t st, const DevPlan& p, const DevParams& pr, const ScanWork& w, double* loglik,
-                int32_t* status, int back) {
-  if (p.n_seg == 0) return;
+void run_levels(hipStream_t st, const DevPlan& p, const DevParams& pr, const ScanWork& w, int back);
+
+template <int N>
+void run_scan_n(hipStream_t st, const DevPlan& p, const DevParams& pr, const ScanWork& w, const CallArgs* args,
+                int back) {
+  // series without measurements have no segment; k_series_finish still gives
+  // them log-likelihood 0 and status 0
+  if (p.n_seg > 0) run_levels<N>(st, p, pr, w, back);
+  prof_begin("k_series_finish", st);
+  hipLaunchKernelGGL(k_series_finish, dim3((unsigned)p.n_series), dim3(WAVE), 0, st, p, pr, w.segll, w.segok, args);
+  prof_end("k_series_finish", st);
+}
+
+template <int N>
+void run_levels(hipStream_t st, const DevPlan& p, const DevParams& pr, const ScanWork& w, int back) {
   prof_begin("k_seg_scan", st);
   hipLaunchKernelGGL(k_seg_scan<N>, dim3(p.n_seg), dim3(WAVE), 0, st, p, w.summ, w.pre, w.suf, w.segtot, back);
   prof_end("k_seg_scan", st);
@@ -396,21 +413,17 @@ void run_scan_n(hipStream_t st, const DevPlan& p, const DevParams& pr, const Sca
   hipLaunchKernelGGL(k_seg_fix<N>, dim3(p.n_seg), dim3(WAVE), 0, st, p, w.summ, w.pre, w.suf, w.segstate, w.segfut,
                      w.bstate, w.badj, w.bsmooth, w.segll, w.segok, back);
   prof_end("k_seg_fix", st);
-  prof_begin("k_series_finish", st);
-  hipLaunchKernelGGL(k_series_finish, dim3((unsigned)p.n_series), dim3(WAVE), 0, st, p, w.segll, w.segok,
-                     loglik, status);
-  prof_end("k_series_finish", st);
 }
 
 }  // namespace
 
-void run_scan(int M, hipStream_t st, const DevPlan& p, const DevParams& pr, const ScanWork& w, double* loglik,
-              int32_t* status, int back) {
+void run_scan(int M, hipStream_t st, const DevPlan& p, const DevParams& pr, const ScanWork& w, const CallArgs* args,
+              int back) {
   switch (M) {
-    case 1: run_scan_n<2>(st, p, pr, w, loglik, status, back); break;
-    case 2: run_scan_n<4>(st, p, pr, w, loglik, status, back); break;
-    case 3: run_scan_n<6>(st, p, pr, w, loglik, status, back); break;
-    default: run_scan_n<8>(st, p, pr, w, loglik, status, back); break;
+    case 1: run_scan_n<2>(st, p, pr, w, args, back); break;
+    case 2: run_scan_n<4>(st, p, pr, w, args, back); break;
+    case 3: run_scan_n<6>(st, p, pr, w, args, back); break;
+    default: run_scan_n<8>(st, p, pr, w, args, back); break;
   }
 }
 

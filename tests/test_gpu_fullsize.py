@@ -106,6 +106,17 @@ def test_long_1e7_two_scan_structures(lib):
     assert np.isfinite(ll0[0]) and np.all(np.isfinite(g0))
     assert abs(ll0[0] - ll1[0]) / abs(ll1[0]) < LL_TOL
     assert _grad_err(g0[0], g1[0]) < GRAD_TOL
+    # the first 1e6 exposures: the scan (default plan) against the plain
+    # sequential filter of the same series, one lane, no time splitting
+    n = 1_000_000
+    p2 = lib.Plan(np.array([0, n], dtype=np.int64), b.t_start[:n], b.t_end[:n], b.y[:n], b.yerr[:n])
+    l_scan = p2.loglik(b.sigma, b.omega0, b.quality, b.jitter).cpu().numpy()
+    l_plain = p2.plain_loglik(b.sigma, b.omega0, b.quality, b.jitter).cpu().numpy()
+    print("1e6 prefix", p2.stats(), l_scan, l_plain)
+    assert p2.stats()["n_segments"] > 64
+    assert abs(l_scan[0] - l_plain[0]) / abs(l_plain[0]) < LL_TOL
+    del p2
+    _free()
 
 
 def test_long_100k_smoother(lib):

@@ -133,11 +133,16 @@ def test_errors(lib):
     plan = _plan(lib, b)
     bad = b.sigma.copy()
     bad[1, 0] = -1.0
+    # hyperparameters are validated on the device: the plan forms report
+    # through the per-series status, the one-shot forms by their return code
     with pytest.raises(lib.GpSsmError) as e:
-        plan.loglik(bad, b.omega0, b.quality, b.jitter)
+        plan.loglik(bad, b.omega0, b.quality, b.jitter, check=True)
     assert e.value.code == -3
     with pytest.raises(lib.GpSsmError) as e:
-        plan.loglik(b.sigma, b.omega0, b.quality, -np.ones(2))
+        plan.loglik(b.sigma, b.omega0, b.quality, -np.ones(2), check=True)
+    assert e.value.code == -3
+    with pytest.raises(lib.GpSsmError) as e:
+        lib.loglik(b.offsets, b.t_start, b.t_end, b.y, b.yerr, bad, b.omega0, b.quality, b.jitter)
     assert e.value.code == -3
     ts = b.t_start.copy()
     ts[[0, 1]] = ts[[1, 0]]

@@ -66,7 +66,7 @@ def _check(P):
     info, meas, t = P["info"].astype(np.int64), i("meas"), P["t"]
     # layout size
     assert wv_chunk.size == P["n_wv"] * WAVE
-    assert np.array_equal(wv_ev0, np.concatenate([[0], np.cumsum(wv_len * WAVE)[:-1]]))
+    assert np.array_equal(wv_ev0, np.concatenate([[0], np.cumsum(wv_len * WAVE)[:-1]])[:wv_len.size])
     assert P["n_pad"] == int(np.sum(wv_len)) * WAVE == t.size
     # series tables
     seen_meas = []
@@ -77,7 +77,7 @@ def _check(P):
         chunks = np.arange(c0, c0 + nc)
         assert np.all(chunk_series[chunks] == b)
         assert int(chunk_len[chunks].sum()) == n_exp_ev
-        assert list(P["chunk_first"][chunks].astype(int)) == [1] + [0] * (nc - 1)
+        assert list(P["chunk_first"][chunks].astype(int)) == ([1] + [0] * (nc - 1) if nc else [])
         # scan segments: consecutive runs of <= 64 chunks covering the series
         s0, ns = int(P["series_seg0"][b]), int(P["series_nseg"][b])
         pos = c0
@@ -178,3 +178,21 @@ def test_balanced_cuts_on_dense_overlaps(driver):
     _check(P)
     L = P["chunk_len"]
     assert L.max() <= 1.35 * L.mean(), (L.max(), L.mean())
+
+
+def test_empty_series(driver):
+    """Series without measurements (between others, at the end, or all of
+    them) get no chunk, segment or work wave; the others are planned as
+    usual."""
+    e = np.array([])
+    ts = [np.array([0.0, 0.5]), e, np.array([1.0, 1.2, 1.4]), e]
+    te = [np.array([0.2, 0.6]), e, np.array([1.1, 1.3, 1.4]), e]
+    for opt in (dict(), dict(chunk_min=1, chunk_target=1)):
+        P = _plan(driver, ts, te, **opt)
+        _check(P)
+        assert list(P["series_nch"].astype(int)[[1, 3]]) == [0, 0]
+        assert list(P["series_nwv"].astype(int)[[1, 3]]) == [0, 0]
+        assert list(P["series_nseg"].astype(int)[[1, 3]]) == [0, 0]
+    P = _plan(driver, [e, e], [e, e])
+    _check(P)
+    assert P["n_ch"] == 0 and P["n_wv"] == 0 and P["n_seg"] == 0 and P["n_pad"] == 0
