@@ -135,6 +135,22 @@ int gp_ssm_plan_get_stats(const gp_ssm_plan* plan, gp_ssm_plan_stats* out);
 int gp_ssm_plan_loglik(gp_ssm_plan* plan, int32_t n_terms, const double* sigma, const double* omega0,
                        const double* quality, const double* jitter, double* loglik, int32_t* status, void* stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the log-likelihood
+ * of gp_ssm_plan_loglik, computed by the same kernels, with its workspace
+ * taken from a static device array of 64 MiB that the library holds on each
+ * GPU it runs on until the process ends.  Calls no hipMalloc, hipFree or
+ * other allocating routine, does not synchronise and captures no graph.
+ * Every array argument must be device memory (GP_SSM_EINVAL otherwise), and
+ * the plan must live on the current device.  A batch whose workspace (about
+ * 2.5 KB per chunk and 4.4 KB per series and term at three terms) exceeds
+ * 64 MiB is refused with GP_SSM_ENOMEM before any device work.  All calls on
+ * one GPU share the array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be ordered by the caller. */
+int gp_ssm_plan_loglik_noalloc(gp_ssm_plan* plan, int32_t n_terms, const double* sigma, const double* omega0,
+                               const double* quality, const double* jitter, double* loglik, int32_t* status,
+                               void* stream);
+
 /* Log-likelihood and its gradient by a reverse-mode adjoint of the filter.
  * grad[b*(3M+1) + k] holds d loglik_b / d(sigma_1..M, omega0_1..M,
  * Q_1..M, jitter) in that order. */

@@ -27,7 +27,8 @@ ERRORS = {-1: "EINVAL", -2: "EDATA", -3: "EPARAM", -4: "EOVERLAP", -5: "ENUMERIC
 # every symbol include/gp_ssm.h declares
 EXPORTS = [
     "gp_ssm_plan_default_options", "gp_ssm_plan_create", "gp_ssm_plan_destroy", "gp_ssm_plan_get_stats",
-    "gp_ssm_plan_loglik", "gp_ssm_plan_loglik_grad", "gp_ssm_plan_smooth", "gp_ssm_plan_smooth_terms",
+    "gp_ssm_plan_loglik", "gp_ssm_plan_loglik_noalloc", "gp_ssm_plan_loglik_grad", "gp_ssm_plan_smooth",
+    "gp_ssm_plan_smooth_terms",
     "gp_ssm_plan_plain_loglik", "gp_ssm_loglik", "gp_ssm_loglik_grad", "gp_ssm_smooth", "gp_ssm_profile_enable", "gp_ssm_profile_reset",
     "gp_ssm_profile_read", "gp_ssm_last_error", "gp_ssm_version",
 ]
@@ -70,6 +71,7 @@ def library():
     L.gp_ssm_plan_destroy.restype = None
     L.gp_ssm_plan_get_stats.argtypes = [vp, ctypes.POINTER(PlanStats)]
     L.gp_ssm_plan_loglik.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.gp_ssm_plan_loglik_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.gp_ssm_plan_loglik_grad.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
     L.gp_ssm_plan_smooth.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.gp_ssm_plan_smooth_terms.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -82,7 +84,8 @@ def library():
                                       ctypes.POINTER(ctypes.c_double), i32]
     L.gp_ssm_last_error.restype = ctypes.c_char_p
     L.gp_ssm_version.restype = ctypes.c_char_p
-    for name in ("gp_ssm_plan_create", "gp_ssm_plan_get_stats", "gp_ssm_plan_loglik", "gp_ssm_plan_loglik_grad",
+    for name in ("gp_ssm_plan_create", "gp_ssm_plan_get_stats", "gp_ssm_plan_loglik", "gp_ssm_plan_loglik_noalloc",
+                 "gp_ssm_plan_loglik_grad",
                  "gp_ssm_plan_smooth", "gp_ssm_plan_smooth_terms", "gp_ssm_plan_plain_loglik", "gp_ssm_loglik",
                  "gp_ssm_loglik_grad",
                  "gp_ssm_smooth", "gp_ssm_profile_enable", "gp_ssm_profile_reset", "gp_ssm_profile_read"):
@@ -195,6 +198,18 @@ class Plan:
         if check:
             check_status(st)
         return (out, st) if status else out
+
+    def loglik_noalloc(self, sigma, omega0, quality, jitter=None, out=None, status=None):
+        """gp_ssm_plan_loglik_noalloc: the log-likelihood with the library's
+        static workspace.  out [B] and status [B] (optional) are the caller's
+        device tensors; this method allocates them only when not given."""
+        torch = _torch()
+        M, s, w, q, j = self._params(sigma, omega0, quality, jitter)
+        if out is None:
+            out = torch.empty(self.n_series, dtype=torch.float64, device="cuda")
+        _check(library().gp_ssm_plan_loglik_noalloc(self._h, M, _ptr(s), _ptr(w), _ptr(q), _ptr(j), _ptr(out),
+                                                    _ptr(status), _stream()))
+        return out
 
     def loglik_grad(self, sigma, omega0, quality, jitter=None, status=False, check=False):
         """Log-likelihood [B] and gradient [B, 3M+1] (d/d sigma_1..M,

@@ -346,6 +346,47 @@ constexpr int64_t DEFAULT_RECORD_BUDGET = int64_t(32) << 30;
 constexpr int ARG_RING = 16;
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// the entry point that allocates nothing (gp_ssm_plan_loglik_noalloc) takes
+// its workspace from this array: one copy per GPU the library runs on, held
+// until the process ends, shared by every such call on that GPU
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t SCRATCH_BYTES = size_t(64) << 20;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_at;  // device -> address of its copy of `scratch`
+
+// the device address of the current device's copy of `scratch` (looked up
+// once per device, with that device current); host code uses this address,
+// never the array's name
+int scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_at.find(device);
+  if (it != g_scratch_at.end()) {
+    *out = it->second;
+    return 0;
+  }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return fail(GP_SSM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  }
+  g_scratch_at[device] = ptr;
+  *out = ptr;
+  return 0;
+}
+
+// writes the call's pointers (a kernel argument) to the argument block
+__global__ void k_set_args(CallArgs a, CallArgs* __restrict__ dst) {
+  if (threadIdx.x == 0) *dst = a;
+}
+}  // namespace
+
 struct gp_ssm_plan {
   int device = 0;
   int n_cu = 1;
@@ -596,51 +637,140 @@ int reserve(gp_ssm_plan* pl, int32_t M, int back, bool smooth) {
   return 0;
 }
 
+// device memory of the log-likelihood part of a call: the prepared
+// hyperparameters, the launch order, the argument block and the scan's
+// workspace (the plan's own buffers, or carved from the static scratch array
+// by the entry point that allocates nothing)
+struct FwdWork {
+  TermConst* tc;
+  double* coef;
+  double* jit;
+  int32_t* bad;
+  int32_t* order;
+  const CallArgs* args;
+  double *summ, *bstate, *pre, *suf, *segtot, *segstate, *segfut, *segll;
+  int32_t* segok;
+  double *pre2, *suf2, *grptot, *grpstate, *grpfut;
+  DevParams params() const { return DevParams{tc, coef, jit, bad}; }
+};
+
+FwdWork plan_work(gp_ssm_plan* pl) {
+  FwdWork W;
+  W.tc = pl->tc.as<TermConst>();
+  W.coef = pl->coef.as<double>();
+  W.jit = pl->jit.as<double>();
+  W.bad = pl->pbad.as<int32_t>();
+  W.order = pl->wv_order.as<int32_t>();
+  W.args = pl->dargs();
+  W.summ = pl->summ.as<double>();
+  W.bstate = pl->bstate.as<double>();
+  W.pre = pl->pre.as<double>();
+  W.suf = pl->suf.as<double>();
+  W.segtot = pl->segtot.as<double>();
+  W.segstate = pl->segstate.as<double>();
+  W.segfut = pl->segfut.as<double>();
+  W.segll = pl->segll.as<double>();
+  W.segok = pl->segok.as<int32_t>();
+  W.pre2 = pl->pre2.as<double>();
+  W.suf2 = pl->suf2.as<double>();
+  W.grptot = pl->grptot.as<double>();
+  W.grpstate = pl->grpstate.as<double>();
+  W.grpfut = pl->grpfut.as<double>();
+  return W;
+}
+
+// Lays the log-likelihood workspace of (plan, M) out from `base` (256-byte
+// aligned pieces); returns the bytes it needs.  Nothing is written.
+size_t carve_work(const gp_ssm_plan* pl, int32_t M, unsigned char* base, FwdWork& W) {
+  const HostPlan& h = pl->host;
+  const int64_t B = h.n_series;
+  const int NX = 2 * M;
+  const int NXP = NX * (NX + 1) / 2;
+  const int64_t C = std::max<int64_t>(1, h.n_chunks);
+  const int64_t S = std::max<int64_t>(1, h.n_seg);
+  const int64_t G = std::max<int64_t>(1, h.n_grp);
+  const int64_t EF = elem_fields(NX);
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* q = base + at;
+    at += (bytes + 255) / 256 * 256;
+    return q;
+  };
+  W.args = (const CallArgs*)take(sizeof(CallArgs));
+  W.tc = (TermConst*)take(sizeof(TermConst) * B * M);
+  W.coef = (double*)take(sizeof(double) * B * M * 2 * NCOEF);
+  W.jit = (double*)take(sizeof(double) * B);
+  W.bad = (int32_t*)take(sizeof(int32_t) * B);
+  W.order = (int32_t*)take(sizeof(int32_t) * std::max<int64_t>(1, h.n_wv));
+  W.summ = (double*)take(sizeof(double) * summary_size(NX) * C);
+  W.bstate = (double*)take(sizeof(double) * (NX + NXP) * C);
+  W.pre = (double*)take(sizeof(double) * EF * C);
+  W.suf = W.pre;  // the suffixes serve the backward passes only
+  W.segtot = (double*)take(sizeof(double) * EF * S);
+  W.segstate = (double*)take(sizeof(double) * (NX + NXP) * S);
+  W.segfut = (double*)take(sizeof(double) * (NX + NXP) * S);
+  W.segll = (double*)take(sizeof(double) * S);
+  W.segok = (int32_t*)take(sizeof(int32_t) * S);
+  W.pre2 = W.suf2 = W.grptot = W.grpstate = W.grpfut = nullptr;
+  if (h.max_series_nseg > WAVE) {
+    W.pre2 = (double*)take(sizeof(double) * EF * S);
+    W.suf2 = W.pre2;
+    W.grptot = (double*)take(sizeof(double) * EF * G);
+    W.grpstate = (double*)take(sizeof(double) * (NX + NXP) * G);
+    W.grpfut = (double*)take(sizeof(double) * (NX + NXP) * G);
+  }
+  return at;
+}
+
 // validation, preparation and launch order of the hyperparameters
-void enqueue_prep(gp_ssm_plan* pl, int32_t M, hipStream_t s) {
+void enqueue_prep(gp_ssm_plan* pl, const FwdWork& W, int32_t M, hipStream_t s) {
   const int64_t B = pl->host.n_series;
   const int threads = 256;
   const int64_t n = std::max<int64_t>(B * M * NI, B);
+  DevPlan p = pl->dev();
+  p.wv_order = W.order;
   prof_begin("k_prep", s);
-  hipLaunchKernelGGL(k_prep, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0, s, B, M, pl->dargs(),
-                     pl->tc.as<TermConst>(), pl->coef.as<double>(), pl->jit.as<double>(), pl->pbad.as<int32_t>());
+  hipLaunchKernelGGL(k_prep, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0, s, B, M, W.args, W.tc,
+                     W.coef, W.jit, W.bad);
   prof_end("k_prep", s);
   prof_begin("k_order", s);
-  hipLaunchKernelGGL(k_order, dim3(1), dim3(ORDER_THREADS), 0, s, pl->dev(), M, pl->tc.as<TermConst>(),
-                     pl->series_dt_cdf.as<float>(), pl->wv_order.as<int32_t>());
+  hipLaunchKernelGGL(k_order, dim3(1), dim3(ORDER_THREADS), 0, s, p, M, W.tc, pl->series_dt_cdf.as<float>(),
+                     W.order);
   prof_end("k_order", s);
 }
 
-void enqueue_forward(gp_ssm_plan* pl, int32_t M, hipStream_t s, int back, bool need_smooth) {
-  const DevPlan p = pl->dev();
-  const DevParams pr = pl->params();
+void enqueue_forward(gp_ssm_plan* pl, const FwdWork& W, int32_t M, hipStream_t s, int back, bool need_smooth) {
+  DevPlan p = pl->dev();
+  p.wv_order = W.order;
+  const DevParams pr = W.params();
   const KernelSet ks = kernel_set(M, pl->host.max_slots);
   Launch L{s};
-  ks.summaries(L, p, pr, pl->summ.as<double>());
+  ks.summaries(L, p, pr, W.summ);
   ScanWork w;
-  w.summ = pl->summ.as<double>();
-  w.pre = pl->pre.as<double>();
-  w.suf = pl->suf.as<double>();
-  w.segtot = pl->segtot.as<double>();
-  w.segstate = pl->segstate.as<double>();
-  w.segfut = pl->segfut.as<double>();
-  w.bstate = pl->bstate.as<double>();
+  w.summ = W.summ;
+  w.pre = W.pre;
+  w.suf = W.suf;
+  w.segtot = W.segtot;
+  w.segstate = W.segstate;
+  w.segfut = W.segfut;
+  w.bstate = W.bstate;
   w.badj = back ? pl->badj.as<double>() : nullptr;
   w.bsmooth = (back && need_smooth) ? pl->bsmooth.as<double>() : nullptr;
-  w.segll = pl->segll.as<double>();
-  w.segok = pl->segok.as<int32_t>();
+  w.segll = W.segll;
+  w.segok = W.segok;
   w.p2 = nullptr;
   DevPlan p2;
   if (pl->host.max_series_nseg > WAVE) {
     p2 = pl->dev_groups();
+    p2.wv_order = W.order;
     w.p2 = &p2;
-    w.pre2 = pl->pre2.as<double>();
-    w.suf2 = pl->suf2.as<double>();
-    w.grptot = pl->grptot.as<double>();
-    w.grpstate = pl->grpstate.as<double>();
-    w.grpfut = pl->grpfut.as<double>();
+    w.pre2 = W.pre2;
+    w.suf2 = W.suf2;
+    w.grptot = W.grptot;
+    w.grpstate = W.grpstate;
+    w.grpfut = W.grpfut;
   }
-  run_scan(M, s, p, pr, w, pl->dargs(), back);
+  run_scan(M, s, p, pr, w, W.args, back);
 }
 
 void enqueue_grad_tail(gp_ssm_plan* pl, int32_t M, hipStream_t s) {
@@ -657,8 +787,9 @@ void enqueue_grad_tail(gp_ssm_plan* pl, int32_t M, hipStream_t s) {
 }
 
 void enqueue_step(gp_ssm_plan* pl, int32_t M, int kind, hipStream_t s) {
-  enqueue_prep(pl, M, s);
-  enqueue_forward(pl, M, s, kind == STEP_GRAD, false);
+  const FwdWork W = plan_work(pl);
+  enqueue_prep(pl, W, M, s);
+  enqueue_forward(pl, W, M, s, kind == STEP_GRAD, false);
   if (kind == STEP_GRAD) enqueue_grad_tail(pl, M, s);
 }
 
@@ -834,6 +965,35 @@ int gp_ssm_plan_loglik(gp_ssm_plan* pl, int32_t M, const double* sigma, const do
   return run_step(pl, M, STEP_LOGLIK, s);
 }
 
+int gp_ssm_plan_loglik_noalloc(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0,
+                               const double* quality, const double* jitter, double* loglik, int32_t* status,
+                               void* stream) {
+  g_err.clear();
+  if (!pl) return fail(GP_SSM_EINVAL, "null plan");
+  if (M < 1 || M > GP_SSM_MAX_TERMS) return fail(GP_SSM_EINVAL, "n_terms out of range");
+  if (!sigma || !omega0 || !quality || !loglik) return fail(GP_SSM_EINVAL, "null pointer");
+  for (const void* q : {(const void*)sigma, (const void*)omega0, (const void*)quality, (const void*)jitter,
+                        (const void*)loglik, (const void*)status})
+    if (q && !device_memory(q)) return fail(GP_SSM_EINVAL, "every array must be device memory");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != pl->device) return fail(GP_SSM_EINVAL, "the plan lives on another device than the current one");
+  void* base = nullptr;
+  if (int rc = scratch_address(dev, &base)) return rc;
+  FwdWork W;
+  const size_t need = carve_work(pl, M, (unsigned char*)base, W);
+  if (need > SCRATCH_BYTES)
+    return fail(GP_SSM_ENOMEM, "the batch needs " + std::to_string(need) + " bytes of workspace; the static scratch "
+                               "holds " + std::to_string(SCRATCH_BYTES) + " (use gp_ssm_plan_loglik)");
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_set_args, dim3(1), dim3(WAVE), 0, s, CallArgs{sigma, omega0, quality, jitter, loglik, nullptr, status},
+                     const_cast<CallArgs*>(W.args));
+  enqueue_prep(pl, W, M, s);
+  enqueue_forward(pl, W, M, s, 0, false);
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
 int gp_ssm_plan_loglik_grad(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0,
                             const double* quality, const double* jitter, double* loglik, double* grad,
                             int32_t* status, void* stream) {
@@ -928,8 +1088,9 @@ static int plan_smooth(gp_ssm_plan* pl, int32_t M, const double* sigma, const do
   int32_t* st = status ? status : pl->status.as<int32_t>();
   double* ll = loglik ? loglik : pl->llbuf.as<double>();
   if (int rc = put_args(pl, M, sigma, omega0, quality, jitter, ll, nullptr, st, s)) return rc;
-  enqueue_prep(pl, M, s);
-  enqueue_forward(pl, M, s, 1, true);
+  const FwdWork W = plan_work(pl);
+  enqueue_prep(pl, W, M, s);
+  enqueue_forward(pl, W, M, s, 1, true);
   const DevPlan p = pl->dev();
   const KernelSet ks = kernel_set(M, h.max_slots);
   RecSlots rs;
@@ -981,7 +1142,7 @@ int gp_ssm_plan_plain_loglik(gp_ssm_plan* pl, int64_t first, int64_t count, int3
   hipStream_t s = (hipStream_t)stream;
   if (int rc = reserve(pl, M, 0, false)) return rc;
   if (int rc = put_args(pl, M, sigma, omega0, quality, jitter, loglik, nullptr, nullptr, s)) return rc;
-  enqueue_prep(pl, M, s);
+  enqueue_prep(pl, plan_work(pl), M, s);
   const DevPlan p = pl->dev();
   const KernelSet ks = kernel_set(M, pl->host.max_slots);
   Launch L{s};
