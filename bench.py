@@ -171,7 +171,11 @@ def _leg_c3(gp, legs, dev, prof_run, steps, warmup):
     b = W.batch_4096()
     gen = time.perf_counter() - t0
     t0 = time.perf_counter()
-    plan = gp.Plan(b.offsets, b.t_start, b.t_end, b.y, b.yerr)
+    opts, _ = gp.autotune(b.offsets, b.t_start, b.t_end, b.y, b.yerr, b.sigma, b.omega0, b.quality, b.jitter,
+                          grad=True)
+    tt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan = gp.Plan(b.offsets, b.t_start, b.t_end, b.y, b.yerr, target_chunks=opts["target_chunks"])
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
     a = (dev(b.sigma), dev(b.omega0), dev(b.quality), dev(b.jitter))
@@ -181,6 +185,7 @@ def _leg_c3(gp, legs, dev, prof_run, steps, warmup):
     ll, _ = plan.loglik_grad(*a)
     legs["C3_batch_4096"] = {
         "series": b.n_series, "points": pts, "terms": b.n_terms, "slots": plan.stats()["max_slots"],
+        "target_chunks": opts["target_chunks"], "autotune_s": tt, "chunks": plan.stats()["n_chunks"],
         "loglik_grad_ms": tg * 1e3, "loglik_grad_points_per_s": pts / tg,
         "loglik_ms": tl * 1e3, "loglik_points_per_s": pts / tl, "nan_series": int(torch.isnan(ll).sum().item()),
         "loglik_grad_median_replay_ms": _median_replay(lambda: plan.loglik_grad(*a), 5) * 1e3,
@@ -279,6 +284,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-legs", action="store_true", help="skip the C2, C3 and C5 configurations")
+    ap.add_argument("--no-autotune", action="store_true", help="default plan options instead of the autotuner's")
     ap.add_argument("--leg", choices=["C2", "C3", "C5"],
                     help="run only this configuration (for profiling) and print its figures as JSON")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -320,8 +326,19 @@ def main():
     print(f"[bench] workload {args.workload}: {B} series, {points} points, M={M} (generated in {t_gen:.1f}s)",
           file=sys.stderr, flush=True)
 
+    # the autotuner picks the target chunk count (the lanes each series gets)
+    tune, plan_opts = None, {}
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        opts, tms = gp.autotune(batch.offsets, batch.t_start, batch.t_end, batch.y, batch.yerr, batch.sigma,
+                                batch.omega0, batch.quality, batch.jitter, grad=True)
+        plan_opts = {"target_chunks": opts["target_chunks"]}
+        tune = {"target_chunks": opts["target_chunks"], "tuned_ms_per_call": tms,
+                "candidates": gp.autotune_candidates(), "seconds": time.perf_counter() - t0}
+        print(f"[bench] autotune {tune}", file=sys.stderr, flush=True)
+
     t0 = time.perf_counter()
-    plan = gp.Plan(batch.offsets, batch.t_start, batch.t_end, batch.y, batch.yerr)
+    plan = gp.Plan(batch.offsets, batch.t_start, batch.t_end, batch.y, batch.yerr, **plan_opts)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     st = plan.stats()
@@ -452,7 +469,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {B} series, {points} exposures, {M} SHO terms + jitter, "
                                f"up to {J} overlapping, fp64 loglik + adjoint gradient",
-                   "series": B, "points": points, "terms": M, "slots": J, "parallelism": "single GPU"},
+                   "series": B, "points": points, "terms": M, "slots": J, "parallelism": "single GPU",
+                   "target_chunks": plan_opts.get("target_chunks", "default"), "chunks": st["n_chunks"]},
+        "autotune": tune,
         "roofline": roof,
         "cpu_baseline": cpu,
         "loglik_only_ms_per_step": ms_ll,

@@ -218,6 +218,30 @@ int gp_ssm_smooth(int64_t n_series, const int64_t* offsets, const double* t_star
                   double* mean_test, double* var_test, double* mean_data, double* var_data, int32_t* status,
                   void* stream);
 
+/* Autotuner of the batched launch.  The plan's chunk length sets how many
+ * lanes each series gets (one lane per chunk, 64 lanes to a work wave) and
+ * how long each lane's sequential run is; it follows from the target chunk
+ * count over the batch.  gp_ssm_autotune builds a plan for each candidate
+ * target chunk count (gp_ssm_autotune_candidates lists them), times three
+ * replays of the log-likelihood (what = 0) or log-likelihood + gradient
+ * (what = 1) call with HIP events on `stream`, and returns in *best the
+ * default options with the fastest target, and in *best_ms (may be NULL) its
+ * time per call.  Inputs as for gp_ssm_plan_create and the plan calls.
+ * With cache_path (may be NULL) the choice is looked up first by the
+ * workload's shape (series, measurements and events to two significant
+ * digits, overlap depth, terms, kind of call, GPU architecture) and
+ * appended to the file after tuning.  The environment variable
+ * GP_SSM_TARGET_CHUNKS, when set to a positive count, overrides it all.
+ * Every candidate is an ordinary plan: they compute the same results up to
+ * rounding order.  Synchronises `stream`; allocates and frees its own
+ * workspace. */
+int gp_ssm_autotune(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end,
+                    const double* y, const double* yerr, int32_t n_terms, const double* sigma, const double* omega0,
+                    const double* quality, const double* jitter, int32_t what, const char* cache_path,
+                    gp_ssm_plan_options* best, double* best_ms, void* stream);
+/* Copies up to cap candidate target chunk counts; returns their number. */
+int gp_ssm_autotune_candidates(int64_t* target_chunks, int32_t cap);
+
 /* Kernel timing.  While enabled, every kernel the library launches is
  * bracketed by HIP events on its stream and its duration is accumulated per
  * kernel name.  gp_ssm_profile_read copies up to `cap` entries (name, count,

@@ -29,7 +29,8 @@ EXPORTS = [
     "gp_ssm_plan_default_options", "gp_ssm_plan_create", "gp_ssm_plan_destroy", "gp_ssm_plan_get_stats",
     "gp_ssm_plan_loglik", "gp_ssm_plan_loglik_noalloc", "gp_ssm_plan_loglik_grad", "gp_ssm_plan_smooth",
     "gp_ssm_plan_smooth_terms",
-    "gp_ssm_plan_plain_loglik", "gp_ssm_loglik", "gp_ssm_loglik_grad", "gp_ssm_smooth", "gp_ssm_profile_enable", "gp_ssm_profile_reset",
+    "gp_ssm_plan_plain_loglik", "gp_ssm_loglik", "gp_ssm_loglik_grad", "gp_ssm_smooth", "gp_ssm_autotune",
+    "gp_ssm_autotune_candidates", "gp_ssm_profile_enable", "gp_ssm_profile_reset",
     "gp_ssm_profile_read", "gp_ssm_last_error", "gp_ssm_version",
 ]
 
@@ -79,6 +80,9 @@ def library():
     L.gp_ssm_loglik.argtypes = [i64, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.gp_ssm_loglik_grad.argtypes = [i64, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
     L.gp_ssm_smooth.argtypes = [i64, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.gp_ssm_autotune.argtypes = [i64, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, i32, ctypes.c_char_p,
+                                  ctypes.POINTER(PlanOptions), ctypes.POINTER(ctypes.c_double), vp]
+    L.gp_ssm_autotune_candidates.argtypes = [ctypes.POINTER(i64), i32]
     L.gp_ssm_profile_enable.argtypes = [i32]
     L.gp_ssm_profile_read.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(i64),
                                       ctypes.POINTER(ctypes.c_double), i32]
@@ -88,7 +92,8 @@ def library():
                  "gp_ssm_plan_loglik_grad",
                  "gp_ssm_plan_smooth", "gp_ssm_plan_smooth_terms", "gp_ssm_plan_plain_loglik", "gp_ssm_loglik",
                  "gp_ssm_loglik_grad",
-                 "gp_ssm_smooth", "gp_ssm_profile_enable", "gp_ssm_profile_reset", "gp_ssm_profile_read"):
+                 "gp_ssm_smooth", "gp_ssm_autotune", "gp_ssm_autotune_candidates", "gp_ssm_profile_enable",
+                 "gp_ssm_profile_reset", "gp_ssm_profile_read"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -356,6 +361,37 @@ def loglik_autograd(plan, sigma, omega0, quality, jitter=None):
     if _LL is None:
         _LL = _autograd_function()
     return _LL.apply(sigma, omega0, quality, jitter, plan)
+
+
+def autotune_candidates():
+    """The target chunk counts the autotuner tries."""
+    n = library().gp_ssm_autotune_candidates(None, 0)
+    buf = (ctypes.c_int64 * n)()
+    library().gp_ssm_autotune_candidates(buf, n)
+    return list(buf)
+
+
+def default_cache_path():
+    """Where the autotuner's choices are kept unless told otherwise."""
+    base = os.environ.get("XDG_CACHE_HOME") or os.path.join(os.path.expanduser("~"), ".cache")
+    return os.path.join(base, "gp_ssm", "autotune.txt")
+
+
+def autotune(offsets, t_start, t_end, y, yerr, sigma, omega0, quality, jitter=None, grad=True, cache=None):
+    """gp_ssm_autotune: plan options (a dict for Plan(**options)) with the
+    fastest target chunk count for this workload, and its time per call in
+    ms.  cache: a file path, False for none, or None for default_cache_path()."""
+    B, M, off, (ts, te, yy, ye), s, w, q, j = _one_shot_inputs(offsets, t_start, t_end, y, yerr, sigma, omega0,
+                                                               quality, jitter)
+    if cache is None:
+        cache = default_cache_path()
+        os.makedirs(os.path.dirname(cache), exist_ok=True)
+    best = PlanOptions()
+    ms = ctypes.c_double()
+    _check(library().gp_ssm_autotune(B, _ptr(off), _ptr(ts), _ptr(te), _ptr(yy), _ptr(ye), M, _ptr(s), _ptr(w),
+                                     _ptr(q), _ptr(j), 1 if grad else 0, cache.encode() if cache else None,
+                                     ctypes.byref(best), ctypes.byref(ms), _stream()))
+    return {f: getattr(best, f) for f, _ in PlanOptions._fields_}, ms.value
 
 
 def profile_enable(on=True):

@@ -1160,6 +1160,139 @@ static int one_shot_plan(int64_t n_series, const int64_t* offsets, const double*
   return gp_ssm_plan_create(n_series, offsets, t_start, t_end, y, yerr, nullptr, stream, pl);
 }
 
+// ---------------------------------------------------------------------------
+// autotuner: the chunk length (hence the lanes each series gets: its events
+// over the chunk length, one lane per chunk, 64 lanes to a work wave) is
+// picked by timing one call per candidate target chunk count
+// ---------------------------------------------------------------------------
+static const int64_t TUNE_CANDIDATES[] = {16384, 32768, 65536, 131072, 262144, 524288};
+constexpr int N_TUNE = (int)(sizeof(TUNE_CANDIDATES) / sizeof(TUNE_CANDIDATES[0]));
+
+static std::string tune_key(const gp_ssm_plan* pl, int32_t M, int32_t what) {
+  hipDeviceProp_t prop;
+  std::string arch = "gpu";
+  if (hipGetDeviceProperties(&prop, pl->device) == hipSuccess) arch = prop.gcnArchName;
+  else (void)hipGetLastError();
+  // the workload's shape: series, measurements and events rounded to two
+  // significant digits, overlap depth, terms, kind of call, device
+  auto r2 = [](int64_t v) {
+    if (v < 100) return v;
+    int64_t p = 1;
+    while (v / p >= 100) p *= 10;
+    return (v / p) * p;
+  };
+  return "B=" + std::to_string(r2(pl->host.n_series)) + ",N=" + std::to_string(r2(pl->host.n_meas)) +
+         ",E=" + std::to_string(r2(pl->host.n_events)) + ",J=" + std::to_string(pl->host.max_slots) +
+         ",M=" + std::to_string(M) + ",kind=" + std::to_string(what) + ",arch=" + arch;
+}
+
+int gp_ssm_autotune_candidates(int64_t* target_chunks, int32_t cap) {
+  for (int i = 0; i < N_TUNE && i < cap; ++i)
+    if (target_chunks) target_chunks[i] = TUNE_CANDIDATES[i];
+  return N_TUNE;
+}
+
+int gp_ssm_autotune(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end,
+                    const double* y, const double* yerr, int32_t n_terms, const double* sigma, const double* omega0,
+                    const double* quality, const double* jitter, int32_t what, const char* cache_path,
+                    gp_ssm_plan_options* best, double* best_ms, void* stream) {
+  g_err.clear();
+  if (!best) return fail(GP_SSM_EINVAL, "null output");
+  if (what != 0 && what != 1) return fail(GP_SSM_EINVAL, "what must be 0 (log-likelihood) or 1 (with gradient)");
+  gp_ssm_plan_default_options(best);
+  if (best_ms) *best_ms = -1.0;
+  hipStream_t s = (hipStream_t)stream;
+  if (const char* e = std::getenv("GP_SSM_TARGET_CHUNKS")) {
+    const long long v = std::atoll(e);
+    if (v > 0) {
+      best->target_chunks = v;
+      return 0;
+    }
+  }
+  const int64_t B = n_series;
+  double* tmp = nullptr;  // log-likelihood, gradient and status of the timing calls
+  const size_t tmp_bytes = sizeof(double) * B * (1 + 3 * (size_t)std::max(1, n_terms) + 1) + sizeof(int32_t) * B;
+  std::string key;
+  int rc = 0;
+  double best_t = 1e300;
+  for (int i = 0; i < N_TUNE && rc == 0; ++i) {
+    gp_ssm_plan_options o;
+    gp_ssm_plan_default_options(&o);
+    o.target_chunks = TUNE_CANDIDATES[i];
+    gp_ssm_plan* pl = nullptr;
+    if ((rc = gp_ssm_plan_create(n_series, offsets, t_start, t_end, y, yerr, &o, stream, &pl))) break;
+    if (i == 0) {
+      key = tune_key(pl, n_terms, what);
+      // a stored choice for this shape of workload
+      if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "r")) {
+          char line[1024];
+          long long tc = 0;
+          double ms = -1.0;
+          while (std::fgets(line, sizeof line, f)) {
+            char k[900];
+            long long v;
+            double t;
+            if (std::sscanf(line, "%899s %lld %lf", k, &v, &t) == 3 && key == k) {
+              tc = v;
+              ms = t;
+            }
+          }
+          std::fclose(f);
+          if (tc > 0) {
+            gp_ssm_plan_destroy(pl);
+            best->target_chunks = tc;
+            if (best_ms) *best_ms = ms;
+            return 0;
+          }
+        }
+      }
+      if (hipMalloc((void**)&tmp, tmp_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        gp_ssm_plan_destroy(pl);
+        return fail(GP_SSM_ENOMEM, "autotune: hipMalloc failed");
+      }
+    }
+    double* ll = tmp;
+    double* gr = tmp + B;
+    int32_t* st = (int32_t*)(tmp + B * (1 + 3 * (size_t)n_terms + 1));
+    auto call = [&]() {
+      return what ? gp_ssm_plan_loglik_grad(pl, n_terms, sigma, omega0, quality, jitter, ll, gr, st, stream)
+                  : gp_ssm_plan_loglik(pl, n_terms, sigma, omega0, quality, jitter, ll, st, stream);
+    };
+    hipEvent_t a = nullptr, b = nullptr;
+    if ((rc = call()) == 0 && (rc = call()) == 0) {  // the first call captures the step
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        rc = fail(GP_SSM_EDEVICE, "autotune: hipEventCreate failed");
+      } else {
+        (void)hipEventRecord(a, s);
+        for (int k = 0; k < 3 && rc == 0; ++k) rc = call();
+        (void)hipEventRecord(b, s);
+        (void)hipEventSynchronize(b);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        if (rc == 0 && ms / 3.0 < best_t) {
+          best_t = ms / 3.0;
+          best->target_chunks = TUNE_CANDIDATES[i];
+        }
+      }
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    gp_ssm_plan_destroy(pl);
+  }
+  if (tmp) (void)hipFree(tmp);
+  if (rc) return rc;
+  if (best_ms) *best_ms = best_t;
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "a")) {
+      std::fprintf(f, "%s %lld %.6f\n", key.c_str(), (long long)best->target_chunks, best_t);
+      std::fclose(f);
+    }
+  }
+  return 0;
+}
+
 int gp_ssm_loglik(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end, const double* y,
                   const double* yerr, int32_t n_terms, const double* sigma, const double* omega0, const double* quality,
                   const double* jitter, double* loglik, int32_t* status, void* stream) {
