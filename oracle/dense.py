@@ -33,24 +33,36 @@ _XG, _WG = leggauss(_NG)
 _LOG2PI = np.log(2 * np.pi)
 
 
-def _rate(omega0, quality):
+def _is_real(kinds, m):
+    return kinds is not None and kinds[m] in ("real", 1)
+
+
+def _rate(omega0, quality, kinds=None):
     omega0 = np.atleast_1d(omega0)
     quality = np.atleast_1d(quality)
-    return float(np.max(omega0 * (1 + 1 / quality)))
+    return float(max(omega0[m] * (1.0 if _is_real(kinds, m) else 1 + 1 / quality[m]) for m in range(len(omega0))))
 
 
-def _kern_sum(u, sigma, omega0, quality, which=None, dtheta=None):
+def _kern_sum(u, sigma, omega0, quality, which=None, dtheta=None, kinds=None):
     """sum_m k_m(|u|), or with which=(m, name) the derivative of term m with
-    respect to sigma, omega0 or Q."""
+    respect to sigma, omega0 or Q.  kinds: per term 'sho' (default) or 'real'
+    (sigma^2 exp(-omega0 |u|), Appendix A with b = d = 0; Q unused)."""
     sigma = np.atleast_1d(sigma)
     omega0 = np.atleast_1d(omega0)
     quality = np.atleast_1d(quality)
     if which is None:
         out = 0.0
         for m in range(len(sigma)):
-            out = out + sho.kernel(u, sigma[m], omega0[m], quality[m])
+            if _is_real(kinds, m):
+                out = out + sho.real_kernel(u, sigma[m], omega0[m])
+            else:
+                out = out + sho.kernel(u, sigma[m], omega0[m], quality[m])
         return out
     m, name = which
+    if _is_real(kinds, m):
+        if name == "quality":
+            return np.zeros_like(np.asarray(u, dtype=np.float64))
+        return sho.real_kernel_grad(u, sigma[m], omega0[m])[{"sigma": 0, "omega0": 1}[name]]
     if name == "sigma":
         return 2.0 / sigma[m] * sho.kernel(u, sigma[m], omega0[m], quality[m])
     g = sho.kernel_grad(u, sigma[m], omega0[m], quality[m])
@@ -117,16 +129,16 @@ def _pair_block(tsi, tei, tsj, tej, kfun, rate):
     return out
 
 
-def covariance(ts, te, sigma, omega0, quality, which=None, block=256):
+def covariance(ts, te, sigma, omega0, quality, which=None, block=256, kinds=None):
     """Dense integrated covariance matrix (or its derivative, see
     ``_kern_sum``)."""
     ts = np.asarray(ts, dtype=np.float64)
     te = np.asarray(te, dtype=np.float64)
     n = len(ts)
-    rate = _rate(omega0, quality)
+    rate = _rate(omega0, quality, kinds)
 
     def kfun(u):
-        return _kern_sum(u, sigma, omega0, quality, which)
+        return _kern_sum(u, sigma, omega0, quality, which, kinds=kinds)
 
     K = np.zeros((n, n))
     for r0 in range(0, n, block):
@@ -135,15 +147,15 @@ def covariance(ts, te, sigma, omega0, quality, which=None, block=256):
     return 0.5 * (K + K.T)
 
 
-def cross_covariance(t_test, ts, te, sigma, omega0, quality, block=256):
+def cross_covariance(t_test, ts, te, sigma, omega0, quality, block=256, kinds=None):
     """K_*: covariance between the latent f(t*) and each exposure average."""
     t_test = np.asarray(t_test, dtype=np.float64)
     ts = np.asarray(ts, dtype=np.float64)
     te = np.asarray(te, dtype=np.float64)
-    rate = _rate(omega0, quality)
+    rate = _rate(omega0, quality, kinds)
 
     def kfun(u):
-        return _kern_sum(u, sigma, omega0, quality)
+        return _kern_sum(u, sigma, omega0, quality, kinds=kinds)
 
     out = np.zeros((len(ts), len(t_test)))
     for r0 in range(0, len(ts), block):
@@ -153,9 +165,9 @@ def cross_covariance(t_test, ts, te, sigma, omega0, quality, block=256):
     return out
 
 
-def loglik(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, K=None):
+def loglik(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, K=None, kinds=None):
     if K is None:
-        K = covariance(ts, te, sigma, omega0, quality)
+        K = covariance(ts, te, sigma, omega0, quality, kinds=kinds)
     y = np.asarray(y, dtype=np.float64)
     Ky = K + np.diag(np.asarray(yerr) ** 2 + jitter ** 2)
     cf = cho_factor(Ky, lower=True)
@@ -186,10 +198,10 @@ def posterior_terms(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=
     return mean, var, Ks
 
 
-def posterior(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=None):
+def posterior(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=None, kinds=None):
     """(mean_data, var_data, mean_test, var_test): exposure-averaged
     posterior at the data and latent posterior at t_test."""
-    K = covariance(ts, te, sigma, omega0, quality)
+    K = covariance(ts, te, sigma, omega0, quality, kinds=kinds)
     Ky = K + np.diag(np.asarray(yerr) ** 2 + jitter ** 2)
     cf = cho_factor(Ky, lower=True)
     alpha = cho_solve(cf, np.asarray(y, dtype=np.float64))
@@ -197,21 +209,21 @@ def posterior(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=None):
     var_d = np.diag(K) - np.sum(K * cho_solve(cf, K), axis=0)
     if t_test is None:
         return mean_d, var_d, None, None
-    Ks = cross_covariance(t_test, ts, te, sigma, omega0, quality)
+    Ks = cross_covariance(t_test, ts, te, sigma, omega0, quality, kinds=kinds)
     mean_t = Ks.T @ alpha
     k0 = float(np.sum(np.atleast_1d(sigma) ** 2))
     var_t = k0 - np.sum(Ks * cho_solve(cf, Ks), axis=0)
     return mean_d, var_d, mean_t, var_t
 
 
-def loglik_grad(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0):
+def loglik_grad(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, kinds=None):
     """Analytic gradient ordered (d sigma_1..M, d omega0_1..M, d Q_1..M,
     d jitter), together with the log-likelihood."""
     sigma = np.atleast_1d(np.asarray(sigma, dtype=np.float64))
     omega0 = np.atleast_1d(np.asarray(omega0, dtype=np.float64))
     quality = np.atleast_1d(np.asarray(quality, dtype=np.float64))
     M = len(sigma)
-    K = covariance(ts, te, sigma, omega0, quality)
+    K = covariance(ts, te, sigma, omega0, quality, kinds=kinds)
     y = np.asarray(y, dtype=np.float64)
     Ky = K + np.diag(np.asarray(yerr) ** 2 + jitter ** 2)
     cf = cho_factor(Ky, lower=True)
@@ -222,7 +234,7 @@ def loglik_grad(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0):
     g = np.zeros(3 * M + 1)
     for k, name in enumerate(("sigma", "omega0", "quality")):
         for m in range(M):
-            dK = covariance(ts, te, sigma, omega0, quality, which=(m, name))
+            dK = covariance(ts, te, sigma, omega0, quality, which=(m, name), kinds=kinds)
             g[k * M + m] = 0.5 * np.sum(W * dK)
     g[3 * M] = 0.5 * np.trace(W) * 2 * jitter
     return L, g

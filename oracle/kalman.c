@@ -20,6 +20,8 @@
  *     integral of the augmented matrices, Sec. 3.2 (augmented SDE, augmented
  *     transition and augmented process noise)
  *   - sums of terms as block-diagonal models ........ Appendix C.1
+ *   - the real (exponential) term, the celerite term
+ *     with b = d = 0, as a one-state model .......... Appendix A
  *   - one integrator per instrument label ........... Sec. 3.2.3
  *   - reset at exposure starts, update at ends ...... Sec. 3.2.1
  *   - log-likelihood from innovations ............... Sec. 2.4
@@ -78,12 +80,21 @@ static void mul3(const ld a[3][3], const ld b[3][3], ld c[3][3]) {
   memcpy(c, t, sizeof(t));
 }
 
+enum { TERM_SHO = 0, TERM_REAL = 1 };
+
 /* Transition and process noise of the augmented single-term model
- * (x, xdot, z) over a step dt, in unscaled coordinates. */
-static void term_discretise(ld w0, ld quality, ld sigma, ld dt, ld phi[3][3], ld q[3][3]) {
-  /* scaled feedback matrix: d/ds (x, y, u) = (y, -x - y/Q, x) + noise on y */
-  const ld F[3][3] = {{0, 1, 0}, {-1, -1 / quality, 0}, {1, 0, 0}};
-  const ld nrm = 1 + 1 / quality; /* infinity norm of F */
+ * (x, xdot, z) over a step dt, in unscaled coordinates.  A real term
+ * k = sigma^2 exp(-w0 |tau|) is the one-state model dx = -w0 x dt + noise with
+ * its integrator; its second state (the "xdot" slot) is unused and stays 0. */
+static void term_discretise(ld w0, ld quality, ld sigma, ld dt, int kind, ld phi[3][3], ld q[3][3]) {
+  const int real = kind == TERM_REAL;
+  /* scaled feedback matrix (time s = w0 t): SHO d/ds (x, y, u) = (y, -x - y/Q, x)
+   * with noise on y; real term d/ds (x, y, u) = (-x, 0, x) with noise on x */
+  const ld F_sho[3][3] = {{0, 1, 0}, {-1, real ? 0 : -1 / quality, 0}, {1, 0, 0}};
+  const ld F_real[3][3] = {{-1, 0, 0}, {0, 0, 0}, {1, 0, 0}};
+  ld F[3][3];
+  memcpy(F, real ? F_real : F_sho, sizeof(F));
+  const ld nrm = real ? 1 : 1 + 1 / quality; /* infinity norm of F */
   ld h = w0 * dt;
   int nsq = 0;
   while (h * nrm > 0.25L) {
@@ -102,8 +113,13 @@ static void term_discretise(ld w0, ld quality, ld sigma, ld dt, ld phi[3][3], ld
         P[i][j] += term[i][j];
       }
   }
-  /* integral_0^h exp(Fs) B exp(F^T s) ds with B = e_y e_y^T (unit noise) */
-  ld T[3][3] = {{0, 0, 0}, {0, 1, 0}, {0, 0, 0}};
+  /* integral_0^h exp(Fs) B exp(F^T s) ds with B = e_y e_y^T (SHO) or
+   * e_x e_x^T (real term), unit noise */
+  ld T[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  if (real)
+    T[0][0] = 1;
+  else
+    T[1][1] = 1;
   ld coef = h;
   ld Qs[3][3];
   for (int i = 0; i < 3; ++i)
@@ -138,10 +154,11 @@ static void term_discretise(ld w0, ld quality, ld sigma, ld dt, ld phi[3][3], ld
       for (int j = 0; j < 3; ++j) Qs[i][j] += PQPt[i][j];
     mul3(P, P, P);
   }
-  /* scaled noise density 2 sigma^2 / Q; unscale (x, xdot, z) = T (x, y, u),
-   * T = diag(1, w0, 1/w0) */
-  const ld qhat = 2 * sigma * sigma / quality;
-  const ld Tsc[3] = {1, w0, 1 / w0};
+  /* scaled noise density 2 sigma^2 / Q (SHO) or 2 sigma^2 (real term);
+   * unscale (x, xdot, z) = T (x, y, u), T = diag(1, w0, 1/w0) (SHO) or
+   * diag(1, 1, 1/w0) (real term) */
+  const ld qhat = real ? 2 * sigma * sigma : 2 * sigma * sigma / quality;
+  const ld Tsc[3] = {1, real ? 1 : w0, 1 / w0};
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
       phi[i][j] = Tsc[i] * P[i][j] / Tsc[j];
@@ -152,7 +169,7 @@ static void term_discretise(ld w0, ld quality, ld sigma, ld dt, ld phi[3][3], ld
 int oracle_term_discretise(double omega0, double quality, double sigma, double dt, double* phi9, double* q9) {
   if (!(omega0 > 0) || !(quality > 0) || !(sigma > 0) || !(dt >= 0)) return OR_EPARAM;
   ld phi[3][3], q[3][3];
-  term_discretise(omega0, quality, sigma, dt, phi, q);
+  term_discretise(omega0, quality, sigma, dt, TERM_SHO, phi, q);
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
       phi9[3 * i + j] = (double)phi[i][j];
@@ -168,6 +185,7 @@ int oracle_term_discretise(double omega0, double quality, double sigma, double d
 typedef struct {
   int M, J, D;
   ld sigma[OR_MAXM], w0[OR_MAXM], qual[OR_MAXM];
+  int kind[OR_MAXM];
 } model_t;
 
 /* Augmented transition A and noise Qa over dt: terms stacked block-diagonally,
@@ -184,7 +202,7 @@ static void assemble(const model_t* md, ld dt, ld A[OR_MAXD][OR_MAXD], ld Qa[OR_
   ld q22 = 0;
   for (int m = 0; m < M; ++m) {
     ld phi[3][3], q[3][3];
-    term_discretise(md->w0[m], md->qual[m], md->sigma[m], dt, phi, q);
+    term_discretise(md->w0[m], md->qual[m], md->sigma[m], dt, md->kind[m], phi, q);
     const int a = 2 * m;
     for (int r = 0; r < 2; ++r)
       for (int c = 0; c < 2; ++c) {
@@ -331,12 +349,15 @@ typedef struct {
 } state_t;
 
 static int check_inputs(int64_t n, const double* ts, const double* te, const double* y, const double* yerr, int32_t M,
-                        const double* sigma, const double* omega0, const double* quality, double jitter) {
+                        const double* sigma, const double* omega0, const double* quality, const int32_t* kind,
+                        double jitter) {
   if (n < 1 || M < 1 || M > OR_MAXM) return OR_EINVAL;
-  for (int m = 0; m < M; ++m)
-    if (!(sigma[m] > 0) || !(omega0[m] > 0) || !(quality[m] > 0) || !isfinite(sigma[m]) || !isfinite(omega0[m]) ||
-        !isfinite(quality[m]))
-      return OR_EPARAM;
+  for (int m = 0; m < M; ++m) {
+    const int real = kind && kind[m] == TERM_REAL;
+    if (kind && kind[m] != TERM_SHO && kind[m] != TERM_REAL) return OR_EINVAL;
+    if (!(sigma[m] > 0) || !(omega0[m] > 0) || !isfinite(sigma[m]) || !isfinite(omega0[m])) return OR_EPARAM;
+    if (!real && (!(quality[m] > 0) || !isfinite(quality[m]))) return OR_EPARAM;
+  }
   if (!(jitter >= 0) || !isfinite(jitter)) return OR_EPARAM;
   for (int64_t i = 0; i < n; ++i) {
     if (!isfinite(ts[i]) || !isfinite(te[i]) || !isfinite(y[i]) || !isfinite(yerr[i])) return OR_EDATA;
@@ -354,7 +375,7 @@ static int run_filter(const model_t* md, int64_t n_ev, const ev_t* ev, const dou
   memset(&s, 0, sizeof(s));
   for (int m = 0; m < M; ++m) {
     s.P[2 * m][2 * m] = md->sigma[m] * md->sigma[m];
-    s.P[2 * m + 1][2 * m + 1] = md->sigma[m] * md->sigma[m] * md->w0[m] * md->w0[m];
+    s.P[2 * m + 1][2 * m + 1] = md->kind[m] == TERM_REAL ? 0 : md->sigma[m] * md->sigma[m] * md->w0[m] * md->w0[m];
   }
   for (int j = 0; j < md->J; ++j) s.P[2 * M + j][2 * M + j] = 1;
   ld L = 0;
@@ -399,9 +420,9 @@ static int run_filter(const model_t* md, int64_t n_ev, const ev_t* ev, const dou
 }
 
 static int setup(int64_t n, const double* ts, const double* te, const double* y, const double* yerr, const int32_t* slot_in,
-                 int32_t M, const double* sigma, const double* omega0, const double* quality, double jitter, model_t* md,
-                 ev_t** ev, int64_t* n_ev, int32_t** slot_out) {
-  int rc = check_inputs(n, ts, te, y, yerr, M, sigma, omega0, quality, jitter);
+                 int32_t M, const double* sigma, const double* omega0, const double* quality, const int32_t* kind,
+                 double jitter, model_t* md, ev_t** ev, int64_t* n_ev, int32_t** slot_out) {
+  int rc = check_inputs(n, ts, te, y, yerr, M, sigma, omega0, quality, kind, jitter);
   if (rc) return rc;
   int32_t* slot = (int32_t*)malloc(sizeof(int32_t) * n);
   if (!slot) return OR_ENOMEM;
@@ -429,6 +450,7 @@ static int setup(int64_t n, const double* ts, const double* te, const double* y,
     md->sigma[m] = sigma[m];
     md->w0[m] = omega0[m];
     md->qual[m] = quality[m];
+    md->kind[m] = kind ? kind[m] : TERM_SHO;
   }
   rc = build_events(n, ts, te, slot, ev, n_ev);
   if (rc) {
@@ -457,13 +479,14 @@ static int setup(int64_t n, const double* ts, const double* te, const double* y,
 }
 
 int oracle_loglik(int64_t n, const double* ts, const double* te, const double* y, const double* yerr, const int32_t* slot_in,
-                  int32_t M, const double* sigma, const double* omega0, const double* quality, double jitter, int32_t extra_slots,
+                  int32_t M, const double* sigma, const double* omega0, const double* quality, const int32_t* kind,
+                  double jitter, int32_t extra_slots,
                   double* out_hilo) {
   model_t md;
   ev_t* ev = NULL;
   int64_t n_ev = 0;
   int32_t* slot = NULL;
-  int rc = setup(n, ts, te, y, yerr, slot_in, M, sigma, omega0, quality, jitter, &md, &ev, &n_ev, &slot);
+  int rc = setup(n, ts, te, y, yerr, slot_in, M, sigma, omega0, quality, kind, jitter, &md, &ev, &n_ev, &slot);
   if (rc) return rc;
   if (extra_slots > 0) {
     md.J += extra_slots;
@@ -588,14 +611,15 @@ static void latent_terms(const model_t* md, const state_t* s, int64_t q, double*
 }
 
 int oracle_smooth(int64_t n, const double* ts, const double* te, const double* y, const double* yerr, const int32_t* slot_in,
-                  int32_t M, const double* sigma, const double* omega0, const double* quality, double jitter, int64_t n_test,
+                  int32_t M, const double* sigma, const double* omega0, const double* quality, const int32_t* kind,
+                  double jitter, int64_t n_test,
                   const double* t_test, double* mean_test, double* var_test, double* mean_data, double* var_data,
                   double* term_mean, double* term_var, double* out_hilo) {
   model_t md;
   ev_t* ev = NULL;
   int64_t K = 0;
   int32_t* slot = NULL;
-  int rc = setup(n, ts, te, y, yerr, slot_in, M, sigma, omega0, quality, jitter, &md, &ev, &K, &slot);
+  int rc = setup(n, ts, te, y, yerr, slot_in, M, sigma, omega0, quality, kind, jitter, &md, &ev, &K, &slot);
   if (rc) return rc;
   const int D = md.D;
   state_t* pred = (state_t*)malloc(sizeof(state_t) * K);
@@ -662,7 +686,7 @@ int oracle_smooth(int64_t n, const double* ts, const double* te, const double* y
         }
       for (int m = 0; m < md.M; ++m) {
         Pinf[2 * m][2 * m] = md.sigma[m] * md.sigma[m];
-        Pinf[2 * m + 1][2 * m + 1] = md.sigma[m] * md.sigma[m] * md.w0[m] * md.w0[m];
+        Pinf[2 * m + 1][2 * m + 1] = md.kind[m] == TERM_REAL ? 0 : md.sigma[m] * md.sigma[m] * md.w0[m] * md.w0[m];
       }
       rc = rts_gain(D, Pinf, Ax, Pinf, Gx);
       if (rc) goto done;

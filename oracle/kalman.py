@@ -43,10 +43,10 @@ def lib():
             L.oracle_term_discretise.restype = ctypes.c_int
             L.oracle_greedy_slots.argtypes = [ctypes.c_int64, _dp, _dp, _ip, _ip]
             L.oracle_greedy_slots.restype = ctypes.c_int
-            L.oracle_loglik.argtypes = [ctypes.c_int64, _dp, _dp, _dp, _dp, _ip, ctypes.c_int32, _dp, _dp, _dp,
+            L.oracle_loglik.argtypes = [ctypes.c_int64, _dp, _dp, _dp, _dp, _ip, ctypes.c_int32, _dp, _dp, _dp, _ip,
                                         ctypes.c_double, ctypes.c_int32, _dp]
             L.oracle_loglik.restype = ctypes.c_int
-            L.oracle_smooth.argtypes = [ctypes.c_int64, _dp, _dp, _dp, _dp, _ip, ctypes.c_int32, _dp, _dp, _dp,
+            L.oracle_smooth.argtypes = [ctypes.c_int64, _dp, _dp, _dp, _dp, _ip, ctypes.c_int32, _dp, _dp, _dp, _ip,
                                         ctypes.c_double, ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
             L.oracle_smooth.restype = ctypes.c_int
             _lib = L
@@ -86,6 +86,19 @@ def greedy_slots(ts, te):
     return slot, int(nj[0])
 
 
+KINDS = {"sho": 0, "real": 1}
+
+
+def _kinds(kinds, M):
+    """Term kinds as an int32 array (0: SHO, 1: real exponential term), or
+    (None, None) for all SHO."""
+    if kinds is None:
+        return None, None
+    k = np.ascontiguousarray([KINDS.get(v, v) for v in kinds], dtype=np.int32)
+    assert len(k) == M
+    return k, k.ctypes.data_as(_ip)
+
+
 def _prep(ts, te, y, yerr, sigma, omega0, quality, slots):
     arrs = [_d(a) for a in (ts, te, y, yerr)]
     terms = [_d(np.atleast_1d(a)) for a in (sigma, omega0, quality)]
@@ -97,24 +110,26 @@ def _prep(ts, te, y, yerr, sigma, omega0, quality, slots):
     return arrs, terms, sl, slp
 
 
-def loglik_hilo(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, slots=None, extra_slots=0):
-    """Log-likelihood as a (hi, lo) double-double pair."""
+def loglik_hilo(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, slots=None, extra_slots=0, kinds=None):
+    """Log-likelihood as a (hi, lo) double-double pair.  kinds: per term
+    'sho' (default) or 'real' (sigma^2 exp(-omega0 |tau|), quality unused)."""
     arrs, terms, sl, slp = _prep(ts, te, y, yerr, sigma, omega0, quality, slots)
     out = np.zeros(2)
     M = len(terms[0][0])
+    kd, kp = _kinds(kinds, M)
     rc = lib().oracle_loglik(len(arrs[0][0]), arrs[0][1], arrs[1][1], arrs[2][1], arrs[3][1], slp, M, terms[0][1],
-                             terms[1][1], terms[2][1], float(jitter), int(extra_slots), _d(out)[1])
+                             terms[1][1], terms[2][1], kp, float(jitter), int(extra_slots), _d(out)[1])
     if rc:
         raise OracleError(rc)
     return float(out[0]), float(out[1])
 
 
-def loglik(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, slots=None, extra_slots=0):
-    hi, lo = loglik_hilo(ts, te, y, yerr, sigma, omega0, quality, jitter, slots, extra_slots)
+def loglik(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, slots=None, extra_slots=0, kinds=None):
+    hi, lo = loglik_hilo(ts, te, y, yerr, sigma, omega0, quality, jitter, slots, extra_slots, kinds)
     return hi + lo
 
 
-def smooth(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=None, slots=None, terms=False):
+def smooth(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=None, slots=None, terms=False, kinds=None):
     """Returns (loglik, mean_test, var_test, mean_data, var_data), and with
     terms=True also the per-term latent posterior at t_test (term_mean,
     term_var, each [n_test, M]: H^m applied to the smoothed state, Appendix
@@ -131,8 +146,9 @@ def smooth(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=None, slo
     M = len(terms[0][0])
     tm = np.zeros((len(tt), M))
     tv = np.zeros((len(tt), M))
+    kd, kp = _kinds(kinds, M)
     rc = lib().oracle_smooth(n, arrs[0][1], arrs[1][1], arrs[2][1], arrs[3][1], slp, M, terms[0][1], terms[1][1],
-                             terms[2][1], float(jitter), len(tt), _d(tt)[1], _d(mt)[1], _d(vt)[1], _d(md)[1], _d(vd)[1],
+                             terms[2][1], kp, float(jitter), len(tt), _d(tt)[1], _d(mt)[1], _d(vt)[1], _d(md)[1], _d(vd)[1],
                              _d(tm)[1] if want_terms else None, _d(tv)[1] if want_terms else None, _d(out)[1])
     if rc:
         raise OracleError(rc)
@@ -141,7 +157,7 @@ def smooth(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=None, slo
     return out[0] + out[1], mt, vt, md, vd
 
 
-def loglik_grad_fd(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, rel_step=1e-6, slots=None):
+def loglik_grad_fd(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, rel_step=1e-6, slots=None, kinds=None):
     """Central finite differences of the log-likelihood with relative steps
     h_i = rel_step * |theta_i| in the natural parameters.  Returns the
     gradient ordered (d sigma_1..M, d omega0_1..M, d Q_1..M, d jitter).
@@ -154,7 +170,7 @@ def loglik_grad_fd(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, rel_step
     g = np.zeros_like(theta)
 
     def L(th):
-        hi, lo = loglik_hilo(ts, te, y, yerr, th[:M], th[M:2 * M], th[2 * M:3 * M], th[3 * M], slots)
+        hi, lo = loglik_hilo(ts, te, y, yerr, th[:M], th[M:2 * M], th[2 * M:3 * M], th[3 * M], slots, kinds=kinds)
         return hi, lo
 
     for i in range(len(theta)):

@@ -111,6 +111,18 @@ def kernel_grad(tau, sigma, omega0, quality):
     return d_sigma, d_omega0, d_quality
 
 
+def real_kernel(tau, sigma, c):
+    """Real (exponential) term, the celerite term of Appendix A with
+    b = d = 0: sigma^2 exp(-c |tau|)."""
+    return sigma * sigma * np.exp(-c * np.abs(tau))
+
+
+def real_kernel_grad(tau, sigma, c):
+    """Partial derivatives of ``real_kernel`` with respect to (sigma, c)."""
+    k = real_kernel(tau, sigma, c)
+    return 2 * k / sigma, -np.abs(tau) * k
+
+
 def psd(omega, sigma, omega0, quality):
     """Power spectral density of the SHO (Appendix B, PSD) with
     S0 = sigma^2 / (omega0 Q)."""

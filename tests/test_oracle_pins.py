@@ -530,3 +530,97 @@ def test_greedy_labels_use_overlap_depth_and_never_self_overlap():
             sel = np.where(slots == j)[0]
             order = sel[np.argsort(ts[sel])]
             assert np.all(te[order[:-1]] <= ts[order[1:]])
+
+
+# ---------------------------------------------------------------------------
+# real (exponential) terms: the celerite term of Appendix A with b = d = 0,
+# sigma^2 exp(-c |tau|), a one-state model; and the Matern-3/2 kernel as the
+# SHO term at Q = 1/2
+# ---------------------------------------------------------------------------
+
+def test_dense_real_term_matches_appendix_a():
+    s, c = 0.8, 2.3
+    delta = 0.4
+    mids = np.array([0.0, 0.13, 0.4, 0.9, 2.5])
+    K = dense.covariance(mids - delta / 2, mids + delta / 2, [s], [c], [1.0], kinds=["real"])
+    for i in range(len(mids)):
+        for j in range(len(mids)):
+            ref = _celerite_integrated(s * s, 0.0, c, 0.0, delta, abs(mids[i] - mids[j]))
+            assert abs(K[i, j] - ref) < 1e-14 * s * s, (i, j)
+
+
+def test_real_term_single_exposure_closed_form():
+    """N = 1 with a real term: K11 from Appendix A at b = d = 0."""
+    s, c = 1.3, 0.7
+    delta, y, r = 0.9, -0.21, 0.03
+    K11 = _celerite_integrated(s * s, 0.0, c, 0.0, delta, 0.0)
+    ref = -0.5 * (math.log(2 * math.pi * (K11 + r)) + y * y / (K11 + r))
+    L = kalman.loglik([2.0], [2.0 + delta], [y], [math.sqrt(r)], [s], [c], [0.0], kinds=["real"])
+    assert abs(L - ref) < 1e-14
+
+
+def test_real_term_instantaneous_ar1():
+    """Noiseless instantaneous samples of one real term: the textbook AR(1)
+    likelihood, x_k | x_{k-1} ~ N(rho_k x_{k-1}, s^2 (1 - rho_k^2)),
+    rho_k = exp(-c dt_k), x_1 ~ N(0, s^2)."""
+    rng = np.random.default_rng(11)
+    t = np.sort(rng.uniform(0, 5, 30))
+    x = rng.normal(size=30)
+    s, c = 0.9, 1.7
+    ref = -0.5 * (math.log(2 * math.pi * s * s) + x[0] ** 2 / (s * s))
+    for k in range(1, 30):
+        rho = math.exp(-c * (t[k] - t[k - 1]))
+        v = s * s * (1 - rho * rho)
+        ref += -0.5 * (math.log(2 * math.pi * v) + (x[k] - rho * x[k - 1]) ** 2 / v)
+    L = kalman.loglik(t, t, x, np.zeros(30), [s], [c], [1.0], kinds=["real"])
+    assert abs(L - ref) < 1e-12 * abs(ref)
+
+
+@pytest.mark.parametrize("kinds", [["real"], ["real", "sho"], ["sho", "real", "real"]])
+def test_kalman_equals_dense_with_real_terms(kinds):
+    M = len(kinds)
+    b = W.random_small_batch(40 + M, B=2, n_lo=10, n_hi=35, M=M, J=3)
+    for i in range(b.n_series):
+        s = b.series(i)
+        args = (s["ts"], s["te"], s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"], s["jitter"])
+        Ld = dense.loglik(*args, kinds=kinds)
+        Lk = kalman.loglik(*args, kinds=kinds)
+        assert abs(Ld - Lk) <= 1e-11 * abs(Ld), (kinds, i, Ld, Lk)
+        tt = np.linspace(s["ts"].min() - 0.05, s["te"].max() + 0.05, 11)
+        md, vd, mt, vt = dense.posterior(*args, t_test=tt, kinds=kinds)
+        _, mt2, vt2, md2, vd2 = kalman.smooth(*args, t_test=tt, kinds=kinds)
+        k0 = float(np.sum(np.asarray(s["sigma"]) ** 2))
+        assert np.max(np.abs(md - md2)) < 1e-11 * math.sqrt(k0) and np.max(np.abs(vd - vd2)) < 1e-11 * k0
+        assert np.max(np.abs(mt - mt2)) < 1e-11 * math.sqrt(k0) and np.max(np.abs(vt - vt2)) < 1e-11 * k0
+
+
+def test_dense_gradient_with_real_terms_matches_fd_of_kalman():
+    kinds = ["sho", "real"]
+    b = W.random_small_batch(51, B=1, n_lo=25, n_hi=25, M=2, J=2)
+    s = b.series(0)
+    args = (s["ts"], s["te"], s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"], s["jitter"])
+    _, g = dense.loglik_grad(*args, kinds=kinds)
+    gfd = kalman.loglik_grad_fd(*args, kinds=kinds)
+    assert g[2 * 2 + 1] == 0.0 and gfd[2 * 2 + 1] == 0.0  # Q of the real term
+    den = np.maximum(np.abs(gfd), 1e-3 * np.max(np.abs(gfd)))
+    assert np.max(np.abs(g - gfd) / den) < 1e-6
+
+
+def test_matern32_is_the_sho_term_at_half():
+    """The Matern-3/2 kernel s^2 (1 + sqrt3 u/rho) exp(-sqrt3 u/rho), written
+    out here and integrated over exposures by the same quadrature, equals the
+    SHO term with Q = 1/2 and omega0 = sqrt3/rho."""
+    s, rho = 0.7, 0.35
+    rng = np.random.default_rng(2)
+    ts = np.sort(rng.uniform(0, 2, 12))
+    te = ts + rng.uniform(0, 0.2, 12)
+    te[3] = ts[3]
+    r3 = math.sqrt(3.0) / rho
+
+    def matern(u):
+        a = r3 * np.abs(u)
+        return s * s * (1 + a) * np.exp(-a)
+
+    Km = dense._pair_block(ts[:, None], te[:, None], ts[None, :], te[None, :], matern, r3)
+    Ks = dense.covariance(ts, te, [s], [r3], [0.5])
+    assert np.max(np.abs(Km - Ks)) < 1e-14 * s * s
