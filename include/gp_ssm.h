@@ -65,6 +65,10 @@ extern "C" {
 #define GP_SSM_MAX_TERMS 4
 #define GP_SSM_MAX_SLOTS 4
 
+/* term kinds (gp_ssm_plan_set_term_kinds) */
+#define GP_SSM_TERM_SHO 0  /* stochastically driven damped harmonic oscillator (sigma, omega0, Q) */
+#define GP_SSM_TERM_REAL 1 /* real exponential term sigma^2 exp(-omega0 |tau|); Q unused */
+
 #define GP_SSM_OK 0
 #define GP_SSM_EINVAL (-1)   /* null pointer, B < 1, M out of range, bad offsets */
 #define GP_SSM_EDATA (-2)    /* non-finite data, t_end < t_start, unsorted t_start, yerr < 0 */
@@ -122,6 +126,18 @@ void gp_ssm_plan_default_options(gp_ssm_plan_options* opt);
 int gp_ssm_plan_create(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end,
                        const double* y, const double* yerr, const gp_ssm_plan_options* opt, void* stream,
                        gp_ssm_plan** out);
+
+/* Kinds of the n_terms terms of later calls (kinds: host array, every
+ * series the same; NULL or n_terms = 0: all SHO, the default).  An SHO term
+ * has the kernel of Appendix B (sigma, omega0, Q); with Q = 1/2 it is the
+ * Matern-3/2 kernel sigma^2 (1 + sqrt(3) tau / rho) exp(-sqrt(3) tau / rho)
+ * at omega0 = sqrt(3) / rho.  A real term (GP_SSM_TERM_REAL) has the kernel
+ * sigma^2 exp(-omega0 |tau|), the real celerite term of Appendix A (b = d =
+ * 0) with rate c = omega0, as a one-state process with its integrator: its
+ * quality entries are not read (any value; not validated) and its Q
+ * derivative is 0.  Calls with another number of terms fail with
+ * GP_SSM_EINVAL.  Synchronises the device. */
+int gp_ssm_plan_set_term_kinds(gp_ssm_plan* plan, int32_t n_terms, const int32_t* kinds);
 
 /* Releases the plan and its device memory (and any workspace it grew). */
 void gp_ssm_plan_destroy(gp_ssm_plan* plan);

@@ -22,11 +22,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgp_ssm.so")
 
 GP_SSM_OK = 0
+TERM_SHO, TERM_REAL = 0, 1
+TERM_CODES = {"sho": TERM_SHO, "real": TERM_REAL}
 ERRORS = {-1: "EINVAL", -2: "EDATA", -3: "EPARAM", -4: "EOVERLAP", -5: "ENUMERIC", -6: "EDEVICE", -7: "ENOMEM"}
 
 # every symbol include/gp_ssm.h declares
 EXPORTS = [
-    "gp_ssm_plan_default_options", "gp_ssm_plan_create", "gp_ssm_plan_destroy", "gp_ssm_plan_get_stats",
+    "gp_ssm_plan_default_options", "gp_ssm_plan_create", "gp_ssm_plan_destroy", "gp_ssm_plan_set_term_kinds",
+    "gp_ssm_plan_get_stats",
     "gp_ssm_plan_loglik", "gp_ssm_plan_loglik_noalloc", "gp_ssm_plan_loglik_grad", "gp_ssm_plan_smooth",
     "gp_ssm_plan_smooth_terms",
     "gp_ssm_plan_plain_loglik", "gp_ssm_loglik", "gp_ssm_loglik_grad", "gp_ssm_smooth", "gp_ssm_autotune",
@@ -71,6 +74,7 @@ def library():
     L.gp_ssm_plan_destroy.argtypes = [vp]
     L.gp_ssm_plan_destroy.restype = None
     L.gp_ssm_plan_get_stats.argtypes = [vp, ctypes.POINTER(PlanStats)]
+    L.gp_ssm_plan_set_term_kinds.argtypes = [vp, i32, ctypes.POINTER(i32)]
     L.gp_ssm_plan_loglik.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.gp_ssm_plan_loglik_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.gp_ssm_plan_loglik_grad.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -88,7 +92,7 @@ def library():
                                       ctypes.POINTER(ctypes.c_double), i32]
     L.gp_ssm_last_error.restype = ctypes.c_char_p
     L.gp_ssm_version.restype = ctypes.c_char_p
-    for name in ("gp_ssm_plan_create", "gp_ssm_plan_get_stats", "gp_ssm_plan_loglik", "gp_ssm_plan_loglik_noalloc",
+    for name in ("gp_ssm_plan_create", "gp_ssm_plan_set_term_kinds", "gp_ssm_plan_get_stats", "gp_ssm_plan_loglik", "gp_ssm_plan_loglik_noalloc",
                  "gp_ssm_plan_loglik_grad",
                  "gp_ssm_plan_smooth", "gp_ssm_plan_smooth_terms", "gp_ssm_plan_plain_loglik", "gp_ssm_loglik",
                  "gp_ssm_loglik_grad",
@@ -175,6 +179,16 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def set_term_kinds(self, kinds):
+        """Term kinds of later calls: a sequence of 'sho' / 'real' (or
+        TERM_SHO / TERM_REAL); None for all SHO."""
+        if kinds is None:
+            _check(library().gp_ssm_plan_set_term_kinds(self._h, 0, None))
+            return
+        codes = [TERM_CODES.get(k, k) for k in kinds]
+        arr = (ctypes.c_int32 * len(codes))(*codes)
+        _check(library().gp_ssm_plan_set_term_kinds(self._h, len(codes), arr))
 
     def stats(self):
         s = PlanStats()

@@ -83,13 +83,15 @@ void prof_flush() {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool param_ok(double v) { return v > 0.0 && isfinite(v); }
 
-// hyperparameters of series b valid: sigma, omega0, Q > 0 and finite for every
-// term, jitter >= 0 and finite (or absent)
-__device__ __forceinline__ bool series_params_ok(const CallArgs& a, int64_t b, int M) {
+// hyperparameters of series b valid: sigma, omega0 (the rate of a real
+// term) and Q (SHO terms only) > 0 and finite for every term, jitter >= 0
+// and finite (or absent)
+__device__ __forceinline__ bool series_params_ok(const CallArgs& a, const int32_t* kinds, int64_t b, int M) {
   bool ok = true;
   for (int t = 0; t < M; ++t) {
     const int64_t i = b * M + t;
-    ok = ok && param_ok(a.sigma[i]) && param_ok(a.omega0[i]) && param_ok(a.quality[i]);
+    const bool real = kinds && kinds[t] == GP_SSM_TERM_REAL;
+    ok = ok && param_ok(a.sigma[i]) && param_ok(a.omega0[i]) && (real || param_ok(a.quality[i]));
   }
   if (a.jitter) ok = ok && a.jitter[b] >= 0.0 && isfinite(a.jitter[b]);
   return ok;
@@ -101,21 +103,25 @@ __device__ __forceinline__ bool series_params_ok(const CallArgs& a, int64_t b, i
 // validation is prepared with sigma = omega0 = Q = 1 and jitter 0, so that
 // every kernel runs on finite, in-range values; its outputs are set to NaN
 // and its status to GP_SSM_EPARAM where they are written.
-__global__ void k_prep(int64_t B, int M, const CallArgs* __restrict__ args, TermConst* __restrict__ tc,
-                       double* __restrict__ coef, double* __restrict__ jit, int32_t* __restrict__ bad) {
+__global__ void k_prep(int64_t B, int M, const CallArgs* __restrict__ args, const int32_t* __restrict__ kinds,
+                       TermConst* __restrict__ tc, double* __restrict__ coef, double* __restrict__ jit,
+                       int32_t* __restrict__ bad) {
   const CallArgs a = *args;
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j < B * M * NI) {
     const int64_t i = j / NI;
     const int iv = (int)(j - i * NI);
-    const bool ok = series_params_ok(a, i / M, M);
-    const TermConst t = ok ? make_term(a.sigma[i], a.omega0[i], a.quality[i]) : make_term(1.0, 1.0, 1.0);
+    const bool ok = series_params_ok(a, kinds, i / M, M);
+    const bool real = kinds && kinds[i % M] == GP_SSM_TERM_REAL;
+    const TermConst t = !ok ? make_term(1.0, 1.0, 1.0)
+                            : (real ? make_real_term(a.sigma[i], a.omega0[i])
+                                    : make_term(a.sigma[i], a.omega0[i], a.quality[i]));
     if (iv == 0) tc[i] = t;
     double* c = coef + i * 2 * NCOEF + iv * ISTRIDE;
     series_interval_table(t.beta, interval_centre(iv, t.b1ser, t.wser), c, c + NCOEF);
   }
   if (j < B) {
-    const bool ok = series_params_ok(a, j, M);
+    const bool ok = series_params_ok(a, kinds, j, M);
     jit[j] = (ok && a.jitter) ? a.jitter[j] : 0.0;
     bad[j] = ok ? 0 : 1;
   }
@@ -391,6 +397,7 @@ struct gp_ssm_plan {
   int device = 0;
   int n_cu = 1;
   int64_t record_budget = 0;  // bytes of per-event records before the backward kernels run in rounds
+  int32_t kinds_M = 0;        // number of terms gp_ssm_plan_set_term_kinds described (0: all SHO)
   uint64_t gen = 0;  // workspace generation (see DBuf)
   HostPlan host;
   DBuf dt, t, y, r, invd, info, meas;
@@ -403,7 +410,7 @@ struct gp_ssm_plan {
   DBuf pre, suf, segtot, segstate, segfut, segll, segok;
   DBuf pre2, suf2, grptot, grpstate, grpfut;
   DBuf tests_t, tests_idx, tests_c0, tests_before, prior_idx, prior_series;
-  DBuf wv_order, args;
+  DBuf wv_order, args, kinds;
   // the call's pointers go to `args` on the call's stream from a ring of
   // pinned host slots; an event per slot marks when its copy has been done
   CallArgs* args_host = nullptr;
@@ -421,7 +428,7 @@ struct gp_ssm_plan {
     return {&tc,       &coef,   &jit,     &pbad,      &summ,      &bstate,    &badj,         &bsmooth,
             &gpart,    &rec,    &status,  &llbuf,     &stage,     &pre,       &suf,          &segtot,
             &segstate, &segfut, &segll,   &segok,     &pre2,      &suf2,      &grptot,       &grpstate,
-            &grpfut,   &wv_order, &args,  &tests_t,   &tests_idx, &tests_c0,  &tests_before,
+            &grpfut,   &wv_order, &args,  &kinds,     &tests_t,   &tests_idx, &tests_c0,  &tests_before,
             &prior_idx, &prior_series};
   }
   std::vector<const DBuf*> all_buffers() const {
@@ -529,6 +536,9 @@ int put_args(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omeg
   if (!pl) return fail(GP_SSM_EINVAL, "null plan");
   if (M < 1 || M > GP_SSM_MAX_TERMS) return fail(GP_SSM_EINVAL, "n_terms out of range");
   if (!sigma || !omega0 || !quality) return fail(GP_SSM_EINVAL, "null hyperparameter pointer");
+  if (pl->kinds_M != 0 && pl->kinds_M != M)
+    return fail(GP_SSM_EINVAL, "term kinds were set for " + std::to_string(pl->kinds_M) + " terms, the call has " +
+                                   std::to_string(M));
   const int64_t B = pl->host.n_series;
   if ((loglik && !device_memory(loglik)) || (grad && !device_memory(grad)) || (status && !device_memory(status)))
     return fail(GP_SSM_EINVAL, "output arrays must be device memory");
@@ -730,8 +740,9 @@ void enqueue_prep(gp_ssm_plan* pl, const FwdWork& W, int32_t M, hipStream_t s) {
   DevPlan p = pl->dev();
   p.wv_order = W.order;
   prof_begin("k_prep", s);
-  hipLaunchKernelGGL(k_prep, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0, s, B, M, W.args, W.tc,
-                     W.coef, W.jit, W.bad);
+  const int32_t* kinds = pl->kinds_M == M ? pl->kinds.as<int32_t>() : nullptr;
+  hipLaunchKernelGGL(k_prep, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0, s, B, M, W.args, kinds,
+                     W.tc, W.coef, W.jit, W.bad);
   prof_end("k_prep", s);
   prof_begin("k_order", s);
   hipLaunchKernelGGL(k_order, dim3(1), dim3(ORDER_THREADS), 0, s, p, M, W.tc, pl->series_dt_cdf.as<float>(),
@@ -940,6 +951,23 @@ int gp_ssm_plan_create(int64_t n_series, const int64_t* offsets, const double* t
 
 void gp_ssm_plan_destroy(gp_ssm_plan* plan) { delete plan; }
 
+int gp_ssm_plan_set_term_kinds(gp_ssm_plan* pl, int32_t n_terms, const int32_t* kinds) {
+  g_err.clear();
+  if (!pl) return fail(GP_SSM_EINVAL, "null plan");
+  if (n_terms == 0 || !kinds) {
+    pl->kinds_M = 0;
+    return 0;
+  }
+  if (n_terms < 1 || n_terms > GP_SSM_MAX_TERMS) return fail(GP_SSM_EINVAL, "n_terms out of range");
+  std::vector<int32_t> k(kinds, kinds + n_terms);
+  for (int32_t v : k)
+    if (v != GP_SSM_TERM_SHO && v != GP_SSM_TERM_REAL) return fail(GP_SSM_EINVAL, "unknown term kind");
+  HIP_TRY(hipDeviceSynchronize());  // earlier calls may still read the kinds
+  if (int rc = upload(pl->kinds, k)) return rc;
+  pl->kinds_M = n_terms;
+  return 0;
+}
+
 int gp_ssm_plan_get_stats(const gp_ssm_plan* pl, gp_ssm_plan_stats* out) {
   if (!pl || !out) return fail(GP_SSM_EINVAL, "null pointer");
   out->n_series = pl->host.n_series;
@@ -972,6 +1000,7 @@ int gp_ssm_plan_loglik_noalloc(gp_ssm_plan* pl, int32_t M, const double* sigma, 
   if (!pl) return fail(GP_SSM_EINVAL, "null plan");
   if (M < 1 || M > GP_SSM_MAX_TERMS) return fail(GP_SSM_EINVAL, "n_terms out of range");
   if (!sigma || !omega0 || !quality || !loglik) return fail(GP_SSM_EINVAL, "null pointer");
+  if (pl->kinds_M != 0 && pl->kinds_M != M) return fail(GP_SSM_EINVAL, "term kinds were set for another number of terms");
   for (const void* q : {(const void*)sigma, (const void*)omega0, (const void*)quality, (const void*)jitter,
                         (const void*)loglik, (const void*)status})
     if (q && !device_memory(q)) return fail(GP_SSM_EINVAL, "every array must be device memory");

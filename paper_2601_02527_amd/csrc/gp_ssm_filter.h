@@ -882,6 +882,10 @@ template <int M, class Acc = DiscFull, int TS = NCOEF>
 GPD void discretise(const TermConst* tc, const double* coef, double dt, TermQ* tq) {
 #pragma unroll
   for (int t = 0; t < M; ++t) {
+    if (is_real(tc[t])) {  // wavefront-uniform: the term's kind
+      tq[t] = real_step(tc[t], dt);
+      continue;
+    }
     const double x = tc[t].w0 * dt;
     Base<double> b;
     if (Acc::series(x, tc[t]))
@@ -899,6 +903,12 @@ template <int M, class Acc = DiscFull, class DB>
 GPD void discretise_dual(const TermConst* tc, const double* coef, double dt, DB&& db, TermQ* tq) {
 #pragma unroll
   for (int t = 0; t < M; ++t) {
+    if (is_real(tc[t])) {  // no beta: real_backprop differentiates the step itself
+      tq[t] = real_step(tc[t], dt);
+#pragma unroll
+      for (int f = 0; f < 6; ++f) db[t * 6 + f] = 0.0;
+      continue;
+    }
     const double x = tc[t].w0 * dt;
     Base<Dual> bd;
     if (Acc::series(x, tc[t]))
@@ -1105,7 +1115,10 @@ GPD void adjoint_step(const double* m, const double* P, double* mb, double* Pb, 
       else
         d6[f] = dbr[6 * t + f];
     }
-    term_backprop(tc[t], tq[t], d6, dt, w, acc.s(t), acc.w(t), acc.q(t));
+    if (is_real(tc[t]))
+      real_backprop(tc[t], dt, w, acc.s(t), acc.w(t));
+    else
+      term_backprop(tc[t], tq[t], d6, dt, w, acc.s(t), acc.w(t), acc.q(t));
   }
 
   // adjoint to the state before the predict

@@ -310,6 +310,51 @@ GPD TermConst make_term(double sigma, double w0, double quality) {
   return t;
 }
 
+// A real (exponential) term, k(tau) = sigma^2 exp(-c |tau|) (the real
+// celerite term of Appendix A: b = d = 0), rides in an SHO term's two
+// states: the first is the process (an Ornstein-Uhlenbeck process with rate
+// c, kept in omega0), the second stays at exactly zero (no transition into
+// it, no noise, no prior variance).  It is marked by a negative series switch
+// point (its steps never take the SHO series); the other fields are those of
+// an SHO term with Q = 1, so the tables built for it are valid and unused.
+GPD TermConst make_real_term(double sigma, double c) {
+  TermConst t = make_term(sigma, c, 1.0);  // qhat = 2 sigma^2, inv_w0 = 1/c
+  t.xser = -1.0;
+  t.xser_g = -1.0;
+  return t;
+}
+GPD bool is_real(const TermConst& t) { return t.xser < 0.0; }
+// stationary variance of the term's second state over sigma^2
+GPD double second_prior(const TermConst& t) { return is_real(t) ? 0.0 : 1.0; }
+
+// x - 2 (1 - e^-x) + (1 - e^-2x)/2 (the integrated process's variance over
+// 2 sigma^2 / c^2), by its series below x = 0.5, where the closed form
+// cancels: sum over n >= 3 of (-1)^(n+1) (2^(n-1) - 2) x^n / n!
+GPD double real_gfun(double x, double em1, double e1) {
+  if (x >= 0.5) return x - em1 * (3.0 - e1) * 0.5;
+  double term = x * x * x / 6.0, s = 0.0, p2 = 4.0;  // x^n/n! and 2^(n-1) at n = 3
+#pragma unroll
+  for (int n = 3; n <= 22; ++n) {
+    s += ((n & 1) ? 1.0 : -1.0) * (p2 - 2.0) * term;
+    term *= x / (n + 1);
+    p2 *= 2.0;
+  }
+  return s;
+}
+
+// x e^-x - (1 - e^-x), by its series below x = 0.5: sum over n >= 2 of
+// (-1)^(n-1) (n - 1) x^n / n!
+GPD double real_hfun(double x, double em1, double e1) {
+  if (x >= 0.5) return x * e1 - em1;
+  double term = x * x * 0.5, s = 0.0;
+#pragma unroll
+  for (int n = 2; n <= 21; ++n) {
+    s += ((n & 1) ? 1.0 : -1.0) * (n - 1) * term;
+    term *= x / (n + 1);
+  }
+  return s;
+}
+
 // the series at x truncated after degree K (coef: the term's tables, value
 // part then beta-derivative)
 template <int K = KSER>
@@ -507,6 +552,48 @@ GPD TermQ term_step(const TermConst& t, const Base<double>& b) {
   q.c1 = t.qhat * (b.G1 * b.g - b.Igg) * t.inv_w0;
   q.zz = t.qhat * b.IGG * t.inv_w0 * t.inv_w0;
   return q;
+}
+
+// one step of a real term (state (x, 0) and an integrator): transition e^-x,
+// integrated row (1 - e^-x)/c, noise sigma^2 (1 - e^-2x), cross noise
+// sigma^2 (1 - e^-x)^2 / c, integrator noise 2 sigma^2 g(x) / c^2, x = c dt
+GPD TermQ real_step(const TermConst& t, double dt) {
+  const double x = t.w0 * dt;
+  const double em1 = -expm1(-x), e1 = 1.0 - em1;
+  const double s2 = 0.5 * t.qhat;  // sigma^2
+  TermQ q;
+  q.a00 = e1;
+  q.a01 = 0.0;
+  q.a11 = 0.0;
+  q.f0 = em1 * t.inv_w0;
+  q.f1 = 0.0;
+  q.q00 = s2 * em1 * (1.0 + e1);
+  q.q01 = 0.0;
+  q.q11 = 0.0;
+  q.c0 = s2 * em1 * em1 * t.inv_w0;
+  q.c1 = 0.0;
+  q.zz = 2.0 * s2 * real_gfun(x, em1, e1) * t.inv_w0 * t.inv_w0;
+  return q;
+}
+
+// Gradient of one real-term step: W holds the weights of the step's fields
+// (see term_backprop); the fields depend on sigma (noise, cross noise and
+// integrator noise are proportional to sigma^2) and on c through x = c dt.
+GPD void real_backprop(const TermConst& t, double dt, const double* W, double& gs, double& gw) {
+  const double c = t.w0, ic = t.inv_w0, x = c * dt;
+  const double em1 = -expm1(-x), e1 = 1.0 - em1;
+  const double s2 = 0.5 * t.qhat;
+  const double g = real_gfun(x, em1, e1);
+  // d/dc of each field
+  const double da00 = -dt * e1;
+  const double df0 = real_hfun(x, em1, e1) * ic * ic;
+  const double dq00 = 2.0 * s2 * dt * e1 * e1;
+  const double dc0 = s2 * em1 * (2.0 * x * e1 - em1) * ic * ic;
+  const double dzz = 2.0 * s2 * (x * em1 * em1 - 2.0 * g) * ic * ic * ic;
+  gw += W[0] * da00 + W[3] * df0 + W[5] * dq00 + W[8] * dc0 + W[10] * dzz;
+  // d/dsigma: the noise fields over sigma, twice
+  const double q00 = s2 * em1 * (1.0 + e1), c0 = s2 * em1 * em1 * ic, zz = 2.0 * s2 * g * ic * ic;
+  gs += 2.0 * (W[5] * q00 + W[8] * c0 + W[10] * zz) / t.sigma;
 }
 
 // ---------------------------------------------------------------------------

@@ -239,7 +239,7 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
       // prior of the SHO states: sigma_t^2 I in scaled coordinates
 #pragma unroll
       for (int t = 0; t < M; ++t)
-        acc.s(t) += 2.0 * tc[t].sigma * (Pb[sidx(2 * t, 2 * t, D)] + Pb[sidx(2 * t + 1, 2 * t + 1, D)]);
+        acc.s(t) += 2.0 * tc[t].sigma * (Pb[sidx(2 * t, 2 * t, D)] + second_prior(tc[t]) * Pb[sidx(2 * t + 1, 2 * t + 1, D)]);
     }
     // sum over the wave's lanes (one series), one partial per work wave
     const int64_t S = p.n_wv;
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(WAVE) void k_plain(DevPlan p, DevParams pr, int64_t
 #pragma unroll
   for (int t = 0; t < M; ++t) {
     P[sidx(2 * t, 2 * t, D)] = tc[t].sigma * tc[t].sigma;
-    P[sidx(2 * t + 1, 2 * t + 1, D)] = tc[t].sigma * tc[t].sigma;
+    P[sidx(2 * t + 1, 2 * t + 1, D)] = tc[t].sigma * tc[t].sigma * second_prior(tc[t]);
   }
   double ll = 0.0;
   const int32_t c0 = p.series_chunk0[b], nch = p.series_nch[b];
@@ -549,7 +549,7 @@ __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& p
 #pragma unroll
         for (int t = 0; t < M; ++t) {
           pP[sidx(2 * t, 2 * t, D)] = tc[t].sigma * tc[t].sigma;
-          pP[sidx(2 * t + 1, 2 * t + 1, D)] = tc[t].sigma * tc[t].sigma;
+          pP[sidx(2 * t + 1, 2 * t + 1, D)] = tc[t].sigma * tc[t].sigma * second_prior(tc[t]);
         }
       }
       const double tprev = ts.chunk_tprev[c];

@@ -44,7 +44,7 @@ __device__ __forceinline__ void prior_state(const DevParams& pr, int64_t b, doub
   for (int t = 0; t < M; ++t) {
     const double s2 = pr.tc[b * M + t].sigma * pr.tc[b * M + t].sigma;
     P[sidx(2 * t, 2 * t, N)] = s2;
-    P[sidx(2 * t + 1, 2 * t + 1, N)] = s2;
+    P[sidx(2 * t + 1, 2 * t + 1, N)] = s2 * second_prior(pr.tc[b * M + t]);
   }
 }
 
