@@ -19,6 +19,12 @@ augmented state-space method reaches exactly, only faster.
 * Gradient: 1/2 tr((alpha alpha^T - K_y^-1) dK_y/dtheta) (standard Gaussian
   marginal-likelihood gradient; not in the paper), dK/dtheta from the same
   quadrature of the kernel's analytic derivative.
+* Per-instrument amplitude and offset (Sec. 2.2, the observation matrix
+  scaled per instrument; Sec. 3.2.3, instrument labels): measurement n reads
+  a_n times its exposure average plus c_n, so K_y = A K A + diag(noise) with
+  A = diag(a_n), and the residual is y - c.  The gradient in a_i uses
+  dK_y/da_i = E_i K A + A K E_i (E_i the indicator of instrument i's rows);
+  the one in c_i is the sum of alpha over instrument i's rows.
 """
 from __future__ import annotations
 
@@ -165,10 +171,21 @@ def cross_covariance(t_test, ts, te, sigma, omega0, quality, block=256, kinds=No
     return out
 
 
-def loglik(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, K=None, kinds=None):
+def _scaled(K, y, amp, off):
+    """(A K A, y - c) for per-measurement amplitudes and offsets (None: 1, 0)."""
+    y = np.asarray(y, dtype=np.float64)
+    if amp is not None:
+        a = np.asarray(amp, dtype=np.float64)
+        K = a[:, None] * K * a[None, :]
+    if off is not None:
+        y = y - np.asarray(off, dtype=np.float64)
+    return K, y
+
+
+def loglik(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, K=None, kinds=None, amp=None, off=None):
     if K is None:
         K = covariance(ts, te, sigma, omega0, quality, kinds=kinds)
-    y = np.asarray(y, dtype=np.float64)
+    K, y = _scaled(K, y, amp, off)
     Ky = K + np.diag(np.asarray(yerr) ** 2 + jitter ** 2)
     cf = cho_factor(Ky, lower=True)
     alpha = cho_solve(cf, y)
@@ -198,43 +215,61 @@ def posterior_terms(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=
     return mean, var, Ks
 
 
-def posterior(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=None, kinds=None):
-    """(mean_data, var_data, mean_test, var_test): exposure-averaged
-    posterior at the data and latent posterior at t_test."""
-    K = covariance(ts, te, sigma, omega0, quality, kinds=kinds)
+def posterior(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=None, kinds=None, amp=None, off=None):
+    """(mean_data, var_data, mean_test, var_test): posterior of the
+    noise-free measured quantity a_n * (exposure average) + c_n at the data
+    and latent posterior at t_test."""
+    K, yr = _scaled(covariance(ts, te, sigma, omega0, quality, kinds=kinds), y, amp, off)
     Ky = K + np.diag(np.asarray(yerr) ** 2 + jitter ** 2)
     cf = cho_factor(Ky, lower=True)
-    alpha = cho_solve(cf, np.asarray(y, dtype=np.float64))
-    mean_d = K @ alpha
+    alpha = cho_solve(cf, yr)
+    mean_d = K @ alpha + (0.0 if off is None else np.asarray(off, dtype=np.float64))
     var_d = np.diag(K) - np.sum(K * cho_solve(cf, K), axis=0)
     if t_test is None:
         return mean_d, var_d, None, None
     Ks = cross_covariance(t_test, ts, te, sigma, omega0, quality, kinds=kinds)
+    if amp is not None:
+        Ks = np.asarray(amp, dtype=np.float64)[:, None] * Ks
     mean_t = Ks.T @ alpha
     k0 = float(np.sum(np.atleast_1d(sigma) ** 2))
     var_t = k0 - np.sum(Ks * cho_solve(cf, Ks), axis=0)
     return mean_d, var_d, mean_t, var_t
 
 
-def loglik_grad(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, kinds=None):
+def loglik_grad(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, kinds=None, instrument=None, amp=None,
+                off=None):
     """Analytic gradient ordered (d sigma_1..M, d omega0_1..M, d Q_1..M,
-    d jitter), together with the log-likelihood."""
+    d jitter), together with the log-likelihood.  With instrument labels
+    (int per measurement) and per-instrument amp and off (length I), the
+    gradient continues with (d amp_0..I-1, d off_0..I-1)."""
     sigma = np.atleast_1d(np.asarray(sigma, dtype=np.float64))
     omega0 = np.atleast_1d(np.asarray(omega0, dtype=np.float64))
     quality = np.atleast_1d(np.asarray(quality, dtype=np.float64))
     M = len(sigma)
-    K = covariance(ts, te, sigma, omega0, quality, kinds=kinds)
-    y = np.asarray(y, dtype=np.float64)
+    K0 = covariance(ts, te, sigma, omega0, quality, kinds=kinds)
+    a_n = c_n = None
+    if instrument is not None:
+        inst = np.asarray(instrument, dtype=np.int64)
+        a_n = np.asarray(amp, dtype=np.float64)[inst]
+        c_n = np.asarray(off, dtype=np.float64)[inst]
+    K, y = _scaled(K0, y, a_n, c_n)
     Ky = K + np.diag(np.asarray(yerr) ** 2 + jitter ** 2)
     cf = cho_factor(Ky, lower=True)
     alpha = cho_solve(cf, y)
     Kinv = cho_solve(cf, np.eye(len(y)))
     W = np.outer(alpha, alpha) - Kinv
     L = float(-0.5 * y @ alpha - np.sum(np.log(np.diag(cf[0]))) - 0.5 * len(y) * _LOG2PI)
-    g = np.zeros(3 * M + 1)
+    ni = 0 if instrument is None else len(amp)
+    g = np.zeros(3 * M + 1 + 2 * ni)
     for k, name in enumerate(("sigma", "omega0", "quality")):
         for m in range(M):
             dK = covariance(ts, te, sigma, omega0, quality, which=(m, name), kinds=kinds)
-            g[k * M + m] = 0.5 * np.sum(W * dK)
+            g[k * M + m] = 0.5 * np.sum(W * _scaled(dK, y, a_n, None)[0])
     g[3 * M] = 0.5 * np.trace(W) * 2 * jitter
+    for i in range(ni):
+        E = (inst == i).astype(np.float64)
+        KA = K0 * a_n[None, :]
+        dK = E[:, None] * KA + KA.T * E[None, :]
+        g[3 * M + 1 + i] = 0.5 * np.sum(W * dK)
+        g[3 * M + 1 + ni + i] = float(np.sum(alpha[inst == i]))
     return L, g

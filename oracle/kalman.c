@@ -23,6 +23,10 @@
  *   - the real (exponential) term, the celerite term
  *     with b = d = 0, as a one-state model .......... Appendix A
  *   - one integrator per instrument label ........... Sec. 3.2.3
+ *   - per-measurement amplitude and offset of the
+ *     instrument in the observation model (measured
+ *     a_n times the exposure average plus c_n) ...... Sec. 2.2 (observation
+ *                                                     matrix), Sec. 3.2.3
  *   - reset at exposure starts, update at ends ...... Sec. 3.2.1
  *   - log-likelihood from innovations ............... Sec. 2.4
  *   - integrated RTS smoother ....................... Sec. 3.2.2
@@ -369,7 +373,8 @@ static int check_inputs(int64_t n, const double* ts, const double* te, const dou
 /* Runs the integrated Kalman filter.  When pred/filt are non-NULL the
  * predicted and filtered moments of every event are stored there. */
 static int run_filter(const model_t* md, int64_t n_ev, const ev_t* ev, const double* ts, const double* te, const double* y,
-                      const double* yerr, ld jitter, ld* loglik, state_t* pred, state_t* filt) {
+                      const double* yerr, const double* amp, const double* off, ld jitter, ld* loglik, state_t* pred,
+                      state_t* filt) {
   const int D = md->D, M = md->M;
   state_t s;
   memset(&s, 0, sizeof(s));
@@ -392,11 +397,12 @@ static int run_filter(const model_t* md, int64_t n_ev, const ev_t* ev, const dou
       for (int a = 0; a < D; ++a) s.P[z][a] = s.P[a][z] = 0;
     } else {
       ld h[OR_MAXD];
+      const ld an = amp ? (ld)amp[i] : 1;
       for (int a = 0; a < D; ++a) h[a] = 0;
       if (ev[k].kind == EV_END) {
-        h[2 * M + ev[k].slot] = 1 / ((ld)te[i] - (ld)ts[i]);
+        h[2 * M + ev[k].slot] = an / ((ld)te[i] - (ld)ts[i]);
       } else {
-        for (int m = 0; m < M; ++m) h[2 * m] = 1;
+        for (int m = 0; m < M; ++m) h[2 * m] = an;
       }
       ld u[OR_MAXD], hm = 0, S = (ld)yerr[i] * yerr[i] + jitter * jitter;
       for (int a = 0; a < D; ++a) {
@@ -407,7 +413,7 @@ static int run_filter(const model_t* md, int64_t n_ev, const ev_t* ev, const dou
       }
       for (int a = 0; a < D; ++a) S += h[a] * u[a];
       if (!(S > 0)) return OR_ENUMERIC;
-      const ld v = (ld)y[i] - hm;
+      const ld v = (ld)y[i] - (off ? (ld)off[i] : 0) - hm;
       for (int a = 0; a < D; ++a) s.m[a] += u[a] * v / S;
       for (int a = 0; a < D; ++a)
         for (int b = 0; b < D; ++b) s.P[a][b] -= u[a] * u[b] / S;
@@ -421,9 +427,14 @@ static int run_filter(const model_t* md, int64_t n_ev, const ev_t* ev, const dou
 
 static int setup(int64_t n, const double* ts, const double* te, const double* y, const double* yerr, const int32_t* slot_in,
                  int32_t M, const double* sigma, const double* omega0, const double* quality, const int32_t* kind,
-                 double jitter, model_t* md, ev_t** ev, int64_t* n_ev, int32_t** slot_out) {
+                 const double* amp, const double* off, double jitter, model_t* md, ev_t** ev, int64_t* n_ev,
+                 int32_t** slot_out) {
   int rc = check_inputs(n, ts, te, y, yerr, M, sigma, omega0, quality, kind, jitter);
   if (rc) return rc;
+  for (int64_t i = 0; i < n; ++i) {
+    if (amp && (!(amp[i] > 0) || !isfinite(amp[i]))) return OR_EPARAM;
+    if (off && !isfinite(off[i])) return OR_EPARAM;
+  }
   int32_t* slot = (int32_t*)malloc(sizeof(int32_t) * n);
   if (!slot) return OR_ENOMEM;
   int32_t J = 0;
@@ -480,13 +491,13 @@ static int setup(int64_t n, const double* ts, const double* te, const double* y,
 
 int oracle_loglik(int64_t n, const double* ts, const double* te, const double* y, const double* yerr, const int32_t* slot_in,
                   int32_t M, const double* sigma, const double* omega0, const double* quality, const int32_t* kind,
-                  double jitter, int32_t extra_slots,
+                  const double* amp, const double* off, double jitter, int32_t extra_slots,
                   double* out_hilo) {
   model_t md;
   ev_t* ev = NULL;
   int64_t n_ev = 0;
   int32_t* slot = NULL;
-  int rc = setup(n, ts, te, y, yerr, slot_in, M, sigma, omega0, quality, kind, jitter, &md, &ev, &n_ev, &slot);
+  int rc = setup(n, ts, te, y, yerr, slot_in, M, sigma, omega0, quality, kind, amp, off, jitter, &md, &ev, &n_ev, &slot);
   if (rc) return rc;
   if (extra_slots > 0) {
     md.J += extra_slots;
@@ -498,7 +509,7 @@ int oracle_loglik(int64_t n, const double* ts, const double* te, const double* y
     return OR_EOVERLAP;
   }
   ld L = 0;
-  rc = run_filter(&md, n_ev, ev, ts, te, y, yerr, jitter, &L, NULL, NULL);
+  rc = run_filter(&md, n_ev, ev, ts, te, y, yerr, amp, off, jitter, &L, NULL, NULL);
   out_hilo[0] = (double)L;
   out_hilo[1] = (double)(L - (ld)out_hilo[0]);
   free(ev);
@@ -612,14 +623,14 @@ static void latent_terms(const model_t* md, const state_t* s, int64_t q, double*
 
 int oracle_smooth(int64_t n, const double* ts, const double* te, const double* y, const double* yerr, const int32_t* slot_in,
                   int32_t M, const double* sigma, const double* omega0, const double* quality, const int32_t* kind,
-                  double jitter, int64_t n_test,
+                  const double* amp, const double* off, double jitter, int64_t n_test,
                   const double* t_test, double* mean_test, double* var_test, double* mean_data, double* var_data,
                   double* term_mean, double* term_var, double* out_hilo) {
   model_t md;
   ev_t* ev = NULL;
   int64_t K = 0;
   int32_t* slot = NULL;
-  int rc = setup(n, ts, te, y, yerr, slot_in, M, sigma, omega0, quality, kind, jitter, &md, &ev, &K, &slot);
+  int rc = setup(n, ts, te, y, yerr, slot_in, M, sigma, omega0, quality, kind, amp, off, jitter, &md, &ev, &K, &slot);
   if (rc) return rc;
   const int D = md.D;
   state_t* pred = (state_t*)malloc(sizeof(state_t) * K);
@@ -630,7 +641,7 @@ int oracle_smooth(int64_t n, const double* ts, const double* te, const double* y
     goto done;
   }
   ld L = 0;
-  rc = run_filter(&md, K, ev, ts, te, y, yerr, jitter, &L, pred, filt);
+  rc = run_filter(&md, K, ev, ts, te, y, yerr, amp, off, jitter, &L, pred, filt);
   if (out_hilo) {
     out_hilo[0] = (double)L;
     out_hilo[1] = (double)(L - (ld)out_hilo[0]);
@@ -660,13 +671,19 @@ int oracle_smooth(int64_t n, const double* ts, const double* te, const double* y
   if (mean_data && var_data) {
     for (int64_t k = 0; k < K; ++k) {
       const int64_t i = ev[k].n;
+      /* the measured quantity without noise: amplitude times the exposure
+       * average (or the latent value) plus the offset */
+      const ld an = amp ? (ld)amp[i] : 1, cn = off ? (ld)off[i] : 0;
       if (ev[k].kind == EV_END) {
         const int z = 2 * md.M + ev[k].slot;
         const ld dl = (ld)te[i] - (ld)ts[i];
-        mean_data[i] = (double)(smo[k].m[z] / dl);
-        var_data[i] = (double)(smo[k].P[z][z] / (dl * dl));
+        mean_data[i] = (double)(an * smo[k].m[z] / dl + cn);
+        var_data[i] = (double)(an * an * smo[k].P[z][z] / (dl * dl));
       } else if (ev[k].kind == EV_INSTANT) {
-        latent(&md, &smo[k], &mean_data[i], &var_data[i]);
+        double mu, va;
+        latent(&md, &smo[k], &mu, &va);
+        mean_data[i] = (double)(an * (ld)mu + cn);
+        var_data[i] = (double)(an * an * (ld)va);
       }
     }
   }

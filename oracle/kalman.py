@@ -44,10 +44,10 @@ def lib():
             L.oracle_greedy_slots.argtypes = [ctypes.c_int64, _dp, _dp, _ip, _ip]
             L.oracle_greedy_slots.restype = ctypes.c_int
             L.oracle_loglik.argtypes = [ctypes.c_int64, _dp, _dp, _dp, _dp, _ip, ctypes.c_int32, _dp, _dp, _dp, _ip,
-                                        ctypes.c_double, ctypes.c_int32, _dp]
+                                        _dp, _dp, ctypes.c_double, ctypes.c_int32, _dp]
             L.oracle_loglik.restype = ctypes.c_int
             L.oracle_smooth.argtypes = [ctypes.c_int64, _dp, _dp, _dp, _dp, _ip, ctypes.c_int32, _dp, _dp, _dp, _ip,
-                                        ctypes.c_double, ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+                                        _dp, _dp, ctypes.c_double, ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
             L.oracle_smooth.restype = ctypes.c_int
             _lib = L
     return _lib
@@ -99,6 +99,24 @@ def _kinds(kinds, M):
     return k, k.ctypes.data_as(_ip)
 
 
+def expand_instruments(instrument, amp=None, off=None):
+    """Per-measurement amplitude and offset from per-instrument values:
+    measurement n takes amp[instrument[n]] and off[instrument[n]] (Sec. 2.2,
+    the observation matrix scaled per instrument; Sec. 3.2.3, labels)."""
+    instrument = np.asarray(instrument, dtype=np.int64)
+    a = None if amp is None else np.asarray(amp, dtype=np.float64)[instrument]
+    c = None if off is None else np.asarray(off, dtype=np.float64)[instrument]
+    return a, c
+
+
+def _opt(a, n):
+    if a is None:
+        return None, None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    assert a.shape == (n,)
+    return a, a.ctypes.data_as(_dp)
+
+
 def _prep(ts, te, y, yerr, sigma, omega0, quality, slots):
     arrs = [_d(a) for a in (ts, te, y, yerr)]
     terms = [_d(np.atleast_1d(a)) for a in (sigma, omega0, quality)]
@@ -110,30 +128,40 @@ def _prep(ts, te, y, yerr, sigma, omega0, quality, slots):
     return arrs, terms, sl, slp
 
 
-def loglik_hilo(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, slots=None, extra_slots=0, kinds=None):
+def loglik_hilo(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, slots=None, extra_slots=0, kinds=None, amp=None,
+                off=None):
     """Log-likelihood as a (hi, lo) double-double pair.  kinds: per term
-    'sho' (default) or 'real' (sigma^2 exp(-omega0 |tau|), quality unused)."""
+    'sho' (default) or 'real' (sigma^2 exp(-omega0 |tau|), quality unused).
+    amp, off: per-measurement amplitude a_n and offset c_n of the
+    observation, y_n = a_n * (exposure average) + c_n + noise (default 1, 0)."""
     arrs, terms, sl, slp = _prep(ts, te, y, yerr, sigma, omega0, quality, slots)
     out = np.zeros(2)
     M = len(terms[0][0])
+    n = len(arrs[0][0])
     kd, kp = _kinds(kinds, M)
-    rc = lib().oracle_loglik(len(arrs[0][0]), arrs[0][1], arrs[1][1], arrs[2][1], arrs[3][1], slp, M, terms[0][1],
-                             terms[1][1], terms[2][1], kp, float(jitter), int(extra_slots), _d(out)[1])
+    ad, ap = _opt(amp, n)
+    od, op = _opt(off, n)
+    rc = lib().oracle_loglik(n, arrs[0][1], arrs[1][1], arrs[2][1], arrs[3][1], slp, M, terms[0][1],
+                             terms[1][1], terms[2][1], kp, ap, op, float(jitter), int(extra_slots), _d(out)[1])
     if rc:
         raise OracleError(rc)
     return float(out[0]), float(out[1])
 
 
-def loglik(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, slots=None, extra_slots=0, kinds=None):
-    hi, lo = loglik_hilo(ts, te, y, yerr, sigma, omega0, quality, jitter, slots, extra_slots, kinds)
+def loglik(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, slots=None, extra_slots=0, kinds=None, amp=None,
+           off=None):
+    hi, lo = loglik_hilo(ts, te, y, yerr, sigma, omega0, quality, jitter, slots, extra_slots, kinds, amp, off)
     return hi + lo
 
 
-def smooth(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=None, slots=None, terms=False, kinds=None):
+def smooth(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=None, slots=None, terms=False, kinds=None,
+           amp=None, off=None):
     """Returns (loglik, mean_test, var_test, mean_data, var_data), and with
     terms=True also the per-term latent posterior at t_test (term_mean,
     term_var, each [n_test, M]: H^m applied to the smoothed state, Appendix
-    C, component-wise predictive means and variances)."""
+    C, component-wise predictive means and variances).  mean_test/var_test
+    are the latent process; mean_data/var_data the noise-free measured
+    quantity a_n * (exposure average) + c_n."""
     want_terms = terms
     arrs, terms, sl, slp = _prep(ts, te, y, yerr, sigma, omega0, quality, slots)
     n = len(arrs[0][0])
@@ -147,8 +175,10 @@ def smooth(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=None, slo
     tm = np.zeros((len(tt), M))
     tv = np.zeros((len(tt), M))
     kd, kp = _kinds(kinds, M)
+    ad, ap = _opt(amp, n)
+    od, op = _opt(off, n)
     rc = lib().oracle_smooth(n, arrs[0][1], arrs[1][1], arrs[2][1], arrs[3][1], slp, M, terms[0][1], terms[1][1],
-                             terms[2][1], kp, float(jitter), len(tt), _d(tt)[1], _d(mt)[1], _d(vt)[1], _d(md)[1], _d(vd)[1],
+                             terms[2][1], kp, ap, op, float(jitter), len(tt), _d(tt)[1], _d(mt)[1], _d(vt)[1], _d(md)[1], _d(vd)[1],
                              _d(tm)[1] if want_terms else None, _d(tv)[1] if want_terms else None, _d(out)[1])
     if rc:
         raise OracleError(rc)
@@ -157,7 +187,8 @@ def smooth(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, t_test=None, slo
     return out[0] + out[1], mt, vt, md, vd
 
 
-def loglik_grad_fd(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, rel_step=1e-6, slots=None, kinds=None):
+def loglik_grad_fd(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, rel_step=1e-6, slots=None, kinds=None, amp=None,
+                   off=None):
     """Central finite differences of the log-likelihood with relative steps
     h_i = rel_step * |theta_i| in the natural parameters.  Returns the
     gradient ordered (d sigma_1..M, d omega0_1..M, d Q_1..M, d jitter).
@@ -170,7 +201,8 @@ def loglik_grad_fd(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, rel_step
     g = np.zeros_like(theta)
 
     def L(th):
-        hi, lo = loglik_hilo(ts, te, y, yerr, th[:M], th[M:2 * M], th[2 * M:3 * M], th[3 * M], slots, kinds=kinds)
+        hi, lo = loglik_hilo(ts, te, y, yerr, th[:M], th[M:2 * M], th[2 * M:3 * M], th[3 * M], slots, kinds=kinds,
+                             amp=amp, off=off)
         return hi, lo
 
     for i in range(len(theta)):
@@ -188,4 +220,37 @@ def loglik_grad_fd(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, rel_step
         hp, lp = L(tp)
         hm, lm = L(tm)
         g[i] = ((hp - hm) + (lp - lm)) / (tp[i] - tm[i])
+    return g
+
+
+def loglik_grad_inst_fd(ts, te, y, yerr, sigma, omega0, quality, jitter, instrument, amp, off, rel_step=1e-6,
+                        kinds=None):
+    """Central differences of the log-likelihood in the per-instrument
+    amplitudes and offsets (Sec. 2.2 observation model with one amplitude a_i
+    and offset c_i per instrument label).  Returns (d amp_0..I-1, d off_0..I-1).
+    Offsets use an absolute step of rel_step * max(1, |c_i|)."""
+    amp = np.asarray(amp, dtype=np.float64)
+    off = np.asarray(off, dtype=np.float64)
+    ni = len(amp)
+
+    def L(a, c):
+        ea, ec = expand_instruments(instrument, a, c)
+        return loglik_hilo(ts, te, y, yerr, sigma, omega0, quality, jitter, kinds=kinds, amp=ea, off=ec)
+
+    g = np.zeros(2 * ni)
+    for i in range(2 * ni):
+        base = amp if i < ni else off
+        k = i % ni
+        h = rel_step * abs(base[k]) if i < ni else rel_step * max(1.0, abs(base[k]))
+        p = base.copy()
+        m = base.copy()
+        p[k] += h
+        m[k] -= h
+        if i < ni:
+            hp, lp = L(p, off)
+            hm, lm = L(m, off)
+        else:
+            hp, lp = L(amp, p)
+            hm, lm = L(amp, m)
+        g[i] = ((hp - hm) + (lp - lm)) / (p[k] - m[k])
     return g

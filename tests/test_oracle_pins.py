@@ -624,3 +624,112 @@ def test_matern32_is_the_sho_term_at_half():
     Km = dense._pair_block(ts[:, None], te[:, None], ts[None, :], te[None, :], matern, r3)
     Ks = dense.covariance(ts, te, [s], [r3], [0.5])
     assert np.max(np.abs(Km - Ks)) < 1e-14 * s * s
+
+
+# ---------------------------------------------------------------------------
+# per-instrument amplitude and offset in the observation model (Sec. 2.2,
+# the observation matrix scaled per instrument; Sec. 3.2.3, labels)
+# ---------------------------------------------------------------------------
+
+def _inst_case(seed, n=45, ni=3, J=3):
+    b = W.random_small_batch(seed, B=1, n_lo=n, n_hi=n, M=2, J=J)
+    s = b.series(0)
+    rng = np.random.default_rng(seed + 100)
+    inst = rng.integers(0, ni, len(s["ts"]))
+    amp = rng.uniform(0.5, 1.8, ni)
+    off = rng.normal(0.0, 0.5, ni)
+    return s, inst, amp, off
+
+
+def test_single_instrument_amplitude_scales_sigma():
+    """One amplitude a for every measurement equals scaling each term's
+    sigma by a (the kernel is quadratic in sigma); the offset c equals
+    subtracting c from the data."""
+    s, _, _, _ = _inst_case(61)
+    n = len(s["ts"])
+    a, c = 1.7, -0.35
+    base = (s["ts"], s["te"])
+    L1 = kalman.loglik(*base, s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"], s["jitter"],
+                       amp=np.full(n, a), off=np.full(n, c))
+    L2 = kalman.loglik(*base, s["y"] - c, s["yerr"], a * np.asarray(s["sigma"]), s["omega0"], s["quality"],
+                       s["jitter"])
+    assert abs(L1 - L2) < 1e-13 * abs(L2)
+
+
+def test_amplitude_change_of_variables():
+    """With no jitter, dividing each measurement (residual and noise) by its
+    own a_n gives the amplitude-free problem, and the density changes by the
+    Jacobian: L(y; a, c, yerr) = L((y - c)/a; 1, 0, yerr/a) - sum log a_n."""
+    s, inst, amp, off = _inst_case(62)
+    a_n, c_n = kalman.expand_instruments(inst, amp, off)
+    args = (s["sigma"], s["omega0"], s["quality"], 0.0)
+    L1 = kalman.loglik(s["ts"], s["te"], s["y"], s["yerr"], *args, amp=a_n, off=c_n)
+    L2 = kalman.loglik(s["ts"], s["te"], (s["y"] - c_n) / a_n, s["yerr"] / a_n, *args)
+    assert abs(L1 - (L2 - np.sum(np.log(a_n)))) < 1e-12 * abs(L1)
+    # the dense side, same identity
+    D1 = dense.loglik(s["ts"], s["te"], s["y"], s["yerr"], *args, amp=a_n, off=c_n)
+    D2 = dense.loglik(s["ts"], s["te"], (s["y"] - c_n) / a_n, s["yerr"] / a_n, *args)
+    assert abs(D1 - (D2 - np.sum(np.log(a_n)))) < 1e-12 * abs(D1)
+
+
+def test_instruments_instantaneous_textbook_gp():
+    """Instantaneous samples from several instruments: the Gaussian density
+    of y with covariance A K A + diag(yerr^2 + jitter^2) and mean c, from
+    scipy's multivariate normal."""
+    import scipy.stats as ss
+    rng = np.random.default_rng(63)
+    t = np.sort(rng.uniform(0, 3, 30))
+    inst = rng.integers(0, 3, 30)
+    amp, off = np.array([1.0, 0.6, 1.4]), np.array([0.1, -0.3, 0.25])
+    a_n, c_n = kalman.expand_instruments(inst, amp, off)
+    y = rng.normal(size=30)
+    yerr = rng.uniform(0.1, 0.3, 30)
+    sig, w0, q, jit = [1.0, 0.5], [2.0, 9.0], [0.8, 0.4], 0.07
+    K = sum(sho.kernel(t[:, None] - t[None, :], sig[m], w0[m], q[m]) for m in range(2))
+    ref = ss.multivariate_normal(mean=c_n, cov=a_n[:, None] * K * a_n[None, :] + np.diag(yerr ** 2 + jit ** 2)).logpdf(y)
+    L = kalman.loglik(t, t, y, yerr, sig, w0, q, jit, amp=a_n, off=c_n)
+    assert abs(L - ref) < 1e-12 * abs(ref)
+
+
+@pytest.mark.parametrize("seed", [64, 65])
+def test_kalman_equals_dense_with_instruments(seed):
+    s, inst, amp, off = _inst_case(seed)
+    a_n, c_n = kalman.expand_instruments(inst, amp, off)
+    args = (s["ts"], s["te"], s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"], s["jitter"])
+    Ld = dense.loglik(*args, amp=a_n, off=c_n)
+    Lk = kalman.loglik(*args, amp=a_n, off=c_n)
+    assert abs(Ld - Lk) <= 1e-11 * abs(Ld)
+    tt = np.linspace(s["ts"].min() - 0.05, s["te"].max() + 0.05, 9)
+    md, vd, mt, vt = dense.posterior(*args, t_test=tt, amp=a_n, off=c_n)
+    _, mt2, vt2, md2, vd2 = kalman.smooth(*args, t_test=tt, amp=a_n, off=c_n)
+    k0 = float(np.sum(np.asarray(s["sigma"]) ** 2))
+    assert np.max(np.abs(md - md2)) < 1e-11 * math.sqrt(k0) and np.max(np.abs(vd - vd2)) < 1e-11 * k0
+    assert np.max(np.abs(mt - mt2)) < 1e-11 * math.sqrt(k0) and np.max(np.abs(vt - vt2)) < 1e-11 * k0
+
+
+def test_dense_gradient_with_instruments_matches_fd_of_kalman():
+    s, inst, amp, off = _inst_case(66, n=30)
+    a_n, c_n = kalman.expand_instruments(inst, amp, off)
+    args = (s["ts"], s["te"], s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"], s["jitter"])
+    L, g = dense.loglik_grad(*args, instrument=inst, amp=amp, off=off)
+    gt = kalman.loglik_grad_fd(*args, amp=a_n, off=c_n)
+    gi = kalman.loglik_grad_inst_fd(*args, inst, amp, off)
+    gfd = np.concatenate([gt, gi])
+    assert g.shape == (3 * 2 + 1 + 6,)
+    den = np.maximum(np.abs(gfd), 1e-3 * np.max(np.abs(gfd)))
+    assert np.max(np.abs(g - gfd) / den) < 1e-6
+
+
+def test_instrument_parameters_validated():
+    s, inst, amp, off = _inst_case(67, n=10)
+    a_n, c_n = kalman.expand_instruments(inst, amp, off)
+    args = (s["ts"], s["te"], s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"], s["jitter"])
+    for bad in (0.0, -1.0, np.nan, np.inf):
+        a2 = a_n.copy()
+        a2[3] = bad
+        with pytest.raises(kalman.OracleError):
+            kalman.loglik(*args, amp=a2, off=c_n)
+    c2 = c_n.copy()
+    c2[0] = np.nan
+    with pytest.raises(kalman.OracleError):
+        kalman.loglik(*args, amp=a_n, off=c2)
