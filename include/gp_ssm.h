@@ -64,6 +64,7 @@ extern "C" {
 
 #define GP_SSM_MAX_TERMS 4
 #define GP_SSM_MAX_SLOTS 4
+#define GP_SSM_MAX_INSTRUMENTS 8
 
 /* term kinds (gp_ssm_plan_set_term_kinds) */
 #define GP_SSM_TERM_SHO 0  /* stochastically driven damped harmonic oscillator (sigma, omega0, Q) */
@@ -72,7 +73,8 @@ extern "C" {
 #define GP_SSM_OK 0
 #define GP_SSM_EINVAL (-1)   /* null pointer, B < 1, M out of range, bad offsets */
 #define GP_SSM_EDATA (-2)    /* non-finite data, t_end < t_start, unsorted t_start, yerr < 0 */
-#define GP_SSM_EPARAM (-3)   /* sigma, omega0 or Q <= 0 or non-finite; jitter < 0 or non-finite */
+#define GP_SSM_EPARAM (-3)   /* sigma, omega0, Q or an amplitude <= 0 or non-finite; jitter < 0 or
+                                non-finite; an offset non-finite */
 #define GP_SSM_EOVERLAP (-4) /* more than GP_SSM_MAX_SLOTS exposures open at once */
 #define GP_SSM_ENUMERIC (-5) /* some series had a non-finite result; see status[] */
 #define GP_SSM_EDEVICE (-6)  /* no usable gfx950 device or a HIP error */
@@ -139,6 +141,22 @@ int gp_ssm_plan_create(int64_t n_series, const int64_t* offsets, const double* t
  * GP_SSM_EINVAL.  Synchronises the device. */
 int gp_ssm_plan_set_term_kinds(gp_ssm_plan* plan, int32_t n_terms, const int32_t* kinds);
 
+/* Instrument of every measurement, for the observation model with one
+ * amplitude a_i and one offset c_i per instrument i (Sec. 2.2: the
+ * observation matrix of a measurement, scaled per instrument; Sec. 3.2.3:
+ * instrument labels; Sec. 1: combining instruments of different
+ * calibration):
+ *   y_n = a_{i(n)} (1/delta_n) int f dt + c_{i(n)} + eps_n,
+ * the noise not scaled.  instrument[offsets[B]] (host or device int32, in
+ * the order of the plan's measurements) holds labels 0..n_inst-1, n_inst <=
+ * GP_SSM_MAX_INSTRUMENTS; NULL or n_inst = 0 removes the labels.  These
+ * labels are the caller's calibration groups, unrelated to the integrator
+ * slots the plan assigns to overlapping exposures.  The *_inst entry points
+ * then take the per-series amplitudes and offsets; the other entry points
+ * use a = 1, c = 0.  Synchronises the device.  GP_SSM_EINVAL for a label
+ * out of range. */
+int gp_ssm_plan_set_instruments(gp_ssm_plan* plan, int32_t n_inst, const int32_t* instrument, void* stream);
+
 /* Releases the plan and its device memory (and any workspace it grew). */
 void gp_ssm_plan_destroy(gp_ssm_plan* plan);
 
@@ -174,6 +192,25 @@ int gp_ssm_plan_loglik_grad(gp_ssm_plan* plan, int32_t n_terms, const double* si
                             const double* quality, const double* jitter, double* loglik, double* grad, int32_t* status,
                             void* stream);
 
+/* Log-likelihood with per-instrument amplitudes and offsets (after
+ * gp_ssm_plan_set_instruments): amp[b*n_inst + i] (> 0, finite) and
+ * off[b*n_inst + i] (finite) of series b, host or device; either may be
+ * NULL (1, resp. 0).  A series with an amplitude or offset out of range gets
+ * status GP_SSM_EPARAM.  GP_SSM_EINVAL when the plan has no instruments.
+ * Other arguments as for gp_ssm_plan_loglik. */
+int gp_ssm_plan_loglik_inst(gp_ssm_plan* plan, int32_t n_terms, const double* sigma, const double* omega0,
+                            const double* quality, const double* jitter, const double* amp, const double* off,
+                            double* loglik, int32_t* status, void* stream);
+
+/* Its gradient as well: grad[b*G + k], G = 3M + 1 + 2 n_inst, holds d
+ * loglik_b / d(sigma_1..M, omega0_1..M, Q_1..M, jitter, amp_0..n_inst-1,
+ * off_0..n_inst-1).  The amplitude derivative comes from the adjoint of the
+ * observation vector (h = a h0), the offset derivative is minus the
+ * adjoint of the innovation. */
+int gp_ssm_plan_loglik_grad_inst(gp_ssm_plan* plan, int32_t n_terms, const double* sigma, const double* omega0,
+                                 const double* quality, const double* jitter, const double* amp, const double* off,
+                                 double* loglik, double* grad, int32_t* status, void* stream);
+
 /* Posterior (the RTS smoother's result, Sec. 3.2.2, and prediction at
  * arbitrary times, Sec. 2.5 Algorithm 1).  test_offsets[B+1] (host or device int64) delimits
  * each series' test times in t_test (device, any order within a series).
@@ -198,6 +235,17 @@ int gp_ssm_plan_smooth_terms(gp_ssm_plan* plan, int32_t n_terms, const double* s
                              const double* t_test, double* mean_test, double* var_test, double* term_mean,
                              double* term_var, double* mean_data, double* var_data, double* loglik, int32_t* status,
                              void* stream);
+
+/* The posterior with per-instrument amplitudes and offsets (amp, off as for
+ * gp_ssm_plan_loglik_inst).  mean_test/var_test (and the per-term outputs,
+ * when term_mean and term_var are given) are the latent process;
+ * mean_data/var_data are the noise-free measured quantity a_i (1/delta_n)
+ * int f dt + c_i.  Other arguments as for gp_ssm_plan_smooth_terms. */
+int gp_ssm_plan_smooth_inst(gp_ssm_plan* plan, int32_t n_terms, const double* sigma, const double* omega0,
+                            const double* quality, const double* jitter, const double* amp, const double* off,
+                            const int64_t* test_offsets, const double* t_test, double* mean_test, double* var_test,
+                            double* term_mean, double* term_var, double* mean_data, double* var_data, double* loglik,
+                            int32_t* status, void* stream);
 
 /* Reference "plain" GPU filter: the same per-event device code, one series at
  * a time, one lane, no time splitting, one launch per series.  Computes the

@@ -29,9 +29,9 @@ ERRORS = {-1: "EINVAL", -2: "EDATA", -3: "EPARAM", -4: "EOVERLAP", -5: "ENUMERIC
 # every symbol include/gp_ssm.h declares
 EXPORTS = [
     "gp_ssm_plan_default_options", "gp_ssm_plan_create", "gp_ssm_plan_destroy", "gp_ssm_plan_set_term_kinds",
-    "gp_ssm_plan_get_stats",
-    "gp_ssm_plan_loglik", "gp_ssm_plan_loglik_noalloc", "gp_ssm_plan_loglik_grad", "gp_ssm_plan_smooth",
-    "gp_ssm_plan_smooth_terms",
+    "gp_ssm_plan_set_instruments", "gp_ssm_plan_get_stats",
+    "gp_ssm_plan_loglik", "gp_ssm_plan_loglik_noalloc", "gp_ssm_plan_loglik_grad", "gp_ssm_plan_loglik_inst",
+    "gp_ssm_plan_loglik_grad_inst", "gp_ssm_plan_smooth", "gp_ssm_plan_smooth_terms", "gp_ssm_plan_smooth_inst",
     "gp_ssm_plan_plain_loglik", "gp_ssm_loglik", "gp_ssm_loglik_grad", "gp_ssm_smooth", "gp_ssm_autotune",
     "gp_ssm_autotune_candidates", "gp_ssm_profile_enable", "gp_ssm_profile_reset",
     "gp_ssm_profile_read", "gp_ssm_last_error", "gp_ssm_version",
@@ -75,6 +75,10 @@ def library():
     L.gp_ssm_plan_destroy.restype = None
     L.gp_ssm_plan_get_stats.argtypes = [vp, ctypes.POINTER(PlanStats)]
     L.gp_ssm_plan_set_term_kinds.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    L.gp_ssm_plan_set_instruments.argtypes = [vp, i32, vp, vp]
+    L.gp_ssm_plan_loglik_inst.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.gp_ssm_plan_loglik_grad_inst.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.gp_ssm_plan_smooth_inst.argtypes = [vp, i32] + [vp] * 17
     L.gp_ssm_plan_loglik.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.gp_ssm_plan_loglik_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.gp_ssm_plan_loglik_grad.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -92,8 +96,10 @@ def library():
                                       ctypes.POINTER(ctypes.c_double), i32]
     L.gp_ssm_last_error.restype = ctypes.c_char_p
     L.gp_ssm_version.restype = ctypes.c_char_p
-    for name in ("gp_ssm_plan_create", "gp_ssm_plan_set_term_kinds", "gp_ssm_plan_get_stats", "gp_ssm_plan_loglik", "gp_ssm_plan_loglik_noalloc",
-                 "gp_ssm_plan_loglik_grad",
+    for name in ("gp_ssm_plan_create", "gp_ssm_plan_set_term_kinds", "gp_ssm_plan_set_instruments",
+                 "gp_ssm_plan_get_stats", "gp_ssm_plan_loglik", "gp_ssm_plan_loglik_noalloc",
+                 "gp_ssm_plan_loglik_grad", "gp_ssm_plan_loglik_inst", "gp_ssm_plan_loglik_grad_inst",
+                 "gp_ssm_plan_smooth_inst",
                  "gp_ssm_plan_smooth", "gp_ssm_plan_smooth_terms", "gp_ssm_plan_plain_loglik", "gp_ssm_loglik",
                  "gp_ssm_loglik_grad",
                  "gp_ssm_smooth", "gp_ssm_autotune", "gp_ssm_autotune_candidates", "gp_ssm_profile_enable",
@@ -168,6 +174,7 @@ class Plan:
         _check(L.gp_ssm_plan_create(self.n_series, _ptr(self.offsets), _ptr(ts), _ptr(te), _ptr(yy), _ptr(ye),
                                     ctypes.byref(opt), _stream(), ctypes.byref(h)))
         self._h = h
+        self.n_inst = 0
 
     def close(self):
         if getattr(self, "_h", None):
@@ -189,6 +196,58 @@ class Plan:
         codes = [TERM_CODES.get(k, k) for k in kinds]
         arr = (ctypes.c_int32 * len(codes))(*codes)
         _check(library().gp_ssm_plan_set_term_kinds(self._h, len(codes), arr))
+
+    def set_instruments(self, instrument, n_inst=None):
+        """Instrument label of every measurement (int, 0..n_inst-1, in the
+        plan's measurement order) for the per-instrument amplitude and offset
+        of the *_inst calls; None removes the labels."""
+        torch = _torch()
+        if instrument is None:
+            _check(library().gp_ssm_plan_set_instruments(self._h, 0, None, _stream()))
+            self.n_inst = 0
+            return
+        lab = _dev(instrument, torch.int32).reshape(-1)
+        if lab.numel() != self.n_meas:
+            raise ValueError("one instrument label per measurement")
+        ni = int(lab.max().item()) + 1 if n_inst is None else int(n_inst)
+        _check(library().gp_ssm_plan_set_instruments(self._h, ni, _ptr(lab), _stream()))
+        self.n_inst = ni
+
+    def _inst(self, amp, off):
+        # (without labels the library refuses the call)
+        shape = (self.n_series, self.n_inst) if self.n_inst else (-1,)
+        a = None if amp is None else _dev(amp).reshape(shape)
+        c = None if off is None else _dev(off).reshape(shape)
+        return a, c
+
+    def loglik_inst(self, sigma, omega0, quality, jitter=None, amp=None, off=None, status=False, check=False):
+        """Log-likelihood [B] with per-instrument amplitudes and offsets
+        (amp, off: [B, n_inst]; None: 1 and 0)."""
+        torch = _torch()
+        M, s, w, q, j = self._params(sigma, omega0, quality, jitter)
+        a, c = self._inst(amp, off)
+        out = torch.empty(self.n_series, dtype=torch.float64, device="cuda")
+        st = torch.empty(self.n_series, dtype=torch.int32, device="cuda")
+        _check(library().gp_ssm_plan_loglik_inst(self._h, M, _ptr(s), _ptr(w), _ptr(q), _ptr(j), _ptr(a), _ptr(c),
+                                                 _ptr(out), _ptr(st), _stream()))
+        if check:
+            check_status(st)
+        return (out, st) if status else out
+
+    def loglik_grad_inst(self, sigma, omega0, quality, jitter=None, amp=None, off=None, status=False, check=False):
+        """Log-likelihood [B] and gradient [B, 3M+1+2 n_inst]: d/d sigma,
+        omega0, Q, jitter, then amp_0..n_inst-1 and off_0..n_inst-1."""
+        torch = _torch()
+        M, s, w, q, j = self._params(sigma, omega0, quality, jitter)
+        a, c = self._inst(amp, off)
+        out = torch.empty(self.n_series, dtype=torch.float64, device="cuda")
+        g = torch.empty(self.n_series, 3 * M + 1 + 2 * self.n_inst, dtype=torch.float64, device="cuda")
+        st = torch.empty(self.n_series, dtype=torch.int32, device="cuda")
+        _check(library().gp_ssm_plan_loglik_grad_inst(self._h, M, _ptr(s), _ptr(w), _ptr(q), _ptr(j), _ptr(a),
+                                                      _ptr(c), _ptr(out), _ptr(g), _ptr(st), _stream()))
+        if check:
+            check_status(st)
+        return (out, g, st) if status else (out, g)
 
     def stats(self):
         s = PlanStats()
@@ -253,10 +312,13 @@ class Plan:
                                                   _ptr(out), _stream()))
         return out
 
-    def smooth(self, sigma, omega0, quality, jitter, test_offsets, t_test, data=True, terms=False):
+    def smooth(self, sigma, omega0, quality, jitter, test_offsets, t_test, data=True, terms=False, amp=None,
+               off=None):
         """Posterior at the data and at the test times; with terms=True also
         each term's latent posterior at the test times (term_mean, term_var:
-        [n_test, M])."""
+        [n_test, M]).  amp, off ([B, n_inst], after set_instruments): the
+        per-instrument amplitudes and offsets; mean_data/var_data are then
+        those of the noise-free measured quantity."""
         torch = _torch()
         M, s, w, q, j = self._params(sigma, omega0, quality, jitter)
         to = _dev(test_offsets, torch.int64)
@@ -268,7 +330,17 @@ class Plan:
         ll = torch.empty(self.n_series, dtype=torch.float64, device="cuda")
         st = torch.empty(self.n_series, dtype=torch.int32, device="cuda")
         out = dict(mean_test=mt, var_test=vt, mean_data=md, var_data=vd, loglik=ll, status=st)
-        if terms:
+        if amp is not None or off is not None:
+            a, c = self._inst(amp, off)
+            tm = tv = None
+            if terms:
+                tm = torch.empty((tt.numel(), M), dtype=torch.float64, device="cuda")
+                tv = torch.empty_like(tm)
+                out.update(term_mean=tm, term_var=tv)
+            _check(library().gp_ssm_plan_smooth_inst(self._h, M, _ptr(s), _ptr(w), _ptr(q), _ptr(j), _ptr(a), _ptr(c),
+                                                     _ptr(to), _ptr(tt), _ptr(mt), _ptr(vt), _ptr(tm), _ptr(tv),
+                                                     _ptr(md), _ptr(vd), _ptr(ll), _ptr(st), _stream()))
+        elif terms:
             tm = torch.empty((tt.numel(), M), dtype=torch.float64, device="cuda")
             tv = torch.empty_like(tm)
             _check(library().gp_ssm_plan_smooth_terms(self._h, M, _ptr(s), _ptr(w), _ptr(q), _ptr(j), _ptr(to),

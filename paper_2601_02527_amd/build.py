@@ -28,7 +28,8 @@ DEVICE_FLAGS = [
 ]
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC"]
 
-HIP_SOURCES = ["capi.hip", "scan.hip", "kernels_m1.hip", "kernels_m2.hip", "kernels_m3.hip", "kernels_m4.hip"]
+HIP_SOURCES = ["capi.hip", "scan.hip", "kernels_m1.hip", "kernels_m2.hip", "kernels_m3.hip", "kernels_m4.hip",
+               "kernels_m1x.hip", "kernels_m2x.hip", "kernels_m3x.hip", "kernels_m4x.hip"]
 CPP_SOURCES = ["plan.cpp"]
 
 

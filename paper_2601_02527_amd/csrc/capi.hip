@@ -21,6 +21,8 @@
 
 using namespace gpssm;
 
+static_assert(GP_SSM_MAX_INSTRUMENTS == MAX_INST, "instrument table width");
+
 namespace {
 
 thread_local std::string g_err;
@@ -86,7 +88,9 @@ __device__ __forceinline__ bool param_ok(double v) { return v > 0.0 && isfinite(
 // hyperparameters of series b valid: sigma, omega0 (the rate of a real
 // term) and Q (SHO terms only) > 0 and finite for every term, jitter >= 0
 // and finite (or absent)
-__device__ __forceinline__ bool series_params_ok(const CallArgs& a, const int32_t* kinds, int64_t b, int M) {
+// and finite (or absent); with ni instruments, their amplitudes > 0 and
+// finite and offsets finite (when given)
+__device__ __forceinline__ bool series_params_ok(const CallArgs& a, const int32_t* kinds, int64_t b, int M, int ni) {
   bool ok = true;
   for (int t = 0; t < M; ++t) {
     const int64_t i = b * M + t;
@@ -94,24 +98,29 @@ __device__ __forceinline__ bool series_params_ok(const CallArgs& a, const int32_
     ok = ok && param_ok(a.sigma[i]) && param_ok(a.omega0[i]) && (real || param_ok(a.quality[i]));
   }
   if (a.jitter) ok = ok && a.jitter[b] >= 0.0 && isfinite(a.jitter[b]);
+  for (int i = 0; i < ni; ++i) {
+    if (a.amp) ok = ok && param_ok(a.amp[b * ni + i]);
+    if (a.off) ok = ok && isfinite(a.off[b * ni + i]);
+  }
   return ok;
 }
 
 // Validates the hyperparameters and prepares them: per (series, term) the
 // step constants and the Taylor tables of one series interval per thread,
-// per series the jitter and the validation flag.  A series that fails
-// validation is prepared with sigma = omega0 = Q = 1 and jitter 0, so that
-// every kernel runs on finite, in-range values; its outputs are set to NaN
-// and its status to GP_SSM_EPARAM where they are written.
-__global__ void k_prep(int64_t B, int M, const CallArgs* __restrict__ args, const int32_t* __restrict__ kinds,
+// per series the jitter, the instrument table (ni > 0) and the validation
+// flag.  A series that fails validation is prepared with sigma = omega0 = Q
+// = 1, jitter 0, amplitudes 1 and offsets 0, so that every kernel runs on
+// finite, in-range values; its outputs are set to NaN and its status to
+// GP_SSM_EPARAM where they are written.
+__global__ void k_prep(int64_t B, int M, int ni, const CallArgs* __restrict__ args, const int32_t* __restrict__ kinds,
                        TermConst* __restrict__ tc, double* __restrict__ coef, double* __restrict__ jit,
-                       int32_t* __restrict__ bad) {
+                       int32_t* __restrict__ bad, double* __restrict__ itab) {
   const CallArgs a = *args;
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j < B * M * NI) {
     const int64_t i = j / NI;
     const int iv = (int)(j - i * NI);
-    const bool ok = series_params_ok(a, kinds, i / M, M);
+    const bool ok = series_params_ok(a, kinds, i / M, M, ni);
     const bool real = kinds && kinds[i % M] == GP_SSM_TERM_REAL;
     const TermConst t = !ok ? make_term(1.0, 1.0, 1.0)
                             : (real ? make_real_term(a.sigma[i], a.omega0[i])
@@ -121,10 +130,34 @@ __global__ void k_prep(int64_t B, int M, const CallArgs* __restrict__ args, cons
     series_interval_table(t.beta, interval_centre(iv, t.b1ser, t.wser), c, c + NCOEF);
   }
   if (j < B) {
-    const bool ok = series_params_ok(a, kinds, j, M);
+    const bool ok = series_params_ok(a, kinds, j, M, ni);
     jit[j] = (ok && a.jitter) ? a.jitter[j] : 0.0;
     bad[j] = ok ? 0 : 1;
+    if (ni > 0) {
+      double* row = itab + j * ITAB_W;
+      for (int i = 0; i < MAX_INST; ++i) {
+        const bool have = ok && i < ni;
+        const double amp = (have && a.amp) ? a.amp[j * ni + i] : 1.0;
+        row[ITAB_INVA + i] = 1.0 / amp;
+        row[ITAB_OFF + i] = (have && a.off) ? a.off[j * ni + i] : 0.0;
+        row[ITAB_AMP + i] = amp;
+        row[ITAB_LOGA + i] = log(amp);
+      }
+    }
   }
+}
+
+// writes each measurement's instrument label into bits 16-18 of its event's
+// encoding (ends and instantaneous measurements; other events keep 0)
+__global__ void k_set_inst(int64_t n_ev, uint32_t* __restrict__ info, const int64_t* __restrict__ meas,
+                           const int32_t* __restrict__ label) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_ev) return;
+  uint32_t v = info[e] & ~(7u << EV_INST_SHIFT);
+  const int64_t n = meas[e];
+  const uint32_t k = v & 3u;
+  if (label && n >= 0 && (k == EV_END || k == EV_INSTANT)) v |= (uint32_t)label[n] << EV_INST_SHIFT;
+  info[e] = v;
 }
 
 // Launch order of the work waves, computed on the device each call (it
@@ -206,19 +239,25 @@ __global__ __launch_bounds__(ORDER_THREADS) void k_order(DevPlan p, int M, const
 // gradient partials of a series' work waves summed: one wavefront per series,
 // lane l takes waves l, l + 64, ..., then a fixed-order wave reduction; NaN for
 // a series whose status is not 0
-__global__ __launch_bounds__(WAVE) void k_reduce_grad(DevPlan p, int M, const double* __restrict__ gpart,
+// (with instruments the partials carry 2 ni more rows, written to grad only
+// when the call asks for their derivatives; an amplitude's derivative gains
+// -N_i/a_i from the -log(a_i) of each of the N_i measurements)
+__global__ __launch_bounds__(WAVE) void k_reduce_grad(DevPlan p, DevParams pr, int M, const double* __restrict__ gpart,
                                                       const CallArgs* __restrict__ args) {
   const int64_t b = blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t S = p.n_wv;
   const int32_t s0 = p.series_wv0[b], n = p.series_nwv[b];
-  const int G = 3 * M + 1;
+  const int ni = pr.ni;
+  const int G = 3 * M + 1 + (args->grad_inst ? 2 * ni : 0);
   double* const grad = args->grad;
   const bool good = args->status[b] == 0;
   for (int f = 0; f < G; ++f) {
     double s = 0.0;
     for (int32_t q = lane; q < n; q += WAVE) s += gpart[(int64_t)f * S + s0 + q];
     s = wave_sum(s);
+    const int i = f - (3 * M + 1);
+    if (i >= 0 && i < ni) s -= (double)pr.icnt[b * MAX_INST + i] * pr.itab[b * ITAB_W + ITAB_INVA + i];
     if (lane == 0) grad[b * G + f] = (good && isfinite(s)) ? s : __builtin_nan("");
   }
 }
@@ -246,13 +285,14 @@ __global__ void k_prior_tests(int64_t n, const int64_t* __restrict__ idx, const 
   var_test[o] = v + poison;
 }
 
-KernelSet kernel_set(int M, int J) {
+// X: the plan has real terms or instrument labels
+KernelSet kernel_set(int M, int J, bool X) {
   J = std::max(1, J);
   switch (M) {
-    case 1: return kernels_m1(J);
-    case 2: return kernels_m2(J);
-    case 3: return kernels_m3(J);
-    default: return kernels_m4(J);
+    case 1: return X ? kernels_m1x(J) : kernels_m1(J);
+    case 2: return X ? kernels_m2x(J) : kernels_m2(J);
+    case 3: return X ? kernels_m3x(J) : kernels_m3(J);
+    default: return X ? kernels_m4x(J) : kernels_m4(J);
   }
 }
 
@@ -398,6 +438,9 @@ struct gp_ssm_plan {
   int n_cu = 1;
   int64_t record_budget = 0;  // bytes of per-event records before the backward kernels run in rounds
   int32_t kinds_M = 0;        // number of terms gp_ssm_plan_set_term_kinds described (0: all SHO)
+  int32_t n_inst = 0;         // instruments gp_ssm_plan_set_instruments described (0: none)
+  bool kinds_real = false;    // some term of the kinds is a real term
+  std::vector<int64_t> offsets;  // the series' measurement ranges
   uint64_t gen = 0;  // workspace generation (see DBuf)
   HostPlan host;
   DBuf dt, t, y, r, invd, info, meas;
@@ -410,7 +453,7 @@ struct gp_ssm_plan {
   DBuf pre, suf, segtot, segstate, segfut, segll, segok;
   DBuf pre2, suf2, grptot, grpstate, grpfut;
   DBuf tests_t, tests_idx, tests_c0, tests_before, prior_idx, prior_series;
-  DBuf wv_order, args, kinds;
+  DBuf wv_order, args, kinds, itab, icnt;
   // the call's pointers go to `args` on the call's stream from a ring of
   // pinned host slots; an event per slot marks when its copy has been done
   CallArgs* args_host = nullptr;
@@ -428,7 +471,7 @@ struct gp_ssm_plan {
     return {&tc,       &coef,   &jit,     &pbad,      &summ,      &bstate,    &badj,         &bsmooth,
             &gpart,    &rec,    &status,  &llbuf,     &stage,     &pre,       &suf,          &segtot,
             &segstate, &segfut, &segll,   &segok,     &pre2,      &suf2,      &grptot,       &grpstate,
-            &grpfut,   &wv_order, &args,  &kinds,     &tests_t,   &tests_idx, &tests_c0,  &tests_before,
+            &grpfut,   &wv_order, &args,  &kinds,     &itab,      &tests_t,   &tests_idx, &tests_c0,  &tests_before,
             &prior_idx, &prior_series};
   }
   std::vector<const DBuf*> all_buffers() const {
@@ -436,7 +479,8 @@ struct gp_ssm_plan {
     std::vector<const DBuf*> v = {&dt, &t, &y, &r, &invd, &info, &meas, &seg_chunk0, &seg_nch, &grp_seg0, &grp_nseg,
                                   &series_grp0, &series_ngrp, &wv_series, &wv_nch, &wv_len, &wv_chunk, &wv_ev0,
                                   &chunk_len, &chunk_series, &chunk_wv, &chunk_lane, &chunk_first, &series_chunk0,
-                                  &series_nch, &series_seg0, &series_nseg, &series_wv0, &series_nwv, &series_dt_cdf};
+                                  &series_nch, &series_seg0, &series_nseg, &series_wv0, &series_nwv, &series_dt_cdf,
+                                  &icnt};
     for (DBuf* d : self->workspace()) v.push_back(d);
     return v;
   }
@@ -508,10 +552,16 @@ struct gp_ssm_plan {
     pr.coef = coef.as<double>();
     pr.jit = jit.as<double>();
     pr.bad = pbad.as<int32_t>();
+    pr.itab = n_inst ? itab.as<double>() : nullptr;
+    pr.icnt = n_inst ? icnt.as<int32_t>() : nullptr;
+    pr.ni = n_inst;
     return pr;
   }
 
   const CallArgs* dargs() const { return args.as<CallArgs>(); }
+  // calls with M terms take the kernels with real terms and instrument tables
+  bool extended(int32_t M) const { return has_real(M) || n_inst > 0; }
+  bool has_real(int32_t M) const { return kinds_M == M && kinds_real; }
 };
 
 namespace {
@@ -532,7 +582,8 @@ int check_device() {
 // the call's stream.  Hyperparameters in host memory are first copied into
 // the plan's staging buffer; outputs must be device memory.
 int put_args(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0, const double* quality,
-             const double* jitter, double* loglik, double* grad, int32_t* status, hipStream_t s) {
+             const double* jitter, double* loglik, double* grad, int32_t* status, hipStream_t s,
+             const double* amp = nullptr, const double* off = nullptr, int32_t grad_inst = 0) {
   if (!pl) return fail(GP_SSM_EINVAL, "null plan");
   if (M < 1 || M > GP_SSM_MAX_TERMS) return fail(GP_SSM_EINVAL, "n_terms out of range");
   if (!sigma || !omega0 || !quality) return fail(GP_SSM_EINVAL, "null hyperparameter pointer");
@@ -542,19 +593,24 @@ int put_args(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omeg
   const int64_t B = pl->host.n_series;
   if ((loglik && !device_memory(loglik)) || (grad && !device_memory(grad)) || (status && !device_memory(status)))
     return fail(GP_SSM_EINVAL, "output arrays must be device memory");
-  CallArgs a{sigma, omega0, quality, jitter, loglik, grad, status};
+  if ((amp || off || grad_inst) && pl->n_inst == 0)
+    return fail(GP_SSM_EINVAL, "instrument parameters given, but the plan has no instrument labels "
+                               "(gp_ssm_plan_set_instruments)");
+  const int64_t NI_ = pl->n_inst;
+  CallArgs a{sigma, omega0, quality, jitter, loglik, grad, status, amp, off, grad_inst};
   const bool host_in = !device_memory(sigma) || !device_memory(omega0) || !device_memory(quality) ||
-                       (jitter && !device_memory(jitter));
+                       (jitter && !device_memory(jitter)) || (amp && !device_memory(amp)) ||
+                       (off && !device_memory(off));
   if (host_in) {
     // host hyperparameters: staged through device memory (the copies are
     // ordered on the stream before the kernels that read them)
-    if (int rc = pl->stage.ensure(sizeof(double) * (3 * B * M + B))) return rc;
+    if (int rc = pl->stage.ensure(sizeof(double) * (3 * B * M + B + 2 * B * NI_))) return rc;
     double* d = pl->stage.as<double>();
-    const double* src[4] = {sigma, omega0, quality, jitter};
-    const int64_t cnt[4] = {B * M, B * M, B * M, B};
-    double* dst[4] = {d, d + B * M, d + 2 * B * M, d + 3 * B * M};
-    for (int k = 0; k < 4; ++k) {
-      if (!src[k]) continue;
+    const double* src[6] = {sigma, omega0, quality, jitter, amp, off};
+    const int64_t cnt[6] = {B * M, B * M, B * M, B, B * NI_, B * NI_};
+    double* dst[6] = {d, d + B * M, d + 2 * B * M, d + 3 * B * M, d + 3 * B * M + B, d + 3 * B * M + B + B * NI_};
+    for (int k = 0; k < 6; ++k) {
+      if (!src[k] || cnt[k] == 0) continue;
       HIP_TRY(hipMemcpyAsync(dst[k], src[k], sizeof(double) * cnt[k],
                              device_memory(src[k]) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
     }
@@ -562,6 +618,8 @@ int put_args(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omeg
     a.omega0 = dst[1];
     a.quality = dst[2];
     a.jitter = jitter ? dst[3] : nullptr;
+    a.amp = amp ? dst[4] : nullptr;
+    a.off = off ? dst[5] : nullptr;
   }
   if (!pl->args_host) {
     HIP_TRY(hipHostMalloc((void**)&pl->args_host, sizeof(CallArgs) * ARG_RING, hipHostMallocDefault));
@@ -582,7 +640,7 @@ int put_args(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omeg
 // allocates) and the launches of one step
 // ---------------------------------------------------------------------------
 int record_slots(gp_ssm_plan* pl, int32_t M, bool smooth, RecSlots& rs) {
-  const KernelSet ks = kernel_set(M, pl->host.max_slots);
+  const KernelSet ks = kernel_set(M, pl->host.max_slots, pl->extended(M));
   const int NX = 2 * M;
   const int J = std::max(1, pl->host.max_slots);
   const int D = NX + J;
@@ -619,6 +677,7 @@ int reserve(gp_ssm_plan* pl, int32_t M, int back, bool smooth) {
   int rc = 0;
   if ((rc = pl->tc.ensure(sizeof(TermConst) * B * M)) || (rc = pl->coef.ensure(sizeof(double) * B * M * 2 * NCOEF)) ||
       (rc = pl->jit.ensure(sizeof(double) * B)) || (rc = pl->pbad.ensure(sizeof(int32_t) * B)) ||
+      (rc = pl->itab.ensure(sizeof(double) * ITAB_W * std::max<int64_t>(1, B))) ||
       (rc = pl->wv_order.ensure(sizeof(int32_t) * std::max<int64_t>(1, h.n_wv))) ||
       (rc = pl->args.ensure(sizeof(CallArgs))) ||
       (rc = pl->summ.ensure(sizeof(double) * summary_size(NX) * C)) ||
@@ -640,7 +699,9 @@ int reserve(gp_ssm_plan* pl, int32_t M, int back, bool smooth) {
   if (back) {
     if ((rc = pl->badj.ensure(sizeof(double) * (NX + NXP) * C))) return rc;
     if (smooth && (rc = pl->bsmooth.ensure(sizeof(double) * (NX + NXP) * C))) return rc;
-    if (!smooth && (rc = pl->gpart.ensure(sizeof(double) * (3 * M + 1) * std::max<int64_t>(1, h.n_wv)))) return rc;
+    if (!smooth &&
+        (rc = pl->gpart.ensure(sizeof(double) * (3 * M + 1 + 2 * pl->n_inst) * std::max<int64_t>(1, h.n_wv))))
+      return rc;
     RecSlots rs;
     if ((rc = record_slots(pl, M, smooth, rs))) return rc;
   }
@@ -656,12 +717,15 @@ struct FwdWork {
   double* coef;
   double* jit;
   int32_t* bad;
+  double* itab;
+  const int32_t* icnt;
+  int32_t ni;
   int32_t* order;
   const CallArgs* args;
   double *summ, *bstate, *pre, *suf, *segtot, *segstate, *segfut, *segll;
   int32_t* segok;
   double *pre2, *suf2, *grptot, *grpstate, *grpfut;
-  DevParams params() const { return DevParams{tc, coef, jit, bad}; }
+  DevParams params() const { return DevParams{tc, coef, jit, bad, ni ? itab : nullptr, ni ? icnt : nullptr, ni}; }
 };
 
 FwdWork plan_work(gp_ssm_plan* pl) {
@@ -670,6 +734,9 @@ FwdWork plan_work(gp_ssm_plan* pl) {
   W.coef = pl->coef.as<double>();
   W.jit = pl->jit.as<double>();
   W.bad = pl->pbad.as<int32_t>();
+  W.itab = pl->itab.as<double>();
+  W.icnt = pl->icnt.as<int32_t>();
+  W.ni = pl->n_inst;
   W.order = pl->wv_order.as<int32_t>();
   W.args = pl->dargs();
   W.summ = pl->summ.as<double>();
@@ -711,6 +778,9 @@ size_t carve_work(const gp_ssm_plan* pl, int32_t M, unsigned char* base, FwdWork
   W.coef = (double*)take(sizeof(double) * B * M * 2 * NCOEF);
   W.jit = (double*)take(sizeof(double) * B);
   W.bad = (int32_t*)take(sizeof(int32_t) * B);
+  W.ni = pl->n_inst;
+  W.itab = W.ni ? (double*)take(sizeof(double) * ITAB_W * B) : nullptr;
+  W.icnt = pl->icnt.as<int32_t>();
   W.order = (int32_t*)take(sizeof(int32_t) * std::max<int64_t>(1, h.n_wv));
   W.summ = (double*)take(sizeof(double) * summary_size(NX) * C);
   W.bstate = (double*)take(sizeof(double) * (NX + NXP) * C);
@@ -741,8 +811,8 @@ void enqueue_prep(gp_ssm_plan* pl, const FwdWork& W, int32_t M, hipStream_t s) {
   p.wv_order = W.order;
   prof_begin("k_prep", s);
   const int32_t* kinds = pl->kinds_M == M ? pl->kinds.as<int32_t>() : nullptr;
-  hipLaunchKernelGGL(k_prep, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0, s, B, M, W.args, kinds,
-                     W.tc, W.coef, W.jit, W.bad);
+  hipLaunchKernelGGL(k_prep, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0, s, B, M, W.ni, W.args,
+                     kinds, W.tc, W.coef, W.jit, W.bad, W.itab);
   prof_end("k_prep", s);
   prof_begin("k_order", s);
   hipLaunchKernelGGL(k_order, dim3(1), dim3(ORDER_THREADS), 0, s, p, M, W.tc, pl->series_dt_cdf.as<float>(),
@@ -754,7 +824,7 @@ void enqueue_forward(gp_ssm_plan* pl, const FwdWork& W, int32_t M, hipStream_t s
   DevPlan p = pl->dev();
   p.wv_order = W.order;
   const DevParams pr = W.params();
-  const KernelSet ks = kernel_set(M, pl->host.max_slots);
+  const KernelSet ks = kernel_set(M, pl->host.max_slots, pl->extended(M));
   Launch L{s};
   ks.summaries(L, p, pr, W.summ);
   ScanWork w;
@@ -786,13 +856,13 @@ void enqueue_forward(gp_ssm_plan* pl, const FwdWork& W, int32_t M, hipStream_t s
 
 void enqueue_grad_tail(gp_ssm_plan* pl, int32_t M, hipStream_t s) {
   const DevPlan p = pl->dev();
-  const KernelSet ks = kernel_set(M, pl->host.max_slots);
+  const KernelSet ks = kernel_set(M, pl->host.max_slots, pl->extended(M));
   RecSlots rs;
   (void)record_slots(pl, M, false, rs);  // reserved: no allocation here
   Launch L{s};
   ks.adjoint(L, p, pl->params(), pl->bstate.as<double>(), pl->badj.as<double>(), rs, pl->gpart.as<double>());
   prof_begin("k_reduce_grad", s);
-  hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)pl->host.n_series), dim3(WAVE), 0, s, p, M,
+  hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)pl->host.n_series), dim3(WAVE), 0, s, p, pl->params(), M,
                      pl->gpart.as<double>(), pl->dargs());
   prof_end("k_reduce_grad", s);
 }
@@ -852,7 +922,8 @@ int sync_status(gp_ssm_plan* pl, const int32_t* status, hipStream_t s) {
       if (st[b] == GP_SSM_EPARAM) ++nparam;
       if (first < 0) first = b;
     }
-  if (nparam) return fail(GP_SSM_EPARAM, "sigma, omega0 and Q must be positive and finite, jitter >= 0 and finite (" +
+  if (nparam) return fail(GP_SSM_EPARAM, "sigma, omega0 and Q must be positive and finite, jitter >= 0 and finite, "
+                                             "instrument amplitudes positive and finite, offsets finite (" +
                                              std::to_string(nparam) + " series, first " + std::to_string(first) + ")");
   if (nbad)
     return fail(GP_SSM_ENUMERIC, "non-finite result in " + std::to_string(nbad) + " series (first " +
@@ -914,6 +985,7 @@ int gp_ssm_plan_create(int64_t n_series, const int64_t* offsets, const double* t
     return fail(rc, err);
   }
   pl->record_budget = (opt && opt->record_budget > 0) ? opt->record_budget : DEFAULT_RECORD_BUDGET;
+  pl->offsets = std::move(off);
   (void)hipGetDevice(&pl->device);
   if (hipDeviceGetAttribute(&pl->n_cu, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess ||
       pl->n_cu < 1) {
@@ -956,6 +1028,8 @@ int gp_ssm_plan_set_term_kinds(gp_ssm_plan* pl, int32_t n_terms, const int32_t* 
   if (!pl) return fail(GP_SSM_EINVAL, "null plan");
   if (n_terms == 0 || !kinds) {
     pl->kinds_M = 0;
+    pl->kinds_real = false;
+    ++pl->gen;
     return 0;
   }
   if (n_terms < 1 || n_terms > GP_SSM_MAX_TERMS) return fail(GP_SSM_EINVAL, "n_terms out of range");
@@ -965,6 +1039,46 @@ int gp_ssm_plan_set_term_kinds(gp_ssm_plan* pl, int32_t n_terms, const int32_t* 
   HIP_TRY(hipDeviceSynchronize());  // earlier calls may still read the kinds
   if (int rc = upload(pl->kinds, k)) return rc;
   pl->kinds_M = n_terms;
+  pl->kinds_real = false;
+  for (int32_t v : k) pl->kinds_real = pl->kinds_real || v == GP_SSM_TERM_REAL;
+  ++pl->gen;  // captured steps hold the kernels of the term kinds
+  return 0;
+}
+
+int gp_ssm_plan_set_instruments(gp_ssm_plan* pl, int32_t n_inst, const int32_t* instrument, void* stream) {
+  g_err.clear();
+  if (!pl) return fail(GP_SSM_EINVAL, "null plan");
+  const bool clear = n_inst == 0 || !instrument;
+  if (!clear && (n_inst < 1 || n_inst > GP_SSM_MAX_INSTRUMENTS)) return fail(GP_SSM_EINVAL, "n_inst out of range");
+  const int64_t N = pl->host.n_meas;
+  std::vector<int32_t> lab;
+  if (!clear) {
+    lab.resize(N);
+    if (int rc = host_copy(instrument, sizeof(int32_t) * N, lab.data(), (hipStream_t)stream)) return rc;
+    for (int64_t i = 0; i < N; ++i)
+      if (lab[i] < 0 || lab[i] >= n_inst)
+        return fail(GP_SSM_EINVAL, "instrument label out of range at measurement " + std::to_string(i));
+  }
+  HIP_TRY(hipDeviceSynchronize());  // earlier calls may still read the event encoding
+  DBuf d;
+  if (!clear) {
+    if (int rc = upload(d, lab)) return rc;
+    // measurements of each instrument per series
+    const int64_t B = pl->host.n_series;
+    std::vector<int32_t> cnt(std::max<int64_t>(1, B) * MAX_INST, 0);
+    for (int64_t b = 0; b < B; ++b)
+      for (int64_t i = pl->offsets[b]; i < pl->offsets[b + 1]; ++i) ++cnt[b * MAX_INST + lab[i]];
+    if (int rc = upload(pl->icnt, cnt)) return rc;
+  }
+  const int64_t n_ev = pl->host.n_ev_pad;
+  if (n_ev > 0) {
+    hipLaunchKernelGGL(k_set_inst, dim3((unsigned)((n_ev + 255) / 256)), dim3(256), 0, 0, n_ev, pl->info.as<uint32_t>(),
+                       pl->meas.as<int64_t>(), clear ? nullptr : d.as<int32_t>());
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipDeviceSynchronize());
+  }
+  pl->n_inst = clear ? 0 : n_inst;
+  ++pl->gen;  // captured steps hold the instrument table's presence
   return 0;
 }
 
@@ -990,6 +1104,16 @@ int gp_ssm_plan_loglik(gp_ssm_plan* pl, int32_t M, const double* sigma, const do
   if (!loglik) return fail(GP_SSM_EINVAL, "null loglik");
   hipStream_t s = (hipStream_t)stream;
   if (int rc = put_args(pl, M, sigma, omega0, quality, jitter, loglik, nullptr, status, s)) return rc;
+  return run_step(pl, M, STEP_LOGLIK, s);
+}
+
+int gp_ssm_plan_loglik_inst(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0,
+                            const double* quality, const double* jitter, const double* amp, const double* off,
+                            double* loglik, int32_t* status, void* stream) {
+  g_err.clear();
+  if (!loglik) return fail(GP_SSM_EINVAL, "null loglik");
+  hipStream_t s = (hipStream_t)stream;
+  if (int rc = put_args(pl, M, sigma, omega0, quality, jitter, loglik, nullptr, status, s, amp, off, 0)) return rc;
   return run_step(pl, M, STEP_LOGLIK, s);
 }
 
@@ -1023,9 +1147,9 @@ int gp_ssm_plan_loglik_noalloc(gp_ssm_plan* pl, int32_t M, const double* sigma, 
   return 0;
 }
 
-int gp_ssm_plan_loglik_grad(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0,
-                            const double* quality, const double* jitter, double* loglik, double* grad,
-                            int32_t* status, void* stream) {
+static int plan_loglik_grad(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0,
+                            const double* quality, const double* jitter, const double* amp, const double* off,
+                            int32_t grad_inst, double* loglik, double* grad, int32_t* status, void* stream) {
   g_err.clear();
   if (!loglik || !grad) return fail(GP_SSM_EINVAL, "null output");
   if (!pl) return fail(GP_SSM_EINVAL, "null plan");
@@ -1034,13 +1158,29 @@ int gp_ssm_plan_loglik_grad(gp_ssm_plan* pl, int32_t M, const double* sigma, con
   // when the caller passes none
   if (int rc = pl->status.ensure(sizeof(int32_t) * pl->host.n_series)) return rc;
   int32_t* st = status ? status : pl->status.as<int32_t>();
-  if (int rc = put_args(pl, M, sigma, omega0, quality, jitter, loglik, grad, st, s)) return rc;
+  if (int rc = put_args(pl, M, sigma, omega0, quality, jitter, loglik, grad, st, s, amp, off, grad_inst)) return rc;
   return run_step(pl, M, STEP_GRAD, s);
+}
+
+int gp_ssm_plan_loglik_grad(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0,
+                            const double* quality, const double* jitter, double* loglik, double* grad,
+                            int32_t* status, void* stream) {
+  return plan_loglik_grad(pl, M, sigma, omega0, quality, jitter, nullptr, nullptr, 0, loglik, grad, status, stream);
+}
+
+int gp_ssm_plan_loglik_grad_inst(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0,
+                                 const double* quality, const double* jitter, const double* amp, const double* off,
+                                 double* loglik, double* grad, int32_t* status, void* stream) {
+  if (pl && pl->n_inst == 0) {
+    g_err.clear();
+    return fail(GP_SSM_EINVAL, "the plan has no instrument labels (gp_ssm_plan_set_instruments)");
+  }
+  return plan_loglik_grad(pl, M, sigma, omega0, quality, jitter, amp, off, 1, loglik, grad, status, stream);
 }
 
 // the smoother with optional per-term outputs at the test times
 static int plan_smooth(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0, const double* quality,
-                       const double* jitter, const int64_t* test_offsets, const double* t_test, double* mean_test,
+                       const double* jitter, const double* amp, const double* off, const int64_t* test_offsets, const double* t_test, double* mean_test,
                        double* var_test, double* term_mean, double* term_var, bool want_terms, double* mean_data,
                        double* var_data, double* loglik, int32_t* status, void* stream) {
   g_err.clear();
@@ -1116,12 +1256,12 @@ static int plan_smooth(gp_ssm_plan* pl, int32_t M, const double* sigma, const do
   if (int rc = reserve(pl, M, 1, true)) return rc;
   int32_t* st = status ? status : pl->status.as<int32_t>();
   double* ll = loglik ? loglik : pl->llbuf.as<double>();
-  if (int rc = put_args(pl, M, sigma, omega0, quality, jitter, ll, nullptr, st, s)) return rc;
+  if (int rc = put_args(pl, M, sigma, omega0, quality, jitter, ll, nullptr, st, s, amp, off, 0)) return rc;
   const FwdWork W = plan_work(pl);
   enqueue_prep(pl, W, M, s);
   enqueue_forward(pl, W, M, s, 1, true);
   const DevPlan p = pl->dev();
-  const KernelSet ks = kernel_set(M, h.max_slots);
+  const KernelSet ks = kernel_set(M, h.max_slots, pl->extended(M));
   RecSlots rs;
   if (int rc = record_slots(pl, M, true, rs)) return rc;
   DevTests dt;
@@ -1148,8 +1288,8 @@ int gp_ssm_plan_smooth(gp_ssm_plan* pl, int32_t M, const double* sigma, const do
                        const double* jitter, const int64_t* test_offsets, const double* t_test, double* mean_test,
                        double* var_test, double* mean_data, double* var_data, double* loglik, int32_t* status,
                        void* stream) {
-  return plan_smooth(pl, M, sigma, omega0, quality, jitter, test_offsets, t_test, mean_test, var_test, nullptr,
-                     nullptr, false, mean_data, var_data, loglik, status, stream);
+  return plan_smooth(pl, M, sigma, omega0, quality, jitter, nullptr, nullptr, test_offsets, t_test, mean_test,
+                     var_test, nullptr, nullptr, false, mean_data, var_data, loglik, status, stream);
 }
 
 int gp_ssm_plan_smooth_terms(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0,
@@ -1157,8 +1297,17 @@ int gp_ssm_plan_smooth_terms(gp_ssm_plan* pl, int32_t M, const double* sigma, co
                              const double* t_test, double* mean_test, double* var_test, double* term_mean,
                              double* term_var, double* mean_data, double* var_data, double* loglik, int32_t* status,
                              void* stream) {
-  return plan_smooth(pl, M, sigma, omega0, quality, jitter, test_offsets, t_test, mean_test, var_test, term_mean,
-                     term_var, true, mean_data, var_data, loglik, status, stream);
+  return plan_smooth(pl, M, sigma, omega0, quality, jitter, nullptr, nullptr, test_offsets, t_test, mean_test,
+                     var_test, term_mean, term_var, true, mean_data, var_data, loglik, status, stream);
+}
+
+int gp_ssm_plan_smooth_inst(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0,
+                            const double* quality, const double* jitter, const double* amp, const double* off,
+                            const int64_t* test_offsets, const double* t_test, double* mean_test, double* var_test,
+                            double* term_mean, double* term_var, double* mean_data, double* var_data, double* loglik,
+                            int32_t* status, void* stream) {
+  return plan_smooth(pl, M, sigma, omega0, quality, jitter, amp, off, test_offsets, t_test, mean_test, var_test,
+                     term_mean, term_var, term_mean || term_var, mean_data, var_data, loglik, status, stream);
 }
 
 int gp_ssm_plan_plain_loglik(gp_ssm_plan* pl, int64_t first, int64_t count, int32_t M, const double* sigma,
@@ -1173,7 +1322,7 @@ int gp_ssm_plan_plain_loglik(gp_ssm_plan* pl, int64_t first, int64_t count, int3
   if (int rc = put_args(pl, M, sigma, omega0, quality, jitter, loglik, nullptr, nullptr, s)) return rc;
   enqueue_prep(pl, plan_work(pl), M, s);
   const DevPlan p = pl->dev();
-  const KernelSet ks = kernel_set(M, pl->host.max_slots);
+  const KernelSet ks = kernel_set(M, pl->host.max_slots, pl->extended(M));
   Launch L{s};
   for (int64_t b = first; b < first + count; ++b) {
     ks.plain(L, p, pl->params(), b, loglik);

@@ -797,13 +797,23 @@ struct GradAcc {
   // them out of the register file across the backward sweep leaves room for
   // the step itself
   double* base;
+  // with instruments: the lane's slots of [amplitude 0..7, offset 0..7][lane],
+  // and the series' row of the instrument table
+  double* ib = nullptr;
+  const double* itab = nullptr;
   GPD double& s(int t) const { return base[(0 * M + t) * 64]; }
   GPD double& w(int t) const { return base[(1 * M + t) * 64]; }
   GPD double& q(int t) const { return base[(2 * M + t) * 64]; }
   GPD double& jit() const { return base[(3 * M) * 64]; }
+  GPD double& amp(int i) const { return ib[i * 64]; }
+  GPD double& off(int i) const { return ib[(MAX_INST + i) * 64]; }
   GPD void init() const {
 #pragma unroll
     for (int f = 0; f < 3 * M + 1; ++f) base[f * 64] = 0.0;
+    if (ib) {
+#pragma unroll
+      for (int f = 0; f < 2 * MAX_INST; ++f) ib[f * 64] = 0.0;
+    }
   }
 };
 
@@ -878,11 +888,11 @@ struct DiscGrad {
 
 // discretisation of all terms over one step (values only); the tables of
 // term t start at coef + t * TS
-template <int M, class Acc = DiscFull, int TS = NCOEF>
+template <int M, class Acc = DiscFull, int TS = NCOEF, bool X = true>
 GPD void discretise(const TermConst* tc, const double* coef, double dt, TermQ* tq) {
 #pragma unroll
   for (int t = 0; t < M; ++t) {
-    if (is_real(tc[t])) {  // wavefront-uniform: the term's kind
+    if (is_real<X>(tc[t])) {  // wavefront-uniform: the term's kind
       tq[t] = real_step(tc[t], dt);
       continue;
     }
@@ -899,11 +909,11 @@ GPD void discretise(const TermConst* tc, const double* coef, double dt, TermQ* t
 // with the beta-derivatives of the base functions (db[t*6 + f], a register
 // array or a LaneLds view); the tables of term t (values, then
 // beta-derivatives) start at coef + t * 2 NCOEF
-template <int M, class Acc = DiscFull, class DB>
+template <int M, class Acc = DiscFull, bool X = true, class DB>
 GPD void discretise_dual(const TermConst* tc, const double* coef, double dt, DB&& db, TermQ* tq) {
 #pragma unroll
   for (int t = 0; t < M; ++t) {
-    if (is_real(tc[t])) {  // no beta: real_backprop differentiates the step itself
+    if (is_real<X>(tc[t])) {  // no beta: real_backprop differentiates the step itself
       tq[t] = real_step(tc[t], dt);
 #pragma unroll
       for (int f = 0; f < 6; ++f) db[t * 6 + f] = 0.0;
@@ -939,7 +949,7 @@ GPD void discretise_dual(const TermConst* tc, const double* coef, double dt, DB&
 // computed as A (P (A^T h)) + Q h, and (A P) one column at a time.
 // DBL: the beta-derivatives of the base functions, needed only at the end of
 // the step, wait in the lane's LDS slots dbl instead of registers.
-template <class Dm, bool DBL = false>
+template <class Dm, bool DBL = false, bool X = true>
 GPD void adjoint_step(const double* m, const double* P, double* mb, double* Pb, const TermConst* tc, const double* coef,
                       double dt, uint32_t info, const Obs& o, double jit, const GradAcc<Dm::M>& acc,
                       LaneLds dbl = LaneLds{nullptr}) {
@@ -948,9 +958,9 @@ GPD void adjoint_step(const double* m, const double* P, double* mb, double* Pb, 
   double dbr[DBL ? 1 : 6 * M];
   TermQ tq[M];
   if constexpr (DBL)
-    discretise_dual<M, DiscGrad>(tc, coef, dt, dbl, tq);
+    discretise_dual<M, DiscGrad, X>(tc, coef, dt, dbl, tq);
   else
-    discretise_dual<M, DiscGrad>(tc, coef, dt, dbr, tq);
+    discretise_dual<M, DiscGrad, X>(tc, coef, dt, dbr, tq);
   double oj[J > 0 ? J : 1];
 #pragma unroll
   for (int j = 0; j < J; ++j) oj[j] = ((open >> j) & 1u) ? 1.0 : 0.0;
@@ -1027,13 +1037,25 @@ GPD void adjoint_step(const double* m, const double* P, double* mb, double* Pb, 
     double ub[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) ub[i] = hs * (mb[i] * v - 2.0 * Pu[i]) * iS + h[i] * Sbar;
+    double jw = 2.0 * jit;  // dR/djitter
+    if (X && acc.ib) {
+      // instrument i: the filter sees y' = (y - c)/a and R' = R/a^2, so
+      // dl/da = -(vbar y' + 2 Sbar R')/a, dl/dc = -vbar/a and dR'/djitter =
+      // 2 jitter/a^2 (the -log a per measurement is added per series).
+      // Events without a measurement add zeros (to instrument 0).
+      const uint32_t ii = ev_inst(info);
+      const double ia = acc.itab[ITAB_INVA + ii];
+      acc.amp(ii) -= fma(vbar, o.y, 2.0 * Sbar * o.R) * ia;
+      acc.off(ii) -= vbar * ia;
+      jw *= ia * ia;
+    }
 #pragma unroll
     for (int i = 0; i < D; ++i) mb[i] = fma(-h[i], vbar, mb[i]);
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
       for (int j = i; j < D; ++j) Pb[sidx(i, j, D)] += 0.5 * (ub[i] * h[j] + h[i] * ub[j]);
-    acc.jit() = fma(2.0 * jit, Sbar, acc.jit());
+    acc.jit() = fma(jw, Sbar, acc.jit());
   }
 
   // predict: weights of the step quantities.  Abar = mb- m^T + 2 Pb- (A P).
@@ -1115,7 +1137,7 @@ GPD void adjoint_step(const double* m, const double* P, double* mb, double* Pb, 
       else
         d6[f] = dbr[6 * t + f];
     }
-    if (is_real(tc[t]))
+    if (is_real<X>(tc[t]))
       real_backprop(tc[t], dt, w, acc.s(t), acc.w(t));
     else
       term_backprop(tc[t], tq[t], d6, dt, w, acc.s(t), acc.w(t), acc.q(t));

@@ -323,9 +323,17 @@ GPD TermConst make_real_term(double sigma, double c) {
   t.xser_g = -1.0;
   return t;
 }
-GPD bool is_real(const TermConst& t) { return t.xser < 0.0; }
+// X: real terms may occur (kernels built without them take X = false, and
+// the test folds away)
+template <bool X = true>
+GPD bool is_real(const TermConst& t) {
+  return X && t.xser < 0.0;
+}
 // stationary variance of the term's second state over sigma^2
-GPD double second_prior(const TermConst& t) { return is_real(t) ? 0.0 : 1.0; }
+template <bool X = true>
+GPD double second_prior(const TermConst& t) {
+  return is_real<X>(t) ? 0.0 : 1.0;
+}
 
 // x - 2 (1 - e^-x) + (1 - e^-2x)/2 (the integrated process's variance over
 // 2 sigma^2 / c^2), by its series below x = 0.5, where the closed form
@@ -614,11 +622,18 @@ struct Dims {
 };
 
 // event encoding (32 bits): kind in bits 0-1, slot in bits 2-4, the set of
-// slots open during the step that ends at this event in bits 8-15
+// slots open during the step that ends at this event in bits 8-15, the
+// instrument of a measurement in bits 16-18
 enum : uint32_t { EV_END = 0u, EV_INSTANT = 1u, EV_START = 2u, EV_PAD = 3u };
+constexpr int MAX_INST = 8;
+constexpr uint32_t EV_INST_SHIFT = 16u;
+// a series' row of the instrument table: per instrument 1/amplitude, offset,
+// amplitude and log(amplitude), each block MAX_INST wide
+enum : int { ITAB_INVA = 0, ITAB_OFF = MAX_INST, ITAB_AMP = 2 * MAX_INST, ITAB_LOGA = 3 * MAX_INST, ITAB_W = 4 * MAX_INST };
 GPD uint32_t ev_kind(uint32_t info) { return info & 3u; }
 GPD uint32_t ev_slot(uint32_t info) { return (info >> 2) & 7u; }
 GPD uint32_t ev_open(uint32_t info) { return (info >> 8) & 0xffu; }
+GPD uint32_t ev_inst(uint32_t info) { return (info >> EV_INST_SHIFT) & 7u; }
 
 // ---------------------------------------------------------------------------
 // predict: m <- A m, P <- A P A^T + Q on the augmented state
@@ -729,6 +744,11 @@ GPD void predict_cov(double* P, const TermQ* tq, uint32_t open) {
 // ---------------------------------------------------------------------------
 // observation of one event.  h = e_{z_slot}/delta at an exposure end,
 // h = sum_m e_{x_m} at an instantaneous measurement, none at a start.
+// With instruments, a measurement of instrument i reads a_i h.x + c_i plus
+// noise of variance R (Sec. 2.2's observation matrix scaled per instrument
+// label of Sec. 3.2.3); the filter takes it as the equivalent measurement
+// (y - c_i)/a_i of h.x with variance R/a_i^2, whose density differs by the
+// constant factor 1/a_i (added to the log-likelihood once per series).
 // ---------------------------------------------------------------------------
 struct Obs {
   double a[8];  // weight of each integrator in h (a_j = 1/delta for the slot)
@@ -737,8 +757,9 @@ struct Obs {
   bool has;     // a measurement is made at this event
 };
 
+// itab: the series' row of the instrument table, or null without instruments
 template <class Dm>
-GPD Obs make_obs(uint32_t info, double y, double r, double invd, double jit2) {
+GPD Obs make_obs(uint32_t info, double y, double r, double invd, double jit2, const double* itab = nullptr) {
   Obs o;
   const uint32_t kind = ev_kind(info), slot = ev_slot(info);
   const bool end = (kind == EV_END), inst = (kind == EV_INSTANT);
@@ -746,8 +767,15 @@ GPD Obs make_obs(uint32_t info, double y, double r, double invd, double jit2) {
   for (int j = 0; j < 8; ++j) o.a[j] = (end && (uint32_t)j == slot) ? invd : 0.0;
   o.b = inst ? 1.0 : 0.0;
   o.has = end || inst;
-  o.y = o.has ? y : 0.0;
-  o.R = o.has ? r + jit2 : 1.0;
+  double yy = y, rr = r + jit2;
+  if (itab) {
+    const uint32_t i = ev_inst(info);
+    const double ia = itab[ITAB_INVA + i];
+    yy = (y - itab[ITAB_OFF + i]) * ia;
+    rr = rr * (ia * ia);
+  }
+  o.y = o.has ? yy : 0.0;
+  o.R = o.has ? rr : 1.0;
   return o;
 }
 

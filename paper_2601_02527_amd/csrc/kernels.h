@@ -26,13 +26,28 @@ struct DevPlan {
 // hyperparameters prepared on the device: per (series, term) TermConst and the
 // Taylor coefficients followed by their beta-derivatives (2*NCOEF doubles);
 // bad[b] = 1 when series b's hyperparameters failed validation (its constants
-// are then those of sigma = omega0 = Q = 1, jitter 0, and its outputs NaN)
+// are then those of sigma = omega0 = Q = 1, jitter 0, and its outputs NaN).
+// With instruments (ni > 0): itab[b] is series b's row of the instrument
+// table (ITAB_W doubles, see ITAB_INVA), icnt[b] its number of measurements
+// of each instrument (MAX_INST), and the gradient partials carry 2 ni more
+// rows (amplitudes, then offsets).
 struct DevParams {
   const TermConst* tc;
   const double* coef;
   const double* jit;
   const int32_t* bad;
+  const double* itab = nullptr;
+  const int32_t* icnt = nullptr;
+  int32_t ni = 0;
 };
+
+// -sum over series b's measurements of log(amplitude): the density factor of
+// the rescaled measurements the filter sees (0 without instruments)
+__device__ __forceinline__ double inst_loglik(const DevParams& pr, int64_t b) {
+  double s = 0.0;
+  for (int i = 0; i < pr.ni; ++i) s -= (double)pr.icnt[b * MAX_INST + i] * pr.itab[b * ITAB_W + ITAB_LOGA + i];
+  return s;
+}
 
 // the caller's pointers of one call, read by the kernels from device memory
 // (written there on the call's stream before the kernels), so that a captured
@@ -41,9 +56,11 @@ struct CallArgs {
   const double *sigma, *omega0, *quality, *jitter;
   double *loglik, *grad;
   int32_t* status;
+  // per-series instrument amplitudes and offsets [series][instrument] (null:
+  // 1 and 0), and whether grad rows carry their derivatives
+  const double *amp = nullptr, *off = nullptr;
+  int32_t grad_inst = 0;
 };
-
-
 
 // test-time work of the smoother, assigned to chunks on the host
 struct DevTests {
@@ -92,10 +109,16 @@ struct KernelSet {
   int (*smooth_occupancy)();
 };
 
+// per number of terms: the plain model, and (x) the kernels that also take
+// real exponential terms and instrument tables
 KernelSet kernels_m1(int J);
 KernelSet kernels_m2(int J);
 KernelSet kernels_m3(int J);
 KernelSet kernels_m4(int J);
+KernelSet kernels_m1x(int J);
+KernelSet kernels_m2x(int J);
+KernelSet kernels_m3x(int J);
+KernelSet kernels_m4x(int J);
 
 // kernel timing hooks (capi)
 void prof_begin(const char* name, hipStream_t s);

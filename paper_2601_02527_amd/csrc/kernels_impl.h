@@ -29,10 +29,19 @@ __device__ __forceinline__ void load_terms(const DevParams& pr, int64_t b, TermC
 }
 
 template <class Dm>
-__device__ __forceinline__ Obs load_event(const DevPlan& p, int64_t e, double jit2, double& dt, uint32_t& info) {
+__device__ __forceinline__ Obs load_event(const DevPlan& p, int64_t e, double jit2, double& dt, uint32_t& info,
+                                          const double* itab) {
   dt = p.dt[e];
   info = p.info[e];
-  return make_obs<Dm>(info, p.y[e], p.r[e], p.invd[e], jit2);
+  return make_obs<Dm>(info, p.y[e], p.r[e], p.invd[e], jit2, itab);
+}
+
+// the series' row of the instrument table, copied to LDS (made visible by
+// the barrier of stage_coef, which follows); null without instruments
+__device__ __forceinline__ const double* stage_inst(const DevParams& pr, int64_t b, double* ltab) {
+  if (pr.ni == 0) return nullptr;
+  if (threadIdx.x < ITAB_W) ltab[threadIdx.x] = pr.itab[b * ITAB_W + threadIdx.x];
+  return ltab;
 }
 
 // the series' Taylor tables of all terms, staged in LDS by the workgroup's
@@ -96,7 +105,7 @@ __device__ __forceinline__ double plain_step(double* m, double* P, const TermQ* 
 // ---------------------------------------------------------------------------
 // chunk summaries (conditional filter), one chunk per lane
 // ---------------------------------------------------------------------------
-template <int J>
+template <int J, bool X>
 __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, double* __restrict__ summ) {
   using Dm = Dims<M, J>;
   constexpr int NX = Dm::NX, NXP = Dm::NXP;
@@ -108,6 +117,8 @@ __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, dou
   TermConst tc[M];
   load_terms<Dm>(pr, b, tc);
   __shared__ double lcoef[M * NCOEF];
+  __shared__ double ltab[X ? ITAB_W : 1];
+  const double* itab = X ? stage_inst(pr, b, ltab) : nullptr;
   const double* coef = stage_coef<Dm, false>(pr, b, lcoef);
   const double jit = pr.jit[b];
   const double jit2 = jit * jit;
@@ -128,9 +139,9 @@ __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, dou
   for (int32_t k = 0; k < L; ++k) {
     const EvRaw cur = nxt;
     if (k + 1 < L) nxt = fetch_event(p, ev0 + (int64_t)(k + 1) * WAVE + lane);
-    const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2);
+    const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2, itab);
     TermQ tq[M];
-    discretise<M>(tc, coef, cur.dt, tq);
+    discretise<M, DiscFull, NCOEF, X>(tc, coef, cur.dt, tq);
     st.step(tq, cur.info, o);
   }
   if (lane < nch) {
@@ -160,7 +171,7 @@ __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, dou
 // ---------------------------------------------------------------------------
 // one work wave per workgroup: entry rs.first + blockIdx.x of the launch
 // order; the per-event states of the wave live in the workgroup's record slot
-template <int J>
+template <int J, bool X>
 __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const double* __restrict__ bstate,
                                                   const double* __restrict__ badj, RecSlots rs,
                                                   double* __restrict__ gpart) {
@@ -171,6 +182,8 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
   const int64_t C = p.n_chunks;
   __shared__ double lcoef[M * 2 * NCOEF];
   __shared__ double lacc[(3 * M + 1) * WAVE];
+  __shared__ double ltab[X ? ITAB_W : 1];
+  __shared__ double linst[X ? 2 * MAX_INST * WAVE : 1];
   // with four open exposures the step's registers spill; the beta-derivatives
   // then wait in LDS (9 KB at M = 3)
   constexpr bool DBL = J >= 4;
@@ -186,6 +199,7 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
     const int64_t c = p.wv_chunk[(int64_t)w * WAVE + (active ? lane : 0)];
     TermConst tc[M];
     load_terms<Dm>(pr, b, tc);
+    const double* itab = X ? stage_inst(pr, b, ltab) : nullptr;
     const double* coef = stage_coef<Dm, true>(pr, b, lcoef);
     const double jit = pr.jit[b];
     const double jit2 = jit * jit;
@@ -209,9 +223,9 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
       for (int f = 0; f < D; ++f) __builtin_nontemporal_store(m[f], &rb[((int64_t)k * F + f) * WAVE + lane]);
 #pragma unroll
       for (int f = 0; f < NP; ++f) __builtin_nontemporal_store(P[f], &rb[((int64_t)k * F + D + f) * WAVE + lane]);
-      const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2);
+      const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2, itab);
       TermQ tq[M];
-      discretise<M, DiscGrad, 2 * NCOEF>(tc, coef, cur.dt, tq);
+      discretise<M, DiscGrad, 2 * NCOEF, X>(tc, coef, cur.dt, tq);
       plain_step<Dm, false>(m, P, tq, cur.info, o);
     }
 
@@ -222,7 +236,7 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
     for (int i = 0; i < D; ++i)
 #pragma unroll
       for (int j = i; j < D; ++j) Pb[sidx(i, j, D)] = (j < NX && active) ? badj[(NX + sidx(i, j, NX)) * C + c] : 0.0;
-    const GradAcc<M> acc{lacc + lane};
+    const GradAcc<M> acc{lacc + lane, itab ? linst + lane : nullptr, itab};
     acc.init();
     nxt = fetch_event(p, ev0 + (int64_t)(L - 1) * WAVE + lane);
     for (int32_t k = L - 1; k >= 0; --k) {
@@ -232,14 +246,14 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
       for (int f = 0; f < D; ++f) m[f] = __builtin_nontemporal_load(&rb[((int64_t)k * F + f) * WAVE + lane]);
 #pragma unroll
       for (int f = 0; f < NP; ++f) P[f] = __builtin_nontemporal_load(&rb[((int64_t)k * F + D + f) * WAVE + lane]);
-      const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2);
-      adjoint_step<Dm, DBL>(m, P, mb, Pb, tc, coef, cur.dt, cur.info, o, jit, acc, LaneLds{ldb + lane});
+      const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2, itab);
+      adjoint_step<Dm, DBL, X>(m, P, mb, Pb, tc, coef, cur.dt, cur.info, o, jit, acc, LaneLds{ldb + lane});
     }
     if (active && p.chunk_first[c]) {
       // prior of the SHO states: sigma_t^2 I in scaled coordinates
 #pragma unroll
       for (int t = 0; t < M; ++t)
-        acc.s(t) += 2.0 * tc[t].sigma * (Pb[sidx(2 * t, 2 * t, D)] + second_prior(tc[t]) * Pb[sidx(2 * t + 1, 2 * t + 1, D)]);
+        acc.s(t) += 2.0 * tc[t].sigma * (Pb[sidx(2 * t, 2 * t, D)] + second_prior<X>(tc[t]) * Pb[sidx(2 * t + 1, 2 * t + 1, D)]);
     }
     // sum over the wave's lanes (one series), one partial per work wave
     const int64_t S = p.n_wv;
@@ -256,17 +270,27 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
     }
     const double aj = wave_sum(active ? acc.jit() : 0.0);
     if (lane == 0) gpart[(3 * M) * S + w] = aj;
+    for (int i = 0; i < pr.ni; ++i) {
+      const double ga = wave_sum(active ? acc.amp(i) : 0.0);
+      const double go = wave_sum(active ? acc.off(i) : 0.0);
+      if (lane == 0) {
+        gpart[(3 * M + 1 + i) * S + w] = ga;
+        gpart[(3 * M + 1 + pr.ni + i) * S + w] = go;
+      }
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
 // plain sequential filter of one series (one lane): the reference launch
 // ---------------------------------------------------------------------------
-template <int J>
+template <int J, bool X>
 __global__ __launch_bounds__(WAVE) void k_plain(DevPlan p, DevParams pr, int64_t b, double* __restrict__ loglik) {
   using Dm = Dims<M, J>;
   constexpr int D = Dm::D, NP = Dm::NP;
   __shared__ double lcoef[M * NCOEF];
+  __shared__ double ltab[X ? ITAB_W : 1];
+  const double* itab = X ? stage_inst(pr, b, ltab) : nullptr;
   const double* coef = stage_coef<Dm, false>(pr, b, lcoef);
   if (threadIdx.x != 0) return;
   TermConst tc[M];
@@ -281,7 +305,7 @@ __global__ __launch_bounds__(WAVE) void k_plain(DevPlan p, DevParams pr, int64_t
 #pragma unroll
   for (int t = 0; t < M; ++t) {
     P[sidx(2 * t, 2 * t, D)] = tc[t].sigma * tc[t].sigma;
-    P[sidx(2 * t + 1, 2 * t + 1, D)] = tc[t].sigma * tc[t].sigma * second_prior(tc[t]);
+    P[sidx(2 * t + 1, 2 * t + 1, D)] = tc[t].sigma * tc[t].sigma * second_prior<X>(tc[t]);
   }
   double ll = 0.0;
   const int32_t c0 = p.series_chunk0[b], nch = p.series_nch[b];
@@ -294,13 +318,13 @@ __global__ __launch_bounds__(WAVE) void k_plain(DevPlan p, DevParams pr, int64_t
       const int64_t e = ev0 + (int64_t)k * WAVE + l;
       double dt;
       uint32_t info;
-      const Obs o = load_event<Dm>(p, e, jit2, dt, info);
+      const Obs o = load_event<Dm>(p, e, jit2, dt, info, itab);
       TermQ tq[M];
-      discretise<M>(tc, coef, dt, tq);
+      discretise<M, DiscFull, NCOEF, X>(tc, coef, dt, tq);
       ll += plain_step<Dm>(m, P, tq, info, o);
     }
   }
-  loglik[b] = pr.bad[b] ? __builtin_nan("") : ll;
+  loglik[b] = pr.bad[b] ? __builtin_nan("") : ll + inst_loglik(pr, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -317,7 +341,7 @@ __global__ __launch_bounds__(WAVE) void k_plain(DevPlan p, DevParams pr, int64_t
 // open over the whole step.  With tmean/tvar (a row of M entries) also each
 // term's own process (Appendix C, component-wise predictive means and
 // variances: h = e_{x_m}).
-template <class Dm>
+template <class Dm, bool X>
 __device__ __forceinline__ void bf_test(const double* m0, const double* P0, const TermConst* tc, const double* coef,
                                         double a, double b, uint32_t open, const double* lam0, const double* Lam0,
                                         double& mean, double& var, double* tmean, double* tvar) {
@@ -328,7 +352,7 @@ __device__ __forceinline__ void bf_test(const double* m0, const double* P0, cons
 #pragma unroll
   for (int i = 0; i < NP; ++i) P[i] = P0[i];
   TermQ tq[M];
-  discretise<M>(tc, coef, a, tq);
+  discretise<M, DiscFull, NCOEF, X>(tc, coef, a, tq);
   predict_mean<Dm>(m, tq, open);
   predict_cov<Dm>(P, tq, open);
   double l[D], L[NP];
@@ -336,7 +360,7 @@ __device__ __forceinline__ void bf_test(const double* m0, const double* P0, cons
   for (int i = 0; i < D; ++i) l[i] = lam0[i];
 #pragma unroll
   for (int i = 0; i < NP; ++i) L[i] = Lam0[i];
-  discretise<M>(tc, coef, b, tq);
+  discretise<M, DiscFull, NCOEF, X>(tc, coef, b, tq);
   bf_predict<Dm>(l, L, tq, open);
   // h = sum of the SHO x components
   double u[D], hm = 0.0, hu = 0.0;
@@ -374,10 +398,10 @@ __device__ __forceinline__ void poison_terms(const DevTests& ts, int64_t o, doub
   }
 }
 
-template <int J>
+template <int J, bool X>
 __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& pr, const double* __restrict__ bstate,
                                             const double* __restrict__ bsmooth, double* __restrict__ rb, int w,
-                                            double* lcoef, const DevTests& ts, double* __restrict__ mean_test,
+                                            double* lcoef, double* ltab, const DevTests& ts, double* __restrict__ mean_test,
                                             double* __restrict__ var_test, double* __restrict__ mean_data,
                                             double* __restrict__ var_data) {
   using Dm = Dims<M, J>;
@@ -393,6 +417,7 @@ __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& p
   const int32_t len = active ? p.chunk_len[c] : 0;
   TermConst tc[M];
   load_terms<Dm>(pr, b, tc);
+  const double* itab = X ? stage_inst(pr, b, ltab) : nullptr;
   const double* coef = stage_coef<Dm, false>(pr, b, lcoef);
   const double jit = pr.jit[b];
   const double jit2 = jit * jit;
@@ -407,7 +432,7 @@ __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& p
   };
   // the update of one event applied to its predicted moments, then its close
   auto update_close = [&](const EvRaw& e, double* m, double* P) {
-    const Obs o = make_obs<Dm>(e.info, e.y, e.r, e.invd, jit2);
+    const Obs o = make_obs<Dm>(e.info, e.y, e.r, e.invd, jit2, itab);
     double u[D];
     obs_gain<Dm>(P, o, u);
     const double iS = 1.0 / (obs_dot<Dm>(u, o) + o.R);
@@ -434,7 +459,7 @@ __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& p
   for (int32_t k = 0; k < len; ++k) {
     const EvRaw cur = fetch_event(p, ev(k));
     TermQ tq[M];
-    discretise<M>(tc, coef, cur.dt, tq);
+    discretise<M, DiscFull, NCOEF, X>(tc, coef, cur.dt, tq);
     const uint32_t open = ev_open(cur.info);
     predict_mean<Dm>(m, tq, open);
     predict_cov<Dm>(P, tq, open);
@@ -460,7 +485,7 @@ __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& p
 #pragma unroll
       for (int i = 0; i < NP; ++i) PP[i] = P[i];
       TermQ tqq[M];
-      discretise<M>(tc, coef, ts.t[tp] - tl, tqq);
+      discretise<M, DiscFull, NCOEF, X>(tc, coef, ts.t[tp] - tl, tqq);
       predict_mean<Dm>(mm, tqq, 0u);
       predict_cov<Dm>(PP, tqq, 0u);
       double mean = 0.0, var = 0.0;
@@ -500,16 +525,23 @@ __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& p
     {
       double mp[D], Pp[NP];
       load_rec(k, mp, Pp);
-      const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2);
+      const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2, itab);
       double u[D];
       obs_gain<Dm>(Pp, o, u);
       const double hu = obs_dot<Dm>(u, o), hm = obs_dot<Dm>(mp, o);
       bf_update<Dm>(lam, Lam, u, o, hu + o.R, o.y - hm);
       // posterior at the measurement (the exposure average, or the latent
-      // process for an instantaneous one): the same h as the update
+      // process for an instantaneous one; with instruments, times the
+      // amplitude plus the offset): the same h as the update
       if (o.has) {
         double mean, var;
         bf_posterior<Dm>(hm, hu, u, lam, Lam, mean, var);
+        if (itab) {
+          const uint32_t ii = ev_inst(cur.info);
+          const double a = itab[ITAB_AMP + ii];
+          mean = fma(a, mean, itab[ITAB_OFF + ii]);
+          var *= a * a;
+        }
         const int64_t n = p.meas[ev(k)];
         if (mean_data) mean_data[n] = mean + poison;
         if (var_data) var_data[n] = var + poison;
@@ -526,7 +558,7 @@ __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& p
           const double tq = ts.t[tp];
           double mean, var;
           const int64_t o = ts.out_index[tp];
-          bf_test<Dm>(mf, Pf, tc, coef, tq - tprev, tk - tq, ev_open(cur.info), lam, Lam, mean, var,
+          bf_test<Dm, X>(mf, Pf, tc, coef, tq - tprev, tk - tq, ev_open(cur.info), lam, Lam, mean, var,
                       ts.term_mean ? ts.term_mean + o * M : nullptr, ts.term_var ? ts.term_var + o * M : nullptr);
           poison_terms(ts, o, poison);
           mean_test[o] = mean + poison;
@@ -549,7 +581,7 @@ __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& p
 #pragma unroll
         for (int t = 0; t < M; ++t) {
           pP[sidx(2 * t, 2 * t, D)] = tc[t].sigma * tc[t].sigma;
-          pP[sidx(2 * t + 1, 2 * t + 1, D)] = tc[t].sigma * tc[t].sigma * second_prior(tc[t]);
+          pP[sidx(2 * t + 1, 2 * t + 1, D)] = tc[t].sigma * tc[t].sigma * second_prior<X>(tc[t]);
         }
       }
       const double tprev = ts.chunk_tprev[c];
@@ -557,7 +589,7 @@ __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& p
         const double tq = ts.t[tp];
         double mean, var;
         const int64_t o = ts.out_index[tp];
-        bf_test<Dm>(pm, pP, tc, coef, first ? 0.0 : tq - tprev, tk - tq, ev_open(cur.info), lam, Lam, mean, var,
+        bf_test<Dm, X>(pm, pP, tc, coef, first ? 0.0 : tq - tprev, tk - tq, ev_open(cur.info), lam, Lam, mean, var,
                     ts.term_mean ? ts.term_mean + o * M : nullptr, ts.term_var ? ts.term_var + o * M : nullptr);
         poison_terms(ts, o, poison);
         mean_test[o] = mean + poison;
@@ -567,34 +599,35 @@ __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& p
     }
     // back through this event's predict
     TermQ tq[M];
-    discretise<M>(tc, coef, cur.dt, tq);
+    discretise<M, DiscFull, NCOEF, X>(tc, coef, cur.dt, tq);
     bf_predict<Dm>(lam, Lam, tq, ev_open(cur.info));
   }
 }
 
-template <int J>
+template <int J, bool X>
 __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const double* __restrict__ bstate,
                                                  const double* __restrict__ bsmooth, RecSlots rs, DevTests ts,
                                                  double* __restrict__ mean_test, double* __restrict__ var_test,
                                                  double* __restrict__ mean_data, double* __restrict__ var_data) {
   __shared__ double lcoef[M * NCOEF];
+  __shared__ double ltab[X ? ITAB_W : 1];
   const int32_t qi = rs.first + (int32_t)blockIdx.x;
   const int w = p.wv_order ? p.wv_order[qi] : qi;
   double* const rb = rs.records(p.wv_ev0[w], rec_fields<Dims<M, J>>());
-  smooth_wave<J>(p, pr, bstate, bsmooth, rb, w, lcoef, ts, mean_test, var_test, mean_data, var_data);
+  smooth_wave<J, X>(p, pr, bstate, bsmooth, rb, w, lcoef, ltab, ts, mean_test, var_test, mean_data, var_data);
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <int J>
+template <int J, bool X>
 void launch_summaries(const Launch& L, const DevPlan& p, const DevParams& pr, double* summ) {
   if (p.n_wv == 0) return;
   prof_begin("k_summaries", L.stream);
-  hipLaunchKernelGGL(k_summaries<J>, dim3(p.n_wv), dim3(WAVE), 0, L.stream, p, pr, summ);
+  hipLaunchKernelGGL((k_summaries<J, X>), dim3(p.n_wv), dim3(WAVE), 0, L.stream, p, pr, summ);
   prof_end("k_summaries", L.stream);
 }
-template <int J>
+template <int J, bool X>
 void launch_adjoint(const Launch& L, const DevPlan& p, const DevParams& pr, const double* bstate, const double* badj,
                     const RecSlots& rec, double* gpart) {
   // rounds of at most rec.grid work waves in launch order, one record slot
@@ -603,19 +636,19 @@ void launch_adjoint(const Launch& L, const DevPlan& p, const DevParams& pr, cons
     RecSlots r = rec;
     r.first = first;
     prof_begin("k_adjoint", L.stream);
-    hipLaunchKernelGGL(k_adjoint<J>, dim3(std::min(rec.grid, p.n_wv - first)), dim3(WAVE), 0, L.stream, p, pr,
+    hipLaunchKernelGGL((k_adjoint<J, X>), dim3(std::min(rec.grid, p.n_wv - first)), dim3(WAVE), 0, L.stream, p, pr,
                        bstate, badj, r, gpart);
     prof_end("k_adjoint", L.stream);
   }
 }
-template <int J>
+template <int J, bool X>
 void launch_plain(const Launch& L, const DevPlan& p, const DevParams& pr, int64_t series, double* loglik) {
   prof_begin("k_plain", L.stream);
-  hipLaunchKernelGGL(k_plain<J>, dim3(1), dim3(WAVE), 0, L.stream, p, pr, series, loglik);
+  hipLaunchKernelGGL((k_plain<J, X>), dim3(1), dim3(WAVE), 0, L.stream, p, pr, series, loglik);
   prof_end("k_plain", L.stream);
 }
 
-template <int J>
+template <int J, bool X>
 void launch_smooth(const Launch& L, const DevPlan& p, const DevParams& pr, const double* bstate, const double* bsmooth,
                    const RecSlots& rec, const DevTests& tests, double* mean_test, double* var_test, double* mean_data,
                    double* var_data) {
@@ -623,7 +656,7 @@ void launch_smooth(const Launch& L, const DevPlan& p, const DevParams& pr, const
     RecSlots r = rec;
     r.first = first;
     prof_begin("k_smooth", L.stream);
-    hipLaunchKernelGGL(k_smooth<J>, dim3(std::min(rec.grid, p.n_wv - first)), dim3(WAVE), 0, L.stream, p, pr,
+    hipLaunchKernelGGL((k_smooth<J, X>), dim3(std::min(rec.grid, p.n_wv - first)), dim3(WAVE), 0, L.stream, p, pr,
                        bstate, bsmooth, r, tests, mean_test, var_test, mean_data, var_data);
     prof_end("k_smooth", L.stream);
   }
@@ -638,26 +671,26 @@ int occupancy(K kernel) {
   }
   return n > 0 ? n : 1;
 }
-template <int J>
+template <int J, bool X>
 int adjoint_occupancy() {
-  static const int n = occupancy(k_adjoint<J>);
+  static const int n = occupancy(k_adjoint<J, X>);
   return n;
 }
-template <int J>
+template <int J, bool X>
 int smooth_occupancy() {
-  static const int n = occupancy(k_smooth<J>);
+  static const int n = occupancy(k_smooth<J, X>);
   return n;
 }
 
-template <int J>
+template <int J, bool X>
 KernelSet make_set() {
   KernelSet k;
-  k.summaries = &launch_summaries<J>;
-  k.adjoint = &launch_adjoint<J>;
-  k.plain = &launch_plain<J>;
-  k.smooth = &launch_smooth<J>;
-  k.adjoint_occupancy = &adjoint_occupancy<J>;
-  k.smooth_occupancy = &smooth_occupancy<J>;
+  k.summaries = &launch_summaries<J, X>;
+  k.adjoint = &launch_adjoint<J, X>;
+  k.plain = &launch_plain<J, X>;
+  k.smooth = &launch_smooth<J, X>;
+  k.adjoint_occupancy = &adjoint_occupancy<J, X>;
+  k.smooth_occupancy = &smooth_occupancy<J, X>;
   return k;
 }
 

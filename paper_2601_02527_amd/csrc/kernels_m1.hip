@@ -1,4 +1,5 @@
-// Kernels for 1 SHO term(s); see kernels_impl.h.
+// Kernels for 1 term(s), all SHO and without instrument tables (the plain
+// model); see kernels_impl.h.
 #define GPSSM_M 1
 #define GPSSM_NS m1
 #include "kernels_impl.h"
@@ -6,10 +7,10 @@
 namespace gpssm {
 KernelSet kernels_m1(int J) {
   switch (J) {
-    case 1: return m1::make_set<1>();
-    case 2: return m1::make_set<2>();
-    case 3: return m1::make_set<3>();
-    default: return m1::make_set<4>();
+    case 1: return m1::make_set<1, false>();
+    case 2: return m1::make_set<2, false>();
+    case 3: return m1::make_set<3, false>();
+    default: return m1::make_set<4, false>();
   }
 }
 }  // namespace gpssm

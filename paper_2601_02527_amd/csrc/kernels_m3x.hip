@@ -1,0 +1,16 @@
+// Kernels for 3 term(s) with real exponential terms and per-instrument
+// amplitudes and offsets enabled; see kernels_impl.h.
+#define GPSSM_M 3
+#define GPSSM_NS m3
+#include "kernels_impl.h"
+
+namespace gpssm {
+KernelSet kernels_m3x(int J) {
+  switch (J) {
+    case 1: return m3::make_set<1, true>();
+    case 2: return m3::make_set<2, true>();
+    case 3: return m3::make_set<3, true>();
+    default: return m3::make_set<4, true>();
+  }
+}
+}  // namespace gpssm

@@ -15,7 +15,8 @@
 //               chunk's end, from which follow the gradient of the future
 //               likelihood with respect to the boundary moments and the
 //               smoother's adjoint pair there.
-//  k_series_finish  sums the per-segment log-likelihoods of each series.
+//  k_series_finish  sums the per-segment log-likelihoods of each series (and,
+//                   with instruments, its -log(amplitude) terms).
 //
 // When a series has more than 64 segments, the segment totals are treated as
 // chunk summaries one level up: k_seg_scan over groups of 64 segments,
@@ -302,7 +303,7 @@ __global__ __launch_bounds__(WAVE) void k_series_finish(DevPlan p, DevParams pr,
     ll += segll[s0 + k];
     bad = bad || !segok[s0 + k];
   }
-  ll = wave_sum(ll);
+  ll = wave_sum(ll) + inst_loglik(pr, b);
   const bool good = !__any(bad) && isfinite(ll);
   if (lane == 0) {
     const bool pbad = pr.bad[b] != 0;
