@@ -29,6 +29,11 @@
  *                                                     matrix), Sec. 3.2.3
  *   - reset at exposure starts, update at ends ...... Sec. 3.2.1
  *   - log-likelihood from innovations ............... Sec. 2.4
+ *   - the same filter in square-root (Cholesky-
+ *     factor) form .................................. Sec. 3.2.3 and Sec. 5
+ *                                                     (named as the remedy
+ *                                                     for the filter's loss
+ *                                                     of accuracy)
  *   - integrated RTS smoother ....................... Sec. 3.2.2
  *   - prediction at arbitrary times ................. Sec. 2.5, Algorithm 1
  *   - component-wise prediction (H^m applied to the
@@ -510,6 +515,178 @@ int oracle_loglik(int64_t n, const double* ts, const double* te, const double* y
   }
   ld L = 0;
   rc = run_filter(&md, n_ev, ev, ts, te, y, yerr, amp, off, jitter, &L, NULL, NULL);
+  out_hilo[0] = (double)L;
+  out_hilo[1] = (double)(L - (ld)out_hilo[0]);
+  free(ev);
+  free(slot);
+  return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Square-root (Cholesky-factor) filter                                 */
+/* ------------------------------------------------------------------ */
+/* The same filter with the covariance carried as a factor, P = L L^T (the
+ * square-root form the paper names as the remedy for the filter's loss of
+ * accuracy, Sec. 3.2.3 and Sec. 5): the time update takes L- as the
+ * triangular factor of [A L, G] (G G^T = Qa), by Householder reflections of
+ * its transpose; the measurement update rotates the array
+ *     [ sqrt(R)  h^T L- ]        [ sqrt(S)  0  ]
+ *     [   0        L-   ]  -->   [   kb     L+ ]
+ * by Givens rotations (kb = P- h / sqrt(S)), so that no covariance is formed
+ * by subtraction.  The log-likelihood terms are those of Sec. 2.4. */
+
+/* G with G G^T = Q for a symmetric positive semi-definite Q: Cholesky with
+ * pivots at or below a rounding threshold taken as zero (their column then
+ * zero: such a Q is singular, e.g. identical rows of open integrators). */
+static void psd_factor(int D, ld Q[OR_MAXD][OR_MAXD], ld G[OR_MAXD][OR_MAXD]) {
+  ld scale = 0;
+  for (int i = 0; i < D; ++i) scale = fmaxl(scale, fabsl(Q[i][i]));
+  const ld tiny = scale * 1e-30L;
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) G[i][j] = 0;
+  for (int k = 0; k < D; ++k) {
+    ld d = Q[k][k];
+    for (int j = 0; j < k; ++j) d -= G[k][j] * G[k][j];
+    if (d <= tiny) continue; /* column k stays zero */
+    const ld g = sqrtl(d);
+    G[k][k] = g;
+    for (int i = k + 1; i < D; ++i) {
+      ld v = Q[i][k];
+      for (int j = 0; j < k; ++j) v -= G[i][j] * G[k][j];
+      G[i][k] = v / g;
+    }
+  }
+}
+
+/* L <- lower-triangular factor of B B^T with B = [A L, G] (D x 2D):
+ * Householder QR of B^T, L = R^T. */
+static void sqrt_time_update(int D, ld A[OR_MAXD][OR_MAXD], ld G[OR_MAXD][OR_MAXD], ld L[OR_MAXD][OR_MAXD]) {
+  ld W[2 * OR_MAXD][OR_MAXD]; /* W = B^T */
+  const int n = 2 * D;
+  for (int c = 0; c < D; ++c)
+    for (int r = 0; r < D; ++r) {
+      ld s = 0;
+      for (int k = 0; k < D; ++k) s += A[r][k] * L[k][c];
+      W[c][r] = s;       /* (A L)^T */
+      W[D + c][r] = G[r][c];
+    }
+  for (int k = 0; k < D; ++k) {
+    ld nrm = 0;
+    for (int i = k; i < n; ++i) nrm += W[i][k] * W[i][k];
+    nrm = sqrtl(nrm);
+    if (nrm == 0) continue;
+    const ld alpha = W[k][k] > 0 ? -nrm : nrm;
+    ld v[2 * OR_MAXD];
+    for (int i = 0; i < n; ++i) v[i] = 0;
+    v[k] = W[k][k] - alpha;
+    for (int i = k + 1; i < n; ++i) v[i] = W[i][k];
+    ld vv = 0;
+    for (int i = k; i < n; ++i) vv += v[i] * v[i];
+    if (vv == 0) continue;
+    for (int c = k; c < D; ++c) {
+      ld dot = 0;
+      for (int i = k; i < n; ++i) dot += v[i] * W[i][c];
+      const ld f = 2 * dot / vv;
+      for (int i = k; i < n; ++i) W[i][c] -= f * v[i];
+    }
+  }
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) L[i][j] = (j <= i) ? W[j][i] : 0;
+}
+
+static int run_filter_sqrt(const model_t* md, int64_t n_ev, const ev_t* ev, const double* ts, const double* te,
+                           const double* y, const double* yerr, const double* amp, const double* off, ld jitter,
+                           ld* loglik) {
+  const int D = md->D, M = md->M;
+  ld m[OR_MAXD], L[OR_MAXD][OR_MAXD];
+  for (int i = 0; i < D; ++i) {
+    m[i] = 0;
+    for (int j = 0; j < D; ++j) L[i][j] = 0;
+  }
+  for (int k = 0; k < M; ++k) {
+    L[2 * k][2 * k] = md->sigma[k];
+    L[2 * k + 1][2 * k + 1] = md->kind[k] == TERM_REAL ? 0 : md->sigma[k] * md->w0[k];
+  }
+  for (int j = 0; j < md->J; ++j) L[2 * M + j][2 * M + j] = 1;
+  ld total = 0;
+  ld A[OR_MAXD][OR_MAXD], Qa[OR_MAXD][OR_MAXD], G[OR_MAXD][OR_MAXD];
+  for (int64_t k = 0; k < n_ev; ++k) {
+    const ld dt = (k == 0) ? 0 : ev[k].t - ev[k - 1].t;
+    assemble(md, dt, A, Qa);
+    psd_factor(D, Qa, G);
+    {
+      ld mn[OR_MAXD];
+      for (int i = 0; i < D; ++i) {
+        ld s = 0;
+        for (int c = 0; c < D; ++c) s += A[i][c] * m[c];
+        mn[i] = s;
+      }
+      for (int i = 0; i < D; ++i) m[i] = mn[i];
+    }
+    sqrt_time_update(D, A, G, L);
+    const int64_t i = ev[k].n;
+    if (ev[k].kind == EV_START) {
+      const int z = 2 * M + ev[k].slot;
+      m[z] = 0;
+      for (int a = 0; a < D; ++a) L[z][a] = 0;
+      continue;
+    }
+    ld h[OR_MAXD];
+    const ld an = amp ? (ld)amp[i] : 1;
+    for (int a = 0; a < D; ++a) h[a] = 0;
+    if (ev[k].kind == EV_END)
+      h[2 * M + ev[k].slot] = an / ((ld)te[i] - (ld)ts[i]);
+    else
+      for (int t = 0; t < M; ++t) h[2 * t] = an;
+    /* the array: column 0 = (sqrt R, 0...), columns 1..D = (h^T L; L) */
+    ld X[OR_MAXD + 1][OR_MAXD + 1];
+    for (int r = 0; r <= D; ++r)
+      for (int c = 0; c <= D; ++c) X[r][c] = 0;
+    X[0][0] = sqrtl((ld)yerr[i] * yerr[i] + jitter * jitter);
+    for (int c = 0; c < D; ++c) {
+      ld f = 0;
+      for (int r = 0; r < D; ++r) f += h[r] * L[r][c];
+      X[0][c + 1] = f;
+      for (int r = 0; r < D; ++r) X[r + 1][c + 1] = L[r][c];
+    }
+    for (int c = D; c >= 1; --c) {
+      const ld a = X[0][0], b = X[0][c];
+      if (b == 0) continue;
+      const ld rr = hypotl(a, b);
+      const ld cs = a / rr, sn = b / rr;
+      for (int r = 0; r <= D; ++r) {
+        const ld x0 = X[r][0], x1 = X[r][c];
+        X[r][0] = cs * x0 + sn * x1;
+        X[r][c] = -sn * x0 + cs * x1;
+      }
+    }
+    const ld sS = X[0][0];
+    if (!(sS > 0)) return OR_ENUMERIC;
+    ld hm = 0;
+    for (int a = 0; a < D; ++a) hm += h[a] * m[a];
+    const ld v = (ld)y[i] - (off ? (ld)off[i] : 0) - hm;
+    const ld e = v / sS;
+    for (int a = 0; a < D; ++a) m[a] += X[a + 1][0] * e;
+    for (int r = 0; r < D; ++r)
+      for (int c = 0; c < D; ++c) L[r][c] = X[r + 1][c + 1];
+    total += -0.5L * (logl(TWO_PI) + 2 * logl(sS) + e * e);
+  }
+  *loglik = total;
+  return isfinite(total) ? OR_OK : OR_ENUMERIC;
+}
+
+int oracle_loglik_sqrt(int64_t n, const double* ts, const double* te, const double* y, const double* yerr,
+                       const int32_t* slot_in, int32_t M, const double* sigma, const double* omega0,
+                       const double* quality, const int32_t* kind, const double* amp, const double* off,
+                       double jitter, double* out_hilo) {
+  model_t md;
+  ev_t* ev = NULL;
+  int64_t n_ev = 0;
+  int32_t* slot = NULL;
+  int rc = setup(n, ts, te, y, yerr, slot_in, M, sigma, omega0, quality, kind, amp, off, jitter, &md, &ev, &n_ev, &slot);
+  if (rc) return rc;
+  ld L = 0;
+  rc = run_filter_sqrt(&md, n_ev, ev, ts, te, y, yerr, amp, off, jitter, &L);
   out_hilo[0] = (double)L;
   out_hilo[1] = (double)(L - (ld)out_hilo[0]);
   free(ev);

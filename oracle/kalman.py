@@ -46,6 +46,9 @@ def lib():
             L.oracle_loglik.argtypes = [ctypes.c_int64, _dp, _dp, _dp, _dp, _ip, ctypes.c_int32, _dp, _dp, _dp, _ip,
                                         _dp, _dp, ctypes.c_double, ctypes.c_int32, _dp]
             L.oracle_loglik.restype = ctypes.c_int
+            L.oracle_loglik_sqrt.argtypes = [ctypes.c_int64, _dp, _dp, _dp, _dp, _ip, ctypes.c_int32, _dp, _dp, _dp,
+                                             _ip, _dp, _dp, ctypes.c_double, _dp]
+            L.oracle_loglik_sqrt.restype = ctypes.c_int
             L.oracle_smooth.argtypes = [ctypes.c_int64, _dp, _dp, _dp, _dp, _ip, ctypes.c_int32, _dp, _dp, _dp, _ip,
                                         _dp, _dp, ctypes.c_double, ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
             L.oracle_smooth.restype = ctypes.c_int
@@ -146,6 +149,23 @@ def loglik_hilo(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, slots=None,
     if rc:
         raise OracleError(rc)
     return float(out[0]), float(out[1])
+
+
+def loglik_sqrt(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, slots=None, kinds=None, amp=None, off=None):
+    """Log-likelihood by the square-root (Cholesky-factor) form of the same
+    filter (QR time update, Givens array measurement update), long double."""
+    arrs, terms, sl, slp = _prep(ts, te, y, yerr, sigma, omega0, quality, slots)
+    out = np.zeros(2)
+    M = len(terms[0][0])
+    n = len(arrs[0][0])
+    kd, kp = _kinds(kinds, M)
+    ad, ap = _opt(amp, n)
+    od, op = _opt(off, n)
+    rc = lib().oracle_loglik_sqrt(n, arrs[0][1], arrs[1][1], arrs[2][1], arrs[3][1], slp, M, terms[0][1],
+                                  terms[1][1], terms[2][1], kp, ap, op, float(jitter), _d(out)[1])
+    if rc:
+        raise OracleError(rc)
+    return float(out[0]) + float(out[1])
 
 
 def loglik(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, slots=None, extra_slots=0, kinds=None, amp=None,

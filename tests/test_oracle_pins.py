@@ -733,3 +733,74 @@ def test_instrument_parameters_validated():
     c2[0] = np.nan
     with pytest.raises(kalman.OracleError):
         kalman.loglik(*args, amp=a_n, off=c2)
+
+
+# ---------------------------------------------------------------------------
+# high-precision dense oracle (closed-form exposure integrals, mpmath) and
+# the square-root form of the sequential filter
+# ---------------------------------------------------------------------------
+
+def test_exact_covariance_matches_quadrature_and_appendix_a():
+    """The closed-form window integrals (second antiderivative of the kernel)
+    against the dense oracle's quadrature, and against Appendix A's
+    exposure-averaged kernel for equal exposures."""
+    from oracle import exact
+    b = W.random_small_batch(81, B=1, n_lo=25, n_hi=25, M=2, J=3)
+    s = b.series(0)
+    te = s["te"].copy()
+    te[4] = s["ts"][4]  # an instantaneous sample among exposures
+    Ke = np.array(exact.covariance(s["ts"], te, s["sigma"], s["omega0"], s["quality"]).tolist(), dtype=float)
+    Kd = dense.covariance(s["ts"], te, s["sigma"], s["omega0"], s["quality"])
+    assert np.max(np.abs(Ke - Kd)) < 1e-13 * np.max(np.abs(Kd))
+    sg, w0, q = 1.0, 2.0, 1.5
+    eta = math.sqrt(1 - 1 / (4 * q * q))
+    a, bb, c, d = sg * sg, sg * sg / (2 * eta * q), w0 / (2 * q), eta * w0
+    delta = 0.7
+    for lag in (0.0, 0.3, 2.5):
+        ref = _celerite_integrated(a, bb, c, d, delta, lag)
+        K = exact.covariance([0.0, lag], [delta, lag + delta], [sg], [w0], [q])
+        assert abs(float(K[0, 1]) - ref) < 1e-14 * abs(ref) + 1e-16, (lag, float(K[0, 1]), ref)
+
+
+def test_exact_loglik_matches_kalman_and_dense():
+    from oracle import exact
+    for seed in (82, 83):
+        b = W.random_small_batch(seed, B=1, n_lo=30, n_hi=30, M=2, J=3)
+        s = b.series(0)
+        args = (s["ts"], s["te"], s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"], s["jitter"])
+        Le = exact.loglik(*args)
+        assert abs(Le - kalman.loglik(*args)) < 1e-12 * abs(Le)
+        assert abs(Le - dense.loglik(*args)) < 1e-10 * abs(Le)
+    g = exact.loglik_grad_fd(*args)
+    gk = kalman.loglik_grad_fd(*args)
+    den = np.maximum(np.abs(gk), 1e-3 * np.max(np.abs(gk)))
+    assert np.max(np.abs(g - gk) / den) < 1e-6
+
+
+@pytest.mark.parametrize("seed", [84, 85])
+def test_sqrt_filter_equals_covariance_filter(seed):
+    """The square-root form computes the same likelihood (with instruments'
+    amplitudes and offsets, real terms and overlapping exposures)."""
+    s, inst, amp, off = _inst_case(seed)
+    a_n, c_n = kalman.expand_instruments(inst, amp, off)
+    args = (s["ts"], s["te"], s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"], s["jitter"])
+    for kinds in (None, ["sho", "real"]):
+        L1 = kalman.loglik(*args, kinds=kinds, amp=a_n, off=c_n)
+        L2 = kalman.loglik_sqrt(*args, kinds=kinds, amp=a_n, off=c_n)
+        assert abs(L1 - L2) < 1e-13 * abs(L1), (kinds, L1, L2)
+
+
+@pytest.mark.parametrize("instantaneous", [True, False])
+def test_sqrt_and_exact_oracles_on_nearly_noise_free_data(instantaneous):
+    """Dense sampling with measurement errors down to 1e-9 of the signal:
+    the long-double filters (covariance and square-root form) against the
+    high-precision dense likelihood."""
+    import conditioning_cases as CC
+    from oracle import exact
+    for noise in (1e-5, 1e-9):
+        ts, te, y, yerr, sig, w0, q = CC.smooth(31, 30, noise, 0.5, instantaneous)
+        Le = exact.loglik(ts, te, y, yerr, sig, w0, q, 0.0, dps=80)
+        Ls = kalman.loglik_sqrt(ts, te, y, yerr, sig, w0, q, 0.0)
+        Lc = kalman.loglik(ts, te, y, yerr, sig, w0, q, 0.0)
+        assert abs(Ls - Le) < 1e-12 * abs(Le), (noise, Le, Ls)
+        assert abs(Lc - Le) < 1e-12 * abs(Le), (noise, Le, Lc)
