@@ -135,6 +135,22 @@ __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, dou
   st.Sl = LaneLds{lS + lane};
   st.Il = LaneLds{lI + lane};
   st.init();
+  if (lane < nch && p.chunk_first[p.wv_chunk[(int64_t)w * WAVE + lane]]) {
+    // a series' first chunk starts from the prior itself rather than from a
+    // known state: its summary is then the plain filter's state and
+    // log-likelihood (A = 0, J = 0, eta = 0).  Conditioning on the series'
+    // first state would make the scan combine the wide prior with the
+    // chunk's information about that state, (I + P0 J)^-1, which for dense,
+    // nearly noise-free data has J ~ 1/R and loses every digit.
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+      const double s2 = tc[t].sigma * tc[t].sigma;
+      st.P[sidx(2 * t, 2 * t, Dm::D)] = s2;
+      st.P[sidx(2 * t + 1, 2 * t + 1, Dm::D)] = s2 * second_prior<X>(tc[t]);
+    }
+#pragma unroll
+    for (int i = 0; i < Dm::D * NX; ++i) st.S(i) = 0.0;
+  }
   EvRaw nxt = fetch_event(p, ev0 + lane);
   for (int32_t k = 0; k < L; ++k) {
     const EvRaw cur = nxt;
