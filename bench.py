@@ -285,6 +285,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-legs", action="store_true", help="skip the C2, C3 and C5 configurations")
     ap.add_argument("--no-autotune", action="store_true", help="default plan options instead of the autotuner's")
+    ap.add_argument("--no-instruments", action="store_true",
+                    help="skip the timing of the same batch with per-instrument amplitudes and offsets")
     ap.add_argument("--leg", choices=["C2", "C3", "C5"],
                     help="run only this configuration (for profiling) and print its figures as JSON")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -450,6 +452,30 @@ def main():
                          f"one core: series 0 ({pts1} points) in {secs1:.1f}s"}
         print(f"[bench] cpu {cpu}", file=sys.stderr, flush=True)
 
+    # the same batch and plan with three instrument labels per series (random,
+    # seeded) and their amplitudes and offsets: the extended kernels, and the
+    # gradient's 2 x 3 extra entries
+    inst = None
+    if not args.no_instruments:
+        rng = np.random.default_rng(7)
+        ni = 3
+        lab = rng.integers(0, ni, points).astype(np.int32)
+        amp, off = dev(rng.uniform(0.8, 1.2, (B, ni))), dev(rng.normal(0.0, 0.1, (B, ni)))
+        plan.set_instruments(lab, ni)
+        t_inst = _timed(lambda: plan.loglik_grad_inst(sig, w0, q, jit, amp, off), args.steps, args.warmup)
+        li, gi = plan.loglik_grad_inst(sig, w0, q, jit, amp, off)
+        gp.profile_enable(True)
+        gp.profile_reset()
+        plan.loglik_grad_inst(sig, w0, q, jit, amp, off)
+        torch.cuda.synchronize()
+        pi = gp.profile_read()
+        gp.profile_enable(False)
+        inst = {"instruments": ni, "loglik_grad_ms": t_inst * 1e3, "points_per_s": points / t_inst,
+                "grad_entries": int(gi.shape[1]), "nan_series": int(torch.isnan(li).sum().item()),
+                "kernels_ms": {k: round(v[1] / max(1, v[0]), 4) for k, v in pi.items()}}
+        plan.set_instruments(None)
+        print(f"[bench] instruments {inst}", file=sys.stderr, flush=True)
+
     legs = None
     if not args.no_legs:
         legs = run_legs(gp)
@@ -477,6 +503,7 @@ def main():
         "loglik_only_ms_per_step": ms_ll,
         "loglik_only_points_per_s": points / (ms_ll * 1e-3),
         "plain_gpu": plain,
+        "with_instruments": inst,
         "plan_seconds": t_plan,
         "median_replay_ms": med_ms,
         "ms_per_step_kernel_by_kernel": ms_step_direct,

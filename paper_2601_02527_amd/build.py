@@ -29,6 +29,7 @@ DEVICE_FLAGS = [
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC"]
 
 HIP_SOURCES = ["capi.hip", "scan.hip", "kernels_m1.hip", "kernels_m2.hip", "kernels_m3.hip", "kernels_m4.hip",
+               "kernels_m1i.hip", "kernels_m2i.hip", "kernels_m3i.hip", "kernels_m4i.hip",
                "kernels_m1x.hip", "kernels_m2x.hip", "kernels_m3x.hip", "kernels_m4x.hip"]
 CPP_SOURCES = ["plan.cpp"]
 

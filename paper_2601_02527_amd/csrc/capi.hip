@@ -285,14 +285,30 @@ __global__ void k_prior_tests(int64_t n, const int64_t* __restrict__ idx, const 
   var_test[o] = v + poison;
 }
 
-// X: the plan has real terms or instrument labels
-KernelSet kernel_set(int M, int J, bool X) {
+// features: bit 0 the plan has real terms, bit 1 instrument labels
+KernelSet kernel_set(int M, int J, int features) {
   J = std::max(1, J);
+  if (features & 1) {
+    switch (M) {
+      case 1: return kernels_m1x(J);
+      case 2: return kernels_m2x(J);
+      case 3: return kernels_m3x(J);
+      default: return kernels_m4x(J);
+    }
+  }
+  if (features & 2) {
+    switch (M) {
+      case 1: return kernels_m1i(J);
+      case 2: return kernels_m2i(J);
+      case 3: return kernels_m3i(J);
+      default: return kernels_m4i(J);
+    }
+  }
   switch (M) {
-    case 1: return X ? kernels_m1x(J) : kernels_m1(J);
-    case 2: return X ? kernels_m2x(J) : kernels_m2(J);
-    case 3: return X ? kernels_m3x(J) : kernels_m3(J);
-    default: return X ? kernels_m4x(J) : kernels_m4(J);
+    case 1: return kernels_m1(J);
+    case 2: return kernels_m2(J);
+    case 3: return kernels_m3(J);
+    default: return kernels_m4(J);
   }
 }
 
@@ -559,8 +575,8 @@ struct gp_ssm_plan {
   }
 
   const CallArgs* dargs() const { return args.as<CallArgs>(); }
-  // calls with M terms take the kernels with real terms and instrument tables
-  bool extended(int32_t M) const { return has_real(M) || n_inst > 0; }
+  // the optional features the kernels of calls with M terms must take
+  int features(int32_t M) const { return (has_real(M) ? 1 : 0) | (n_inst > 0 ? 2 : 0); }
   bool has_real(int32_t M) const { return kinds_M == M && kinds_real; }
 };
 
@@ -640,7 +656,7 @@ int put_args(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omeg
 // allocates) and the launches of one step
 // ---------------------------------------------------------------------------
 int record_slots(gp_ssm_plan* pl, int32_t M, bool smooth, RecSlots& rs) {
-  const KernelSet ks = kernel_set(M, pl->host.max_slots, pl->extended(M));
+  const KernelSet ks = kernel_set(M, pl->host.max_slots, pl->features(M));
   const int NX = 2 * M;
   const int J = std::max(1, pl->host.max_slots);
   const int D = NX + J;
@@ -824,7 +840,7 @@ void enqueue_forward(gp_ssm_plan* pl, const FwdWork& W, int32_t M, hipStream_t s
   DevPlan p = pl->dev();
   p.wv_order = W.order;
   const DevParams pr = W.params();
-  const KernelSet ks = kernel_set(M, pl->host.max_slots, pl->extended(M));
+  const KernelSet ks = kernel_set(M, pl->host.max_slots, pl->features(M));
   Launch L{s};
   ks.summaries(L, p, pr, W.summ);
   ScanWork w;
@@ -856,7 +872,7 @@ void enqueue_forward(gp_ssm_plan* pl, const FwdWork& W, int32_t M, hipStream_t s
 
 void enqueue_grad_tail(gp_ssm_plan* pl, int32_t M, hipStream_t s) {
   const DevPlan p = pl->dev();
-  const KernelSet ks = kernel_set(M, pl->host.max_slots, pl->extended(M));
+  const KernelSet ks = kernel_set(M, pl->host.max_slots, pl->features(M));
   RecSlots rs;
   (void)record_slots(pl, M, false, rs);  // reserved: no allocation here
   Launch L{s};
@@ -1261,7 +1277,7 @@ static int plan_smooth(gp_ssm_plan* pl, int32_t M, const double* sigma, const do
   enqueue_prep(pl, W, M, s);
   enqueue_forward(pl, W, M, s, 1, true);
   const DevPlan p = pl->dev();
-  const KernelSet ks = kernel_set(M, h.max_slots, pl->extended(M));
+  const KernelSet ks = kernel_set(M, h.max_slots, pl->features(M));
   RecSlots rs;
   if (int rc = record_slots(pl, M, true, rs)) return rc;
   DevTests dt;
@@ -1322,7 +1338,7 @@ int gp_ssm_plan_plain_loglik(gp_ssm_plan* pl, int64_t first, int64_t count, int3
   if (int rc = put_args(pl, M, sigma, omega0, quality, jitter, loglik, nullptr, nullptr, s)) return rc;
   enqueue_prep(pl, plan_work(pl), M, s);
   const DevPlan p = pl->dev();
-  const KernelSet ks = kernel_set(M, pl->host.max_slots, pl->extended(M));
+  const KernelSet ks = kernel_set(M, pl->host.max_slots, pl->features(M));
   Launch L{s};
   for (int64_t b = first; b < first + count; ++b) {
     ks.plain(L, p, pl->params(), b, loglik);

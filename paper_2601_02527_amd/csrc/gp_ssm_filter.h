@@ -1038,7 +1038,7 @@ GPD void adjoint_step(const double* m, const double* P, double* mb, double* Pb, 
 #pragma unroll
     for (int i = 0; i < D; ++i) ub[i] = hs * (mb[i] * v - 2.0 * Pu[i]) * iS + h[i] * Sbar;
     double jw = 2.0 * jit;  // dR/djitter
-    if (X && acc.ib) {
+    if (acc.ib) {
       // instrument i: the filter sees y' = (y - c)/a and R' = R/a^2, so
       // dl/da = -(vbar y' + 2 Sbar R')/a, dl/dc = -vbar/a and dR'/djitter =
       // 2 jitter/a^2 (the -log a per measurement is added per series).

@@ -109,12 +109,16 @@ struct KernelSet {
   int (*smooth_occupancy)();
 };
 
-// per number of terms: the plain model, and (x) the kernels that also take
-// real exponential terms and instrument tables
+// per number of terms: the plain model, (i) the kernels that also take
+// instrument tables, and (x) those that take real exponential terms as well
 KernelSet kernels_m1(int J);
 KernelSet kernels_m2(int J);
 KernelSet kernels_m3(int J);
 KernelSet kernels_m4(int J);
+KernelSet kernels_m1i(int J);
+KernelSet kernels_m2i(int J);
+KernelSet kernels_m3i(int J);
+KernelSet kernels_m4i(int J);
 KernelSet kernels_m1x(int J);
 KernelSet kernels_m2x(int J);
 KernelSet kernels_m3x(int J);

@@ -1,5 +1,8 @@
 // Kernels for one number of SHO terms (GPSSM_M, set by the including file)
-// and every slot count J = 1..MAX_SLOTS.
+// and every slot count J = 1..MAX_SLOTS.  The template argument FT selects
+// the optional features compiled in: bit 0 real exponential terms, bit 1
+// instrument tables; without them their branches fold away and the register
+// allocation of the plain model is untouched.
 //
 // Work mapping: one wavefront per work wave (up to 64 chunks of one series of
 // similar length, one chunk per lane, found through the plan's wv_chunk).
@@ -105,7 +108,7 @@ __device__ __forceinline__ double plain_step(double* m, double* P, const TermQ* 
 // ---------------------------------------------------------------------------
 // chunk summaries (conditional filter), one chunk per lane
 // ---------------------------------------------------------------------------
-template <int J, bool X>
+template <int J, int FT>
 __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, double* __restrict__ summ) {
   using Dm = Dims<M, J>;
   constexpr int NX = Dm::NX, NXP = Dm::NXP;
@@ -117,8 +120,8 @@ __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, dou
   TermConst tc[M];
   load_terms<Dm>(pr, b, tc);
   __shared__ double lcoef[M * NCOEF];
-  __shared__ double ltab[X ? ITAB_W : 1];
-  const double* itab = X ? stage_inst(pr, b, ltab) : nullptr;
+  __shared__ double ltab[(FT & 2) ? ITAB_W : 1];
+  const double* itab = (FT & 2) ? stage_inst(pr, b, ltab) : nullptr;
   const double* coef = stage_coef<Dm, false>(pr, b, lcoef);
   const double jit = pr.jit[b];
   const double jit2 = jit * jit;
@@ -146,7 +149,7 @@ __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, dou
     for (int t = 0; t < M; ++t) {
       const double s2 = tc[t].sigma * tc[t].sigma;
       st.P[sidx(2 * t, 2 * t, Dm::D)] = s2;
-      st.P[sidx(2 * t + 1, 2 * t + 1, Dm::D)] = s2 * second_prior<X>(tc[t]);
+      st.P[sidx(2 * t + 1, 2 * t + 1, Dm::D)] = s2 * second_prior<(FT & 1) != 0>(tc[t]);
     }
 #pragma unroll
     for (int i = 0; i < Dm::D * NX; ++i) st.S(i) = 0.0;
@@ -157,7 +160,7 @@ __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, dou
     if (k + 1 < L) nxt = fetch_event(p, ev0 + (int64_t)(k + 1) * WAVE + lane);
     const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2, itab);
     TermQ tq[M];
-    discretise<M, DiscFull, NCOEF, X>(tc, coef, cur.dt, tq);
+    discretise<M, DiscFull, NCOEF, (FT & 1) != 0>(tc, coef, cur.dt, tq);
     st.step(tq, cur.info, o);
   }
   if (lane < nch) {
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(WAVE) void k_summaries(DevPlan p, DevParams pr, dou
 // ---------------------------------------------------------------------------
 // one work wave per workgroup: entry rs.first + blockIdx.x of the launch
 // order; the per-event states of the wave live in the workgroup's record slot
-template <int J, bool X>
+template <int J, int FT>
 __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const double* __restrict__ bstate,
                                                   const double* __restrict__ badj, RecSlots rs,
                                                   double* __restrict__ gpart) {
@@ -198,8 +201,8 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
   const int64_t C = p.n_chunks;
   __shared__ double lcoef[M * 2 * NCOEF];
   __shared__ double lacc[(3 * M + 1) * WAVE];
-  __shared__ double ltab[X ? ITAB_W : 1];
-  __shared__ double linst[X ? 2 * MAX_INST * WAVE : 1];
+  __shared__ double ltab[(FT & 2) ? ITAB_W : 1];
+  __shared__ double linst[(FT & 2) ? 2 * MAX_INST * WAVE : 1];
   // with four open exposures the step's registers spill; the beta-derivatives
   // then wait in LDS (9 KB at M = 3)
   constexpr bool DBL = J >= 4;
@@ -215,7 +218,7 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
     const int64_t c = p.wv_chunk[(int64_t)w * WAVE + (active ? lane : 0)];
     TermConst tc[M];
     load_terms<Dm>(pr, b, tc);
-    const double* itab = X ? stage_inst(pr, b, ltab) : nullptr;
+    const double* itab = (FT & 2) ? stage_inst(pr, b, ltab) : nullptr;
     const double* coef = stage_coef<Dm, true>(pr, b, lcoef);
     const double jit = pr.jit[b];
     const double jit2 = jit * jit;
@@ -241,7 +244,7 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
       for (int f = 0; f < NP; ++f) __builtin_nontemporal_store(P[f], &rb[((int64_t)k * F + D + f) * WAVE + lane]);
       const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2, itab);
       TermQ tq[M];
-      discretise<M, DiscGrad, 2 * NCOEF, X>(tc, coef, cur.dt, tq);
+      discretise<M, DiscGrad, 2 * NCOEF, (FT & 1) != 0>(tc, coef, cur.dt, tq);
       plain_step<Dm, false>(m, P, tq, cur.info, o);
     }
 
@@ -263,13 +266,13 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
 #pragma unroll
       for (int f = 0; f < NP; ++f) P[f] = __builtin_nontemporal_load(&rb[((int64_t)k * F + D + f) * WAVE + lane]);
       const Obs o = make_obs<Dm>(cur.info, cur.y, cur.r, cur.invd, jit2, itab);
-      adjoint_step<Dm, DBL, X>(m, P, mb, Pb, tc, coef, cur.dt, cur.info, o, jit, acc, LaneLds{ldb + lane});
+      adjoint_step<Dm, DBL, (FT & 1) != 0>(m, P, mb, Pb, tc, coef, cur.dt, cur.info, o, jit, acc, LaneLds{ldb + lane});
     }
     if (active && p.chunk_first[c]) {
       // prior of the SHO states: sigma_t^2 I in scaled coordinates
 #pragma unroll
       for (int t = 0; t < M; ++t)
-        acc.s(t) += 2.0 * tc[t].sigma * (Pb[sidx(2 * t, 2 * t, D)] + second_prior<X>(tc[t]) * Pb[sidx(2 * t + 1, 2 * t + 1, D)]);
+        acc.s(t) += 2.0 * tc[t].sigma * (Pb[sidx(2 * t, 2 * t, D)] + second_prior<(FT & 1) != 0>(tc[t]) * Pb[sidx(2 * t + 1, 2 * t + 1, D)]);
     }
     // sum over the wave's lanes (one series), one partial per work wave
     const int64_t S = p.n_wv;
@@ -300,13 +303,13 @@ __global__ __launch_bounds__(WAVE) void k_adjoint(DevPlan p, DevParams pr, const
 // ---------------------------------------------------------------------------
 // plain sequential filter of one series (one lane): the reference launch
 // ---------------------------------------------------------------------------
-template <int J, bool X>
+template <int J, int FT>
 __global__ __launch_bounds__(WAVE) void k_plain(DevPlan p, DevParams pr, int64_t b, double* __restrict__ loglik) {
   using Dm = Dims<M, J>;
   constexpr int D = Dm::D, NP = Dm::NP;
   __shared__ double lcoef[M * NCOEF];
-  __shared__ double ltab[X ? ITAB_W : 1];
-  const double* itab = X ? stage_inst(pr, b, ltab) : nullptr;
+  __shared__ double ltab[(FT & 2) ? ITAB_W : 1];
+  const double* itab = (FT & 2) ? stage_inst(pr, b, ltab) : nullptr;
   const double* coef = stage_coef<Dm, false>(pr, b, lcoef);
   if (threadIdx.x != 0) return;
   TermConst tc[M];
@@ -321,7 +324,7 @@ __global__ __launch_bounds__(WAVE) void k_plain(DevPlan p, DevParams pr, int64_t
 #pragma unroll
   for (int t = 0; t < M; ++t) {
     P[sidx(2 * t, 2 * t, D)] = tc[t].sigma * tc[t].sigma;
-    P[sidx(2 * t + 1, 2 * t + 1, D)] = tc[t].sigma * tc[t].sigma * second_prior<X>(tc[t]);
+    P[sidx(2 * t + 1, 2 * t + 1, D)] = tc[t].sigma * tc[t].sigma * second_prior<(FT & 1) != 0>(tc[t]);
   }
   double ll = 0.0;
   const int32_t c0 = p.series_chunk0[b], nch = p.series_nch[b];
@@ -336,7 +339,7 @@ __global__ __launch_bounds__(WAVE) void k_plain(DevPlan p, DevParams pr, int64_t
       uint32_t info;
       const Obs o = load_event<Dm>(p, e, jit2, dt, info, itab);
       TermQ tq[M];
-      discretise<M, DiscFull, NCOEF, X>(tc, coef, dt, tq);
+      discretise<M, DiscFull, NCOEF, (FT & 1) != 0>(tc, coef, dt, tq);
       ll += plain_step<Dm>(m, P, tq, info, o);
     }
   }
@@ -414,7 +417,7 @@ __device__ __forceinline__ void poison_terms(const DevTests& ts, int64_t o, doub
   }
 }
 
-template <int J, bool X>
+template <int J, int FT>
 __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& pr, const double* __restrict__ bstate,
                                             const double* __restrict__ bsmooth, double* __restrict__ rb, int w,
                                             double* lcoef, double* ltab, const DevTests& ts, double* __restrict__ mean_test,
@@ -433,7 +436,7 @@ __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& p
   const int32_t len = active ? p.chunk_len[c] : 0;
   TermConst tc[M];
   load_terms<Dm>(pr, b, tc);
-  const double* itab = X ? stage_inst(pr, b, ltab) : nullptr;
+  const double* itab = (FT & 2) ? stage_inst(pr, b, ltab) : nullptr;
   const double* coef = stage_coef<Dm, false>(pr, b, lcoef);
   const double jit = pr.jit[b];
   const double jit2 = jit * jit;
@@ -475,7 +478,7 @@ __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& p
   for (int32_t k = 0; k < len; ++k) {
     const EvRaw cur = fetch_event(p, ev(k));
     TermQ tq[M];
-    discretise<M, DiscFull, NCOEF, X>(tc, coef, cur.dt, tq);
+    discretise<M, DiscFull, NCOEF, (FT & 1) != 0>(tc, coef, cur.dt, tq);
     const uint32_t open = ev_open(cur.info);
     predict_mean<Dm>(m, tq, open);
     predict_cov<Dm>(P, tq, open);
@@ -501,7 +504,7 @@ __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& p
 #pragma unroll
       for (int i = 0; i < NP; ++i) PP[i] = P[i];
       TermQ tqq[M];
-      discretise<M, DiscFull, NCOEF, X>(tc, coef, ts.t[tp] - tl, tqq);
+      discretise<M, DiscFull, NCOEF, (FT & 1) != 0>(tc, coef, ts.t[tp] - tl, tqq);
       predict_mean<Dm>(mm, tqq, 0u);
       predict_cov<Dm>(PP, tqq, 0u);
       double mean = 0.0, var = 0.0;
@@ -574,7 +577,7 @@ __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& p
           const double tq = ts.t[tp];
           double mean, var;
           const int64_t o = ts.out_index[tp];
-          bf_test<Dm, X>(mf, Pf, tc, coef, tq - tprev, tk - tq, ev_open(cur.info), lam, Lam, mean, var,
+          bf_test<Dm, (FT & 1) != 0>(mf, Pf, tc, coef, tq - tprev, tk - tq, ev_open(cur.info), lam, Lam, mean, var,
                       ts.term_mean ? ts.term_mean + o * M : nullptr, ts.term_var ? ts.term_var + o * M : nullptr);
           poison_terms(ts, o, poison);
           mean_test[o] = mean + poison;
@@ -597,7 +600,7 @@ __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& p
 #pragma unroll
         for (int t = 0; t < M; ++t) {
           pP[sidx(2 * t, 2 * t, D)] = tc[t].sigma * tc[t].sigma;
-          pP[sidx(2 * t + 1, 2 * t + 1, D)] = tc[t].sigma * tc[t].sigma * second_prior<X>(tc[t]);
+          pP[sidx(2 * t + 1, 2 * t + 1, D)] = tc[t].sigma * tc[t].sigma * second_prior<(FT & 1) != 0>(tc[t]);
         }
       }
       const double tprev = ts.chunk_tprev[c];
@@ -605,7 +608,7 @@ __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& p
         const double tq = ts.t[tp];
         double mean, var;
         const int64_t o = ts.out_index[tp];
-        bf_test<Dm, X>(pm, pP, tc, coef, first ? 0.0 : tq - tprev, tk - tq, ev_open(cur.info), lam, Lam, mean, var,
+        bf_test<Dm, (FT & 1) != 0>(pm, pP, tc, coef, first ? 0.0 : tq - tprev, tk - tq, ev_open(cur.info), lam, Lam, mean, var,
                     ts.term_mean ? ts.term_mean + o * M : nullptr, ts.term_var ? ts.term_var + o * M : nullptr);
         poison_terms(ts, o, poison);
         mean_test[o] = mean + poison;
@@ -615,35 +618,35 @@ __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& p
     }
     // back through this event's predict
     TermQ tq[M];
-    discretise<M, DiscFull, NCOEF, X>(tc, coef, cur.dt, tq);
+    discretise<M, DiscFull, NCOEF, (FT & 1) != 0>(tc, coef, cur.dt, tq);
     bf_predict<Dm>(lam, Lam, tq, ev_open(cur.info));
   }
 }
 
-template <int J, bool X>
+template <int J, int FT>
 __global__ __launch_bounds__(WAVE) void k_smooth(DevPlan p, DevParams pr, const double* __restrict__ bstate,
                                                  const double* __restrict__ bsmooth, RecSlots rs, DevTests ts,
                                                  double* __restrict__ mean_test, double* __restrict__ var_test,
                                                  double* __restrict__ mean_data, double* __restrict__ var_data) {
   __shared__ double lcoef[M * NCOEF];
-  __shared__ double ltab[X ? ITAB_W : 1];
+  __shared__ double ltab[(FT & 2) ? ITAB_W : 1];
   const int32_t qi = rs.first + (int32_t)blockIdx.x;
   const int w = p.wv_order ? p.wv_order[qi] : qi;
   double* const rb = rs.records(p.wv_ev0[w], rec_fields<Dims<M, J>>());
-  smooth_wave<J, X>(p, pr, bstate, bsmooth, rb, w, lcoef, ltab, ts, mean_test, var_test, mean_data, var_data);
+  smooth_wave<J, FT>(p, pr, bstate, bsmooth, rb, w, lcoef, ltab, ts, mean_test, var_test, mean_data, var_data);
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <int J, bool X>
+template <int J, int FT>
 void launch_summaries(const Launch& L, const DevPlan& p, const DevParams& pr, double* summ) {
   if (p.n_wv == 0) return;
   prof_begin("k_summaries", L.stream);
-  hipLaunchKernelGGL((k_summaries<J, X>), dim3(p.n_wv), dim3(WAVE), 0, L.stream, p, pr, summ);
+  hipLaunchKernelGGL((k_summaries<J, FT>), dim3(p.n_wv), dim3(WAVE), 0, L.stream, p, pr, summ);
   prof_end("k_summaries", L.stream);
 }
-template <int J, bool X>
+template <int J, int FT>
 void launch_adjoint(const Launch& L, const DevPlan& p, const DevParams& pr, const double* bstate, const double* badj,
                     const RecSlots& rec, double* gpart) {
   // rounds of at most rec.grid work waves in launch order, one record slot
@@ -652,19 +655,19 @@ void launch_adjoint(const Launch& L, const DevPlan& p, const DevParams& pr, cons
     RecSlots r = rec;
     r.first = first;
     prof_begin("k_adjoint", L.stream);
-    hipLaunchKernelGGL((k_adjoint<J, X>), dim3(std::min(rec.grid, p.n_wv - first)), dim3(WAVE), 0, L.stream, p, pr,
+    hipLaunchKernelGGL((k_adjoint<J, FT>), dim3(std::min(rec.grid, p.n_wv - first)), dim3(WAVE), 0, L.stream, p, pr,
                        bstate, badj, r, gpart);
     prof_end("k_adjoint", L.stream);
   }
 }
-template <int J, bool X>
+template <int J, int FT>
 void launch_plain(const Launch& L, const DevPlan& p, const DevParams& pr, int64_t series, double* loglik) {
   prof_begin("k_plain", L.stream);
-  hipLaunchKernelGGL((k_plain<J, X>), dim3(1), dim3(WAVE), 0, L.stream, p, pr, series, loglik);
+  hipLaunchKernelGGL((k_plain<J, FT>), dim3(1), dim3(WAVE), 0, L.stream, p, pr, series, loglik);
   prof_end("k_plain", L.stream);
 }
 
-template <int J, bool X>
+template <int J, int FT>
 void launch_smooth(const Launch& L, const DevPlan& p, const DevParams& pr, const double* bstate, const double* bsmooth,
                    const RecSlots& rec, const DevTests& tests, double* mean_test, double* var_test, double* mean_data,
                    double* var_data) {
@@ -672,7 +675,7 @@ void launch_smooth(const Launch& L, const DevPlan& p, const DevParams& pr, const
     RecSlots r = rec;
     r.first = first;
     prof_begin("k_smooth", L.stream);
-    hipLaunchKernelGGL((k_smooth<J, X>), dim3(std::min(rec.grid, p.n_wv - first)), dim3(WAVE), 0, L.stream, p, pr,
+    hipLaunchKernelGGL((k_smooth<J, FT>), dim3(std::min(rec.grid, p.n_wv - first)), dim3(WAVE), 0, L.stream, p, pr,
                        bstate, bsmooth, r, tests, mean_test, var_test, mean_data, var_data);
     prof_end("k_smooth", L.stream);
   }
@@ -687,26 +690,26 @@ int occupancy(K kernel) {
   }
   return n > 0 ? n : 1;
 }
-template <int J, bool X>
+template <int J, int FT>
 int adjoint_occupancy() {
-  static const int n = occupancy(k_adjoint<J, X>);
+  static const int n = occupancy(k_adjoint<J, FT>);
   return n;
 }
-template <int J, bool X>
+template <int J, int FT>
 int smooth_occupancy() {
-  static const int n = occupancy(k_smooth<J, X>);
+  static const int n = occupancy(k_smooth<J, FT>);
   return n;
 }
 
-template <int J, bool X>
+template <int J, int FT>
 KernelSet make_set() {
   KernelSet k;
-  k.summaries = &launch_summaries<J, X>;
-  k.adjoint = &launch_adjoint<J, X>;
-  k.plain = &launch_plain<J, X>;
-  k.smooth = &launch_smooth<J, X>;
-  k.adjoint_occupancy = &adjoint_occupancy<J, X>;
-  k.smooth_occupancy = &smooth_occupancy<J, X>;
+  k.summaries = &launch_summaries<J, FT>;
+  k.adjoint = &launch_adjoint<J, FT>;
+  k.plain = &launch_plain<J, FT>;
+  k.smooth = &launch_smooth<J, FT>;
+  k.adjoint_occupancy = &adjoint_occupancy<J, FT>;
+  k.smooth_occupancy = &smooth_occupancy<J, FT>;
   return k;
 }
 

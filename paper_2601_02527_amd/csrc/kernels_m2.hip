@@ -7,10 +7,10 @@
 namespace gpssm {
 KernelSet kernels_m2(int J) {
   switch (J) {
-    case 1: return m2::make_set<1, false>();
-    case 2: return m2::make_set<2, false>();
-    case 3: return m2::make_set<3, false>();
-    default: return m2::make_set<4, false>();
+    case 1: return m2::make_set<1, 0>();
+    case 2: return m2::make_set<2, 0>();
+    case 3: return m2::make_set<3, 0>();
+    default: return m2::make_set<4, 0>();
   }
 }
 }  // namespace gpssm

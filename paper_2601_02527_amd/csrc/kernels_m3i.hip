@@ -1,0 +1,16 @@
+// Kernels for 3 term(s), all SHO, with per-instrument amplitudes and
+// offsets enabled; see kernels_impl.h.
+#define GPSSM_M 3
+#define GPSSM_NS m3
+#include "kernels_impl.h"
+
+namespace gpssm {
+KernelSet kernels_m3i(int J) {
+  switch (J) {
+    case 1: return m3::make_set<1, 2>();
+    case 2: return m3::make_set<2, 2>();
+    case 3: return m3::make_set<3, 2>();
+    default: return m3::make_set<4, 2>();
+  }
+}
+}  // namespace gpssm

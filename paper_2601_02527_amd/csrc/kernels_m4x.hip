@@ -7,10 +7,10 @@
 namespace gpssm {
 KernelSet kernels_m4x(int J) {
   switch (J) {
-    case 1: return m4::make_set<1, true>();
-    case 2: return m4::make_set<2, true>();
-    case 3: return m4::make_set<3, true>();
-    default: return m4::make_set<4, true>();
+    case 1: return m4::make_set<1, 3>();
+    case 2: return m4::make_set<2, 3>();
+    case 3: return m4::make_set<3, 3>();
+    default: return m4::make_set<4, 3>();
   }
 }
 }  // namespace gpssm
