@@ -546,6 +546,7 @@ struct gp_ssm_plan {
     p.n_chunks = host.n_chunks;
     p.n_seg = host.n_seg;
     p.n_wv = host.n_wv;
+    p.max_series_nseg = host.max_series_nseg;
     return p;
   }
 
@@ -559,6 +560,7 @@ struct gp_ssm_plan {
     p.series_nseg = series_ngrp.as<int32_t>();
     p.n_chunks = host.n_seg;
     p.n_seg = host.n_grp;
+    p.max_series_nseg = host.max_series_ngrp;
     return p;
   }
 

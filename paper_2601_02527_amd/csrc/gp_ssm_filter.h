@@ -417,18 +417,19 @@ struct Elem {
   }
 };
 
-// A lane's element in an LDS exchange area laid out [field][lane] in the
-// summary field numbering, with the same indexing as Elem<N>.
-template <int N>
+// A lane's element in an LDS exchange area laid out [field][lane] (ST lanes
+// per field) in the summary field numbering, with the same indexing as
+// Elem<N>.
+template <int N, int ST = 64>
 struct ElemLds {
   struct Field {
     const double* p;
-    GPD double operator[](int i) const { return p[i * 64]; }
+    GPD double operator[](int i) const { return p[i * ST]; }
   };
   Field A, b, C, eta, J;
   GPD explicit ElemLds(const double* base)
-      : A{base + sum_A(N) * 64}, b{base + sum_b(N) * 64}, C{base + sum_C(N) * 64}, eta{base + sum_eta(N) * 64},
-        J{base + sum_J(N) * 64} {}
+      : A{base + sum_A(N) * ST}, b{base + sum_b(N) * ST}, C{base + sum_C(N) * ST}, eta{base + sum_eta(N) * ST},
+        J{base + sum_J(N) * ST} {}
 };
 
 // Associative composition of two consecutive summaries (i earlier, j

@@ -21,6 +21,7 @@ struct DevPlan {
   const int32_t* wv_order;  // launch order of the work waves (null: natural order)
   int64_t n_series;
   int32_t n_chunks, n_seg, n_wv;
+  int32_t max_series_nseg;  // the most segments (second level: groups) of one series
 };
 
 // hyperparameters prepared on the device: per (series, term) TermConst and the

@@ -329,6 +329,7 @@ int build_plan(int64_t n_series, const int64_t* offsets, const double* t_start, 
       ++P.n_grp;
     }
     P.series_ngrp[b] = P.n_grp - P.series_grp0[b];
+    P.max_series_ngrp = std::max(P.max_series_ngrp, P.series_ngrp[b]);
     // work waves: the series' chunks longest first, WAVE to a wave
     std::vector<int32_t> order(P.n_chunks - c_first);
     for (size_t q = 0; q < order.size(); ++q) order[q] = c_first + (int32_t)q;

@@ -31,7 +31,7 @@ struct HostPlan {
   int64_t n_events = 0;   // real events
   int64_t n_ev_pad = 0;   // events in the interleaved layout (with padding)
   int32_t n_chunks = 0, n_seg = 0, n_wv = 0, max_chunk_len = 0;
-  int32_t n_grp = 0, max_series_nseg = 0;
+  int32_t n_grp = 0, max_series_nseg = 0, max_series_ngrp = 0;
 
   // interleaved events: work wave w, step k, lane l at wv_ev0[w] + k*WAVE + l
   std::vector<double> dt, t, y, r, invd;

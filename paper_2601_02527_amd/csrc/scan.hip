@@ -50,8 +50,8 @@ __device__ __forceinline__ void prior_state(const DevParams& pr, int64_t b, doub
 }
 
 template <int N>
-__device__ __forceinline__ void lds_put(double* lds, int lane, const Elem<N>& e) {
-  e.store([&](int f, double v) { lds[f * WAVE + lane] = v; });
+__device__ __forceinline__ void lds_put(double* lds, int lane, const Elem<N>& e, int stride = WAVE) {
+  e.store([&](int f, double v) { lds[f * stride + lane] = v; });
 }
 
 template <int N>
@@ -105,16 +105,17 @@ __global__ __launch_bounds__(WAVE) void k_seg_scan(DevPlan p, const double* __re
   (void)ok;
 }
 
-template <int N>
+template <int N, int SW>
 __global__ __launch_bounds__(WAVE) void k_series_scan(DevPlan p, DevParams pr, const double* __restrict__ segtot,
                                                       double* __restrict__ segstate, double* __restrict__ segfut,
                                                       int want_back) {
   constexpr int EF = elem_fields(N);
   constexpr int NP = N * (N + 1) / 2;
-  // xch: the exchange area of the lane scans; blk: each lane's block total
-  __shared__ double lds[2 * EF * WAVE];
+  // xch: the exchange area of the lane scans; blk: each lane's block total;
+  // SW lanes per field (the launch guarantees that no more lanes hold a block)
+  __shared__ double lds[2 * EF * SW];
   double* const xch = lds;
-  double* const blk = lds + EF * WAVE;
+  double* const blk = lds + EF * SW;
   const int64_t b = blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t S = p.n_seg;
@@ -131,22 +132,22 @@ __global__ __launch_bounds__(WAVE) void k_series_scan(DevPlan p, DevParams pr, c
   // each segment total is staged in the lane's exchange slot, so that both
   // operands of the composition are LDS views at fixed offsets)
   if (has) {
-    for (int f = 0; f < EF; ++f) blk[f * WAVE + lane] = segtot[(int64_t)f * S + s0 + lo];
+    for (int f = 0; f < EF; ++f) blk[f * SW + lane] = segtot[(int64_t)f * S + s0 + lo];
     for (int32_t k = lo + 1; k < hi; ++k) {
-      for (int f = 0; f < EF; ++f) xch[f * WAVE + lane] = segtot[(int64_t)f * S + s0 + k];
-      compose<N>(ElemLds<N>(blk + lane), ElemLds<N>(xch + lane), tmp, ok);
-      lds_put<N>(blk, lane, tmp);
+      for (int f = 0; f < EF; ++f) xch[f * SW + lane] = segtot[(int64_t)f * S + s0 + k];
+      compose<N>(ElemLds<N, SW>(blk + lane), ElemLds<N, SW>(xch + lane), tmp, ok);
+      lds_put<N>(blk, lane, tmp, SW);
     }
-    for (int f = 0; f < EF; ++f) xch[f * WAVE + lane] = blk[f * WAVE + lane];
+    for (int f = 0; f < EF; ++f) xch[f * SW + lane] = blk[f * SW + lane];
   }
   __syncthreads();
   // inclusive prefix over the lanes holding a block
 #pragma unroll 1
   for (int d = 1; d < nl; d <<= 1) {
     const bool act = lane >= d && has;
-    if (act) compose<N>(ElemLds<N>(xch + lane - d), ElemLds<N>(xch + lane), tmp, ok);
+    if (act) compose<N>(ElemLds<N, SW>(xch + lane - d), ElemLds<N, SW>(xch + lane), tmp, ok);
     __syncthreads();
-    if (act) lds_put<N>(xch, lane, tmp);
+    if (act) lds_put<N>(xch, lane, tmp, SW);
     __syncthreads();
   }
   // the state entering this lane's block: the prior advanced through the
@@ -156,7 +157,7 @@ __global__ __launch_bounds__(WAVE) void k_series_scan(DevPlan p, DevParams pr, c
     prior_state<N>(pr, b, m, P);
     if (lane > 0) {
       combine_forward<N>(
-          m, P, [&](int f) { return f == sum_c0(N) ? 0.0 : xch[f * WAVE + lane - 1]; }, mn, Pn, ok);
+          m, P, [&](int f) { return f == sum_c0(N) ? 0.0 : xch[f * SW + lane - 1]; }, mn, Pn, ok);
 #pragma unroll
       for (int i = 0; i < N; ++i) m[i] = mn[i];
 #pragma unroll
@@ -179,23 +180,23 @@ __global__ __launch_bounds__(WAVE) void k_series_scan(DevPlan p, DevParams pr, c
   // lane's block is the information of the next lane's suffix
   __syncthreads();
   if (has)
-    for (int f = 0; f < EF; ++f) xch[f * WAVE + lane] = blk[f * WAVE + lane];
+    for (int f = 0; f < EF; ++f) xch[f * SW + lane] = blk[f * SW + lane];
   __syncthreads();
 #pragma unroll 1
   for (int d = 1; d < nl; d <<= 1) {
     const bool act = lane + d < nl;
-    if (act) compose<N>(ElemLds<N>(xch + lane), ElemLds<N>(xch + lane + d), tmp, ok);
+    if (act) compose<N>(ElemLds<N, SW>(xch + lane), ElemLds<N, SW>(xch + lane + d), tmp, ok);
     __syncthreads();
-    if (act) lds_put<N>(xch, lane, tmp);
+    if (act) lds_put<N>(xch, lane, tmp, SW);
     __syncthreads();
   }
   if (!has) return;
   double Jf[NP], ef[N];
   if (lane + 1 < nl) {
 #pragma unroll
-    for (int i = 0; i < NP; ++i) Jf[i] = xch[(sum_J(N) + i) * WAVE + lane + 1];
+    for (int i = 0; i < NP; ++i) Jf[i] = xch[(sum_J(N) + i) * SW + lane + 1];
 #pragma unroll
-    for (int i = 0; i < N; ++i) ef[i] = xch[(sum_eta(N) + i) * WAVE + lane + 1];
+    for (int i = 0; i < N; ++i) ef[i] = xch[(sum_eta(N) + i) * SW + lane + 1];
   } else {
 #pragma unroll
     for (int i = 0; i < NP; ++i) Jf[i] = 0.0;
@@ -383,6 +384,23 @@ void run_scan_n(hipStream_t st, const DevPlan& p, const DevParams& pr, const Sca
   prof_end("k_series_finish", st);
 }
 
+// k_series_scan with LDS for 16 lanes when no series has more than 16
+// segments (the common case of many series): its exchange areas then take
+// 23 KB instead of 93 KB at N = 6, and four workgroups fit in a CU instead
+// of one
+template <int N>
+void launch_series_scan(hipStream_t st, const DevPlan& p, const DevParams& pr, const double* tot, double* state,
+                        double* fut, int back) {
+  prof_begin("k_series_scan", st);
+  if (p.max_series_nseg <= 16)
+    hipLaunchKernelGGL((k_series_scan<N, 16>), dim3((unsigned)p.n_series), dim3(WAVE), 0, st, p, pr, tot, state, fut,
+                       back);
+  else
+    hipLaunchKernelGGL((k_series_scan<N, WAVE>), dim3((unsigned)p.n_series), dim3(WAVE), 0, st, p, pr, tot, state,
+                       fut, back);
+  prof_end("k_series_scan", st);
+}
+
 template <int N>
 void run_levels(hipStream_t st, const DevPlan& p, const DevParams& pr, const ScanWork& w, int back) {
   prof_begin("k_seg_scan", st);
@@ -396,19 +414,13 @@ void run_levels(hipStream_t st, const DevPlan& p, const DevParams& pr, const Sca
     hipLaunchKernelGGL(k_seg_scan<N>, dim3(p2.n_seg), dim3(WAVE), 0, st, p2, w.segtot, w.pre2, w.suf2, w.grptot,
                        back);
     prof_end("k_grp_scan", st);
-    prof_begin("k_series_scan", st);
-    hipLaunchKernelGGL(k_series_scan<N>, dim3((unsigned)p2.n_series), dim3(WAVE), 0, st, p2, pr, w.grptot,
-                       w.grpstate, w.grpfut, back);
-    prof_end("k_series_scan", st);
+    launch_series_scan<N>(st, p2, pr, w.grptot, w.grpstate, w.grpfut, back);
     prof_begin("k_grp_fix", st);
     hipLaunchKernelGGL(k_grp_fix<N>, dim3(p2.n_seg), dim3(WAVE), 0, st, p2, w.pre2, w.suf2, w.grpstate, w.grpfut,
                        w.segstate, w.segfut, back);
     prof_end("k_grp_fix", st);
   } else {
-    prof_begin("k_series_scan", st);
-    hipLaunchKernelGGL(k_series_scan<N>, dim3((unsigned)p.n_series), dim3(WAVE), 0, st, p, pr, w.segtot, w.segstate,
-                       w.segfut, back);
-    prof_end("k_series_scan", st);
+    launch_series_scan<N>(st, p, pr, w.segtot, w.segstate, w.segfut, back);
   }
   prof_begin("k_seg_fix", st);
   hipLaunchKernelGGL(k_seg_fix<N>, dim3(p.n_seg), dim3(WAVE), 0, st, p, w.summ, w.pre, w.suf, w.segstate, w.segfut,
