@@ -17,6 +17,10 @@ covariance form of the long-double filter, lose digits.
   antiderivative, two use k itself.
 * Log-likelihood (Sec. 2.4): Cholesky of K + diag(yerr^2 + jitter^2); its
   gradient by central differences at high precision.
+* Posterior (Sec. 2.1, GP conditioning): at the data, K K_y^-1 y and
+  diag(K - K K_y^-1 K); at test times, with the cross-covariances of the
+  latent f(t*) and the exposure averages (the first antiderivative) and
+  k(0).
 Q = 1/2 exactly (eta = 0) is not supported.
 """
 from __future__ import annotations
@@ -124,6 +128,62 @@ def _loglik_mp(ts, te, y, yerr, sigma, omega0, quality, jitter, dps):
         quad = sum(z[i] ** 2 for i in range(n))
         logdet = 2 * sum(mp.log(L[i, i]) for i in range(n))
         return -(quad + logdet + n * mp.log(2 * mp.pi)) / 2
+
+
+def posterior_data(ts, te, y, yerr, sigma, omega0, quality, jitter=0.0, dps=40):
+    """Posterior mean and variance of the noise-free exposure averages at the
+    data (Sec. 2.1 GP conditioning): K K_y^-1 y and diag(K - K K_y^-1 K)."""
+    with mp.workdps(dps):
+        K = covariance(ts, te, sigma, omega0, quality, dps)
+        n = len(y)
+        Ky = K.copy()
+        for i in range(n):
+            Ky[i, i] += mp.mpf(yerr[i]) ** 2 + mp.mpf(jitter) ** 2
+        L = mp.cholesky(Ky)
+        z = _forward(L, mp.matrix([mp.mpf(v) for v in y]))
+        alpha = _backward(L, z)
+        mean = np.array([float(sum(K[i, k] * alpha[k] for k in range(n))) for i in range(n)])
+        var = np.zeros(n)
+        for i in range(n):
+            w = _forward(L, mp.matrix([K[k, i] for k in range(n)]))
+            var[i] = float(K[i, i] - sum(w[k] ** 2 for k in range(n)))
+        return mean, var
+
+
+def posterior_test(ts, te, y, yerr, sigma, omega0, quality, t_test, jitter=0.0, dps=40):
+    """Posterior mean and variance of the latent f at the test times (Sec. 2.1
+    GP conditioning, with the exposure-averaged cross-covariances)."""
+    with mp.workdps(dps):
+        T = _terms(list(np.atleast_1d(sigma)), list(np.atleast_1d(omega0)), list(np.atleast_1d(quality)))
+        K = covariance(ts, te, sigma, omega0, quality, dps)
+        n = len(y)
+        for i in range(n):
+            K[i, i] += mp.mpf(yerr[i]) ** 2 + mp.mpf(jitter) ** 2
+        L = mp.cholesky(K)
+        alpha = _backward(L, _forward(L, mp.matrix([mp.mpf(v) for v in y])))
+        k0 = _k(T, mp.mpf(0))
+        mean, var = np.zeros(len(t_test)), np.zeros(len(t_test))
+        for q, tq in enumerate(t_test):
+            tq = mp.mpf(tq)
+            ks = mp.matrix(n, 1)
+            for i in range(n):
+                a, b = mp.mpf(ts[i]), mp.mpf(te[i])
+                ks[i] = _k(T, tq - a) if b == a else (_k1(T, tq - a) - _k1(T, tq - b)) / (b - a)
+            mean[q] = float(sum(ks[i] * alpha[i] for i in range(n)))
+            w = _forward(L, ks)
+            var[q] = float(k0 - sum(w[i] ** 2 for i in range(n)))
+        return mean, var
+
+
+def _backward(L, z):
+    n = L.rows
+    x = mp.matrix(n, 1)
+    for i in reversed(range(n)):
+        s = z[i]
+        for k in range(i + 1, n):
+            s -= L[k, i] * x[k]
+        x[i] = s / L[i, i]
+    return x
 
 
 def _forward(L, b):

@@ -711,9 +711,17 @@ GPD void bf_predict(double* lam, double* Lam, const TermQ* tq, uint32_t open) {
 }
 
 // back through a measurement update (u = P h of the predicted covariance,
-// S = h.u + R, v = y - h.m of the predicted mean); no-op without a measurement
+// S = h.u + R, v = y - h.m of the predicted mean); no-op without a
+// measurement.  With ed, also the two numbers that give the posterior of the
+// measured quantity h.x in disturbance form: ed[0] = (v - u.lam)/S and
+// ed[1] = 1/S + u.Lam.u/S^2 from the pair after the update, so that
+//   mean = y - R ed[0],   var = R (1 - R ed[1]).
+// Unlike h.m + u.lam and h.P h - u.Lam.u (the pair before the update, with
+// the predicted moments) these keep their relative accuracy when the
+// posterior variance is far below the predicted one (nearly noise-free
+// data, where the smoothed variance is of order R).
 template <class Dm>
-GPD void bf_update(double* lam, double* Lam, const double* u, const Obs& o, double S, double v) {
+GPD void bf_update(double* lam, double* Lam, const double* u, const Obs& o, double S, double v, double* ed = nullptr) {
   constexpr int M = Dm::M, J = Dm::J, NX = Dm::NX, D = Dm::D;
   if (!o.has) return;
   double hv[D];
@@ -729,6 +737,7 @@ GPD void bf_update(double* lam, double* Lam, const double* u, const Obs& o, doub
 #pragma unroll
   for (int i = 0; i < D; ++i) ul = fma(u[i], lam[i], ul);
   const double c1 = (v - ul) * iS;
+  if (ed) ed[0] = c1;
 #pragma unroll
   for (int i = 0; i < D; ++i) lam[i] = fma(hv[i], c1, lam[i]);
   // w = Lambda u / S, c = u^T Lambda u / S^2 + 1 / S
@@ -744,6 +753,7 @@ GPD void bf_update(double* lam, double* Lam, const double* u, const Obs& o, doub
 #pragma unroll
   for (int i = 0; i < D; ++i) uw = fma(u[i], w[i], uw);
   const double c = (uw + 1.0) * iS;
+  if (ed) ed[1] = c;
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll

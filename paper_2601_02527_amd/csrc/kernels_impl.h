@@ -548,13 +548,15 @@ __device__ __forceinline__ void smooth_wave(const DevPlan& p, const DevParams& p
       double u[D];
       obs_gain<Dm>(Pp, o, u);
       const double hu = obs_dot<Dm>(u, o), hm = obs_dot<Dm>(mp, o);
-      bf_update<Dm>(lam, Lam, u, o, hu + o.R, o.y - hm);
+      double ed[2];
+      bf_update<Dm>(lam, Lam, u, o, hu + o.R, o.y - hm, ed);
       // posterior at the measurement (the exposure average, or the latent
       // process for an instantaneous one; with instruments, times the
-      // amplitude plus the offset): the same h as the update
+      // amplitude plus the offset): the same h as the update, in the
+      // disturbance form of bf_update
       if (o.has) {
-        double mean, var;
-        bf_posterior<Dm>(hm, hu, u, lam, Lam, mean, var);
+        double mean = fma(-o.R, ed[0], o.y);
+        double var = o.R * fma(-o.R, ed[1], 1.0);
         if (itab) {
           const uint32_t ii = ev_inst(cur.info);
           const double a = itab[ITAB_AMP + ii];

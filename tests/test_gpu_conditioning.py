@@ -72,3 +72,31 @@ def test_nearly_noise_free_gradient(lib, instantaneous, omega0):
         e = _grad_err(g[:-1], gref[:-1])
         print(instantaneous, omega0, opt, e)
         assert e < 1e-6
+
+
+@pytest.mark.parametrize("instantaneous", [True, False])
+def test_nearly_noise_free_smoother(lib, instantaneous):
+    """Posterior of the measured quantities at the data, against the
+    high-precision dense posterior, relative to the posterior itself: means
+    within 1e-9 of the posterior standard deviation, variances within 1e-9
+    relative (the smoother takes them in disturbance form, of order R here,
+    far below the predicted variances).  At the test times, where the
+    posterior comes from the predicted moments and the adjoint pair, means
+    within 1e-9 of the posterior standard deviation and variances within
+    1e-5 relative: their absolute error is that of the predicted covariance,
+    a few ulp of the prior variance, against posterior variances down to
+    1e-10 of it."""
+    for noise in (1e-3, 1e-5, 1e-7):
+        ts, te, y, yerr, sig, w0, q = CC.smooth(31, 40, noise, 0.5, instantaneous)
+        tt = np.sort(np.concatenate([np.linspace(ts[0] - 0.2, te[-1] + 0.2, 15), 0.5 * (ts[5:9] + te[6:10])]))
+        md_e, vd_e = exact.posterior_data(ts, te, y, yerr, sig, w0, q, 0.0, dps=60)
+        mt_e, vt_e = exact.posterior_test(ts, te, y, yerr, sig, w0, q, tt, 0.0, dps=60)
+        for opt in (dict(), dict(chunk_min=4, chunk_target=8)):
+            plan = _plan(lib, ts, te, y, yerr, **opt)
+            o = plan.smooth(sig[None], w0[None], q[None], np.zeros(1), np.array([0, len(tt)], dtype=np.int64), tt)
+            md, vd, mt, vt = (o[k].cpu().numpy() for k in ("mean_data", "var_data", "mean_test", "var_test"))
+            errs = (np.max(np.abs(md - md_e) / np.sqrt(vd_e)), np.max(np.abs(vd - vd_e) / vd_e),
+                    np.max(np.abs(mt - mt_e) / np.sqrt(vt_e)), np.max(np.abs(vt - vt_e) / vt_e))
+            print(instantaneous, noise, opt, errs)
+            assert errs[0] < 1e-9 and errs[1] < 1e-9 and errs[2] < 1e-9, errs
+            assert errs[3] < 1e-5, errs

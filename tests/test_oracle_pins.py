@@ -804,3 +804,22 @@ def test_sqrt_and_exact_oracles_on_nearly_noise_free_data(instantaneous):
         Lc = kalman.loglik(ts, te, y, yerr, sig, w0, q, 0.0)
         assert abs(Ls - Le) < 1e-12 * abs(Le), (noise, Le, Ls)
         assert abs(Lc - Le) < 1e-12 * abs(Le), (noise, Le, Lc)
+
+
+def test_exact_posterior_matches_dense_and_kalman():
+    """The high-precision posterior (data and test times) against the dense
+    oracle's and the long-double smoother's, at ordinary noise."""
+    from oracle import exact
+    b = W.random_small_batch(86, B=1, n_lo=25, n_hi=25, M=2, J=3)
+    s = b.series(0)
+    args = (s["ts"], s["te"], s["y"], s["yerr"], s["sigma"], s["omega0"], s["quality"], s["jitter"])
+    tt = np.linspace(s["ts"].min() - 0.05, s["te"].max() + 0.05, 9)
+    md, vd = exact.posterior_data(*args)
+    mt, vt = exact.posterior_test(*args[:7], tt, args[7])
+    md2, vd2, mt2, vt2 = dense.posterior(*args, t_test=tt)
+    _, mt3, vt3, md3, vd3 = kalman.smooth(*args, t_test=tt)
+    k0 = float(np.sum(np.asarray(s["sigma"]) ** 2))
+    for a, b_, c in ((md, md2, md3), (mt, mt2, mt3)):
+        assert np.max(np.abs(a - b_)) < 1e-11 * math.sqrt(k0) and np.max(np.abs(a - c)) < 1e-12 * math.sqrt(k0)
+    for a, b_, c in ((vd, vd2, vd3), (vt, vt2, vt3)):
+        assert np.max(np.abs(a - b_)) < 1e-11 * k0 and np.max(np.abs(a - c)) < 1e-12 * k0
