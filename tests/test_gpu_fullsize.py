@@ -71,6 +71,43 @@ def test_grad_1024_sampled(lib):
     _free()
 
 
+def test_grad_1024_instruments_sampled(lib):
+    """The gradient batch with three instrument labels per series and their
+    amplitudes and offsets, drawn as bench.py draws them for its
+    with_instruments timing: sampled series' log-likelihood and one series'
+    full gradient (hyperparameters, amplitudes, offsets) against the oracle."""
+    b = W.grad_1024()
+    B, points = b.n_series, int(b.offsets[-1])
+    rng = np.random.default_rng(7)
+    ni = 3
+    lab = rng.integers(0, ni, points).astype(np.int32)
+    amp, off = rng.uniform(0.8, 1.2, (B, ni)), rng.normal(0.0, 0.1, (B, ni))
+    plan = lib.Plan(b.offsets, b.t_start, b.t_end, b.y, b.yerr)
+    plan.set_instruments(lab, ni)
+    ll, g = plan.loglik_grad_inst(b.sigma, b.omega0, b.quality, b.jitter, amp, off)
+    ll, g = ll.cpu().numpy(), g.cpu().numpy()
+    assert np.all(np.isfinite(ll)) and np.all(np.isfinite(g)) and g.shape == (B, 3 * b.n_terms + 1 + 2 * ni)
+    for i in (0, 700, 1023):
+        s = b.series(i)
+        lo, hi = int(b.offsets[i]), int(b.offsets[i + 1])
+        a_n, c_n = kalman.expand_instruments(lab[lo:hi], amp[i], off[i])
+        ref = kalman.loglik(*_args(s), amp=a_n, off=c_n)
+        rel = abs(ll[i] - ref) / abs(ref)
+        print("series", i, "rel", rel)
+        assert rel < LL_TOL, (i, rel)
+    i = 700
+    s = b.series(i)
+    lo, hi = int(b.offsets[i]), int(b.offsets[i + 1])
+    a_n, c_n = kalman.expand_instruments(lab[lo:hi], amp[i], off[i])
+    gref = np.concatenate([kalman.loglik_grad_fd(*_args(s), amp=a_n, off=c_n),
+                           kalman.loglik_grad_inst_fd(*_args(s), lab[lo:hi], amp[i], off[i])])
+    e = _grad_err(g[i], gref)
+    print("gradient of series", i, "err", e)
+    assert e < GRAD_TOL, e
+    del plan
+    _free()
+
+
 def test_batch_4096_sampled(lib):
     """4096 series of 1e3-5e4 exposures: the shortest, a median and the
     longest series against the oracle, the shortest's gradient against finite
