@@ -10,6 +10,12 @@ the device is missing.
     ll = plan.loglik(sigma, omega0, quality, jitter)        # [B]
     ll, g = plan.loglik_grad(sigma, omega0, quality, jitter)  # g: [B, 3M+1]
     ll = loglik_autograd(plan, sigma, omega0, quality, jitter)  # differentiable
+    out = plan.smooth(sigma, omega0, quality, jitter, test_offsets, t_test)
+
+    plan.set_term_kinds(["sho", "real"])                    # real exponential terms
+    plan.set_instruments(labels, n_inst)                    # per-measurement labels
+    ll, g = plan.loglik_grad_inst(sigma, omega0, quality, jitter, amp, off)
+    ll = loglik_inst_autograd(plan, sigma, omega0, quality, jitter, amp, off)
 """
 from __future__ import annotations
 
@@ -438,7 +444,42 @@ def _autograd_function():
     return LogLikelihood
 
 
+def _autograd_inst_function():
+    torch = _torch()
+
+    class LogLikelihoodInst(torch.autograd.Function):
+        """log-likelihood per series with per-instrument amplitudes and
+        offsets, and its gradient from the adjoint kernel."""
+
+        @staticmethod
+        def forward(ctx, sigma, omega0, quality, jitter, amp, off, plan):
+            ll, g = plan.loglik_grad_inst(sigma, omega0, quality, jitter, amp, off)
+            ctx.save_for_backward(g)
+            ctx.M = sigma.reshape(plan.n_series, -1).shape[1]
+            ctx.ni = plan.n_inst
+            ctx.shapes = (sigma.shape, omega0.shape, quality.shape, None if jitter is None else jitter.shape,
+                          None if amp is None else amp.shape, None if off is None else off.shape)
+            return ll
+
+        @staticmethod
+        def backward(ctx, gout):
+            (g,) = ctx.saved_tensors
+            M, ni, sh = ctx.M, ctx.ni, ctx.shapes
+            gg = g * gout[:, None]
+            ds = gg[:, :M].reshape(sh[0])
+            dw = gg[:, M:2 * M].reshape(sh[1])
+            dq = gg[:, 2 * M:3 * M].reshape(sh[2])
+            dj = None if sh[3] is None else gg[:, 3 * M].reshape(sh[3])
+            k = 3 * M + 1
+            da = None if sh[4] is None else gg[:, k:k + ni].reshape(sh[4])
+            dc = None if sh[5] is None else gg[:, k + ni:k + 2 * ni].reshape(sh[5])
+            return ds, dw, dq, dj, da, dc, None
+
+    return LogLikelihoodInst
+
+
 _LL = None
+_LLI = None
 
 
 def loglik_autograd(plan, sigma, omega0, quality, jitter=None):
@@ -447,6 +488,15 @@ def loglik_autograd(plan, sigma, omega0, quality, jitter=None):
     if _LL is None:
         _LL = _autograd_function()
     return _LL.apply(sigma, omega0, quality, jitter, plan)
+
+
+def loglik_inst_autograd(plan, sigma, omega0, quality, jitter=None, amp=None, off=None):
+    """Differentiable log-likelihood with per-instrument amplitudes and
+    offsets ([B, n_inst] tensors, after plan.set_instruments)."""
+    global _LLI
+    if _LLI is None:
+        _LLI = _autograd_inst_function()
+    return _LLI.apply(sigma, omega0, quality, jitter, amp, off, plan)
 
 
 def autotune_candidates():

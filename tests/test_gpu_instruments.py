@@ -199,3 +199,23 @@ def test_instrument_parameters_from_host_memory(lib):
     assert rc == 0
     torch.cuda.synchronize()
     assert np.all(out.cpu().numpy() == ref)
+
+
+def test_instrument_autograd_function(lib):
+    """loglik_inst_autograd: the library's gradient reaches every input
+    (hyperparameters, amplitudes, offsets), scaled by the upstream weights."""
+    import torch
+    b, lab, amp, off = _case(717, B=3)
+    plan = lib.Plan(b.offsets, b.t_start, b.t_end, b.y, b.yerr)
+    plan.set_instruments(lab, 3)
+    t = [torch.tensor(a, device="cuda", requires_grad=True) for a in (b.sigma, b.omega0, b.quality, b.jitter, amp, off)]
+    ll = lib.loglik_inst_autograd(plan, *t)
+    wts = torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64, device="cuda")
+    (ll * wts).sum().backward()
+    _, g = plan.loglik_grad_inst(b.sigma, b.omega0, b.quality, b.jitter, amp, off)
+    g = g.cpu().numpy() * np.array([1.0, -2.0, 0.5])[:, None]
+    M = b.n_terms
+    cols = [slice(0, M), slice(M, 2 * M), slice(2 * M, 3 * M), 3 * M, slice(3 * M + 1, 3 * M + 4),
+            slice(3 * M + 4, 3 * M + 7)]
+    for x, c in zip(t, cols):
+        assert np.allclose(x.grad.cpu().numpy(), g[:, c], rtol=1e-14, atol=0)
