@@ -140,8 +140,9 @@ def _plan_memory(plan):
 def run_legs(gp, steps=3, warmup=1, which=("C3", "C2", "C5")):
     """The other configurations of the hot path, each on one GPU:
     C3 (4096 series of 1e3..5e4 exposures, M = 2: batched launch),
-    C5 (one series of 1e7 exposures, M = 3, J = 4: time-parallel scan) with the
-    plain one-lane filter's rate projected to that length, and C2 (one series
+    C5 (one series of 1e7 exposures, M = 3, J = 4: time-parallel scan for the
+    likelihood, its gradient and the smoother) with the plain one-lane
+    filter's rate projected to that length, and C2 (one series
     of 1e5 exposures, M = 2, 1e4 test times: smoother and prediction)."""
     import torch
     legs = {}
@@ -233,6 +234,12 @@ def _leg_c5(gp, legs, dev, prof_run, steps, warmup):
     tl = _timed(lambda: plan.loglik(*a), steps, warmup)
     tg = _timed(lambda: plan.loglik_grad(*a), steps, warmup)
     ll, _ = plan.loglik_grad(*a)
+    # the smoother: posterior at all 1e7 measurements and at 1e4 test times over the span
+    t_test = np.linspace(float(b.t_start[0]), float(b.t_end[-1]), 10_000)
+    to = np.array([0, len(t_test)], dtype=np.int64)
+    ts_ = _timed(lambda: plan.smooth(*a, to, t_test), steps, warmup)
+    sm = plan.smooth(*a, to, t_test)
+    sm_finite = all(bool(torch.isfinite(sm[k]).all().item()) for k in ("mean_data", "var_data", "mean_test", "var_test"))
     # the plain filter on the first 1e5 exposures of the same series (a sub-plan), projected to 1e7
     nsub = 100_000
     sub = gp.Plan(np.array([0, nsub], dtype=np.int64), b.t_start[:nsub], b.t_end[:nsub], b.y[:nsub], b.yerr[:nsub])
@@ -242,13 +249,14 @@ def _leg_c5(gp, legs, dev, prof_run, steps, warmup):
     legs["C5_long_1e7"] = {
         "points": pts, "terms": b.n_terms, "slots": st["max_slots"], "chunks": st["n_chunks"],
         "segments": st["n_segments"], "loglik_ms": tl * 1e3, "loglik_grad_ms": tg * 1e3,
+        "smooth_ms": ts_ * 1e3, "smooth_test_times": len(t_test), "smooth_finite": sm_finite,
         "plain_gpu_filter_projected_ms": proj * 1e3, "plain_gpu_filter_measured": f"{nsub} exposures in {tsub * 1e3:.1f} ms",
         "scan_speedup_vs_plain": proj / tl, "loglik_finite": bool(torch.isfinite(ll).all().item()),
         "loglik_grad_median_replay_ms": _median_replay(lambda: plan.loglik_grad(*a), 5) * 1e3,
         "kernels_ms": prof_run(lambda: plan.loglik_grad(*a)), "plan_s": tp, "generate_s": gen,
         "device_memory": _plan_memory(plan)}
     print(f"[bench] C5 {legs['C5_long_1e7']}", file=sys.stderr, flush=True)
-    del plan, sub, b, a
+    del plan, sub, b, a, sm
     torch.cuda.empty_cache()
 
 

@@ -156,6 +156,42 @@ def test_long_1e7_two_scan_structures(lib):
     _free()
 
 
+def test_long_1e7_smoother(lib):
+    """The smoother on the 1e7-exposure series (bench.py's C5 smoother call:
+    every measurement and 1e4 test times): the default plan and a plan with
+    at most 64 segments agree (means within 1e-9 of the prior standard
+    deviation, variances within 1e-9 of the prior variance), and properties
+    that hold at any size: every posterior variance at a measurement lies in
+    [0, yerr^2] (conditioning on more data than the measurement itself cannot
+    raise it above R), every test-time variance in [0, prior variance]."""
+    b = W.long_1e7()
+    t_test = np.linspace(float(b.t_start[0]), float(b.t_end[-1]), 10_000)
+    to = np.array([0, len(t_test)], dtype=np.int64)
+    k0 = float(np.sum(np.asarray(b.sigma) ** 2))
+    outs = []
+    for opt in (dict(), dict(chunk_target=-(-2 * int(b.offsets[-1]) // (64 * 60)))):
+        plan = lib.Plan(b.offsets, b.t_start, b.t_end, b.y, b.yerr, **opt)
+        o = plan.smooth(b.sigma, b.omega0, b.quality, b.jitter, to, t_test)
+        outs.append({k: o[k].cpu().numpy() for k in ("mean_data", "var_data", "mean_test", "var_test", "status")})
+        print(opt, plan.stats())
+        del plan, o
+        _free()
+    a, c = outs
+    assert np.all(a["status"] == 0) and np.all(c["status"] == 0)
+    R = np.asarray(b.yerr) ** 2 + float(b.jitter[0]) ** 2
+    for o in outs:
+        for k in ("mean_data", "var_data", "mean_test", "var_test"):
+            assert np.all(np.isfinite(o[k])), k
+        assert np.all(o["var_data"] >= 0.0) and np.all(o["var_data"] <= R * (1 + 1e-12))
+        assert np.all(o["var_test"] >= 0.0) and np.all(o["var_test"] <= k0 * (1 + 1e-12))
+    errs = (np.max(np.abs(a["mean_data"] - c["mean_data"])) / np.sqrt(k0),
+            np.max(np.abs(a["var_data"] - c["var_data"])) / k0,
+            np.max(np.abs(a["mean_test"] - c["mean_test"])) / np.sqrt(k0),
+            np.max(np.abs(a["var_test"] - c["var_test"])) / k0)
+    print("two plans", errs)
+    assert max(errs) < 1e-9, errs
+
+
 def test_long_100k_smoother(lib):
     """One series of 1e5 exposures with 1e4 test times: every smoothed moment
     at the data and at the test times against the oracle.
