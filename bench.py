@@ -395,6 +395,18 @@ def main():
     # log-likelihood alone (batched)
     ms_ll = _timed(lambda: plan.loglik(sig, w0, q, jit), args.steps, args.warmup) * 1e3
 
+    # the same step through the torch.autograd.Function: forward (log-likelihood
+    # and gradient), a scalar objective and backward (the stored gradient
+    # scaled per series)
+    ps = [t.clone().requires_grad_(True) for t in (sig, w0, q, jit)]
+
+    def autograd_step():
+        for t in ps:
+            t.grad = None
+        gp.loglik_autograd(plan, *ps).sum().backward()
+
+    ms_ag = _timed(autograd_step, args.steps, args.warmup) * 1e3
+
     # plain one-series-at-a-time GPU filter on a sample
     plain = None
     if not args.no_plain and args.plain_sample > 0:
@@ -509,6 +521,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "loglik_only_ms_per_step": ms_ll,
+        "autograd_ms_per_step": ms_ag,
         "loglik_only_points_per_s": points / (ms_ll * 1e-3),
         "plain_gpu": plain,
         "with_instruments": inst,
