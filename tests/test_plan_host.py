@@ -196,3 +196,28 @@ def test_empty_series(driver):
     P = _plan(driver, [e, e], [e, e])
     _check(P)
     assert P["n_ch"] == 0 and P["n_wv"] == 0 and P["n_seg"] == 0 and P["n_pad"] == 0
+
+
+# ---------------------------------------------------------------------------
+# hypothesis-generated exposure sets: ties, zero-length exposures, overlaps
+# up to four deep, empty series
+# ---------------------------------------------------------------------------
+from hypothesis import HealthCheck, given, settings, strategies as st  # noqa: E402
+
+import interval_strategies as IS  # noqa: E402
+from oracle import kalman  # noqa: E402
+
+
+@settings(max_examples=80, derandomize=True, deadline=None, suppress_health_check=[HealthCheck.function_scoped_fixture])
+@given(series=st.lists(IS.exposure_series(), min_size=1, max_size=3),
+       opt=st.sampled_from([dict(), dict(chunk_min=1, chunk_target=1), dict(chunk_min=2, chunk_target=3),
+                            dict(single=1)]))
+def test_hypothesis_exposure_sets(driver, series, opt):
+    ts = [s[0] for s in series]
+    te = [s[1] for s in series]
+    P = _plan(driver, ts, te, **opt)
+    _check(P)
+    # the overlap depth the planner reports is the oracle's greedy labelling depth
+    depth = max([kalman.greedy_slots(a, b)[1] for a, b in zip(ts, te) if len(a)] or [0])
+    assert int(P["scalars"][5]) == depth
+    assert depth <= max(s[2] for s in series)
