@@ -167,3 +167,38 @@ def test_four_slots_and_four_terms(lib, M, J, T):
         k0 = float(np.sum(np.asarray(s["sigma"]) ** 2))
         assert np.max(np.abs(out["term_mean"][sl] - tm)) < TOL * np.sqrt(k0)
         assert np.max(np.abs(out["term_var"][sl] - tv)) < TOL * k0
+
+
+def test_scan_equals_sequential(lib):
+    """The time-parallel scan against the same computation without time
+    splitting (one chunk per series, so one lane runs each series from its
+    prior): log-likelihood within 1e-12 relative, and the one-lane plain
+    filter; smoothed moments within 1e-12 of the prior standard deviation /
+    variance."""
+    b = W.random_small_batch(808, B=6, n_lo=60, n_hi=300, M=2, J=3, T=8.0)
+    nt = 25
+    tt = np.concatenate([np.linspace(b.series(i)["ts"].min() - 0.1, b.series(i)["te"].max() + 0.1, nt)
+                         for i in range(b.n_series)])
+    to = np.arange(b.n_series + 1, dtype=np.int64) * nt
+    k0 = np.sum(np.asarray(b.sigma) ** 2, axis=1)
+    res = {}
+    for name, opt in (("seq", dict(single_chunk=1)), ("scan", dict(chunk_min=1, chunk_target=2)), ("dflt", dict())):
+        plan = lib.Plan(b.offsets, b.t_start, b.t_end, b.y, b.yerr, **opt)
+        o = plan.smooth(b.sigma, b.omega0, b.quality, b.jitter, to, tt)
+        res[name] = {k: v.cpu().numpy() for k, v in o.items() if v is not None}
+        res[name]["plain"] = plan.plain_loglik(b.sigma, b.omega0, b.quality, b.jitter).cpu().numpy()
+        print(name, plan.stats())
+    seq = res["seq"]
+    for name in ("scan", "dflt"):
+        r = res[name]
+        assert np.max(np.abs(r["loglik"] - seq["loglik"]) / np.abs(seq["loglik"])) < 1e-12
+        assert np.max(np.abs(r["loglik"] - seq["plain"]) / np.abs(seq["plain"])) < 1e-12
+        for i in range(b.n_series):
+            lo, hi = int(b.offsets[i]), int(b.offsets[i + 1])
+            s0, s1 = int(to[i]), int(to[i + 1])
+            e = (np.max(np.abs(r["mean_data"][lo:hi] - seq["mean_data"][lo:hi])) / np.sqrt(k0[i]),
+                 np.max(np.abs(r["var_data"][lo:hi] - seq["var_data"][lo:hi])) / k0[i],
+                 np.max(np.abs(r["mean_test"][s0:s1] - seq["mean_test"][s0:s1])) / np.sqrt(k0[i]),
+                 np.max(np.abs(r["var_test"][s0:s1] - seq["var_test"][s0:s1])) / k0[i])
+            print(name, i, e)
+            assert max(e) < 1e-12, (name, i, e)
