@@ -247,6 +247,23 @@ int gp_ssm_plan_smooth_inst(gp_ssm_plan* plan, int32_t n_terms, const double* si
                             double* term_mean, double* term_var, double* mean_data, double* var_data, double* loglik,
                             int32_t* status, void* stream);
 
+/* Log-likelihood by the square-root (Cholesky-factor) form of the filter, the
+ * remedy Sec. 3.2.3 and Sec. 5 name for the covariance form's loss of
+ * accuracy on nearly noise-free data: the covariance of the augmented state is
+ * carried as a triangular factor, updated by plane rotations (time update:
+ * the transition's columns and the process noise as rank-one updates;
+ * measurement update: the array form), so that it stays positive
+ * semidefinite.  The same model, term kinds and instrument labels as
+ * gp_ssm_plan_loglik_inst (amp and off may be NULL; with a plan without
+ * instrument labels both must be NULL).  Whole series, one per GPU lane, no
+ * time splitting: a robust alternative, not the batched path's speed.
+ * loglik[B] and status[B] (optional) in device memory, NaN and a nonzero
+ * status for a failed series as for gp_ssm_plan_loglik.  Asynchronous on
+ * `stream`. */
+int gp_ssm_plan_loglik_sqrt(gp_ssm_plan* plan, int32_t n_terms, const double* sigma, const double* omega0,
+                            const double* quality, const double* jitter, const double* amp, const double* off,
+                            double* loglik, int32_t* status, void* stream);
+
 /* Reference "plain" GPU filter: the same per-event device code, one series at
  * a time, one lane, no time splitting, one launch per series.  Computes the
  * log-likelihood of series [first, first+count) of the plan.  Used as the

@@ -1349,6 +1349,23 @@ int gp_ssm_plan_plain_loglik(gp_ssm_plan* pl, int64_t first, int64_t count, int3
   return 0;
 }
 
+int gp_ssm_plan_loglik_sqrt(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0,
+                            const double* quality, const double* jitter, const double* amp, const double* off,
+                            double* loglik, int32_t* status, void* stream) {
+  g_err.clear();
+  if (!loglik) return fail(GP_SSM_EINVAL, "null loglik");
+  if (!pl) return fail(GP_SSM_EINVAL, "null plan");
+  hipStream_t s = (hipStream_t)stream;
+  if (int rc = put_args(pl, M, sigma, omega0, quality, jitter, loglik, nullptr, status, s, amp, off, 0)) return rc;
+  if (int rc = reserve(pl, M, 0, false)) return rc;
+  enqueue_prep(pl, plan_work(pl), M, s);
+  const KernelSet ks = kernel_set(M, pl->host.max_slots, pl->features(M));
+  Launch L{s};
+  ks.sqrt(L, pl->dev(), pl->params(), pl->dargs());
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
 // One-shot forms: plan with default options, run, wait, destroy.  They return
 // GP_SSM_EPARAM or GP_SSM_ENUMERIC when any series failed (its outputs NaN).
 static int one_shot_plan(int64_t n_series, const int64_t* offsets, const double* t_start, const double* t_end,

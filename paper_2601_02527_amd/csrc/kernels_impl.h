@@ -13,8 +13,10 @@
 // measurement), which leave the state unchanged.
 #pragma once
 
+#include "../../include/gp_ssm.h"
 #include "kernels.h"
 #include "plan.h"
+#include "sqrt_filter.h"
 
 #ifndef GPSSM_M
 #error "define GPSSM_M before including kernels_impl.h"
@@ -347,6 +349,58 @@ __global__ __launch_bounds__(WAVE) void k_plain(DevPlan p, DevParams pr, int64_t
 }
 
 // ---------------------------------------------------------------------------
+// square-root (Cholesky-factor) filter of whole series, one series per lane
+// ---------------------------------------------------------------------------
+// writes the log-likelihood and status of each series as the scan's
+// finishing kernel does; the steps are those of sqrt_filter.h
+template <int J, int FT>
+__global__ __launch_bounds__(WAVE) void k_sqrt(DevPlan p, DevParams pr, const CallArgs* __restrict__ args) {
+  using Dm = Dims<M, J>;
+  constexpr int D = Dm::D, NL = D * (D + 1) / 2;
+  const int64_t b = (int64_t)blockIdx.x * WAVE + threadIdx.x;
+  if (b >= p.n_series) return;
+  TermConst tc[M];
+  load_terms<Dm>(pr, b, tc);
+  const double* coef = pr.coef + b * M * 2 * NCOEF;  // value tables at term stride 2 NCOEF
+  const double* itab = ((FT & 2) && pr.ni > 0) ? pr.itab + b * ITAB_W : nullptr;
+  const double jit = pr.jit[b];
+  const double jit2 = jit * jit;
+  double m[D], L[NL];
+#pragma unroll
+  for (int i = 0; i < D; ++i) m[i] = 0.0;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) L[i] = 0.0;
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    L[lidx(2 * t, 2 * t)] = tc[t].sigma;
+    L[lidx(2 * t + 1, 2 * t + 1)] = tc[t].sigma * second_prior<(FT & 1) != 0>(tc[t]);
+  }
+  double ll = 0.0;
+  const int32_t c0 = p.series_chunk0[b], nch = p.series_nch[b];
+  for (int32_t q = 0; q < nch; ++q) {
+    const int32_t c = c0 + q;
+    const int32_t l = p.chunk_lane[c];
+    const int64_t ev0 = p.wv_ev0[p.chunk_wv[c]];
+    const int32_t len = p.chunk_len[c];
+    for (int32_t k = 0; k < len; ++k) {
+      double dt;
+      uint32_t info;
+      const Obs o = load_event<Dm>(p, ev0 + (int64_t)k * WAVE + l, jit2, dt, info, itab);
+      TermQ tq[M];
+      discretise<M, DiscFull, 2 * NCOEF, (FT & 1) != 0>(tc, coef, dt, tq);
+      sqrt_predict<Dm>(m, L, tq, ev_open(info));
+      ll += sqrt_update<Dm>(m, L, info, o);
+    }
+  }
+  ll += inst_loglik(pr, b);
+  const bool pbad = pr.bad[b] != 0, good = isfinite(ll);
+  double* const loglik = args->loglik;
+  int32_t* const status = args->status;
+  if (loglik) loglik[b] = (good && !pbad) ? ll : __builtin_nan("");
+  if (status) status[b] = pbad ? GP_SSM_EPARAM : (good ? 0 : GP_SSM_ENUMERIC);
+}
+
+// ---------------------------------------------------------------------------
 // smoother (Sec. 3.2.2, Algorithm 1): a forward pass storing each event's
 // predicted state, then the backward sweep of the adjoint pair (lambda,
 // Lambda) from its value at the chunk's end, with the exposure-averaged
@@ -670,6 +724,15 @@ void launch_plain(const Launch& L, const DevPlan& p, const DevParams& pr, int64_
 }
 
 template <int J, int FT>
+void launch_sqrt(const Launch& L, const DevPlan& p, const DevParams& pr, const CallArgs* args) {
+  if (p.n_series == 0) return;
+  prof_begin("k_sqrt", L.stream);
+  hipLaunchKernelGGL((k_sqrt<J, FT>), dim3((unsigned)((p.n_series + WAVE - 1) / WAVE)), dim3(WAVE), 0, L.stream, p,
+                     pr, args);
+  prof_end("k_sqrt", L.stream);
+}
+
+template <int J, int FT>
 void launch_smooth(const Launch& L, const DevPlan& p, const DevParams& pr, const double* bstate, const double* bsmooth,
                    const RecSlots& rec, const DevTests& tests, double* mean_test, double* var_test, double* mean_data,
                    double* var_data) {
@@ -709,6 +772,7 @@ KernelSet make_set() {
   k.summaries = &launch_summaries<J, FT>;
   k.adjoint = &launch_adjoint<J, FT>;
   k.plain = &launch_plain<J, FT>;
+  k.sqrt = &launch_sqrt<J, FT>;
   k.smooth = &launch_smooth<J, FT>;
   k.adjoint_occupancy = &adjoint_occupancy<J, FT>;
   k.smooth_occupancy = &smooth_occupancy<J, FT>;
