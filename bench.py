@@ -291,6 +291,7 @@ def main():
                     help="threads for the CPU oracle (at most the visible host cores)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-sqrt", action="store_true", help="skip the timing of the square-root filter")
     ap.add_argument("--no-legs", action="store_true", help="skip the C2, C3 and C5 configurations")
     ap.add_argument("--no-autotune", action="store_true", help="default plan options instead of the autotuner's")
     ap.add_argument("--no-instruments", action="store_true",
@@ -425,6 +426,20 @@ def main():
                  "speedup_batched_loglik": batched_rate / rate, "max_rel_diff_vs_batched": diff}
         print(f"[bench] plain {plain}", file=sys.stderr, flush=True)
 
+    # the square-root (Cholesky-factor) filter over the same batch, one series
+    # per lane (a robust alternative to the time-parallel path, timed once)
+    sq = None
+    if not args.no_sqrt:
+        plan.loglik_sqrt(sig, w0, q, jit)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ls = plan.loglik_sqrt(sig, w0, q, jit)
+        torch.cuda.synchronize()
+        ts_ = time.perf_counter() - t0
+        diff = float(torch.max(torch.abs(ls - ll) / torch.abs(ll)).item())
+        sq = {"ms": ts_ * 1e3, "points_per_s": points / ts_, "max_rel_diff_vs_batched": diff}
+        print(f"[bench] sqrt {sq}", file=sys.stderr, flush=True)
+
     # roofline of the dominant kernel
     fwd_pt, grad_pt = algorithmic_flops_per_point(M, J)
     kern = {k: {"count": v[0], "avg_ms": v[1] / max(1, v[0])} for k, v in prof.items()}
@@ -524,6 +539,7 @@ def main():
         "autograd_ms_per_step": ms_ag,
         "loglik_only_points_per_s": points / (ms_ll * 1e-3),
         "plain_gpu": plain,
+        "sqrt_filter": sq,
         "with_instruments": inst,
         "plan_seconds": t_plan,
         "median_replay_ms": med_ms,
