@@ -102,7 +102,7 @@ struct KernelSet {
   void (*adjoint)(const Launch&, const DevPlan&, const DevParams&, const double* bstate, const double* badj,
                   const RecSlots& rec, double* gpart);
   void (*plain)(const Launch&, const DevPlan&, const DevParams&, int64_t series, double* loglik);
-  void (*sqrt)(const Launch&, const DevPlan&, const DevParams&, const CallArgs* args);
+  void (*sqrt)(const Launch&, const DevPlan&, const DevParams&, const int32_t* order, const CallArgs* args);
   void (*smooth)(const Launch&, const DevPlan&, const DevParams&, const double* bstate, const double* bsmooth,
                  const RecSlots& rec, const DevTests& tests, double* mean_test, double* var_test, double* mean_data,
                  double* var_data);

@@ -354,11 +354,13 @@ __global__ __launch_bounds__(WAVE) void k_plain(DevPlan p, DevParams pr, int64_t
 // writes the log-likelihood and status of each series as the scan's
 // finishing kernel does; the steps are those of sqrt_filter.h
 template <int J, int FT>
-__global__ __launch_bounds__(WAVE) void k_sqrt(DevPlan p, DevParams pr, const CallArgs* __restrict__ args) {
+__global__ __launch_bounds__(WAVE) void k_sqrt(DevPlan p, DevParams pr, const int32_t* __restrict__ order,
+                                               const CallArgs* __restrict__ args) {
   using Dm = Dims<M, J>;
   constexpr int D = Dm::D, NL = D * (D + 1) / 2;
-  const int64_t b = (int64_t)blockIdx.x * WAVE + threadIdx.x;
-  if (b >= p.n_series) return;
+  const int64_t i = (int64_t)blockIdx.x * WAVE + threadIdx.x;
+  if (i >= p.n_series) return;
+  const int64_t b = order ? order[i] : i;  // lane i takes the i-th longest series
   TermConst tc[M];
   load_terms<Dm>(pr, b, tc);
   const double* coef = pr.coef + b * M * 2 * NCOEF;  // value tables at term stride 2 NCOEF
@@ -724,11 +726,11 @@ void launch_plain(const Launch& L, const DevPlan& p, const DevParams& pr, int64_
 }
 
 template <int J, int FT>
-void launch_sqrt(const Launch& L, const DevPlan& p, const DevParams& pr, const CallArgs* args) {
+void launch_sqrt(const Launch& L, const DevPlan& p, const DevParams& pr, const int32_t* order, const CallArgs* args) {
   if (p.n_series == 0) return;
   prof_begin("k_sqrt", L.stream);
   hipLaunchKernelGGL((k_sqrt<J, FT>), dim3((unsigned)((p.n_series + WAVE - 1) / WAVE)), dim3(WAVE), 0, L.stream, p,
-                     pr, args);
+                     pr, order, args);
   prof_end("k_sqrt", L.stream);
 }
 
