@@ -250,13 +250,14 @@ int gp_ssm_plan_smooth_inst(gp_ssm_plan* plan, int32_t n_terms, const double* si
 /* Log-likelihood by the square-root (Cholesky-factor) form of the filter, the
  * remedy Sec. 3.2.3 and Sec. 5 name for the covariance form's loss of
  * accuracy on nearly noise-free data: the covariance of the augmented state is
- * carried as a triangular factor, updated by plane rotations (time update:
- * the transition's columns and the process noise as rank-one updates;
- * measurement update: the array form), so that it stays positive
- * semidefinite.  The same model, term kinds and instrument labels as
+ * carried as a triangular factor (time update: Householder reflections of
+ * the transition applied to the factor beside the process noise's factor;
+ * measurement update: the array form, by plane rotations), so that it stays
+ * positive semidefinite.  The same model, term kinds and instrument labels as
  * gp_ssm_plan_loglik_inst (amp and off may be NULL; with a plan without
- * instrument labels both must be NULL).  Whole series, one per GPU lane, no
- * time splitting: a robust alternative, not the batched path's speed.
+ * instrument labels both must be NULL).  Whole series, 16 GPU lanes each
+ * (one row of the factor per lane), no time splitting: a robust alternative,
+ * not the batched path's speed.
  * loglik[B] and status[B] (optional) in device memory, NaN and a nonzero
  * status for a failed series as for gp_ssm_plan_loglik.  Asynchronous on
  * `stream`. */

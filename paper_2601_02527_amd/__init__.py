@@ -312,7 +312,7 @@ class Plan:
 
     def loglik_sqrt(self, sigma, omega0, quality, jitter=None, amp=None, off=None, status=False, check=False):
         """Log-likelihood [B] by the square-root (Cholesky-factor) filter,
-        one series per GPU lane (gp_ssm_plan_loglik_sqrt); amp/off as for
+        16 GPU lanes per series (gp_ssm_plan_loglik_sqrt); amp/off as for
         loglik_inst, status and check as for loglik."""
         torch = _torch()
         M, s, w, q, j = self._params(sigma, omega0, quality, jitter)

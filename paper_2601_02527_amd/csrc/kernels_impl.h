@@ -349,38 +349,41 @@ __global__ __launch_bounds__(WAVE) void k_plain(DevPlan p, DevParams pr, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// square-root (Cholesky-factor) filter of whole series, one series per lane
+// square-root (Cholesky-factor) filter of whole series, SQ_GROUP lanes per
+// series (one row of the factor each; see sqrt_filter.h), series taken in the
+// order given (longest first), four to a wavefront
 // ---------------------------------------------------------------------------
 // writes the log-likelihood and status of each series as the scan's
-// finishing kernel does; the steps are those of sqrt_filter.h
+// finishing kernel does
 template <int J, int FT>
 __global__ __launch_bounds__(WAVE) void k_sqrt(DevPlan p, DevParams pr, const int32_t* __restrict__ order,
                                                const CallArgs* __restrict__ args) {
   using Dm = Dims<M, J>;
-  constexpr int D = Dm::D, NL = D * (D + 1) / 2;
-  const int64_t i = (int64_t)blockIdx.x * WAVE + threadIdx.x;
-  if (i >= p.n_series) return;
-  const int64_t b = order ? order[i] : i;  // lane i takes the i-th longest series
+  constexpr int D = Dm::D, NC = D + 3 * M;
+  const int q = threadIdx.x & (SQ_GROUP - 1);
+  const int64_t i = (int64_t)blockIdx.x * (WAVE / SQ_GROUP) + threadIdx.x / SQ_GROUP;
+  const bool live = i < p.n_series;  // uniform over the group
+  const int64_t b = live ? (order ? order[i] : i) : 0;
   TermConst tc[M];
   load_terms<Dm>(pr, b, tc);
   const double* coef = pr.coef + b * M * 2 * NCOEF;  // value tables at term stride 2 NCOEF
   const double* itab = ((FT & 2) && pr.ni > 0) ? pr.itab + b * ITAB_W : nullptr;
   const double jit = pr.jit[b];
   const double jit2 = jit * jit;
-  double m[D], L[NL];
+  // this lane's row of the factor (then the noise columns) and mean entry,
+  // from the stationary prior
+  double row[NC], mq = 0.0;
 #pragma unroll
-  for (int i = 0; i < D; ++i) m[i] = 0.0;
-#pragma unroll
-  for (int i = 0; i < NL; ++i) L[i] = 0.0;
+  for (int c = 0; c < NC; ++c) row[c] = 0.0;
 #pragma unroll
   for (int t = 0; t < M; ++t) {
-    L[lidx(2 * t, 2 * t)] = tc[t].sigma;
-    L[lidx(2 * t + 1, 2 * t + 1)] = tc[t].sigma * second_prior<(FT & 1) != 0>(tc[t]);
+    row[2 * t] = (q == 2 * t) ? tc[t].sigma : row[2 * t];
+    row[2 * t + 1] = (q == 2 * t + 1) ? tc[t].sigma * second_prior<(FT & 1) != 0>(tc[t]) : row[2 * t + 1];
   }
   double ll = 0.0;
-  const int32_t c0 = p.series_chunk0[b], nch = p.series_nch[b];
-  for (int32_t q = 0; q < nch; ++q) {
-    const int32_t c = c0 + q;
+  const int32_t c0 = live ? p.series_chunk0[b] : 0, nch = live ? p.series_nch[b] : 0;
+  for (int32_t k0 = 0; k0 < nch; ++k0) {
+    const int32_t c = c0 + k0;
     const int32_t l = p.chunk_lane[c];
     const int64_t ev0 = p.wv_ev0[p.chunk_wv[c]];
     const int32_t len = p.chunk_len[c];
@@ -390,10 +393,11 @@ __global__ __launch_bounds__(WAVE) void k_sqrt(DevPlan p, DevParams pr, const in
       const Obs o = load_event<Dm>(p, ev0 + (int64_t)k * WAVE + l, jit2, dt, info, itab);
       TermQ tq[M];
       discretise<M, DiscFull, 2 * NCOEF, (FT & 1) != 0>(tc, coef, dt, tq);
-      sqrt_predict<Dm>(m, L, tq, ev_open(info));
-      ll += sqrt_update<Dm>(m, L, info, o);
+      sqrt_predict_row<Dm>(row, mq, q, tq, ev_open(info));
+      ll += sqrt_update_row<Dm>(row, mq, q, info, o);
     }
   }
+  if (!live || q != 0) return;
   ll += inst_loglik(pr, b);
   const bool pbad = pr.bad[b] != 0, good = isfinite(ll);
   double* const loglik = args->loglik;
@@ -729,8 +733,9 @@ template <int J, int FT>
 void launch_sqrt(const Launch& L, const DevPlan& p, const DevParams& pr, const int32_t* order, const CallArgs* args) {
   if (p.n_series == 0) return;
   prof_begin("k_sqrt", L.stream);
-  hipLaunchKernelGGL((k_sqrt<J, FT>), dim3((unsigned)((p.n_series + WAVE - 1) / WAVE)), dim3(WAVE), 0, L.stream, p,
-                     pr, order, args);
+  constexpr int per_wave = WAVE / SQ_GROUP;
+  hipLaunchKernelGGL((k_sqrt<J, FT>), dim3((unsigned)((p.n_series + per_wave - 1) / per_wave)), dim3(WAVE), 0,
+                     L.stream, p, pr, order, args);
   prof_end("k_sqrt", L.stream);
 }
 

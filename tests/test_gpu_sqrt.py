@@ -1,5 +1,5 @@
 """GPU parity of the square-root (Cholesky-factor) filter
-(gp_ssm_plan_loglik_sqrt, one series per lane): against the oracle's
+(gp_ssm_plan_loglik_sqrt, 16 lanes per series): against the oracle's
 covariance-form and square-root filters on random batches at every term and
 slot count, with real terms and per-instrument amplitudes and offsets, on
 nearly noise-free series against the high-precision dense oracle, on the
