@@ -47,10 +47,49 @@ namespace gpssm {
 
 constexpr int SQ_GROUP = 16;  // lanes per series (at least the largest state dimension)
 static_assert(SQ_GROUP >= 2 * MAX_TERMS + MAX_SLOTS, "one lane per state row");
+static_assert(SQ_GROUP == 16, "a group is one DPP row");
 
-// value of v on lane src of this lane's group, and on the lane at xor distance
-__device__ __forceinline__ double grp_get(double v, int src) { return __shfl(v, src, SQ_GROUP); }
-__device__ __forceinline__ double grp_xor(double v, int mask) { return __shfl_xor(v, mask, SQ_GROUP); }
+// Exchanges within a group, which is one 16-lane DPP row: both 32-bit halves
+// of a double moved by a DPP pattern (0xB1: quad_perm 1,0,3,2, the lane at
+// xor distance 1; 0x4E: quad_perm 2,3,0,1, distance 2; 0x141: each half row
+// mirrored; 0x140: the row mirrored; 0x150 + i: lane i of the row broadcast)
+template <int CTRL>
+__device__ __forceinline__ double row_dpp(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// v of the partner row (2t <-> 2t+1)
+__device__ __forceinline__ double grp_partner(double v) { return row_dpp<0xB1>(v); }
+// sum of v over the group, on every lane
+__device__ __forceinline__ double grp_sum(double v) {
+  v += row_dpp<0xB1>(v);
+  v += row_dpp<0x4E>(v);
+  v += row_dpp<0x141>(v);
+  return v + row_dpp<0x140>(v);
+}
+// v of lane i of the group; i must be a constant once the caller's loops are
+// unrolled (the switch then folds to one case)
+__device__ __forceinline__ double grp_get(double v, int i) {
+  switch (i) {
+    case 0: return row_dpp<0x150>(v);
+    case 1: return row_dpp<0x151>(v);
+    case 2: return row_dpp<0x152>(v);
+    case 3: return row_dpp<0x153>(v);
+    case 4: return row_dpp<0x154>(v);
+    case 5: return row_dpp<0x155>(v);
+    case 6: return row_dpp<0x156>(v);
+    case 7: return row_dpp<0x157>(v);
+    case 8: return row_dpp<0x158>(v);
+    case 9: return row_dpp<0x159>(v);
+    case 10: return row_dpp<0x15A>(v);
+    case 11: return row_dpp<0x15B>(v);
+    case 12: return row_dpp<0x15C>(v);
+    case 13: return row_dpp<0x15D>(v);
+    case 14: return row_dpp<0x15E>(v);
+    default: return row_dpp<0x15F>(v);
+  }
+}
 
 // the plane rotation taking (a, b) to (r, 0): c = a / r, s = b / r; the
 // identity when both vanish (scaled as stated above)
@@ -92,9 +131,7 @@ __device__ __forceinline__ void sqrt_predict_row(double* row, double& mq, int q,
     for (int c = 0; c < D; ++c) sum[c] = f * row[c];
     sum[D] = f * mq;
 #pragma unroll
-    for (int s = 1; s < SQ_GROUP; s <<= 1)
-#pragma unroll
-      for (int c = 0; c <= D; ++c) sum[c] += grp_xor(sum[c], s);
+    for (int c = 0; c <= D; ++c) sum[c] = grp_sum(sum[c]);
   }
   // x rows: Phi_t applied to the rows (2t, 2t+1), partners at xor distance 1:
   // row 2t' = a00 row 2t + a01 row 2t+1, row 2t+1' = -a01 row 2t + a11 row 2t+1
@@ -108,10 +145,10 @@ __device__ __forceinline__ void sqrt_predict_row(double* row, double& mq, int q,
     const bool xrow = q < NX;
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-      const double pc = grp_xor(row[c], 1);
+      const double pc = grp_partner(row[c]);
       row[c] = xrow ? fma(as, row[c], ap * pc) : row[c];
     }
-    const double pm = grp_xor(mq, 1);
+    const double pm = grp_partner(mq);
     mq = xrow ? fma(as, mq, ap * pm) : mq;
   }
   // open integrator rows: + the increment
@@ -187,19 +224,35 @@ template <class Dm>
 __device__ __forceinline__ double sqrt_update_row(double* row, double& mq, int q, uint32_t info, const Obs& o) {
   constexpr int M = Dm::M, NX = Dm::NX, D = Dm::D;
   const uint32_t kind = ev_kind(info);
-  const int z = NX + (int)ev_slot(info);
+  const int z = NX + (int)ev_slot(info);  // the closing integrator's row
   double ll = 0.0;
   if (o.has) {
     // h^T L and h . m: the slot's row over its exposure length at an end, the
     // sum of the terms' first rows at an instantaneous measurement
     double a[D], hm;
     if (kind == EV_END) {
+      // the slot's lane, selected among the integrator rows
+      const uint32_t slot = ev_slot(info);
       double invd = 0.0;
 #pragma unroll
       for (int j = 0; j < Dm::J; ++j) invd += o.a[j];  // one nonzero entry, the slot's
 #pragma unroll
-      for (int k = 0; k < D; ++k) a[k] = grp_get(row[k], z) * invd;
-      hm = grp_get(mq, z) * invd;
+      for (int k = 0; k < D; ++k) {
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < Dm::J; ++j) {
+          const double vj = grp_get(row[k], NX + j);
+          v = (slot == (uint32_t)j) ? vj : v;
+        }
+        a[k] = v * invd;
+      }
+      double v = 0.0;
+#pragma unroll
+      for (int j = 0; j < Dm::J; ++j) {
+        const double vj = grp_get(mq, NX + j);
+        v = (slot == (uint32_t)j) ? vj : v;
+      }
+      hm = v * invd;
     } else {
       double wq = 0.0;
 #pragma unroll
@@ -208,11 +261,8 @@ __device__ __forceinline__ double sqrt_update_row(double* row, double& mq, int q
       for (int k = 0; k < D; ++k) a[k] = wq * row[k];
       hm = wq * mq;
 #pragma unroll
-      for (int s = 1; s < SQ_GROUP; s <<= 1) {
-#pragma unroll
-        for (int k = 0; k < D; ++k) a[k] += grp_xor(a[k], s);
-        hm += grp_xor(hm, s);
-      }
+      for (int k = 0; k < D; ++k) a[k] = grp_sum(a[k]);
+      hm = grp_sum(hm);
     }
     double r0 = sqrt(o.R), g = 0.0;
 #pragma unroll

@@ -9,6 +9,9 @@ the full 1024-series gradient workload.
 Tolerances: 1e-9 relative to the oracle (as for the batched path); 1e-10
 relative between the two GPU paths on the full workload, whose likelihoods
 differ only in rounding (both FP64, different accumulation order)."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -130,6 +133,23 @@ def test_sqrt_rotations_near_underflow(lib):
         ll = float(plan.loglik_sqrt(sig[None], w0[None], q[None], np.zeros(1), check=True).cpu()[0])
         print(seed, abs(ll - ref) / abs(ref))
         assert abs(ll - ref) < TOL * abs(ref)
+
+
+@pytest.mark.parametrize("case", ["c5_prefix", "m4"])
+def test_sqrt_long_series_against_stored_oracle(lib, case):
+    """32000 exposures from the generator of the 1e7-exposure workload (three
+    terms, up to four overlapping exposures) and a 12000-exposure four-term
+    series, against the long-double oracle's stored log-likelihoods
+    (tests/golden/kalman_long_scan.json)."""
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "kalman_long_scan.json")) as fh:
+        rows = {r["name"]: r for r in json.load(fh)["cases"]}
+    r = rows[case]
+    b = getattr(W, r["generator"])(**r["kwargs"])
+    plan = _plan(lib, b)
+    ll = float(plan.loglik_sqrt(b.sigma, b.omega0, b.quality, b.jitter, check=True).cpu()[0])
+    rel = abs(ll - r["loglik"]) / abs(r["loglik"])
+    print(case, plan.stats()["max_slots"], b.n_terms, rel)
+    assert rel < TOL
 
 
 def test_sqrt_status(lib):
