@@ -44,3 +44,17 @@ def two_instruments(seed, n, noise, T=5.0):
     yerr = np.full(n, noise * np.sqrt(np.sum(sig ** 2)))
     y = _draw(rng, ts, te, sig, w0, q, yerr)
     return ts, te, y, yerr, sig, w0, q
+
+
+def long_gaps(seed, n=120):
+    """A fast term (omega0 860 / d, Q 1.22) beside a slow one, with gaps of
+    about one day between 1-20 minute exposures: over such a gap the fast
+    term's transition is e^(-350) or so, so that factors of the covariance
+    carry entries whose squares are subnormal in double precision."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.choice([0.5, 0.98, 1.0, 1.01, 1.02, 1.03, 1.04, 1.05, 1.2], n) + rng.uniform(0.0, 0.01, n)
+    ts = np.cumsum(gaps)
+    te = ts + rng.uniform(1.0 / 1440, 20.0 / 1440, n)
+    yerr = rng.uniform(0.15, 0.25, n)
+    y = rng.normal(0.0, 0.5, n)
+    return ts, te, y, yerr, np.array([0.37, 0.15]), np.array([860.0, 0.95]), np.array([1.22, 1.7])

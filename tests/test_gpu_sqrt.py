@@ -108,26 +108,12 @@ def test_sqrt_nearly_noise_free(lib, instantaneous):
             assert abs(ll - Le) < TOL * abs(Le)
 
 
-def _long_gap_case(seed, n=120):
-    """A fast term (omega0 860 / d, Q 1.22) beside a slow one, with gaps of
-    about one day between 1-20 minute exposures: over such a gap the fast
-    term's transition is e^(-350) or so, and the factor's pivot pairs square
-    into the subnormal range."""
-    rng = np.random.default_rng(seed)
-    gaps = rng.choice([0.5, 0.98, 1.0, 1.01, 1.02, 1.03, 1.04, 1.05, 1.2], n) + rng.uniform(0.0, 0.01, n)
-    ts = np.cumsum(gaps)
-    te = ts + rng.uniform(1.0 / 1440, 20.0 / 1440, n)
-    yerr = rng.uniform(0.15, 0.25, n)
-    y = rng.normal(0.0, 0.5, n)
-    return ts, te, y, yerr, np.array([0.37, 0.15]), np.array([860.0, 0.95]), np.array([1.22, 1.7])
-
-
 def test_sqrt_rotations_near_underflow(lib):
     """Rotations of pivot pairs near the bottom of the FP64 range (the
     rotation is scaled by the exponent of its larger entry); without the
     scaling these series are off by 3e-6 ... 1e-4."""
     for seed in range(3):
-        ts, te, y, yerr, sig, w0, q = _long_gap_case(seed)
+        ts, te, y, yerr, sig, w0, q = CC.long_gaps(seed)
         ref = kalman.loglik(ts, te, y, yerr, sig, w0, q, 0.0)
         plan = lib.Plan(np.array([0, len(ts)], dtype=np.int64), ts, te, y, yerr)
         ll = float(plan.loglik_sqrt(sig[None], w0[None], q[None], np.zeros(1), check=True).cpu()[0])

@@ -806,6 +806,23 @@ def test_sqrt_and_exact_oracles_on_nearly_noise_free_data(instantaneous):
         assert abs(Lc - Le) < 1e-12 * abs(Le), (noise, Le, Lc)
 
 
+def test_sqrt_and_covariance_oracles_across_long_gaps():
+    """Series whose covariance factors meet subnormal squares in double
+    precision (a fast term across one-day gaps): the long-double covariance
+    and square-root filters agree with each other and with the dense GP."""
+    import conditioning_cases as CC
+    for seed in range(3):
+        ts, te, y, yerr, sig, w0, q = CC.long_gaps(seed)
+        Lc = kalman.loglik(ts, te, y, yerr, sig, w0, q, 0.0)
+        Ls = kalman.loglik_sqrt(ts, te, y, yerr, sig, w0, q, 0.0)
+        assert abs(Lc - Ls) < 1e-13 * abs(Lc), (seed, Lc, Ls)
+    # the dense GP (quadrature and Cholesky) on a shorter draw of the same kind
+    ts, te, y, yerr, sig, w0, q = CC.long_gaps(0, n=40)
+    Lc = kalman.loglik(ts, te, y, yerr, sig, w0, q, 0.0)
+    Ld = dense.loglik(ts, te, y, yerr, sig, w0, q, 0.0)
+    assert abs(Lc - Ld) < 1e-10 * abs(Lc), (Lc, Ld)
+
+
 def test_exact_posterior_matches_dense_and_kalman():
     """The high-precision posterior (data and test times) against the dense
     oracle's and the long-double smoother's, at ordinary noise."""
