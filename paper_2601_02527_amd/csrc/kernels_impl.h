@@ -380,6 +380,11 @@ __global__ __launch_bounds__(WAVE) void k_sqrt(DevPlan p, DevParams pr, const in
     row[2 * t] = (q == 2 * t) ? tc[t].sigma : row[2 * t];
     row[2 * t + 1] = (q == 2 * t + 1) ? tc[t].sigma * second_prior<(FT & 1) != 0>(tc[t]) : row[2 * t + 1];
   }
+  // lane t < M discretises term t at every event (the others repeat term 0)
+  // and the group shares the results
+  const int tl = q < M ? q : 0;
+  const TermConst tmine = pr.tc[b * M + tl];
+  const double* cmine = coef + tl * 2 * NCOEF;
   double ll = 0.0;
   const int32_t c0 = live ? p.series_chunk0[b] : 0, nch = live ? p.series_nch[b] : 0;
   for (int32_t k0 = 0; k0 < nch; ++k0) {
@@ -391,8 +396,10 @@ __global__ __launch_bounds__(WAVE) void k_sqrt(DevPlan p, DevParams pr, const in
       double dt;
       uint32_t info;
       const Obs o = load_event<Dm>(p, ev0 + (int64_t)k * WAVE + l, jit2, dt, info, itab);
-      TermQ tq[M];
-      discretise<M, DiscFull, 2 * NCOEF, (FT & 1) != 0>(tc, coef, dt, tq);
+      TermQ mine, tq[M];
+      discretise<1, DiscFull, 2 * NCOEF, (FT & 1) != 0>(&tmine, cmine, dt, &mine);
+#pragma unroll
+      for (int t = 0; t < M; ++t) tq[t] = grp_get_term(mine, t);
       sqrt_predict_row<Dm>(row, mq, q, tq, ev_open(info));
       ll += sqrt_update_row<Dm>(row, mq, q, info, o);
     }

@@ -91,6 +91,23 @@ __device__ __forceinline__ double grp_get(double v, int i) {
   }
 }
 
+// the step quantities of lane i's term
+__device__ __forceinline__ TermQ grp_get_term(const TermQ& u, int i) {
+  TermQ r;
+  r.a00 = grp_get(u.a00, i);
+  r.a01 = grp_get(u.a01, i);
+  r.a11 = grp_get(u.a11, i);
+  r.f0 = grp_get(u.f0, i);
+  r.f1 = grp_get(u.f1, i);
+  r.q00 = grp_get(u.q00, i);
+  r.q01 = grp_get(u.q01, i);
+  r.q11 = grp_get(u.q11, i);
+  r.c0 = grp_get(u.c0, i);
+  r.c1 = grp_get(u.c1, i);
+  r.zz = grp_get(u.zz, i);
+  return r;
+}
+
 // the plane rotation taking (a, b) to (r, 0): c = a / r, s = b / r; the
 // identity when both vanish (scaled as stated above)
 __device__ __forceinline__ void plane_rotation(double a, double b, double& c, double& s, double& r) {
