@@ -128,6 +128,13 @@ __device__ __forceinline__ void plane_rotation(double a, double b, double& c, do
   }
 }
 
+// whether the reflection of pivot row i involves column c of [A L | N] (the
+// noise columns D + 3t, D + 3t + 1, D + 3t + 2 belong to term t)
+template <int NX, int D>
+__device__ __forceinline__ constexpr bool sq_involved(int i, int c) {
+  return c == i || (c == i + 1 && i < NX && (i & 1) == 0) || (c >= D && (i >= NX || (c - D) / 3 <= i / 2));
+}
+
 // time update of this lane's row (row[0..D) of L, then the 3M noise columns,
 // rebuilt here) and mean entry mq; q: the lane's row, tq: the terms' step
 // quantities, open: the integrators open during the step
@@ -194,25 +201,32 @@ __device__ __forceinline__ void sqrt_predict_row(double* row, double& mq, int q,
     row[D + 3 * t + 2] = oq * l22;
   }
   // triangularise [A L | N]: for pivot row i, the reflection that takes its
-  // entries in columns i.. to (alpha, 0, ...), applied by every lane to its
-  // row (rows above i are zero there and unchanged)
+  // entries in the columns it involves to (alpha, 0, ...), applied by every
+  // lane to its row.  Row i is nonzero beyond column i only in column i + 1
+  // when that holds its term block's entry above the diagonal, and in the
+  // noise columns of the terms whose rows it has met (terms up to its own for
+  // a term row, every term for an integrator row): the other columns keep
+  // their zeros in the rows above and below and are left out.
 #pragma unroll
   for (int i = 0; i < D; ++i) {
     double v[NC];
 #pragma unroll
-    for (int c = i; c < NC; ++c) v[c] = grp_get(row[c], i);
+    for (int c = i; c < NC; ++c)
+      if (sq_involved<NX, D>(i, c)) v[c] = grp_get(row[c], i);
     double mx = 0.0;
 #pragma unroll
-    for (int c = i; c < NC; ++c) mx = fmax(mx, fabs(v[c]));
+    for (int c = i; c < NC; ++c)
+      if (sq_involved<NX, D>(i, c)) mx = fmax(mx, fabs(v[c]));
     if (mx > 0.0) {
       int e;
       (void)frexp(mx, &e);
       double n2 = 0.0;
 #pragma unroll
-      for (int c = i; c < NC; ++c) {
-        v[c] = ldexp(v[c], -e);
-        n2 = fma(v[c], v[c], n2);
-      }
+      for (int c = i; c < NC; ++c)
+        if (sq_involved<NX, D>(i, c)) {
+          v[c] = ldexp(v[c], -e);
+          n2 = fma(v[c], v[c], n2);
+        }
       const double nrm = sqrt(n2);
       const double alpha = v[i] >= 0.0 ? -nrm : nrm;
       // v - alpha e_i, whose squared norm is 2 nrm (nrm + |v_i|)
@@ -221,10 +235,12 @@ __device__ __forceinline__ void sqrt_predict_row(double* row, double& mq, int q,
       const double beta = 2.0 / vv;
       double w = 0.0;
 #pragma unroll
-      for (int c = i; c < NC; ++c) w = fma(row[c], v[c], w);
+      for (int c = i; c < NC; ++c)
+        if (sq_involved<NX, D>(i, c)) w = fma(row[c], v[c], w);
       w *= beta;
 #pragma unroll
-      for (int c = i; c < NC; ++c) row[c] = fma(-w, v[c], row[c]);
+      for (int c = i; c < NC; ++c)
+        if (sq_involved<NX, D>(i, c)) row[c] = fma(-w, v[c], row[c]);
       if (q == i) {
         row[i] = ldexp(alpha, e);
 #pragma unroll
