@@ -2,8 +2,9 @@
 (quadrature + Cholesky, Sec. 3.1 and Sec. 2.4): exposure sets with equal
 times, zero-length exposures and overlaps up to three deep (the strategies of
 interval_strategies.py), one or two SHO terms with random hyperparameters,
-with and without jitter, under two chunkings.  Log-likelihood within 1e-9
-of max(1, |L|), gradient within 1e-6 (relative to max(|g_i|, 1e-3 max|g|)).
+with and without jitter, under two chunkings, and the square-root filter.
+Log-likelihood within 1e-9 of max(1, |L|), gradient within 1e-6 (relative
+to max(|g_i|, 1e-3 max|g|)).
 The examples are derandomized: every run tries the same ones."""
 import numpy as np
 import pytest
@@ -44,6 +45,8 @@ def test_fuzzed_tiny_problems_match_dense(lib, ser, M, seed, jitter, chunked):
     ll, g = float(ll.cpu().numpy()[0]), g.cpu().numpy()[0]
     assert int(st_.cpu().numpy()[0]) == 0
     assert abs(ll - L) <= 1e-9 * max(1.0, abs(L)), (ll, L)
+    ls = float(plan.loglik_sqrt(sig[None], w0[None], q[None], np.array([jitter]), check=True).cpu().numpy()[0])
+    assert abs(ls - L) <= 1e-9 * max(1.0, abs(L)), (ls, L)
     if jitter == 0.0:
         assert g[-1] == 0.0
     assert _grad_err(g, g_ref) < 1e-6, (g, g_ref)
