@@ -470,7 +470,7 @@ struct gp_ssm_plan {
   DBuf pre2, suf2, grptot, grpstate, grpfut;
   DBuf tests_t, tests_idx, tests_c0, tests_before, prior_idx, prior_series;
   DBuf wv_order, args, kinds, itab, icnt;
-  DBuf sqrt_order;  // series by decreasing event count (the square-root filter's lanes)
+  DBuf sqrt_order;  // series by decreasing event count (the square-root filter's groups)
   // the call's pointers go to `args` on the call's stream from a ring of
   // pinned host slots; an event per slot marks when its copy has been done
   CallArgs* args_host = nullptr;
@@ -1029,6 +1029,18 @@ int gp_ssm_plan_create(int64_t n_series, const int64_t* offsets, const double* t
     delete pl;
     return rc;
   }
+  {
+    // the square-root filter's order of the series, longest first, so that
+    // the groups of a wavefront run series of similar length
+    std::vector<int32_t> order(h.n_series);
+    for (int64_t b = 0; b < h.n_series; ++b) order[b] = (int32_t)b;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return h.series_nev[a] > h.series_nev[b]; });
+    if ((rc = upload(pl->sqrt_order, order))) {
+      delete pl;
+      return rc;
+    }
+  }
   // the event arrays live on the device now; keep only the tables the host needs
   std::vector<double>().swap(h.dt);
   std::vector<double>().swap(h.y);
@@ -1359,15 +1371,6 @@ int gp_ssm_plan_loglik_sqrt(gp_ssm_plan* pl, int32_t M, const double* sigma, con
   hipStream_t s = (hipStream_t)stream;
   if (int rc = put_args(pl, M, sigma, omega0, quality, jitter, loglik, nullptr, status, s, amp, off, 0)) return rc;
   if (int rc = reserve(pl, M, 0, false)) return rc;
-  if (!pl->sqrt_order.p && pl->host.n_series > 0) {
-    // neighbouring lanes get series of similar length (a wavefront runs as
-    // long as its longest series)
-    std::vector<int32_t> order(pl->host.n_series);
-    for (int64_t b = 0; b < pl->host.n_series; ++b) order[b] = (int32_t)b;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int32_t a, int32_t b) { return pl->host.series_nev[a] > pl->host.series_nev[b]; });
-    if (int rc = upload(pl->sqrt_order, order)) return rc;
-  }
   enqueue_prep(pl, plan_work(pl), M, s);
   const KernelSet ks = kernel_set(M, pl->host.max_slots, pl->features(M));
   Launch L{s};
