@@ -357,6 +357,13 @@ int build_plan(int64_t n_series, const int64_t* offsets, const double* t_start, 
     }
     P.series_nwv[b] = P.n_wv - P.series_wv0[b];
   }
+  // a layout that pads the events many times over (one chunk per series puts
+  // one lane of a work wave to use) is refused before its arrays are made
+  if (P.n_ev_pad > 16 * P.n_events + (int64_t(1) << 24)) {
+    err = "the event layout would hold " + std::to_string(P.n_ev_pad) + " padded events for " +
+          std::to_string(P.n_events) + " events (one chunk per series uses one lane of 64; split the series in time)";
+    return -7;
+  }
   // interleaved event arrays
   P.dt.assign(P.n_ev_pad, 0.0);
   P.t.assign(P.n_ev_pad, 0.0);

@@ -198,6 +198,27 @@ def test_empty_series(driver):
     assert P["n_ch"] == 0 and P["n_wv"] == 0 and P["n_seg"] == 0 and P["n_pad"] == 0
 
 
+def test_wasteful_layout_refused(driver):
+    """One chunk per series puts one lane of each 64-lane work wave to use; a
+    batch large enough for that to pad its events many times over (here 400
+    series of 1000 exposures: 64x, 2.6e7 padded events) is refused with
+    GP_SSM_ENOMEM before the layout is built, while time splitting plans it."""
+    exe, d = driver
+    rng = np.random.default_rng(5)
+    ts = [np.arange(1000) * 0.1 + rng.uniform(0.0, 0.05, 1000) for _ in range(400)]
+    te = [t + 0.01 for t in ts]
+    offs = np.concatenate([[0], np.cumsum([len(x) for x in ts])]).astype(np.int64)
+    offs.tofile(str(d / "offs.bin"))
+    np.concatenate(ts).tofile(str(d / "ts.bin"))
+    np.concatenate(te).tofile(str(d / "te.bin"))
+    np.zeros(offs[-1]).tofile(str(d / "y.bin"))
+    np.full(offs[-1], 0.1).tofile(str(d / "yerr.bin"))
+    out = subprocess.run([exe, str(d), "24", "0", "1", "131072"], capture_output=True, text=True, check=True).stdout
+    assert out.splitlines()[0] == "rc -7"
+    P = _plan(driver, ts, te)
+    assert P["n_pad"] < 2 * P["n_ev"]
+
+
 # ---------------------------------------------------------------------------
 # hypothesis-generated exposure sets: ties, zero-length exposures, overlaps
 # up to four deep, empty series
