@@ -91,7 +91,11 @@ typedef struct {
   int32_t chunk_min;     /* shortest chunk in events (default 24) */
   int32_t chunk_target;  /* target chunk length in events; 0 = derived from the batch */
   int64_t target_chunks; /* wanted number of chunks when deriving (default 131072) */
-  int32_t single_chunk;  /* 1 = never split a series in time */
+  int32_t single_chunk;  /* 1 = never split a series in time (each series then
+                          * fills one lane of a 64-lane work wave; a batch
+                          * whose layout would pad its events more than
+                          * 16-fold beyond 2^24 events is refused with
+                          * GP_SSM_ENOMEM) */
   int32_t threads;       /* host threads used to build the plan; 0 = all */
   /* device bytes for the per-event filter states that the gradient and the
    * smoother keep between their forward and backward sweeps (default
