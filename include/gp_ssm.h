@@ -269,6 +269,23 @@ int gp_ssm_plan_loglik_sqrt(gp_ssm_plan* plan, int32_t n_terms, const double* si
                             const double* quality, const double* jitter, const double* amp, const double* off,
                             double* loglik, int32_t* status, void* stream);
 
+/* The square-root filter's log-likelihood with the series split in time at
+ * the plan's chunks (Sec. 3.2.4's time-parallel idea in factor form): for
+ * every chunk at once, the filter conditioned on the chunk's first SHO state
+ * x0, in factor form (16 GPU lanes per chunk, one row of the factor each),
+ * summarised as the end state's x0-affine mean A x0 + b and covariance
+ * factor U, and the chunk's density of its measurements as a function of x0,
+ * exp(-c0 - x0^T Z Z^T x0 / 2 + eta^T x0) with the information factor Z
+ * (rank-one updates by rotations); then, per series, the summaries folded in
+ * order (one lane per series), each combination through the factor of
+ * I + W W^T, W = L^T Z, so that no covariance is formed from a difference.
+ * The same model and arguments as gp_ssm_plan_loglik_sqrt; device memory
+ * for the summaries, about 120 doubles per chunk at three terms, is
+ * allocated on the first call. */
+int gp_ssm_plan_loglik_sqrt_split(gp_ssm_plan* plan, int32_t n_terms, const double* sigma, const double* omega0,
+                                  const double* quality, const double* jitter, const double* amp, const double* off,
+                                  double* loglik, int32_t* status, void* stream);
+
 /* Reference "plain" GPU filter: the same per-event device code, one series at
  * a time, one lane, no time splitting, one launch per series.  Computes the
  * log-likelihood of series [first, first+count) of the plan.  Used as the

@@ -38,7 +38,8 @@ EXPORTS = [
     "gp_ssm_plan_set_instruments", "gp_ssm_plan_get_stats",
     "gp_ssm_plan_loglik", "gp_ssm_plan_loglik_noalloc", "gp_ssm_plan_loglik_grad", "gp_ssm_plan_loglik_inst",
     "gp_ssm_plan_loglik_grad_inst", "gp_ssm_plan_smooth", "gp_ssm_plan_smooth_terms", "gp_ssm_plan_smooth_inst",
-    "gp_ssm_plan_plain_loglik", "gp_ssm_plan_loglik_sqrt", "gp_ssm_loglik", "gp_ssm_loglik_grad", "gp_ssm_smooth", "gp_ssm_autotune",
+    "gp_ssm_plan_plain_loglik", "gp_ssm_plan_loglik_sqrt",
+    "gp_ssm_plan_loglik_sqrt_split", "gp_ssm_loglik", "gp_ssm_loglik_grad", "gp_ssm_smooth", "gp_ssm_autotune",
     "gp_ssm_autotune_candidates", "gp_ssm_profile_enable", "gp_ssm_profile_reset",
     "gp_ssm_profile_read", "gp_ssm_last_error", "gp_ssm_version",
 ]
@@ -92,6 +93,7 @@ def library():
     L.gp_ssm_plan_smooth_terms.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.gp_ssm_plan_plain_loglik.argtypes = [vp, i64, i64, i32, vp, vp, vp, vp, vp, vp]
     L.gp_ssm_plan_loglik_sqrt.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.gp_ssm_plan_loglik_sqrt_split.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.gp_ssm_loglik.argtypes = [i64, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.gp_ssm_loglik_grad.argtypes = [i64, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
     L.gp_ssm_smooth.argtypes = [i64, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -321,6 +323,21 @@ class Plan:
         st = torch.empty(self.n_series, dtype=torch.int32, device="cuda")
         _check(library().gp_ssm_plan_loglik_sqrt(self._h, M, _ptr(s), _ptr(w), _ptr(q), _ptr(j), _ptr(a), _ptr(c),
                                                  _ptr(out), _ptr(st), _stream()))
+        if check:
+            check_status(st)
+        return (out, st) if status else out
+
+    def loglik_sqrt_split(self, sigma, omega0, quality, jitter=None, amp=None, off=None, status=False, check=False):
+        """Log-likelihood [B] by the square-root filter split in time at the
+        plan's chunks (gp_ssm_plan_loglik_sqrt_split); arguments as for
+        loglik_sqrt."""
+        torch = _torch()
+        M, s, w, q, j = self._params(sigma, omega0, quality, jitter)
+        a, c = self._inst(amp, off)
+        out = torch.empty(self.n_series, dtype=torch.float64, device="cuda")
+        st = torch.empty(self.n_series, dtype=torch.int32, device="cuda")
+        _check(library().gp_ssm_plan_loglik_sqrt_split(self._h, M, _ptr(s), _ptr(w), _ptr(q), _ptr(j), _ptr(a),
+                                                       _ptr(c), _ptr(out), _ptr(st), _stream()))
         if check:
             check_status(st)
         return (out, st) if status else out

@@ -16,6 +16,7 @@
 
 #include "../../include/gp_ssm.h"
 #include "kernels.h"
+#include "sqrt_filter.h"
 #include "plan.h"
 #include "scan.h"
 
@@ -471,6 +472,7 @@ struct gp_ssm_plan {
   DBuf tests_t, tests_idx, tests_c0, tests_before, prior_idx, prior_series;
   DBuf wv_order, args, kinds, itab, icnt;
   DBuf sqrt_order;  // series by decreasing event count (the square-root filter's groups)
+  DBuf sqsumm;      // chunk summaries of the time-split square-root filter
   // the call's pointers go to `args` on the call's stream from a ring of
   // pinned host slots; an event per slot marks when its copy has been done
   CallArgs* args_host = nullptr;
@@ -497,7 +499,7 @@ struct gp_ssm_plan {
                                   &series_grp0, &series_ngrp, &wv_series, &wv_nch, &wv_len, &wv_chunk, &wv_ev0,
                                   &chunk_len, &chunk_series, &chunk_wv, &chunk_lane, &chunk_first, &series_chunk0,
                                   &series_nch, &series_seg0, &series_nseg, &series_wv0, &series_nwv, &series_dt_cdf,
-                                  &icnt, &sqrt_order};
+                                  &icnt, &sqrt_order, &sqsumm};
     for (DBuf* d : self->workspace()) v.push_back(d);
     return v;
   }
@@ -1375,6 +1377,25 @@ int gp_ssm_plan_loglik_sqrt(gp_ssm_plan* pl, int32_t M, const double* sigma, con
   const KernelSet ks = kernel_set(M, pl->host.max_slots, pl->features(M));
   Launch L{s};
   ks.sqrt(L, pl->dev(), pl->params(), pl->sqrt_order.as<int32_t>(), pl->dargs());
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int gp_ssm_plan_loglik_sqrt_split(gp_ssm_plan* pl, int32_t M, const double* sigma, const double* omega0,
+                                  const double* quality, const double* jitter, const double* amp, const double* off,
+                                  double* loglik, int32_t* status, void* stream) {
+  g_err.clear();
+  if (!loglik) return fail(GP_SSM_EINVAL, "null loglik");
+  if (!pl) return fail(GP_SSM_EINVAL, "null plan");
+  hipStream_t s = (hipStream_t)stream;
+  if (int rc = put_args(pl, M, sigma, omega0, quality, jitter, loglik, nullptr, status, s, amp, off, 0)) return rc;
+  if (int rc = reserve(pl, M, 0, false)) return rc;
+  if (int rc = pl->sqsumm.ensure(sizeof(double) * sq_fields(2 * M) * std::max<int64_t>(1, pl->host.n_chunks)))
+    return rc;
+  enqueue_prep(pl, plan_work(pl), M, s);
+  const KernelSet ks = kernel_set(M, pl->host.max_slots, pl->features(M));
+  Launch L{s};
+  ks.sqrt_split(L, pl->dev(), pl->params(), pl->sqsumm.as<double>(), pl->dargs());
   HIP_TRY(hipGetLastError());
   return 0;
 }

@@ -400,11 +400,287 @@ __global__ __launch_bounds__(WAVE) void k_sqrt(DevPlan p, DevParams pr, const in
       discretise<1, DiscFull, 2 * NCOEF, (FT & 1) != 0>(&tmine, cmine, dt, &mine);
 #pragma unroll
       for (int t = 0; t < M; ++t) tq[t] = grp_get_term(mine, t);
-      sqrt_predict_row<Dm>(row, mq, q, tq, ev_open(info));
-      ll += sqrt_update_row<Dm>(row, mq, q, info, o);
+      sqrt_predict_row<Dm, 1>(row, &mq, q, tq, ev_open(info));
+      ll += sqrt_update_row<Dm, 1>(row, &mq, q, info, o);
     }
   }
   if (!live || q != 0) return;
+  ll += inst_loglik(pr, b);
+  const bool pbad = pr.bad[b] != 0, good = isfinite(ll);
+  double* const loglik = args->loglik;
+  int32_t* const status = args->status;
+  if (loglik) loglik[b] = (good && !pbad) ? ll : __builtin_nan("");
+  if (status) status[b] = pbad ? GP_SSM_EPARAM : (good ? 0 : GP_SSM_ENUMERIC);
+}
+
+// ---------------------------------------------------------------------------
+// time-split square-root filter: per chunk, the filter conditioned on the
+// chunk's first SHO state x0 in factor form (SQ_GROUP lanes per chunk, four
+// chunks to a wavefront), then per series a fold of the chunk summaries in
+// order (one lane per series)
+// ---------------------------------------------------------------------------
+// Chunk summary (offsets sq_*): the chunk's end state is x0-affine with
+// mean A x0 + b and covariance U U^T; its measurements have density
+// exp(-c0 - |R x0 - rho|^2 / 2 - eps^2 / 2), where [[R, rho], [0, eps]] is
+// the triangular factor (Z^T) of the rows (u_k / sqrt S_k, v_k / sqrt S_k):
+// u_k the x0-sensitivity of measurement k's innovation, v_k its value at
+// x0 = 0, S_k its variance.  Kept as a factor of these rows rather than as
+// information sums, the density involves no difference of terms of order
+// v^2 / S, which nearly noise-free data make huge.  A series' first chunk
+// starts from the prior instead (A = 0, R = 0): its summary is the filter's
+// state and likelihood.
+template <int J, int FT>
+__global__ __launch_bounds__(WAVE) void k_sqrt_summ(DevPlan p, DevParams pr, double* __restrict__ out) {
+  using Dm = Dims<M, J>;
+  constexpr int D = Dm::D, NX = Dm::NX, NC = D + 3 * M, NE = 1 + NX, NPZ = (NX + 1) * (NX + 2) / 2;
+  const int q = threadIdx.x & (SQ_GROUP - 1);
+  const int64_t c = (int64_t)blockIdx.x * (WAVE / SQ_GROUP) + threadIdx.x / SQ_GROUP;
+  const bool live = c < p.n_chunks;  // uniform over the group
+  const int64_t cc = live ? c : 0;
+  const int64_t b = p.chunk_series[cc];
+  TermConst tc[M];
+  load_terms<Dm>(pr, b, tc);
+  const double* itab = ((FT & 2) && pr.ni > 0) ? pr.itab + b * ITAB_W : nullptr;
+  const double jit = pr.jit[b];
+  const double jit2 = jit * jit;
+  const int tl = q < M ? q : 0;
+  const TermConst tmine = pr.tc[b * M + tl];
+  const double* cmine = pr.coef + (b * M + tl) * 2 * NCOEF;
+  // row q of the factor U and of [b | S] (the mean b + S x0)
+  double row[NC], ext[NE];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) row[k] = 0.0;
+#pragma unroll
+  for (int e = 0; e < NE; ++e) ext[e] = 0.0;
+  if (p.chunk_first[cc]) {
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+      row[2 * t] = (q == 2 * t) ? tc[t].sigma : row[2 * t];
+      row[2 * t + 1] = (q == 2 * t + 1) ? tc[t].sigma * second_prior<(FT & 1) != 0>(tc[t]) : row[2 * t + 1];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NX; ++k) ext[1 + k] = (q == k) ? 1.0 : 0.0;
+  }
+  double Z[NPZ], c0 = 0.0;
+#pragma unroll
+  for (int k = 0; k < NPZ; ++k) Z[k] = 0.0;
+  const int32_t l = p.chunk_lane[cc];
+  const int64_t ev0 = p.wv_ev0[p.chunk_wv[cc]];
+  const int32_t len = live ? p.chunk_len[cc] : 0;
+  for (int32_t k = 0; k < len; ++k) {
+    double dt;
+    uint32_t info;
+    const Obs o = load_event<Dm>(p, ev0 + (int64_t)k * WAVE + l, jit2, dt, info, itab);
+    TermQ mine, tq[M];
+    discretise<1, DiscFull, 2 * NCOEF, (FT & 1) != 0>(&tmine, cmine, dt, &mine);
+#pragma unroll
+    for (int t = 0; t < M; ++t) tq[t] = grp_get_term(mine, t);
+    sqrt_predict_row<Dm, NE>(row, ext, q, tq, ev_open(info));
+    double wz[NE], rs;
+    (void)sqrt_update_row<Dm, NE>(row, ext, q, info, o, wz, &rs);
+    // log sqrt(2 pi S) (taken from sqrt S itself: the innovation at x0 = 0,
+    // whose square goes to the factor, can be many times sqrt S); nothing
+    // without a measurement
+    if (o.has) c0 += 0.5 * LOG_2PI + log(rs);
+    // the row (u / sqrt S, v / sqrt S), u = S^T h, appended to the factor by
+    // rotations (wz = (v, u) / sqrt S; zero without a measurement)
+    double n[NX + 1];
+#pragma unroll
+    for (int e = 0; e < NX; ++e) n[e] = wz[1 + e];
+    n[NX] = wz[0];
+#pragma unroll
+    for (int r = 0; r <= NX; ++r) {
+      double cs, sn, rr;
+      plane_rotation(Z[lidx(r, r)], n[r], cs, sn, rr);
+      Z[lidx(r, r)] = rr;
+#pragma unroll
+      for (int i = r + 1; i <= NX; ++i) {
+        const double z = Z[lidx(i, r)];
+        Z[lidx(i, r)] = fma(cs, z, sn * n[i]);
+        n[i] = fma(-sn, z, cs * n[i]);
+      }
+    }
+  }
+  if (!live) return;
+  const int64_t C = p.n_chunks;
+  if (q < NX) {
+#pragma unroll
+    for (int k = 0; k < NX; ++k) out[(sq_A(NX) + q * NX + k) * C + c] = ext[1 + k];
+    out[(sq_b(NX) + q) * C + c] = ext[0];
+#pragma unroll
+    for (int k = 0; k < NX; ++k)
+      if (k <= q) out[(sq_U(NX) + q * (q + 1) / 2 + k) * C + c] = row[k];
+  }
+  if (q == 0) {
+#pragma unroll
+    for (int k = 0; k < NPZ; ++k) out[(sq_Z(NX) + k) * C + c] = Z[k];
+    out[sq_c0(NX) * C + c] = c0;
+  }
+}
+
+// the first NP rows of X (NR x NC) brought to lower-triangular form in place
+// by Householder reflections from the right (each scaled by the exponent of
+// its pivot row's largest entry), applied to every row: on return X[i][k] for
+// k <= i < NP is the factor of the first NP rows, and the rows below carry the
+// same orthogonal transformation
+template <int NR, int NC, int NP>
+__device__ __forceinline__ void sq_tria(double (&X)[NR][NC]) {
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    double mx = 0.0;
+#pragma unroll
+    for (int k = i; k < NC; ++k) mx = fmax(mx, fabs(X[i][k]));
+    if (!(mx > 0.0)) continue;
+    int e;
+    (void)frexp(mx, &e);
+    double v[NC], n2 = 0.0;
+#pragma unroll
+    for (int k = i; k < NC; ++k) {
+      v[k] = ldexp(X[i][k], -e);
+      n2 = fma(v[k], v[k], n2);
+    }
+    const double nrm = sqrt(n2);
+    const double alpha = v[i] >= 0.0 ? -nrm : nrm;
+    const double vv = 2.0 * nrm * (nrm + fabs(v[i]));
+    v[i] -= alpha;
+    const double beta = 2.0 / vv;
+#pragma unroll
+    for (int r = i + 1; r < NR; ++r) {
+      double w = 0.0;
+#pragma unroll
+      for (int k = i; k < NC; ++k) w = fma(X[r][k], v[k], w);
+      w *= beta;
+#pragma unroll
+      for (int k = i; k < NC; ++k) X[r][k] = fma(-w, v[k], X[r][k]);
+    }
+    X[i][i] = ldexp(alpha, e);
+#pragma unroll
+    for (int k = i + 1; k < NC; ++k) X[i][k] = 0.0;
+  }
+}
+
+// the series' log-likelihood from its chunk summaries in time order: the
+// state after the first chunk is Gaussian (m, L L^T); a further chunk acts on
+// its start state x0 as the measurement rho = R x0 + e, e ~ N(0, I), plus the
+// constant -c0 - eps^2 / 2.  In array form, [[I, W], [0, L]] with W = R L is
+// brought to [[Xi, 0], [Kb, L']] by reflections: Xi Xi^T = I + W W^T, the
+// chunk's likelihood adds -c0 - eps^2 / 2 - log det Xi - |y|^2 / 2 with
+// y = Xi^-1 (R m - rho), the start state given the chunk is (m - Kb y,
+// L' L'^T), and the chunk moves it to its end (A m' + b, tria[A L' | U])
+template <int J, int FT>
+__global__ __launch_bounds__(WAVE) void k_sqrt_fold(DevPlan p, DevParams pr, const double* __restrict__ sm,
+                                                    const CallArgs* __restrict__ args) {
+  constexpr int N = 2 * M;
+  const int64_t b = (int64_t)blockIdx.x * WAVE + threadIdx.x;
+  if (b >= p.n_series) return;
+  const int64_t C = p.n_chunks;
+  const int32_t cfirst = p.series_chunk0[b], nch = p.series_nch[b];
+  double m[N], L[N][N], ll = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    m[i] = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) L[i][k] = 0.0;
+  }
+  for (int32_t qq = 0; qq < nch; ++qq) {
+    const int64_t c = cfirst + qq;
+    auto get = [&](int f) { return sm[(int64_t)f * C + c]; };
+    double bb[N], U[N][N], A[N][N], Zf[N + 1][N + 1];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      bb[i] = get(sq_b(N) + i);
+#pragma unroll
+      for (int k = 0; k < N; ++k) U[i][k] = k <= i ? get(sq_U(N) + i * (i + 1) / 2 + k) : 0.0;
+    }
+    const double cz = get(sq_c0(N));
+    if (qq == 0) {  // the series' first chunk, filtered from the prior
+      const double eps = get(sq_Z(N) + lidx(N, N));
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        m[i] = bb[i];
+#pragma unroll
+        for (int k = 0; k < N; ++k) L[i][k] = U[i][k];
+      }
+      ll = -cz - 0.5 * eps * eps;
+      continue;
+    }
+#pragma unroll
+    for (int i = 0; i <= N; ++i)
+#pragma unroll
+      for (int k = 0; k <= N; ++k) Zf[i][k] = k <= i ? get(sq_Z(N) + lidx(i, k)) : 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int k = 0; k < N; ++k) A[i][k] = get(sq_A(N) + i * N + k);
+    // d = R m - rho and the array [[I, W], [0, L]], W = R L, R = Zf^T
+    // restricted to the state, rho the last row of Zf
+    double d[N], X2[2 * N][2 * N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double a = -Zf[N][i];
+#pragma unroll
+      for (int k = i; k < N; ++k) a = fma(Zf[k][i], m[k], a);
+      d[i] = a;
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        double w = 0.0;
+#pragma unroll
+        for (int r = i; r < N; ++r) w = fma(Zf[r][i], L[r][k], w);
+        X2[i][N + k] = w;
+        X2[i][k] = i == k ? 1.0 : 0.0;
+        X2[N + i][k] = 0.0;
+        X2[N + i][N + k] = L[i][k];
+      }
+    }
+    sq_tria<2 * N, 2 * N, N>(X2);  // [[Xi, 0], [Kb, L']]
+    // y = Xi^-1 d
+    double y[N], logdet = 0.0, yy = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double a = d[i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) a = fma(-X2[i][k], y[k], a);
+      y[i] = a / X2[i][i];
+      logdet += log(fabs(X2[i][i]));
+      yy = fma(y[i], y[i], yy);
+    }
+    const double eps = Zf[N][N];
+    ll += -cz - 0.5 * eps * eps - logdet - 0.5 * yy;
+    // the start state given the chunk: m' = m - Kb y, factor L'
+    double mp[N], Lp[N][N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      double a = m[r];
+#pragma unroll
+      for (int k = 0; k < N; ++k) a = fma(-X2[N + r][k], y[k], a);
+      mp[r] = a;
+#pragma unroll
+      for (int k = 0; k < N; ++k) Lp[r][k] = X2[N + r][N + k];
+    }
+    double X[N][2 * N];
+    // to the chunk's end: m = A m' + b, L = tria[A L' | U]
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double a = bb[i];
+#pragma unroll
+      for (int k = 0; k < N; ++k) a = fma(A[i][k], mp[k], a);
+      m[i] = a;
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < N; ++r) s = fma(A[i][r], Lp[r][k], s);
+        X[i][k] = s;
+        X[i][N + k] = U[i][k];
+      }
+    }
+    sq_tria<N, 2 * N, N>(X);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int k = 0; k < N; ++k) L[i][k] = k <= i ? X[i][k] : 0.0;
+  }
   ll += inst_loglik(pr, b);
   const bool pbad = pr.bad[b] != 0, good = isfinite(ll);
   double* const loglik = args->loglik;
@@ -747,6 +1023,22 @@ void launch_sqrt(const Launch& L, const DevPlan& p, const DevParams& pr, const i
 }
 
 template <int J, int FT>
+void launch_sqrt_split(const Launch& L, const DevPlan& p, const DevParams& pr, double* summ, const CallArgs* args) {
+  if (p.n_series == 0) return;
+  constexpr int per_wave = WAVE / SQ_GROUP;
+  if (p.n_chunks > 0) {
+    prof_begin("k_sqrt_summ", L.stream);
+    hipLaunchKernelGGL((k_sqrt_summ<J, FT>), dim3((unsigned)((p.n_chunks + per_wave - 1) / per_wave)), dim3(WAVE), 0,
+                       L.stream, p, pr, summ);
+    prof_end("k_sqrt_summ", L.stream);
+  }
+  prof_begin("k_sqrt_fold", L.stream);
+  hipLaunchKernelGGL((k_sqrt_fold<J, FT>), dim3((unsigned)((p.n_series + WAVE - 1) / WAVE)), dim3(WAVE), 0, L.stream,
+                     p, pr, summ, args);
+  prof_end("k_sqrt_fold", L.stream);
+}
+
+template <int J, int FT>
 void launch_smooth(const Launch& L, const DevPlan& p, const DevParams& pr, const double* bstate, const double* bsmooth,
                    const RecSlots& rec, const DevTests& tests, double* mean_test, double* var_test, double* mean_data,
                    double* var_data) {
@@ -787,6 +1079,7 @@ KernelSet make_set() {
   k.adjoint = &launch_adjoint<J, FT>;
   k.plain = &launch_plain<J, FT>;
   k.sqrt = &launch_sqrt<J, FT>;
+  k.sqrt_split = &launch_sqrt_split<J, FT>;
   k.smooth = &launch_smooth<J, FT>;
   k.adjoint_occupancy = &adjoint_occupancy<J, FT>;
   k.smooth_occupancy = &smooth_occupancy<J, FT>;

@@ -42,6 +42,7 @@
 #pragma once
 
 #include "gp_ssm_filter.h"
+#include "plan.h"
 
 namespace gpssm {
 
@@ -91,6 +92,19 @@ __device__ __forceinline__ double grp_get(double v, int i) {
   }
 }
 
+// fields of a chunk summary of the time-split square-root filter (N the SHO
+// state size; per chunk, field f at f * n_chunks + chunk): A (N x N, row
+// major), b (N), U (lower triangle by rows), Z ((N + 1) x (N + 1) lower
+// triangle by rows), c0
+__host__ __device__ constexpr int sq_A(int) { return 0; }
+__host__ __device__ constexpr int sq_b(int N) { return N * N; }
+__host__ __device__ constexpr int sq_U(int N) { return N * N + N; }
+__host__ __device__ constexpr int sq_Z(int N) { return N * N + N + N * (N + 1) / 2; }
+__host__ __device__ constexpr int sq_c0(int N) { return sq_Z(N) + (N + 1) * (N + 2) / 2; }
+__host__ __device__ constexpr int sq_fields(int N) { return sq_c0(N) + 1; }
+// position of entry (i, j), j <= i, of a lower triangle packed by rows
+__host__ __device__ constexpr int lidx(int i, int j) { return i * (i + 1) / 2 + j; }
+
 // the step quantities of lane i's term
 __device__ __forceinline__ TermQ grp_get_term(const TermQ& u, int i) {
   TermQ r;
@@ -136,14 +150,16 @@ __device__ __forceinline__ constexpr bool sq_involved(int i, int c) {
 }
 
 // time update of this lane's row (row[0..D) of L, then the 3M noise columns,
-// rebuilt here) and mean entry mq; q: the lane's row, tq: the terms' step
-// quantities, open: the integrators open during the step
-template <class Dm>
-__device__ __forceinline__ void sqrt_predict_row(double* row, double& mq, int q, const TermQ* tq, uint32_t open) {
+// rebuilt here) and of its NE entries ext that the transition maps like the
+// mean (ext[0] the mean entry; the conditional filter's sensitivity row
+// follows); q: the lane's row, tq: the terms' step quantities, open: the
+// integrators open during the step
+template <class Dm, int NE>
+__device__ __forceinline__ void sqrt_predict_row(double* row, double* ext, int q, const TermQ* tq, uint32_t open) {
   constexpr int M = Dm::M, J = Dm::J, NX = Dm::NX, D = Dm::D, NC = D + 3 * M;
-  // the integrators' increment fbar . (old x rows | old x means), summed over
-  // the group (lanes outside the x rows contribute zero)
-  double sum[D + 1];
+  // the integrators' increment fbar . (old x rows | old x entries of ext),
+  // summed over the group (lanes outside the x rows contribute zero)
+  double sum[D + NE];
   {
     double f = 0.0;
 #pragma unroll
@@ -153,9 +169,10 @@ __device__ __forceinline__ void sqrt_predict_row(double* row, double& mq, int q,
     }
 #pragma unroll
     for (int c = 0; c < D; ++c) sum[c] = f * row[c];
-    sum[D] = f * mq;
 #pragma unroll
-    for (int c = 0; c <= D; ++c) sum[c] = grp_sum(sum[c]);
+    for (int e = 0; e < NE; ++e) sum[D + e] = f * ext[e];
+#pragma unroll
+    for (int c = 0; c < D + NE; ++c) sum[c] = grp_sum(sum[c]);
   }
   // x rows: Phi_t applied to the rows (2t, 2t+1), partners at xor distance 1:
   // row 2t' = a00 row 2t + a01 row 2t+1, row 2t+1' = -a01 row 2t + a11 row 2t+1
@@ -172,8 +189,11 @@ __device__ __forceinline__ void sqrt_predict_row(double* row, double& mq, int q,
       const double pc = grp_partner(row[c]);
       row[c] = xrow ? fma(as, row[c], ap * pc) : row[c];
     }
-    const double pm = grp_partner(mq);
-    mq = xrow ? fma(as, mq, ap * pm) : mq;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const double pe = grp_partner(ext[e]);
+      ext[e] = xrow ? fma(as, ext[e], ap * pe) : ext[e];
+    }
   }
   // open integrator rows: + the increment
   double oq = 0.0;
@@ -181,7 +201,8 @@ __device__ __forceinline__ void sqrt_predict_row(double* row, double& mq, int q,
   for (int j = 0; j < J; ++j) oq = (q == NX + j && ((open >> j) & 1u)) ? 1.0 : oq;
 #pragma unroll
   for (int c = 0; c < D; ++c) row[c] = fma(oq, sum[c], row[c]);
-  mq = fma(oq, sum[D], mq);
+#pragma unroll
+  for (int e = 0; e < NE; ++e) ext[e] = fma(oq, sum[D + e], ext[e]);
   // noise columns: this row of G_m chol(Q3_m) for every term (a pivot that
   // rounding leaves at or below zero gives a zero column, as for a real term's
   // absent second state)
@@ -251,18 +272,28 @@ __device__ __forceinline__ void sqrt_predict_row(double* row, double& mq, int q,
 }
 
 // measurement update (when the event carries one) and the exposure's reset of
-// this lane's row and mean entry; returns the log-likelihood term (the same on
-// every lane of the group)
-template <class Dm>
-__device__ __forceinline__ double sqrt_update_row(double* row, double& mq, int q, uint32_t info, const Obs& o) {
+// this lane's row and its entries ext (ext[0] the mean entry; the others, a
+// sensitivity row of the mean, are updated like it with the measurement
+// taken as zero); returns the log-likelihood term and, in wz (NE entries, when
+// given), h^T ext / sqrt S with the innovation in place of h^T ext[0], and in
+// *rs sqrt S, all the same on every lane of the group (wz zero and *rs one
+// when there is no measurement)
+template <class Dm, int NE>
+__device__ __forceinline__ double sqrt_update_row(double* row, double* ext, int q, uint32_t info, const Obs& o,
+                                                  double* wz = nullptr, double* rs = nullptr) {
   constexpr int M = Dm::M, NX = Dm::NX, D = Dm::D;
   const uint32_t kind = ev_kind(info);
   const int z = NX + (int)ev_slot(info);  // the closing integrator's row
   double ll = 0.0;
+  if (wz) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) wz[e] = 0.0;
+  }
+  if (rs) *rs = 1.0;
   if (o.has) {
-    // h^T L and h . m: the slot's row over its exposure length at an end, the
-    // sum of the terms' first rows at an instantaneous measurement
-    double a[D], hm;
+    // h^T L and h^T ext: the slot's row over its exposure length at an end,
+    // the sum of the terms' first rows at an instantaneous measurement
+    double a[D + NE];
     if (kind == EV_END) {
       // the slot's lane, selected among the integrator rows
       const uint32_t slot = ev_slot(info);
@@ -270,32 +301,22 @@ __device__ __forceinline__ double sqrt_update_row(double* row, double& mq, int q
 #pragma unroll
       for (int j = 0; j < Dm::J; ++j) invd += o.a[j];  // one nonzero entry, the slot's
 #pragma unroll
-      for (int k = 0; k < D; ++k) {
+      for (int k = 0; k < D + NE; ++k) {
+        const double x = k < D ? row[k] : ext[k - D];
         double v = 0.0;
 #pragma unroll
         for (int j = 0; j < Dm::J; ++j) {
-          const double vj = grp_get(row[k], NX + j);
+          const double vj = grp_get(x, NX + j);
           v = (slot == (uint32_t)j) ? vj : v;
         }
         a[k] = v * invd;
       }
-      double v = 0.0;
-#pragma unroll
-      for (int j = 0; j < Dm::J; ++j) {
-        const double vj = grp_get(mq, NX + j);
-        v = (slot == (uint32_t)j) ? vj : v;
-      }
-      hm = v * invd;
     } else {
       double wq = 0.0;
 #pragma unroll
       for (int t = 0; t < M; ++t) wq = (q == 2 * t) ? 1.0 : wq;
 #pragma unroll
-      for (int k = 0; k < D; ++k) a[k] = wq * row[k];
-      hm = wq * mq;
-#pragma unroll
-      for (int k = 0; k < D; ++k) a[k] = grp_sum(a[k]);
-      hm = grp_sum(hm);
+      for (int k = 0; k < D + NE; ++k) a[k] = grp_sum(wq * (k < D ? row[k] : ext[k - D]));
     }
     double r0 = sqrt(o.R), g = 0.0;
 #pragma unroll
@@ -307,14 +328,23 @@ __device__ __forceinline__ double sqrt_update_row(double* row, double& mq, int q
       row[k] = fma(-s, g, c * l);
       g = fma(c, g, s * l);
     }
-    const double w = (o.y - hm) / r0;
-    mq = fma(g, w, mq);
+    const double w = (o.y - a[D]) / r0;
+    ext[0] = fma(g, w, ext[0]);
+#pragma unroll
+    for (int e = 1; e < NE; ++e) ext[e] = fma(-g, a[D + e] / r0, ext[e]);
+    if (rs) *rs = r0;
+    if (wz) {
+      wz[0] = w;
+#pragma unroll
+      for (int e = 1; e < NE; ++e) wz[e] = a[D + e] / r0;
+    }
     ll = -0.5 * (LOG_2PI + 2.0 * log(r0) + w * w);
   }
   if (kind == EV_END && q == z) {
 #pragma unroll
     for (int c = 0; c < D; ++c) row[c] = 0.0;
-    mq = 0.0;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) ext[e] = 0.0;
   }
   return ll;
 }

@@ -180,3 +180,114 @@ def test_sqrt_full_workloads_against_batched(lib, name):
     rel = np.abs(ll_sqrt - ll) / np.abs(ll)
     print(rel.max(), np.median(rel))
     assert rel.max() < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# the square-root filter split in time (gp_ssm_plan_loglik_sqrt_split)
+# ---------------------------------------------------------------------------
+SPLITS = (dict(chunk_min=1, chunk_target=1), dict(chunk_min=1, chunk_target=3), dict())
+
+
+@pytest.mark.parametrize("M,J,T", [(1, 2, 2.0), (2, 3, 2.0), (3, 3, 2.0), (3, 4, 0.4), (4, 2, 2.0)])
+def test_sqrt_split_matches_oracle(lib, M, J, T):
+    """Chunk summaries in factor form folded per series, at one event per
+    chunk, a few and the default chunks: against the oracle and the
+    sequential square-root filter."""
+    b = W.random_small_batch(970 + 10 * M + J, B=6, n_lo=5, n_hi=70 if T > 1 else 40, M=M, J=J, T=T)
+    ref = np.array([kalman.loglik(*_args(b.series(i))) for i in range(b.n_series)])
+    seq = None
+    for opt in SPLITS:
+        plan = _plan(lib, b, **opt)
+        ll = plan.loglik_sqrt_split(b.sigma, b.omega0, b.quality, b.jitter, check=True).cpu().numpy()
+        if seq is None:
+            seq = plan.loglik_sqrt(b.sigma, b.omega0, b.quality, b.jitter, check=True).cpu().numpy()
+        rel = np.max(np.abs(ll - ref) / np.abs(ref))
+        print(M, J, opt, plan.stats()["n_chunks"], rel, np.max(np.abs(ll - seq) / np.abs(ref)))
+        assert rel < TOL
+        assert np.max(np.abs(ll - seq) / np.abs(ref)) < 1e-10
+
+
+def test_sqrt_split_real_terms_and_instruments(lib):
+    b = W.random_small_batch(981, B=5, n_lo=10, n_hi=80, M=2, J=3)
+    rng = np.random.default_rng(982)
+    ni = 3
+    lab = rng.integers(0, ni, len(b.t_start)).astype(np.int32)
+    amp = rng.uniform(0.5, 1.8, (b.n_series, ni))
+    off = rng.normal(0.0, 0.4, (b.n_series, ni))
+    kinds = ["sho", "real"]
+    ref = []
+    for i in range(b.n_series):
+        lo, hi = int(b.offsets[i]), int(b.offsets[i + 1])
+        a_n, c_n = kalman.expand_instruments(lab[lo:hi], amp[i], off[i])
+        ref.append(kalman.loglik(*_args(b.series(i)), kinds=kinds, amp=a_n, off=c_n))
+    ref = np.array(ref)
+    for opt in SPLITS:
+        plan = _plan(lib, b, **opt)
+        plan.set_term_kinds(kinds)
+        plan.set_instruments(lab, ni)
+        ll = plan.loglik_sqrt_split(b.sigma, b.omega0, b.quality, b.jitter, amp, off, check=True).cpu().numpy()
+        print(opt, np.max(np.abs(ll - ref) / np.abs(ref)))
+        assert np.max(np.abs(ll - ref) / np.abs(ref)) < TOL
+
+
+def test_sqrt_split_nearly_noise_free(lib):
+    """Measurement errors down to 1e-9 of the signal, down to one event per
+    chunk (where the covariance-form scan errs by up to 2e-6), against the
+    dense GP in high precision."""
+    cases = []
+    for noise in (1e-5, 1e-7, 1e-9):
+        for omega0 in (0.5, 5.0):
+            for inst in (True, False):
+                cases.append(CC.smooth(31, 40, noise, omega0, inst))
+    for seed in (21, 22):
+        for noise in (1e-5, 1e-9):
+            cases.append(CC.two_instruments(seed, 50, noise))
+    worst = 0.0
+    for ts, te, y, yerr, sig, w0, q in cases:
+        Le = exact.loglik(ts, te, y, yerr, sig, w0, q, 0.0, dps=80)
+        for opt in SPLITS:
+            plan = lib.Plan(np.array([0, len(ts)], dtype=np.int64), ts, te, y, yerr, **opt)
+            ll = float(plan.loglik_sqrt_split(sig[None], w0[None], q[None], np.zeros(1), check=True).cpu()[0])
+            worst = max(worst, abs(ll - Le) / abs(Le))
+            assert abs(ll - Le) < TOL * abs(Le), (opt, yerr[0], ll, Le)
+    print("worst", worst)
+
+
+@pytest.mark.parametrize("case", ["c5_prefix", "m4"])
+def test_sqrt_split_long_series_against_stored_oracle(lib, case):
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "kalman_long_scan.json")) as fh:
+        rows = {r["name"]: r for r in json.load(fh)["cases"]}
+    r = rows[case]
+    b = getattr(W, r["generator"])(**r["kwargs"])
+    for opt in (dict(chunk_min=1, chunk_target=1), dict()):
+        plan = _plan(lib, b, **opt)
+        ll = float(plan.loglik_sqrt_split(b.sigma, b.omega0, b.quality, b.jitter, check=True).cpu()[0])
+        rel = abs(ll - r["loglik"]) / abs(r["loglik"])
+        print(case, opt, plan.stats()["n_chunks"], rel)
+        assert rel < TOL
+
+
+def test_sqrt_split_status_and_full_batch(lib):
+    """Invalid hyperparameters and empty series as for the other entry
+    points; the full 1024-series gradient workload against the batched
+    path."""
+    b = W.random_small_batch(991, B=4, n_lo=5, n_hi=30, M=2, J=2)
+    offsets = np.concatenate([b.offsets[:3], b.offsets[2:]])
+    plan = lib.Plan(offsets, b.t_start, b.t_end, b.y, b.yerr)
+    rep = lambda a: np.concatenate([a[:2], a[1:2], a[2:]])
+    sig, w0, q, jit = rep(b.sigma), rep(b.omega0), rep(b.quality), rep(b.jitter)
+    good = plan.loglik_sqrt_split(sig, w0, q, jit, check=True).cpu().numpy()
+    assert good[2] == 0.0
+    bad = sig.copy()
+    bad[1, 0] = -1.0
+    ll, st = plan.loglik_sqrt_split(bad, w0, q, jit, status=True)
+    ll, st = ll.cpu().numpy(), st.cpu().numpy()
+    assert st[1] == -3 and np.isnan(ll[1])
+    keep = [i for i in range(len(good)) if i != 1]
+    assert np.all(st[keep] == 0) and np.array_equal(ll[keep], good[keep])
+    g = W.grad_1024()
+    plan = _plan(lib, g)
+    ls = plan.loglik_sqrt_split(g.sigma, g.omega0, g.quality, g.jitter, check=True).cpu().numpy()
+    lb = plan.loglik(g.sigma, g.omega0, g.quality, g.jitter, check=True).cpu().numpy()
+    print(np.max(np.abs(ls - lb) / np.abs(lb)))
+    assert np.max(np.abs(ls - lb) / np.abs(lb)) < 1e-10
