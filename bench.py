@@ -426,8 +426,8 @@ def main():
                  "speedup_batched_loglik": batched_rate / rate, "max_rel_diff_vs_batched": diff}
         print(f"[bench] plain {plain}", file=sys.stderr, flush=True)
 
-    # the square-root (Cholesky-factor) filter over the same batch, one series
-    # per lane (a robust alternative to the time-parallel path, timed once)
+    # the square-root (Cholesky-factor) filter over the same batch, whole
+    # series (a robust alternative to the time-parallel path, timed once)
     sq = None
     if not args.no_sqrt:
         plan.loglik_sqrt(sig, w0, q, jit)
@@ -437,7 +437,17 @@ def main():
         torch.cuda.synchronize()
         ts_ = time.perf_counter() - t0
         diff = float(torch.max(torch.abs(ls - ll) / torch.abs(ll)).item())
-        sq = {"ms": ts_ * 1e3, "points_per_s": points / ts_, "max_rel_diff_vs_batched": diff}
+        # and split in time at the plan's chunks (summaries in parallel, a
+        # fold per series)
+        plan.loglik_sqrt_split(sig, w0, q, jit)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lsp = plan.loglik_sqrt_split(sig, w0, q, jit)
+        torch.cuda.synchronize()
+        tsp = time.perf_counter() - t0
+        dsp = float(torch.max(torch.abs(lsp - ll) / torch.abs(ll)).item())
+        sq = {"ms": ts_ * 1e3, "points_per_s": points / ts_, "max_rel_diff_vs_batched": diff,
+              "split_ms": tsp * 1e3, "split_points_per_s": points / tsp, "split_max_rel_diff_vs_batched": dsp}
         print(f"[bench] sqrt {sq}", file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel
