@@ -472,7 +472,7 @@ struct gp_ssm_plan {
   DBuf tests_t, tests_idx, tests_c0, tests_before, prior_idx, prior_series;
   DBuf wv_order, args, kinds, itab, icnt;
   DBuf sqrt_order;  // series by decreasing event count (the square-root filter's groups)
-  DBuf sqsumm;      // chunk summaries of the time-split square-root filter
+  DBuf sqsumm, sqsumm2;  // chunk summaries of the time-split square-root filter (two tree levels)
   // the call's pointers go to `args` on the call's stream from a ring of
   // pinned host slots; an event per slot marks when its copy has been done
   CallArgs* args_host = nullptr;
@@ -499,7 +499,7 @@ struct gp_ssm_plan {
                                   &series_grp0, &series_ngrp, &wv_series, &wv_nch, &wv_len, &wv_chunk, &wv_ev0,
                                   &chunk_len, &chunk_series, &chunk_wv, &chunk_lane, &chunk_first, &series_chunk0,
                                   &series_nch, &series_seg0, &series_nseg, &series_wv0, &series_nwv, &series_dt_cdf,
-                                  &icnt, &sqrt_order, &sqsumm};
+                                  &icnt, &sqrt_order, &sqsumm, &sqsumm2};
     for (DBuf* d : self->workspace()) v.push_back(d);
     return v;
   }
@@ -1390,12 +1390,17 @@ int gp_ssm_plan_loglik_sqrt_split(gp_ssm_plan* pl, int32_t M, const double* sigm
   hipStream_t s = (hipStream_t)stream;
   if (int rc = put_args(pl, M, sigma, omega0, quality, jitter, loglik, nullptr, status, s, amp, off, 0)) return rc;
   if (int rc = reserve(pl, M, 0, false)) return rc;
-  if (int rc = pl->sqsumm.ensure(sizeof(double) * sq_fields(2 * M) * std::max<int64_t>(1, pl->host.n_chunks)))
-    return rc;
+  const size_t sbytes = sizeof(double) * sq_fields(2 * M) * std::max<int64_t>(1, pl->host.n_chunks);
+  if (int rc = pl->sqsumm.ensure(sbytes)) return rc;
+  if (int rc = pl->sqsumm2.ensure(sbytes)) return rc;
+  // levels of the tree: the most chunks of one series, halved until one
+  int32_t most = 0, levels = 0;
+  for (int32_t n : pl->host.series_nch) most = std::max(most, n);
+  while ((int64_t(1) << levels) < most) ++levels;
   enqueue_prep(pl, plan_work(pl), M, s);
   const KernelSet ks = kernel_set(M, pl->host.max_slots, pl->features(M));
   Launch L{s};
-  ks.sqrt_split(L, pl->dev(), pl->params(), pl->sqsumm.as<double>(), pl->dargs());
+  ks.sqrt_split(L, pl->dev(), pl->params(), pl->sqsumm.as<double>(), pl->sqsumm2.as<double>(), levels, pl->dargs());
   HIP_TRY(hipGetLastError());
   return 0;
 }

@@ -103,7 +103,8 @@ struct KernelSet {
                   const RecSlots& rec, double* gpart);
   void (*plain)(const Launch&, const DevPlan&, const DevParams&, int64_t series, double* loglik);
   void (*sqrt)(const Launch&, const DevPlan&, const DevParams&, const int32_t* order, const CallArgs* args);
-  void (*sqrt_split)(const Launch&, const DevPlan&, const DevParams&, double* summ, const CallArgs* args);
+  void (*sqrt_split)(const Launch&, const DevPlan&, const DevParams&, double* summ, double* tmp, int32_t levels,
+                     const CallArgs* args);
   void (*smooth)(const Launch&, const DevPlan&, const DevParams&, const double* bstate, const double* bsmooth,
                  const RecSlots& rec, const DevTests& tests, double* mean_test, double* var_test, double* mean_data,
                  double* var_data);

@@ -416,8 +416,8 @@ __global__ __launch_bounds__(WAVE) void k_sqrt(DevPlan p, DevParams pr, const in
 // ---------------------------------------------------------------------------
 // time-split square-root filter: per chunk, the filter conditioned on the
 // chunk's first SHO state x0 in factor form (SQ_GROUP lanes per chunk, four
-// chunks to a wavefront), then per series a fold of the chunk summaries in
-// order (one lane per series)
+// chunks to a wavefront), then per series a tree of pairwise combinations of
+// the chunk summaries (one lane per pair, one launch per level)
 // ---------------------------------------------------------------------------
 // Chunk summary (offsets sq_*): the chunk's end state is x0-affine with
 // mean A x0 + b and covariance U U^T; its measurements have density
@@ -560,126 +560,184 @@ __device__ __forceinline__ void sq_tria(double (&X)[NR][NC]) {
   }
 }
 
-// the series' log-likelihood from its chunk summaries in time order: the
-// state after the first chunk is Gaussian (m, L L^T); a further chunk acts on
-// its start state x0 as the measurement rho = R x0 + e, e ~ N(0, I), plus the
-// constant -c0 - eps^2 / 2.  In array form, [[I, W], [0, L]] with W = R L is
-// brought to [[Xi, 0], [Kb, L']] by reflections: Xi Xi^T = I + W W^T, the
-// chunk's likelihood adds -c0 - eps^2 / 2 - log det Xi - |y|^2 / 2 with
-// y = Xi^-1 (R m - rho), the start state given the chunk is (m - Kb y,
-// L' L'^T), and the chunk moves it to its end (A m' + b, tria[A L' | U])
+// a chunk summary of the time-split square-root filter in registers
+template <int N>
+struct SqElem {
+  double A[N][N], b[N], U[N][N], Z[N + 1][N + 1], c0;
+};
+template <int N>
+__device__ __forceinline__ void sq_load(const double* __restrict__ sm, int64_t C, int64_t c, SqElem<N>& e) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    e.b[i] = sm[(int64_t)(sq_b(N) + i) * C + c];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      e.A[i][k] = sm[(int64_t)(sq_A(N) + i * N + k) * C + c];
+      e.U[i][k] = k <= i ? sm[(int64_t)(sq_U(N) + lidx(i, k)) * C + c] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i <= N; ++i)
+#pragma unroll
+    for (int k = 0; k <= N; ++k) e.Z[i][k] = k <= i ? sm[(int64_t)(sq_Z(N) + lidx(i, k)) * C + c] : 0.0;
+  e.c0 = sm[(int64_t)sq_c0(N) * C + c];
+}
+template <int N>
+__device__ __forceinline__ void sq_store(double* __restrict__ sm, int64_t C, int64_t c, const SqElem<N>& e) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    sm[(int64_t)(sq_b(N) + i) * C + c] = e.b[i];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      sm[(int64_t)(sq_A(N) + i * N + k) * C + c] = e.A[i][k];
+      if (k <= i) sm[(int64_t)(sq_U(N) + lidx(i, k)) * C + c] = e.U[i][k];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i <= N; ++i)
+#pragma unroll
+    for (int k = 0; k <= i; ++k) sm[(int64_t)(sq_Z(N) + lidx(i, k)) * C + c] = e.Z[i][k];
+  sm[(int64_t)sq_c0(N) * C + c] = e.c0;
+}
+
+// the summary of two consecutive stretches (e1 then e2) of a series: e2's
+// density is a pseudo-measurement rho2 = R2 x1 + e of e1's end state x1 =
+// A1 x0 + b1 + U1 w.  In array form [[I, W], [0, U1]] with W = R2 U1 becomes
+// [[Xi, 0], [Kb, U1']]; with G = Xi^-1 [R2 A1 | R2 b1 - rho2], the combined
+// density gains the rows (G_A, -G_b) and eps2 in its factor (a triangularised
+// stack) and log det Xi in c0; x1 given e2's data is (A1 - Kb G_A) x0 +
+// b1 - Kb G_b with factor U1', moved on by e2: A = A2 (A1 - Kb G_A),
+// b = A2 (b1 - Kb G_b) + b2, U = tria[A2 U1' | U2]
+template <int N>
+__device__ __forceinline__ void sq_combine(const SqElem<N>& e1, const SqElem<N>& e2, SqElem<N>& e) {
+  double X2[2 * N][2 * N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double w = 0.0;
+#pragma unroll
+      for (int r = i; r < N; ++r) w = fma(e2.Z[r][i], e1.U[r][k], w);
+      X2[i][k] = i == k ? 1.0 : 0.0;
+      X2[i][N + k] = w;
+      X2[N + i][k] = 0.0;
+      X2[N + i][N + k] = e1.U[i][k];
+    }
+  sq_tria<2 * N, 2 * N, N>(X2);
+  // G = Xi^-1 [R2 A1 | R2 b1 - rho2]
+  double G[N][N + 1], logdet = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int k = 0; k <= N; ++k) {
+      double a = k < N ? 0.0 : -e2.Z[N][i];
+#pragma unroll
+      for (int r = i; r < N; ++r) a = fma(e2.Z[r][i], k < N ? e1.A[r][k] : e1.b[r], a);
+#pragma unroll
+      for (int j = 0; j < i; ++j) a = fma(-X2[i][j], G[j][k], a);
+      G[i][k] = a / X2[i][i];
+    }
+    logdet += log(fabs(X2[i][i]));
+  }
+  // the density's factor: tria[Z1 | rows (G_A, -G_b) as columns | eps2 e_N]
+  double Y[N + 1][2 * N + 2];
+#pragma unroll
+  for (int r = 0; r <= N; ++r) {
+#pragma unroll
+    for (int k = 0; k <= N; ++k) Y[r][k] = e1.Z[r][k];
+#pragma unroll
+    for (int i = 0; i < N; ++i) Y[r][N + 1 + i] = r < N ? G[i][r] : -G[i][N];
+    Y[r][2 * N + 1] = r == N ? e2.Z[N][N] : 0.0;
+  }
+  sq_tria<N + 1, 2 * N + 2, N + 1>(Y);
+#pragma unroll
+  for (int r = 0; r <= N; ++r)
+#pragma unroll
+    for (int k = 0; k <= N; ++k) e.Z[r][k] = k <= r ? Y[r][k] : 0.0;
+  e.c0 = e1.c0 + e2.c0 + logdet;
+  // the end state
+  double T[N][N + 1];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int k = 0; k <= N; ++k) {
+      double a = k < N ? e1.A[i][k] : e1.b[i];
+#pragma unroll
+      for (int j = 0; j < N; ++j) a = fma(-X2[N + i][j], G[j][k], a);
+      T[i][k] = a;
+    }
+  double X[N][2 * N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int k = 0; k <= N; ++k) {
+      double a = k < N ? 0.0 : e2.b[i];
+#pragma unroll
+      for (int r = 0; r < N; ++r) a = fma(e2.A[i][r], T[r][k], a);
+      if (k < N)
+        e.A[i][k] = a;
+      else
+        e.b[i] = a;
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double a = 0.0;
+#pragma unroll
+      for (int r = 0; r < N; ++r) a = fma(e2.A[i][r], X2[N + r][N + k], a);
+      X[i][k] = a;
+      X[i][N + k] = e2.U[i][k];
+    }
+  }
+  sq_tria<N, 2 * N, N>(X);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int k = 0; k < N; ++k) e.U[i][k] = k <= i ? X[i][k] : 0.0;
+}
+
+// one level of the tree over each series' summaries: with the series'
+// summaries at positions chunk0 + j, j < cnt (cnt = its chunks halved `level`
+// times, rounded up), position chunk0 + j of `out` gets the combination of
+// j's pair (2j, 2j + 1), or 2j alone when it has no partner
 template <int J, int FT>
-__global__ __launch_bounds__(WAVE) void k_sqrt_fold(DevPlan p, DevParams pr, const double* __restrict__ sm,
-                                                    const CallArgs* __restrict__ args) {
+__global__ __launch_bounds__(WAVE) void k_sqrt_combine(DevPlan p, const double* __restrict__ in,
+                                                       double* __restrict__ out, int32_t level) {
+  constexpr int N = 2 * M;
+  const int64_t c = (int64_t)blockIdx.x * WAVE + threadIdx.x;
+  if (c >= p.n_chunks) return;
+  const int64_t b = p.chunk_series[c];
+  const int64_t c0 = p.series_chunk0[b];
+  const int32_t nch = p.series_nch[b];
+  const int64_t j = c - c0;
+  const int64_t cnt = ((int64_t)nch + (int64_t(1) << level) - 1) >> level;
+  if (2 * j >= cnt) return;
+  const int64_t C = p.n_chunks;
+  SqElem<N> e1;
+  sq_load<N>(in, C, c0 + 2 * j, e1);
+  if (2 * j + 1 < cnt) {
+    SqElem<N> e2, e;
+    sq_load<N>(in, C, c0 + 2 * j + 1, e2);
+    sq_combine<N>(e1, e2, e);
+    sq_store<N>(out, C, c0 + j, e);
+  } else {
+    sq_store<N>(out, C, c0 + j, e1);
+  }
+}
+
+// each series' log-likelihood from its single remaining summary (which
+// starts from the prior, so that its density does not depend on a state):
+// -c0 - eps^2 / 2
+template <int J, int FT>
+__global__ __launch_bounds__(WAVE) void k_sqrt_total(DevPlan p, DevParams pr, const double* __restrict__ sm,
+                                                     const CallArgs* __restrict__ args) {
   constexpr int N = 2 * M;
   const int64_t b = (int64_t)blockIdx.x * WAVE + threadIdx.x;
   if (b >= p.n_series) return;
-  const int64_t C = p.n_chunks;
-  const int32_t cfirst = p.series_chunk0[b], nch = p.series_nch[b];
-  double m[N], L[N][N], ll = 0.0;
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    m[i] = 0.0;
-#pragma unroll
-    for (int k = 0; k < N; ++k) L[i][k] = 0.0;
-  }
-  for (int32_t qq = 0; qq < nch; ++qq) {
-    const int64_t c = cfirst + qq;
-    auto get = [&](int f) { return sm[(int64_t)f * C + c]; };
-    double bb[N], U[N][N], A[N][N], Zf[N + 1][N + 1];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      bb[i] = get(sq_b(N) + i);
-#pragma unroll
-      for (int k = 0; k < N; ++k) U[i][k] = k <= i ? get(sq_U(N) + i * (i + 1) / 2 + k) : 0.0;
-    }
-    const double cz = get(sq_c0(N));
-    if (qq == 0) {  // the series' first chunk, filtered from the prior
-      const double eps = get(sq_Z(N) + lidx(N, N));
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        m[i] = bb[i];
-#pragma unroll
-        for (int k = 0; k < N; ++k) L[i][k] = U[i][k];
-      }
-      ll = -cz - 0.5 * eps * eps;
-      continue;
-    }
-#pragma unroll
-    for (int i = 0; i <= N; ++i)
-#pragma unroll
-      for (int k = 0; k <= N; ++k) Zf[i][k] = k <= i ? get(sq_Z(N) + lidx(i, k)) : 0.0;
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int k = 0; k < N; ++k) A[i][k] = get(sq_A(N) + i * N + k);
-    // d = R m - rho and the array [[I, W], [0, L]], W = R L, R = Zf^T
-    // restricted to the state, rho the last row of Zf
-    double d[N], X2[2 * N][2 * N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      double a = -Zf[N][i];
-#pragma unroll
-      for (int k = i; k < N; ++k) a = fma(Zf[k][i], m[k], a);
-      d[i] = a;
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        double w = 0.0;
-#pragma unroll
-        for (int r = i; r < N; ++r) w = fma(Zf[r][i], L[r][k], w);
-        X2[i][N + k] = w;
-        X2[i][k] = i == k ? 1.0 : 0.0;
-        X2[N + i][k] = 0.0;
-        X2[N + i][N + k] = L[i][k];
-      }
-    }
-    sq_tria<2 * N, 2 * N, N>(X2);  // [[Xi, 0], [Kb, L']]
-    // y = Xi^-1 d
-    double y[N], logdet = 0.0, yy = 0.0;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      double a = d[i];
-#pragma unroll
-      for (int k = 0; k < i; ++k) a = fma(-X2[i][k], y[k], a);
-      y[i] = a / X2[i][i];
-      logdet += log(fabs(X2[i][i]));
-      yy = fma(y[i], y[i], yy);
-    }
-    const double eps = Zf[N][N];
-    ll += -cz - 0.5 * eps * eps - logdet - 0.5 * yy;
-    // the start state given the chunk: m' = m - Kb y, factor L'
-    double mp[N], Lp[N][N];
-#pragma unroll
-    for (int r = 0; r < N; ++r) {
-      double a = m[r];
-#pragma unroll
-      for (int k = 0; k < N; ++k) a = fma(-X2[N + r][k], y[k], a);
-      mp[r] = a;
-#pragma unroll
-      for (int k = 0; k < N; ++k) Lp[r][k] = X2[N + r][N + k];
-    }
-    double X[N][2 * N];
-    // to the chunk's end: m = A m' + b, L = tria[A L' | U]
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      double a = bb[i];
-#pragma unroll
-      for (int k = 0; k < N; ++k) a = fma(A[i][k], mp[k], a);
-      m[i] = a;
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        double s = 0.0;
-#pragma unroll
-        for (int r = 0; r < N; ++r) s = fma(A[i][r], Lp[r][k], s);
-        X[i][k] = s;
-        X[i][N + k] = U[i][k];
-      }
-    }
-    sq_tria<N, 2 * N, N>(X);
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int k = 0; k < N; ++k) L[i][k] = k <= i ? X[i][k] : 0.0;
+  double ll = 0.0;
+  if (p.series_nch[b] > 0) {
+    const int64_t C = p.n_chunks, c = p.series_chunk0[b];
+    const double eps = sm[(int64_t)(sq_Z(N) + lidx(N, N)) * C + c];
+    ll = -sm[(int64_t)sq_c0(N) * C + c] - 0.5 * eps * eps;
   }
   ll += inst_loglik(pr, b);
   const bool pbad = pr.bad[b] != 0, good = isfinite(ll);
@@ -1023,19 +1081,30 @@ void launch_sqrt(const Launch& L, const DevPlan& p, const DevParams& pr, const i
 }
 
 template <int J, int FT>
-void launch_sqrt_split(const Launch& L, const DevPlan& p, const DevParams& pr, double* summ, const CallArgs* args) {
+void launch_sqrt_split(const Launch& L, const DevPlan& p, const DevParams& pr, double* summ, double* tmp,
+                       int32_t levels, const CallArgs* args) {
   if (p.n_series == 0) return;
   constexpr int per_wave = WAVE / SQ_GROUP;
+  double* cur = summ;
   if (p.n_chunks > 0) {
     prof_begin("k_sqrt_summ", L.stream);
     hipLaunchKernelGGL((k_sqrt_summ<J, FT>), dim3((unsigned)((p.n_chunks + per_wave - 1) / per_wave)), dim3(WAVE), 0,
                        L.stream, p, pr, summ);
     prof_end("k_sqrt_summ", L.stream);
+    // the tree over each series' summaries, one level per launch
+    double* nxt = tmp;
+    for (int32_t lv = 0; lv < levels; ++lv) {
+      prof_begin("k_sqrt_combine", L.stream);
+      hipLaunchKernelGGL((k_sqrt_combine<J, FT>), dim3((unsigned)((p.n_chunks + WAVE - 1) / WAVE)), dim3(WAVE), 0,
+                         L.stream, p, cur, nxt, lv);
+      prof_end("k_sqrt_combine", L.stream);
+      std::swap(cur, nxt);
+    }
   }
-  prof_begin("k_sqrt_fold", L.stream);
-  hipLaunchKernelGGL((k_sqrt_fold<J, FT>), dim3((unsigned)((p.n_series + WAVE - 1) / WAVE)), dim3(WAVE), 0, L.stream,
-                     p, pr, summ, args);
-  prof_end("k_sqrt_fold", L.stream);
+  prof_begin("k_sqrt_total", L.stream);
+  hipLaunchKernelGGL((k_sqrt_total<J, FT>), dim3((unsigned)((p.n_series + WAVE - 1) / WAVE)), dim3(WAVE), 0, L.stream,
+                     p, pr, cur, args);
+  prof_end("k_sqrt_total", L.stream);
 }
 
 template <int J, int FT>
