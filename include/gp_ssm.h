@@ -275,13 +275,15 @@ int gp_ssm_plan_loglik_sqrt(gp_ssm_plan* plan, int32_t n_terms, const double* si
  * x0, in factor form (16 GPU lanes per chunk, one row of the factor each),
  * summarised as the end state's x0-affine mean A x0 + b and covariance
  * factor U, and the chunk's density of its measurements as a function of x0,
- * exp(-c0 - x0^T Z Z^T x0 / 2 + eta^T x0) with the information factor Z
- * (rank-one updates by rotations); then, per series, the summaries folded in
- * order (one lane per series), each combination through the factor of
- * I + W W^T, W = L^T Z, so that no covariance is formed from a difference.
+ * exp(-c0 - |R x0 - rho|^2 / 2 - eps^2 / 2) with [[R, rho], [0, eps]] a
+ * triangular factor of the measurements' whitened rows
+ * (rank-one updates by rotations); then, per series, the summaries combined
+ * pairwise in a tree (one GPU lane per pair, one launch per level), each
+ * combination taking the second summary as a measurement of the first's end
+ * state in array form, so that no covariance is formed from a difference.
  * The same model and arguments as gp_ssm_plan_loglik_sqrt; device memory
- * for the summaries, about 120 doubles per chunk at three terms, is
- * allocated on the first call. */
+ * for two levels of summaries, about 2 x 92 doubles per chunk at three terms,
+ * is allocated on the first call. */
 int gp_ssm_plan_loglik_sqrt_split(gp_ssm_plan* plan, int32_t n_terms, const double* sigma, const double* omega0,
                                   const double* quality, const double* jitter, const double* amp, const double* off,
                                   double* loglik, int32_t* status, void* stream);

@@ -2,7 +2,8 @@
 (quadrature + Cholesky, Sec. 3.1 and Sec. 2.4): exposure sets with equal
 times, zero-length exposures and overlaps up to three deep (the strategies of
 interval_strategies.py), one or two SHO terms with random hyperparameters,
-with and without jitter, under two chunkings, and the square-root filter.
+with and without jitter, under two chunkings, and the square-root filter
+(sequential and split in time).
 Log-likelihood within 1e-9 of max(1, |L|), gradient within 1e-6 (relative
 to max(|g_i|, 1e-3 max|g|)).
 The examples are derandomized: every run tries the same ones."""
@@ -46,6 +47,8 @@ def test_fuzzed_tiny_problems_match_dense(lib, ser, M, seed, jitter, chunked):
     assert int(st_.cpu().numpy()[0]) == 0
     assert abs(ll - L) <= 1e-9 * max(1.0, abs(L)), (ll, L)
     ls = float(plan.loglik_sqrt(sig[None], w0[None], q[None], np.array([jitter]), check=True).cpu().numpy()[0])
+    assert abs(ls - L) <= 1e-9 * max(1.0, abs(L)), (ls, L)
+    ls = float(plan.loglik_sqrt_split(sig[None], w0[None], q[None], np.array([jitter]), check=True).cpu().numpy()[0])
     assert abs(ls - L) <= 1e-9 * max(1.0, abs(L)), (ls, L)
     if jitter == 0.0:
         assert g[-1] == 0.0

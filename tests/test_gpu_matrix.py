@@ -2,10 +2,10 @@
 count (1-4) with up to four overlapping exposures, each with real terms
 mixed in, instrument amplitudes and offsets, or both, under two chunkings;
 log-likelihood, gradient (sampled series, central differences of the
-long-double oracle), smoother and square-root filter against the oracle.
-These combinations select the extended kernels (real terms, instrument
-tables) at every slot count, including those whose per-event state spills to
-LDS (four open exposures).
+long-double oracle), smoother and square-root filter (sequential and split in
+time) against the oracle.  These combinations select the extended kernels
+(real terms, instrument tables) at every slot count, including those whose
+per-event state spills to LDS (four open exposures).
 
 Tolerances as in test_gpu_parity: log-likelihood 1e-9 relative, gradient
 1e-6 (relative to max(|g_i|, 1e-3 max|g|)), smoothed moments 1e-9 of the
@@ -105,6 +105,8 @@ def test_feature_matrix(lib, M, J, feature):
         assert rel < 1e-9
         # the square-root filter's kernel of the same feature set
         ls = plan.loglik_sqrt(b.sigma, b.omega0, b.quality, b.jitter, amp, off, check=True).cpu().numpy()
+        assert np.max(np.abs(ls - ref) / np.abs(ref)) < 1e-9
+        ls = plan.loglik_sqrt_split(b.sigma, b.omega0, b.quality, b.jitter, amp, off, check=True).cpu().numpy()
         assert np.max(np.abs(ls - ref) / np.abs(ref)) < 1e-9
         grads.append(g)
         o = plan.smooth(b.sigma, b.omega0, b.quality, b.jitter, to, tt, amp=amp, off=off)
