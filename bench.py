@@ -240,6 +240,10 @@ def _leg_c5(gp, legs, dev, prof_run, steps, warmup):
     ts_ = _timed(lambda: plan.smooth(*a, to, t_test), steps, warmup)
     sm = plan.smooth(*a, to, t_test)
     sm_finite = all(bool(torch.isfinite(sm[k]).all().item()) for k in ("mean_data", "var_data", "mean_test", "var_test"))
+    # the square-root filter split in time (its chunk summaries combined in a tree)
+    tsq = _timed(lambda: plan.loglik_sqrt_split(*a), steps, warmup)
+    lsq = plan.loglik_sqrt_split(*a)
+    sq_rel = float((torch.abs(lsq - ll) / torch.abs(ll)).max().item())
     # the plain filter on the first 1e5 exposures of the same series (a sub-plan), projected to 1e7
     nsub = 100_000
     sub = gp.Plan(np.array([0, nsub], dtype=np.int64), b.t_start[:nsub], b.t_end[:nsub], b.y[:nsub], b.yerr[:nsub])
@@ -250,13 +254,14 @@ def _leg_c5(gp, legs, dev, prof_run, steps, warmup):
         "points": pts, "terms": b.n_terms, "slots": st["max_slots"], "chunks": st["n_chunks"],
         "segments": st["n_segments"], "loglik_ms": tl * 1e3, "loglik_grad_ms": tg * 1e3,
         "smooth_ms": ts_ * 1e3, "smooth_test_times": len(t_test), "smooth_finite": sm_finite,
+        "sqrt_split_loglik_ms": tsq * 1e3, "sqrt_split_max_rel_diff": sq_rel,
         "plain_gpu_filter_projected_ms": proj * 1e3, "plain_gpu_filter_measured": f"{nsub} exposures in {tsub * 1e3:.1f} ms",
         "scan_speedup_vs_plain": proj / tl, "loglik_finite": bool(torch.isfinite(ll).all().item()),
         "loglik_grad_median_replay_ms": _median_replay(lambda: plan.loglik_grad(*a), 5) * 1e3,
         "kernels_ms": prof_run(lambda: plan.loglik_grad(*a)), "plan_s": tp, "generate_s": gen,
         "device_memory": _plan_memory(plan)}
     print(f"[bench] C5 {legs['C5_long_1e7']}", file=sys.stderr, flush=True)
-    del plan, sub, b, a, sm
+    del plan, sub, b, a, sm, lsq
     torch.cuda.empty_cache()
 
 
