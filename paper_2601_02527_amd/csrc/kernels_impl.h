@@ -484,7 +484,9 @@ __global__ __launch_bounds__(WAVE) void k_sqrt_summ(DevPlan p, DevParams pr, dou
     // without a measurement
     if (o.has) c0 += 0.5 * LOG_2PI + log(rs);
     // the row (u / sqrt S, v / sqrt S), u = S^T h, appended to the factor by
-    // rotations (wz = (v, u) / sqrt S; zero without a measurement)
+    // rotations (wz = (v, u) / sqrt S); nothing to append without a
+    // measurement (the branch is uniform over the group)
+    if (!o.has) continue;
     double n[NX + 1];
 #pragma unroll
     for (int e = 0; e < NX; ++e) n[e] = wz[1 + e];
